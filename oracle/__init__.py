@@ -1,0 +1,26 @@
+"""Plain FP64 CPU oracle for the HR DD NM-ROM (arXiv 2305.15163).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library, its Python
+binding, the benchmark's timed leg) may import, call or link this package.  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg use it.
+
+The oracle shares no code with the GPU path.  It is written from the paper, in its
+notation and order, with numpy/scipy primitives (sparse products, dense solves, SVD)
+and no blocking or fusion beyond what the paper states:
+
+  burgers.py         Section 7.1: exact solution, central-difference residual and Jacobian
+                     in the Kronecker/matrix form of the paper, monolithic Newton FOM.
+  ddmaps.py          Section 2: residual/interior/interface sampling, ports, A_i.
+  autoencoder.py     Sections 3.4, 5.1, 7.3: banded masks, shallow sparse autoencoders,
+                     hand-written gradients, Adam training.
+  hyperreduction.py  Sections 3.3, 5.3-5.4: POD energy criterion, greedy collocation
+                     sampling, subnet extraction.
+  rom.py             Section 4: WFPC DD-LSPG objective with collocation HR, Lagrange-
+                     Gauss-Newton SQP with a full dense KKT solve and Armijo backtracking;
+                     DD-FOM SQP; LS-ROM; relative error (eq. relative_error).
+  mlp.py             learned initial-iterate proposal (forward/backward, FP64).
+  build_model.py     offline pipeline (snapshots -> autoencoders -> HR -> model pack).
+
+Parity unpinned: the greedy sampler (hyperreduction.greedy_sample) follows the cited
+algorithm by reading only; it is pinned by invariants, not by values.
+"""

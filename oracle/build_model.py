@@ -1,0 +1,150 @@
+"""Offline pipeline (Sections 7.2-7.3): FOM snapshots -> subdomain autoencoders ->
+residual POD + greedy collocation sampling -> Gaussian C -> model pack (.npz).
+
+The pack holds only inputs of the online solve (decoder weights, sampled nodes, C,
+grid and split); both the oracle and the GPU library derive everything else (DD maps,
+ports, A_i, C A_i, subnets, stencil gathers) on their own.
+
+Usage:  python -m oracle.build_model cfg0 [--out models/cfg0.npz] [--workers 8]
+
+Recipes (sizes from the workload definitions; readings where they are silent):
+  * snapshots: monolithic FOM solves on a tensor (a, lambda) grid, restricted to the
+    subdomains ("top-down", Section 7.2); residual snapshots are the Newton residual
+    histories of the same solves, restricted to each subdomain's rows;
+  * one interior and one interface autoencoder per subdomain, latent sizes (k, k/2);
+  * residual POD with energy tolerance 1e-10, greedy node sampling;
+  * n_C = floor(sum_i n_i^Gamma / 2); C has N(0,1) entries.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+import seeded_inputs as si
+from .autoencoder import ACT_SIGMOID, MaskedAE, export_decoder, train
+from .burgers import BurgersFOM, Grid, solve_fom
+from .ddmaps import build_dd
+from .hyperreduction import greedy_sample, pod_basis
+
+CONFIGS = {
+    # 36x36 grid, 2x2, latent 6 -> (6,3), width 3x, band 5, 200 epochs, 5x5 training grid, HR 20%
+    "cfg0": dict(nx=36, ny=36, nsx=2, nsy=2, n_om=6, n_ga=3, b=5, s=3, act=ACT_SIGMOID,
+                 epochs=200, batch=4, train_grid=(5, 5), hr_frac=0.20, seed=0),
+    # 240x240 grid, 4x4, latent 8 -> (8,4), width 2x, band 9, HR 10%
+    "cfg1": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID,
+                 epochs=1000, batch=32, train_grid=(16, 16), hr_frac=0.10, seed=1),
+    # small configurations for tests
+    "tiny": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID,
+                 epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
+}
+
+
+def _fom_job(args):
+    nx, ny, mu = args
+    fom = BurgersFOM(Grid(nx, ny))
+    res = solve_fom(fom, mu, keep_history=True)
+    return res.x, res.res_history, res.converged
+
+
+def snapshots(nx, ny, mus, workers=1):
+    jobs = [(nx, ny, tuple(m)) for m in mus]
+    if workers > 1:
+        with ProcessPoolExecutor(workers) as ex:
+            out = list(ex.map(_fom_job, jobs, chunksize=1))
+    else:
+        out = [_fom_job(j) for j in jobs]
+    if not all(o[2] for o in out):
+        raise RuntimeError("FOM Newton failed for some training parameter")
+    X = np.stack([o[0] for o in out])
+    R = [r for o in out for r in o[1]]
+    return X, np.stack(R)
+
+
+def _train_job(args):
+    X, N, n, b, s, activation, seed, epochs, batch, tag = args
+    t0 = time.time()
+    ae = MaskedAE(N, n, b, s, activation)
+    p, nm, rep = train(ae, X, seed, epochs, batch)
+    Xn = (X - nm.m) / nm.s
+    center = ae.encode(p, Xn).mean(0)
+    dec = export_decoder(ae, p, nm, center)
+    return tag, dec, rep, time.time() - t0
+
+
+def build(name: str, workers: int = 8, verbose=True):
+    cfg = CONFIGS[name]
+    g = Grid(cfg["nx"], cfg["ny"])
+    dd = build_dd(g, cfg["nsx"], cfg["nsy"])
+    mus = si.training_grid(*cfg["train_grid"])
+    t0 = time.time()
+    X, Rsnap = snapshots(g.nx, g.ny, mus, workers)
+    if verbose:
+        print(f"[{name}] {len(mus)} FOM snapshots, {len(Rsnap)} residual snapshots in {time.time() - t0:.1f}s", flush=True)
+
+    seeds = si.spawn_seeds(cfg["seed"], 2 * dd.n_sub + 1)
+    jobs = []
+    for i, sd in enumerate(dd.subdomains):
+        jobs.append((X[:, sd.omega], len(sd.omega), cfg["n_om"], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i],
+                     cfg["epochs"], cfg["batch"], ("om", i)))
+        jobs.append((X[:, sd.gamma], len(sd.gamma), cfg["n_ga"], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i + 1],
+                     cfg["epochs"], cfg["batch"], ("ga", i)))
+    jobs.sort(key=lambda j: -j[1])        # largest first
+    t0 = time.time()
+    if workers > 1:
+        with ProcessPoolExecutor(workers) as ex:
+            res = list(ex.map(_train_job, jobs, chunksize=1))
+    else:
+        res = [_train_job(j) for j in jobs]
+    decs = {r[0]: r[1] for r in res}
+    reports = {r[0]: r[2] for r in res}
+    if verbose:
+        for tag in sorted(reports):
+            rp = reports[tag]
+            print(f"[{name}] AE {tag}: epochs {rp.epochs} train {rp.train_loss:.3e} best test {rp.test_loss:.3e}")
+        print(f"[{name}] training {time.time() - t0:.1f}s", flush=True)
+
+    hr_nodes = []
+    for i, sd in enumerate(dd.subdomains):
+        Ri = Rsnap[:, sd.res_rows].T                      # N_i^r x n_snap
+        Phi = pod_basis(Ri, 1e-10)
+        n_own = len(sd.own_nodes)
+        k = int(round(cfg["hr_frac"] * n_own))
+        loc = greedy_sample(Phi, n_own, k)
+        hr_nodes.append(sd.own_nodes[loc])
+    n_C = sum(cfg["n_ga"] for _ in dd.subdomains) // 2
+    C = si.gaussian_matrix(n_C, dd.n_A, seeds[-1])
+    pack = dict(nx=g.nx, ny=g.ny, nu=g.nu, ly=g.ly, nsx=cfg["nsx"], nsy=cfg["nsy"], act=cfg["act"],
+                n_sub=dd.n_sub, C=C)
+    for i in range(dd.n_sub):
+        for part in ("om", "ga"):
+            d = decs[(part, i)]
+            pack[f"{part}{i}_W1"] = d.W1
+            pack[f"{part}{i}_b1"] = d.b1
+            pack[f"{part}{i}_W2"] = d.W2vals
+            pack[f"{part}{i}_xref"] = d.x_ref
+            pack[f"{part}{i}_bs"] = np.array([d.b, d.s])
+        pack[f"hr{i}"] = hr_nodes[i]
+    return pack, X, mus, reports
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("config")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
+    a = ap.parse_args(argv)
+    pack, X, mus, _ = build(a.config, a.workers)
+    out = a.out or os.path.join("models", f"{a.config}.npz")
+    os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
+    np.savez(out, **pack)
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    sys.exit(main())

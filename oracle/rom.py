@@ -1,0 +1,357 @@
+"""DD-LSPG ROM with weak FOM-port constraints and collocation HR, solved by the
+Lagrange-Gauss-Newton SQP method (Sections 3.1, 4.1; eqs. dd_lspg_NLP,
+dd_lspg_NLP_general, optimality_residuals, sqp_system, gauss_newton_hessian,
+sqp_update), FP64.
+
+Everything here is the plain definition:
+  * the decoders are evaluated in full and the subdomain residual r_i is evaluated on
+    the whole grid through eq. subdomain_residual_def, then the collocation operator
+    B_i = Z_i keeps the rows of the sampled nodes;
+  * R_i = [dr_i/dx^Omega dg^Omega/dxhat^Omega, dr_i/dx^Gamma dg^Gamma/dxhat^Gamma];
+  * H_i = (Z R_i)^T (Z R_i), rho_i = (Z R_i)^T Z r_i + E_i^T lambda,
+    E_i = [0, C A_i dg^Gamma/dxhat^Gamma], constraint sum_i C A_i g_i^Gamma;
+  * the KKT matrix of eq. sqp_system is assembled densely and solved with LAPACK
+    (numpy.linalg.solve); no Schur complement, no blocking.
+
+Readings (the paper leaves these open): the line search merit is
+phi(alpha) = 0.5 ||F(xhat + alpha s, lambda + alpha s_lambda)||^2 with F the KKT
+right-hand side; a step is accepted when phi(alpha) <= (1 - 2 c1 alpha) phi(0),
+c1 = 1e-4, alpha halving, at most `max_backtracks` halvings; otherwise the solve stops
+with status LINESEARCH_FAIL at the last accepted point.  The solve stops when
+||F||_2 <= max(tol_abs, tol_rel ||F_0||_2) or after max_iter steps.  The initial
+multiplier is the least-squares solution of the interface rows of the first-order
+conditions (eq. optimality_residuals b) at the initial latents.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .autoencoder import Decoder, decode_jacobian, decode
+from .burgers import BurgersFOM, Grid
+from .ddmaps import DDMaps, build_dd, subdomain_residual_jac
+
+CONVERGED, MAX_ITER, LINESEARCH_FAIL, KKT_NOT_PD, NONFINITE = 0, 1, 2, 3, 4
+
+
+@dataclass
+class ROMModel:
+    grid: Grid
+    nsx: int
+    nsy: int
+    dec_om: list            # Decoder per subdomain (interior)
+    dec_ga: list            # Decoder per subdomain (interface)
+    hr_nodes: list | None   # sampled global node ids per subdomain (None: B_i = I)
+    C: np.ndarray           # n_C x N_A
+    dd: DDMaps = None
+    fom: BurgersFOM = None
+    CA: list = None
+
+    def __post_init__(self):
+        if self.dd is None:
+            self.dd = build_dd(self.grid, self.nsx, self.nsy)
+        if self.fom is None:
+            self.fom = BurgersFOM(self.grid)
+        self.CA = [self.C @ A.toarray() for A in self.dd.A]
+        self._zrows = []
+        for i, sd in enumerate(self.dd.subdomains):
+            n_own = len(sd.own_nodes)
+            if self.hr_nodes is None:
+                self._zrows.append(np.arange(2 * n_own))
+            else:
+                loc = np.searchsorted(sd.own_nodes, np.asarray(self.hr_nodes[i]))
+                if not np.array_equal(sd.own_nodes[loc], np.asarray(self.hr_nodes[i])):
+                    raise ValueError("HR nodes must be owned by their subdomain")
+                self._zrows.append(np.concatenate([loc, loc + n_own]))
+
+    @property
+    def n_sub(self):
+        return len(self.dec_om)
+
+    @property
+    def n_C(self):
+        return self.C.shape[0]
+
+    def sizes(self):
+        return [(d.n, e.n) for d, e in zip(self.dec_om, self.dec_ga)]
+
+    @property
+    def n_D(self):
+        return sum(a + b for a, b in self.sizes())
+
+    def offsets(self):
+        off, o = [], 0
+        for a, b in self.sizes():
+            off.append(o)
+            o += a + b
+        return off
+
+    def split(self, xhat):
+        """xhat = [xhat_1^Omega; xhat_1^Gamma; ...] (eq. sqp_notation) -> per-subdomain pairs."""
+        out = []
+        for o, (a, b) in zip(self.offsets(), self.sizes()):
+            out.append((xhat[o:o + a], xhat[o + a:o + a + b]))
+        return out
+
+
+@dataclass
+class Evaluation:
+    H: list          # H_i  (n_i x n_i)
+    g: list          # (Z R_i)^T Z r_i  (n_i)
+    EG: list         # C A_i dg^Gamma/dxhat^Gamma  (n_C x n_i^Gamma)
+    c: np.ndarray    # sum_i C A_i g_i^Gamma
+    Zr: list
+    ZR: list
+
+
+def evaluate(model: ROMModel, mu, xhat: np.ndarray, decoders=None) -> Evaluation:
+    """Per-subdomain SQP quantities at xhat (no multiplier terms)."""
+    H, g, EG, Zr_l, ZR_l = [], [], [], [], []
+    c = np.zeros(model.n_C)
+    for i, (xo, xg) in enumerate(model.split(xhat)):
+        if decoders is None:
+            go, Jo = decode_jacobian(model.dec_om[i], xo)
+            gg, Jg = decode_jacobian(model.dec_ga[i], xg)
+        else:
+            go, Jo, gg, Jg = decoders(i, xo, xg)
+        r, dro, drg = subdomain_residual_jac(model.fom, model.dd, i, go, gg, mu)
+        z = model._zrows[i]
+        Zr = r[z]
+        ZR = np.hstack([dro[z] @ Jo, drg[z] @ Jg])
+        H.append(ZR.T @ ZR)
+        g.append(ZR.T @ Zr)
+        EG.append(model.CA[i] @ Jg)
+        c += model.CA[i] @ gg
+        Zr_l.append(Zr)
+        ZR_l.append(ZR)
+    return Evaluation(H, g, EG, c, Zr_l, ZR_l)
+
+
+def kkt_rhs(model: ROMModel, ev: Evaluation, lam: np.ndarray) -> np.ndarray:
+    """F(xhat, lambda) = -[rho_1; ...; rho_n; sum_i Atilde_i]."""
+    parts = []
+    for i, (a, b) in enumerate(model.sizes()):
+        rho = ev.g[i].copy()
+        rho[a:] += ev.EG[i].T @ lam
+        parts.append(rho)
+    parts.append(ev.c)
+    return -np.concatenate(parts)
+
+
+def kkt_matrix(model: ROMModel, ev: Evaluation) -> np.ndarray:
+    nD, nC = model.n_D, model.n_C
+    K = np.zeros((nD + nC, nD + nC))
+    for i, (o, (a, b)) in enumerate(zip(model.offsets(), model.sizes())):
+        K[o:o + a + b, o:o + a + b] = ev.H[i]
+        K[nD:, o + a:o + a + b] = ev.EG[i]
+        K[o + a:o + a + b, nD:] = ev.EG[i].T
+    return K
+
+
+def kkt_step(model: ROMModel, ev: Evaluation, lam: np.ndarray):
+    """Solve eq. sqp_system; returns (s_x, s_lambda)."""
+    sol = np.linalg.solve(kkt_matrix(model, ev), kkt_rhs(model, ev, lam))
+    return sol[:model.n_D], sol[model.n_D:]
+
+
+def initial_multiplier(model: ROMModel, ev: Evaluation) -> np.ndarray:
+    """argmin_lambda || [ g_i^Gamma + (E_i^Gamma)^T lambda ]_i ||_2."""
+    rows, rhs = [], []
+    for i, (a, b) in enumerate(model.sizes()):
+        rows.append(ev.EG[i].T)
+        rhs.append(-ev.g[i][a:])
+    lam, *_ = np.linalg.lstsq(np.vstack(rows), np.concatenate(rhs), rcond=None)
+    return lam
+
+
+def blocks_positive_definite(ev: Evaluation) -> bool:
+    try:
+        for Hi in ev.H:
+            np.linalg.cholesky(Hi)
+        return True
+    except np.linalg.LinAlgError:
+        return False
+
+
+@dataclass
+class SQPOptions:
+    max_iter: int = 50
+    tol_abs: float = 1e-8
+    tol_rel: float = 0.0
+    c1: float = 1e-4
+    max_backtracks: int = 20
+
+
+@dataclass
+class SQPResult:
+    xhat: np.ndarray
+    lam: np.ndarray
+    status: int
+    iters: int
+    fnorm: float
+    fnorm0: float
+    evaluations: int
+    history: list = field(default_factory=list)
+
+
+def sqp_step(model: ROMModel, mu, xhat, lam, opts: SQPOptions, ev: Evaluation | None = None):
+    """One Lagrange-Gauss-Newton SQP iteration from (xhat, lambda): KKT step, then
+    Armijo backtracking.  Returns (xhat+, lambda+, ev+, ||F+||, status, n_evals, alpha);
+    status is -1 for an accepted step."""
+    if ev is None:
+        ev = evaluate(model, mu, xhat)
+    if not blocks_positive_definite(ev):
+        return xhat, lam, ev, np.linalg.norm(kkt_rhs(model, ev, lam)), KKT_NOT_PD, 0, 0.0
+    F = kkt_rhs(model, ev, lam)
+    phi0 = 0.5 * float(F @ F)
+    sx, sl = kkt_step(model, ev, lam)
+    alpha = 1.0
+    for nb in range(opts.max_backtracks + 1):
+        xt, lt = xhat + alpha * sx, lam + alpha * sl
+        evt = evaluate(model, mu, xt)
+        Ft = kkt_rhs(model, evt, lt)
+        phi = 0.5 * float(Ft @ Ft)
+        if not np.isfinite(phi):
+            pass
+        elif phi <= (1.0 - 2.0 * opts.c1 * alpha) * phi0:
+            return xt, lt, evt, np.sqrt(2.0 * phi), -1, nb + 1, alpha
+        alpha *= 0.5
+    return xhat, lam, ev, np.sqrt(2.0 * phi0), LINESEARCH_FAIL, opts.max_backtracks + 1, 0.0
+
+
+def sqp_solve(model: ROMModel, mu, xhat0: np.ndarray | None = None, lam0: np.ndarray | None = None,
+              opts: SQPOptions = SQPOptions()) -> SQPResult:
+    x = np.zeros(model.n_D) if xhat0 is None else np.array(xhat0, dtype=np.float64)
+    ev = evaluate(model, mu, x)
+    lam = initial_multiplier(model, ev) if lam0 is None else np.array(lam0, dtype=np.float64)
+    F = kkt_rhs(model, ev, lam)
+    f0 = fn = float(np.linalg.norm(F))
+    n_eval = 1
+    hist = [fn]
+    if not np.isfinite(fn):
+        return SQPResult(x, lam, NONFINITE, 0, fn, f0, n_eval, hist)
+    tol = max(opts.tol_abs, opts.tol_rel * f0)
+    for k in range(opts.max_iter):
+        if fn <= tol:
+            return SQPResult(x, lam, CONVERGED, k, fn, f0, n_eval, hist)
+        x, lam, ev, fn, st, ne, _ = sqp_step(model, mu, x, lam, opts, ev)
+        n_eval += ne
+        hist.append(fn)
+        if st >= 0:
+            return SQPResult(x, lam, st, k, fn, f0, n_eval, hist)
+    status = CONVERGED if fn <= tol else MAX_ITER
+    return SQPResult(x, lam, status, opts.max_iter, fn, f0, n_eval, hist)
+
+
+# ----------------------------------------------------------------------------------
+# Post-solve metric (eq. relative_error)
+# ----------------------------------------------------------------------------------
+
+def relative_error(model: ROMModel, xhat: np.ndarray, x_fom: np.ndarray) -> float:
+    tot = 0.0
+    for i, (xo, xg) in enumerate(model.split(xhat)):
+        sd = model.dd.subdomains[i]
+        to, tg = x_fom[sd.omega], x_fom[sd.gamma]
+        num = np.sum((to - decode(model.dec_om[i], xo)) ** 2) + np.sum((tg - decode(model.dec_ga[i], xg)) ** 2)
+        tot += num / (np.sum(to ** 2) + np.sum(tg ** 2))
+    return float(np.sqrt(tot / model.n_sub))
+
+
+def relative_error_states(dd: DDMaps, states: list, x_fom: np.ndarray) -> float:
+    """eq. relative_error for given subdomain states [(x^Omega, x^Gamma)]."""
+    tot = 0.0
+    for sd, (go, gg) in zip(dd.subdomains, states):
+        to, tg = x_fom[sd.omega], x_fom[sd.gamma]
+        tot += (np.sum((to - go) ** 2) + np.sum((tg - gg) ** 2)) / (np.sum(to ** 2) + np.sum(tg ** 2))
+    return float(np.sqrt(tot / len(dd.subdomains)))
+
+
+# ----------------------------------------------------------------------------------
+# LS-ROM (Section 3.3): affine maps g(xhat) = x0 + Phi xhat, constant Jacobians
+# ----------------------------------------------------------------------------------
+
+@dataclass
+class AffineMap:
+    x0: np.ndarray
+    Phi: np.ndarray
+
+
+def lsrom_decoders(maps_om: list, maps_ga: list):
+    def dec(i, xo, xg):
+        mo, mg = maps_om[i], maps_ga[i]
+        return mo.x0 + mo.Phi @ xo, mo.Phi, mg.x0 + mg.Phi @ xg, mg.Phi
+    return dec
+
+
+def sqp_solve_with(model: ROMModel, mu, decoders, xhat0, opts: SQPOptions) -> SQPResult:
+    """The same SQP iteration with user-supplied subdomain maps (used for the LS-ROM)."""
+    x = np.array(xhat0, dtype=np.float64)
+    ev = evaluate(model, mu, x, decoders)
+    lam = initial_multiplier(model, ev)
+    F = kkt_rhs(model, ev, lam)
+    f0 = fn = float(np.linalg.norm(F))
+    tol = max(opts.tol_abs, opts.tol_rel * f0)
+    n_eval = 1
+    for k in range(opts.max_iter):
+        if fn <= tol:
+            return SQPResult(x, lam, CONVERGED, k, fn, f0, n_eval)
+        F = kkt_rhs(model, ev, lam)
+        phi0 = 0.5 * float(F @ F)
+        sx, sl = kkt_step(model, ev, lam)
+        alpha = 1.0
+        for nb in range(opts.max_backtracks + 1):
+            xt, lt = x + alpha * sx, lam + alpha * sl
+            evt = evaluate(model, mu, xt, decoders)
+            Ft = kkt_rhs(model, evt, lt)
+            n_eval += 1
+            if 0.5 * float(Ft @ Ft) <= (1.0 - 2.0 * opts.c1 * alpha) * phi0:
+                break
+            alpha *= 0.5
+        else:
+            return SQPResult(x, lam, LINESEARCH_FAIL, k, fn, f0, n_eval)
+        x, lam, ev, fn = xt, lt, evt, float(np.linalg.norm(Ft))
+    return SQPResult(x, lam, CONVERGED if fn <= tol else MAX_ITER, opts.max_iter, fn, f0, n_eval)
+
+
+# ----------------------------------------------------------------------------------
+# DD FOM through the same SQP (B_i = I, g = identity, constraints sum_i A_i x_i^Gamma = 0)
+# ----------------------------------------------------------------------------------
+
+def dd_fom_sqp(fom: BurgersFOM, dd: DDMaps, mu, x0_states=None, tol=1e-9, max_iter=50):
+    """eq. fom_dd_nlp solved by Lagrange-Gauss-Newton SQP with full steps (Theorem 1
+    setting).  Returns per-subdomain states, multiplier and the KKT residual history."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    subs = dd.subdomains
+    sizes = [(len(s.omega), len(s.gamma)) for s in subs]
+    offs = np.cumsum([0] + [a + b for a, b in sizes])
+    nD, nA = int(offs[-1]), dd.n_A
+    x = np.zeros(nD)
+    if x0_states is not None:
+        x = np.concatenate([np.concatenate(p) for p in x0_states])
+    lam = np.zeros(nA)
+    hist = []
+    for it in range(max_iter + 1):
+        blocks, rhs, Ecols = [], [], []
+        c = np.zeros(nA)
+        for i, (a, b) in enumerate(sizes):
+            xo, xg = x[offs[i]:offs[i] + a], x[offs[i] + a:offs[i + 1]]
+            r, dro, drg = subdomain_residual_jac(fom, dd, i, xo, xg, mu)
+            R = sp.hstack([dro, drg]).tocsr()
+            blocks.append((R.T @ R).tocsr())
+            Ei = sp.hstack([sp.csr_matrix((nA, a)), dd.A[i]]).tocsr()
+            Ecols.append(Ei)
+            rhs.append(R.T @ r + Ei.T @ lam)
+            c += dd.A[i] @ xg
+        F = -np.concatenate(rhs + [c])
+        hist.append(float(np.linalg.norm(F)))
+        if hist[-1] <= tol or it == max_iter:
+            break
+        E = sp.hstack(Ecols).tocsr()
+        K = sp.bmat([[sp.block_diag(blocks), E.T], [E, None]], format="csc")
+        sol = spla.spsolve(K, F)
+        x = x + sol[:nD]
+        lam = lam + sol[nD:]
+    states = [(x[offs[i]:offs[i] + a], x[offs[i] + a:offs[i + 1]]) for i, (a, b) in enumerate(sizes)]
+    return states, lam, hist

@@ -1,0 +1,69 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module draws random numbers and lays out parameter lists; it holds none of the
+method's arithmetic (no residual, no decoder, no solver).  Every generator is a
+numpy PCG64 stream keyed by an explicit integer seed, so the oracle and the HIP path
+receive bit-identical inputs.
+
+Contents
+  * parameter sets mu = (a, lambda) on the Burgers box D = [1, 1e4] x [5, 20]
+    (tensor linspace training grids and uniform held-out draws),
+  * the Gaussian test matrix C of the weak compatibility constraint
+    (Section 3.1: C has i.i.d. normal entries),
+  * Glorot-uniform initial weights for the shallow masked autoencoders,
+  * random latent vectors and multipliers for kernel-level parity cases.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+A_RANGE = (1.0, 1.0e4)
+LAM_RANGE = (5.0, 20.0)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def training_grid(n_a: int, n_lam: int) -> np.ndarray:
+    """Tensor grid of (a, lambda), endpoints included, a-fastest.  Shape [n_a*n_lam, 2]."""
+    a = np.linspace(A_RANGE[0], A_RANGE[1], n_a)
+    lam = np.linspace(LAM_RANGE[0], LAM_RANGE[1], n_lam)
+    aa, ll = np.meshgrid(a, lam, indexing="xy")
+    return np.stack([aa.ravel(), ll.ravel()], axis=1).astype(np.float64)
+
+
+def heldout_mu(n: int, seed: int, exclude: np.ndarray | None = None) -> np.ndarray:
+    """n parameter points drawn uniformly from D, rejecting exact hits on `exclude`."""
+    g = rng(seed)
+    out = []
+    ex = set() if exclude is None else {tuple(p) for p in np.asarray(exclude)}
+    while len(out) < n:
+        p = (g.uniform(*A_RANGE), g.uniform(*LAM_RANGE))
+        if p not in ex:
+            out.append(p)
+    return np.asarray(out, dtype=np.float64).reshape(n, 2)
+
+
+def gaussian_matrix(rows: int, cols: int, seed: int) -> np.ndarray:
+    """i.i.d. N(0,1) matrix (row-major float64)."""
+    return rng(seed).standard_normal((rows, cols))
+
+
+def glorot_uniform(fan_in: float, fan_out: float, shape, g: np.random.Generator) -> np.ndarray:
+    bound = np.sqrt(6.0 / (float(fan_in) + float(fan_out)))
+    return g.uniform(-bound, bound, size=shape)
+
+
+def uniform(shape, lo: float, hi: float, seed: int) -> np.ndarray:
+    return rng(seed).uniform(lo, hi, size=shape)
+
+
+def normal(shape, seed: int, scale: float = 1.0) -> np.ndarray:
+    return scale * rng(seed).standard_normal(size=shape)
+
+
+def spawn_seeds(seed: int, n: int) -> list[int]:
+    """n independent child seeds derived from one seed (SeedSequence.spawn)."""
+    ss = np.random.SeedSequence(int(seed))
+    return [int(c.generate_state(1)[0]) for c in ss.spawn(n)]

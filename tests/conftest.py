@@ -1,0 +1,33 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+@pytest.fixture(scope="session")
+def tiny_pack():
+    """A small trained model pack (12x8 grid, 2x2 subdomains) built by the oracle."""
+    from oracle.build_model import build
+    pack, X, mus, _ = build("tiny", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
+def cfg0_pack():
+    """The 36x36, 2x2 workload's model pack, built by the oracle pipeline (seconds)."""
+    import numpy as np
+    path = os.path.join(ROOT, "models", "cfg0.npz")
+    if os.path.exists(path):
+        return dict(np.load(path, allow_pickle=False))
+    from oracle.build_model import build
+    pack, *_ = build("cfg0", workers=1, verbose=False)
+    return pack
