@@ -1,0 +1,185 @@
+/*
+ * ddrom.h - C ABI of the MI355X library for the online solve of the domain-decomposition
+ * nonlinear-manifold ROM with collocation hyper-reduction (HR DD NM-ROM) of
+ * Diaz, Choi and Heinkenschloss, "A fast and accurate domain decomposition nonlinear
+ * manifold reduced order model" (arXiv 2305.15163), applied to the steady 2D viscous
+ * Burgers problem of its Section 7.1.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named *_d are device memory (HIP, current device), owned by the caller.
+ *     Pointers named *_h are host memory.  The library never frees or keeps caller buffers.
+ *   - All device work is enqueued asynchronously on the given stream (0 = null stream).
+ *   - Return value: 0 on success; a negative DDROM_E* code on bad arguments, shape
+ *     mismatches, allocation or launch failures, with a message in ddrom_last_error().
+ *     Numerical outcomes of a solve never produce a negative return; they are written
+ *     per solve to status_d (DDROM_STATUS_*).
+ *   - Parameters mu are (a, lambda) of the exact solution psi, u_ex, v_ex (Section 7.1).
+ *   - Latent vectors follow the ordering of the SQP section: for subdomains i = 1..n,
+ *     xhat = [xhat_1^Omega; xhat_1^Gamma; ...; xhat_n^Omega; xhat_n^Gamma] (length n_D).
+ *   - A model is immutable after creation; calls on different streams may share it,
+ *     but each call that takes a workspace needs its own workspace.
+ */
+#ifndef DDROM_H
+#define DDROM_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDROM_OK 0
+#define DDROM_EINVAL (-1)
+#define DDROM_ENOMEM (-2)
+#define DDROM_EHIP (-3)
+#define DDROM_ESHAPE (-4)
+
+/* Per-solve outcome codes written to status_d. */
+#define DDROM_STATUS_CONVERGED 0
+#define DDROM_STATUS_MAX_ITER 1
+#define DDROM_STATUS_LINESEARCH_FAIL 2
+#define DDROM_STATUS_KKT_NOT_PD 3     /* Lemma 1 hypotheses fail: an H_i or the Schur complement is not positive definite */
+#define DDROM_STATUS_NONFINITE 4
+
+#define DDROM_ACT_SIGMOID 0
+#define DDROM_ACT_SWISH 1
+#define DDROM_ACT_IDENTITY 2
+
+#define DDROM_PREC_FP64 0            /* decoders, residual, KKT all in FP64 */
+#define DDROM_PREC_FP32_DECODER 1    /* decoders in FP32; residual, GN blocks, KKT, line search in FP64 */
+
+/* One decoder g(xhat) = x_ref + W2 sigma(W1 xhat + b1) of eq. autoencoder_architecture b/d,
+ * with the de-normalisation layer folded into W2 and x_ref.  Host memory, row-major:
+ *   W1 [w][n], b1 [w], W2 [N][3][b], x_ref [N].
+ * W2 holds the values of the three-band mask of Section 7.3: slot (r, k, t) is column
+ * r*s + (k-1)*b*s + t of the dense N x w matrix; slots whose column falls outside [0, w)
+ * are ignored.  w must equal N*s. */
+typedef struct {
+    int N, n, w, b, s;
+    const double* W1;
+    const double* b1;
+    const double* W2;
+    const double* x_ref;
+} ddrom_decoder_desc;
+
+/* Everything the online solve needs (host memory; deep-copied by ddrom_model_create).
+ * Grid: nx x ny interior nodes of [-1, 1] x [0, ly]; a uniform nsx x nsy block split
+ * (subdomain i = sy*nsx + sx).  hr_nodes[i] lists hr_count[i] global node ids
+ * (node = j*nx + i, 0-based interior indices) owned by subdomain i, ascending; they are
+ * the rows kept by the collocation operator Z_i (both the r_u and r_v row of each node).
+ * C is the n_C x N_A Gaussian test matrix of the weak compatibility constraint
+ * (eq. dd_lspg_NLP b), its columns ordered by the library's constraint-row convention:
+ * rows are ordered by the global DoF they duplicate, ascending; a DoF shared by
+ * subdomains i_1 < ... < i_k contributes rows x_{i_t} - x_{i_{t+1}} = 0, t = 1..k-1. */
+typedef struct {
+    int nx, ny;
+    double nu, ly;
+    int nsx, nsy;
+    int activation;                         /* DDROM_ACT_* */
+    int n_C, N_A;
+    const double* C;                        /* [n_C][N_A] */
+    const ddrom_decoder_desc* dec_om;       /* [n_sub] interior decoders g_i^Omega */
+    const ddrom_decoder_desc* dec_ga;       /* [n_sub] interface decoders g_i^Gamma */
+    const int* hr_count;                    /* [n_sub] */
+    const int* const* hr_nodes;             /* [n_sub] -> [hr_count[i]] */
+} ddrom_model_desc;
+
+typedef struct ddrom_model ddrom_model;
+typedef struct ddrom_workspace ddrom_workspace;
+
+typedef struct {
+    int max_iter;           /* SQP iterations (accepted steps) */
+    double tol_abs;         /* stop when ||F||_2 <= max(tol_abs, tol_rel * ||F_0||_2) */
+    double tol_rel;
+    double armijo_c1;       /* accept alpha when phi(alpha) <= (1 - 2 c1 alpha) phi(0) */
+    int max_backtracks;     /* halvings of alpha before LINESEARCH_FAIL */
+    int precision;          /* DDROM_PREC_* */
+} ddrom_opts;
+
+const char* ddrom_last_error(void);
+
+/* Build the device model: DD maps (Section 2), ports and A_i, C A_i, the interior
+ * decoder subnets of eq. subnet for the HR-sampled stencils (Section 5.4), full interface
+ * decoders (Section 5.3: the weak constraint needs every interface row), stencil gather
+ * tables and the boundary points touched by sampled stencils.  Synchronous. */
+int ddrom_model_create(const ddrom_model_desc* desc, ddrom_model** out);
+void ddrom_model_destroy(ddrom_model* m);
+
+/* Sizes: query = 0 n_sub, 1 n_D, 2 n_C, 3 N_A, 4 N_x (= 2 nx ny), 5 sum_i (N_i^Omega + N_i^Gamma),
+ * 6 total HR nodes.  Per subdomain (sd >= 0): 10 n_i^Omega, 11 n_i^Gamma, 12 N_i^Omega,
+ * 13 N_i^Gamma, 14 |I_o| of the interior subnet, 15 |I_h| of the interior subnet,
+ * 16 HR nodes, 17 offset of xhat_i^Omega in xhat, 18 own nodes. */
+long long ddrom_model_size(const ddrom_model* m, int query, int sd);
+
+/* Subnet output rows I_o (local indices into x_i^Omega, ascending) of subdomain sd's
+ * interior decoder (part 0), or all interface rows (part 1).  rows_h has room for
+ * ddrom_model_size(m, 14, sd) (part 0) or N_i^Gamma (part 1) ints. */
+int ddrom_subnet_rows(const ddrom_model* m, int sd, int part, int* rows_h);
+
+/* Workspaces hold the per-batch device buffers (decoder outputs, GN partial sums, KKT
+ * scratch, per-solve state) for up to max_batch solves; allocated once, reused by calls. */
+int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace** out);
+void ddrom_workspace_destroy(ddrom_workspace* ws);
+
+/* DD FOM residual (eq. subdomain_residual_def and eq. burgers_discretized) for B
+ * subdomain-state vectors.  xsd_d [B][sum_i (N_i^Omega + N_i^Gamma)]: per subdomain
+ * [x_i^Omega; x_i^Gamma] in the library's ascending-global-DoF order.  r_d [B][N_x]:
+ * per subdomain r_i = [r_u rows of owned nodes ascending; r_v rows], subdomains in
+ * order.  jac_d (nullable) [B][N_x][6]: row r_u holds d/du_C, d/du_W, d/du_E, d/du_S,
+ * d/du_N, d/dv_C; row r_v holds d/dv_C, d/dv_W, d/dv_E, d/dv_S, d/dv_N, d/du_C; entries
+ * whose neighbour is a Dirichlet boundary point are 0.  mu_d [B][2]. */
+int dd_fom_residual(const ddrom_model* m, const double* mu_d, const double* xsd_d, int B,
+                    double* r_d, double* jac_d, hipStream_t s);
+
+/* Decoder subnet at the HR-sampled rows (eq. subnet): x_d[b][r] = g(xhat_b)[I_o[r]] for
+ * part 0 (interior subnet of subdomain sd) or every interface row (part 1).
+ * xhat_d [B][n] FP64.  x_d is FP64 [B][rows] when precision = FP64, FP32 otherwise. */
+int ae_decode_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
+                 int precision, void* x_d, hipStream_t s);
+
+/* As ae_decode_hr, plus the Jacobian J_d [B][rows][n] = W2~ diag(sigma'(z)) W1~
+ * (the rows of dg/dxhat, Section 4.1); x_d may be NULL. */
+int ae_jacobian_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
+                   int precision, void* x_d, void* J_d, hipStream_t s);
+
+/* Per-subdomain SQP blocks at xhat (eq. gauss_newton_hessian, optimality_residuals_GN):
+ * H_d [B][n_sub][nmax][nmax] (H_i = (Z R_i)^T Z R_i, upper-left n_i x n_i used),
+ * g_d [B][n_D] ((Z R_i)^T Z r_i stacked), EG_d [B][n_sub][n_C][mmax] (C A_i dg_i^Gamma/dxhat),
+ * c_d [B][n_C] (sum_i C A_i g_i^Gamma), rr_d [B] (sum_i ||Z r_i||^2); any output may be NULL.
+ * nmax = max_i n_i, mmax = max_i n_i^Gamma. */
+int ddrom_gn_blocks(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, const double* xhat_d, int B,
+                    int precision, double* H_d, double* g_d, double* EG_d, double* c_d, double* rr_d,
+                    hipStream_t s);
+
+/* One Lagrange-Gauss-Newton SQP iteration (eqs. sqp_system, sqp_update) from
+ * (xhat, lambda) for B solves: KKT step with H_i from eq. gauss_newton_hessian, then
+ * Armijo backtracking on phi = 0.5 ||F||^2.  xhat_d [B][n_D], lam_d [B][n_C] in/out;
+ * fnorm_d [B] receives ||F||_2 at the returned point; status_d [B] receives
+ * DDROM_STATUS_MAX_ITER for an accepted step, else the failure code. */
+int sqp_step(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, double* xhat_d,
+             double* lam_d, double* fnorm_d, int* status_d, const ddrom_opts* o, hipStream_t s);
+
+/* Batched solve of eq. dd_lspg_NLP for B parameters.  xhat0_d (nullable: zero start)
+ * [B][n_D]; lam0_d (nullable: least-squares multiplier of eq. optimality_residuals b at
+ * the initial latents).  Outputs xhat_d [B][n_D], lam_d [B][n_C], iters_d [B],
+ * status_d [B], fnorm_d [B] (||F||_2 at the returned point), fnorm0_d (nullable) [B].
+ * Rounds of (decode, residual + GN blocks, constraint, KKT/line-search update) are
+ * replayed from a captured HIP graph; solves that have stopped cost no work. */
+int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B,
+                    const double* xhat0_d, const double* lam0_d, const ddrom_opts* o,
+                    double* xhat_d, double* lam_d, int* iters_d, int* status_d, double* fnorm_d,
+                    double* fnorm0_d, hipStream_t s);
+
+/* Measurement helper: average device time (ms) per launch of the four evaluation kernels
+ * of one solver round, ms_h[0] interior decoder subnets, [1] interface decoders,
+ * [2] HR residual + Gauss-Newton blocks, [3] weak constraint, each launched `reps` times
+ * back to back between two HIP events on the workspace's stream, with every solve live
+ * at the latents xhat_d [B][n_D].  Synchronous. */
+int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, const double* xhat_d, int B,
+                       int precision, int reps, float* ms_h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -355,3 +355,25 @@ def dd_fom_sqp(fom: BurgersFOM, dd: DDMaps, mu, x0_states=None, tol=1e-9, max_it
         lam = lam + sol[nD:]
     states = [(x[offs[i]:offs[i] + a], x[offs[i] + a:offs[i + 1]]) for i, (a, b) in enumerate(sizes)]
     return states, lam, hist
+
+
+def hr_interior_rows(model: ROMModel, i: int) -> np.ndarray:
+    """Local indices (into x_i^Omega) of the interior DoFs that Z_i r_i reads: the u and v
+    DoFs of the 5-point stencils of the sampled nodes that are interior states of
+    subdomain i (Section 5.3: only these decoder outputs are needed)."""
+    sd = model.dd.subdomains[i]
+    g = model.grid
+    n = g.n_nodes
+    need = set()
+    for q in np.asarray(model.hr_nodes[i]):
+        j, ii = divmod(int(q), g.nx)
+        for di, dj in ((0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)):
+            a, c = ii + di, j + dj
+            if 0 <= a < g.nx and 0 <= c < g.ny:
+                node = c * g.nx + a
+                need.add(node)
+                need.add(node + n)
+    dofs = np.array(sorted(need), dtype=np.int64)
+    pos = np.searchsorted(sd.omega, dofs)
+    ok = (pos < len(sd.omega)) & (sd.omega[np.minimum(pos, len(sd.omega) - 1)] == dofs)
+    return pos[ok]

@@ -1,0 +1,153 @@
+// Internal structures shared by the host model builder and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ddrom.h"
+
+namespace ddrom {
+
+// Stencil source codes of the HR residual gather: top two bits select the source.
+constexpr int SRC_OMEGA = 0;     // row of the interior subnet output (index into I_o)
+constexpr int SRC_GAMMA = 1;     // row of the interface decoder output
+constexpr int SRC_BOUND = 2;     // Dirichlet value slot (per-solve boundary buffer)
+__host__ __device__ inline int src_kind(int code) { return (code >> 28) & 3; }
+__host__ __device__ inline int src_index(int code) { return code & 0x0fffffff; }
+__host__ __device__ inline int src_code(int kind, int idx) { return (kind << 28) | idx; }
+
+// Slot order of the 10 gathered DoFs of one sampled node.
+enum { S_UC = 0, S_UW, S_UE, S_US, S_UN, S_VC, S_VW, S_VE, S_VS, S_VN, N_SLOTS };
+
+// One decoder as seen by the decode kernel (interior subnet or full interface decoder).
+struct DecSeg {
+    int n;          // latent size
+    int rows;       // output rows kept
+    int hid;        // hidden units kept
+    int bmax;       // b (values per band slot)
+    int xoff;       // offset of this decoder's latent inside xhat (n_D vector)
+    int sd;
+    long long w1;   // element offset into the W1 pool  [hid][n]
+    long long b1;   // element offset into the b1 pool  [hid]
+    long long band; // offset into the band pool        [rows][3] (compressed start, length)
+    long long w2;   // element offset into the W2 pool  [rows][3][bmax]
+    long long xref; // element offset into the x_ref pool [rows]
+    long long out;  // first Bp-row of the output: row r, column j (0 value, 1+k Jacobian) at (out + r*(1+n) + j)*Bp
+};
+
+struct DecChunk {
+    int seg;
+    int r0, r1;
+    int pad;
+};
+
+// A contiguous range of sampled nodes of one subdomain (one residual/GN work item).
+struct ResChunk {
+    int sd;
+    int p0, p1;     // node range inside the subdomain's HR node list
+    int slot;       // GN partial-sum slot
+};
+
+struct ResSeg {
+    int n_om, n_ga;
+    int seg_om, seg_ga;     // decoder segment ids
+    long long gather;       // offset into the gather pool [nb][N_SLOTS]
+    long long ca;           // offset of C A_i [n_C][N_i^Gamma] in the CA pool
+    int slot0, slot1;       // GN partial slots of this subdomain
+    int n_rows_ga;          // N_i^Gamma
+    int pad;
+};
+
+struct ConChunk {
+    int sd;
+    int j0, j1;             // constraint rows
+    int pad;
+};
+
+}  // namespace ddrom
+
+struct ddrom_model {
+    int nx, ny, nsx, nsy, n_sub, act, n_C, N_A, n_D, N_x, n_state;
+    double nu, ly, hx, hy;
+    int nmax, mmax, NNmax, estride;     // max latent sizes, GN partial stride
+    std::vector<int> n_om, n_ga, N_om, N_ga, xoff, n_own, nb, hid_om;
+    std::vector<std::vector<int>> subnet_rows;   // I_o per subdomain (interior local indices)
+    std::vector<long long> state_off;            // offset of [x_i^Omega; x_i^Gamma] inside the DD state vector
+    std::vector<long long> res_off;              // offset of r_i inside the DD residual vector
+
+    // decoder pools (both precisions)
+    float *W1f = nullptr, *b1f = nullptr, *W2f = nullptr, *xreff = nullptr;
+    double *W1d = nullptr, *b1d = nullptr, *W2d = nullptr, *xrefd = nullptr;
+    int2* bands = nullptr;
+    std::vector<ddrom::DecSeg> segs_h;           // [0, n_sub): interior subnets; [n_sub, 2 n_sub): interface
+    ddrom::DecSeg* segs_d = nullptr;
+    std::vector<ddrom::DecChunk> chunks_h;       // sorted by segment
+    ddrom::DecChunk* chunks_d = nullptr;
+    std::vector<int> seg_chunk0, seg_chunk1;     // chunk range per segment
+    long long dec_rows = 0;                      // Bp-rows of the decoder output buffer
+
+    // residual / GN
+    int* gather_d = nullptr;
+    std::vector<ddrom::ResSeg> rsegs_h;
+    ddrom::ResSeg* rsegs_d = nullptr;
+    std::vector<ddrom::ResChunk> rchunks_h;
+    ddrom::ResChunk* rchunks_d = nullptr;
+    int n_slots = 0;
+    int n_bc = 0;
+    double* bc_xy_d = nullptr;                   // [n_bc][2] boundary point coordinates
+    int* bc_field_d = nullptr;                   // [n_bc] 0 = u, 1 = v
+
+    // constraint
+    double* CA_d = nullptr;                      // per subdomain [n_C][N_i^Gamma]
+    std::vector<long long> CA_off;
+    ddrom::ConChunk* cchunks_d = nullptr;
+    int n_cchunks = 0;
+
+    // DD FOM residual: per subdomain, per owned node, 5 stencil sources (C, W, E, S, N)
+    int* fom_src_d = nullptr;                    // code: kind<<28 | node position; boundary: (I<<14)|J
+    long long* fom_meta_d = nullptr;             // per subdomain: [own_off, n_own, n_int_nodes, n_if_nodes, state_off, res_off]
+    int total_own = 0;
+    int* fom_sd_of_row_d = nullptr;              // owner subdomain of each flattened own-node slot
+};
+
+struct SolveState {
+    int phase;      // 0 initial evaluation, 1 line-search trial, 2 stopped
+    int status;
+    int iters;
+    int nbt;
+    double alpha, phi0, tol, f0, fn;
+};
+
+struct ddrom_workspace {
+    const ddrom_model* m = nullptr;
+    int max_B = 0, Bp = 0;
+    void* dec_out = nullptr;        // decoder values + Jacobians, [dec_rows][Bp] (float or double)
+    double* bc = nullptr;           // [n_bc][Bp]
+    double* gn_part = nullptr;      // [n_slots][estride][Bp]
+    double* c_part = nullptr;       // [n_sub][n_C][Bp]
+    double* E_part = nullptr;       // [n_sub][n_C][mmax][Bp]
+    double* x = nullptr;            // accepted latents  [Bp][n_D]
+    double* xt = nullptr;           // trial latents     [Bp][n_D]
+    double* lam = nullptr;          // [Bp][n_C]
+    double* lamt = nullptr;
+    double* step = nullptr;         // [Bp][n_D + n_C]
+    double* Y = nullptr;            // KKT scratch [Bp][n_sub][NNmax][n_C + 1]
+    double* mu = nullptr;           // [Bp][2]
+    SolveState* st = nullptr;       // [Bp]
+    int* counter = nullptr;         // active-solve counter (device)
+    int* counter_h = nullptr;       // pinned host mirror
+    // private stream (default priority) on which solves run and graphs are captured
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+    // cached graph of solver rounds
+    hipGraphExec_t graph = nullptr;
+    std::string graph_key;
+};
+
+namespace ddrom {
+void set_error(const std::string& msg);
+int build_model(const ddrom_model_desc* desc, ddrom_model* m);   // host tables + device upload
+void free_model(ddrom_model* m);
+}  // namespace ddrom

@@ -1,0 +1,1431 @@
+// HIP kernels for gfx950 and the C ABI of the HR DD NM-ROM online solve.
+//
+// Batch layout: one solve per wavefront lane.  Every per-solve buffer that a
+// batch-as-lanes kernel touches is stored [...][Bp] (solve index fastest, Bp = B rounded up
+// to 64), so a wave's 64 lanes read and write 64 consecutive elements, while the weights
+// of a decoder, the gather tables and C A_i are indexed only by wave-uniform values and are
+// fetched through the scalar cache, shared by the 64 solves of the wave.
+//
+// One solver round (one evaluation of every active solve at its trial point) is
+//   k_decode   interior subnets (eq. subnet) and full interface decoders, value + Jacobian
+//   k_res_gn   HR Burgers residual at the sampled nodes, Z R_i by the chain rule, and the
+//              Gauss-Newton blocks H_i = (Z R_i)^T Z R_i, g_i = (Z R_i)^T Z r_i (partial sums)
+//   k_con      weak constraint sum_i C A_i g_i^Gamma and E_i^Gamma = C A_i dg_i^Gamma/dxhat
+//   k_update   one wave per solve: merit, Armijo test, KKT solve by Schur complement on the
+//              block-arrow system (eq. sqp_system), next trial point
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+
+#include "internal.h"
+
+using namespace ddrom;
+
+namespace ddrom {
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace ddrom
+
+#define HIPCHECK(x)                                                                         \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) {                                                             \
+            set_error(std::string(#x) + ": " + hipGetErrorString(e_));                      \
+            return DDROM_EHIP;                                                              \
+        }                                                                                   \
+    } while (0)
+
+static constexpr int RING = 64;
+static constexpr int PH_INIT = 0, PH_TRIAL = 1, PH_DONE = 2;
+static constexpr int KKT_NN = 24;     // max n_i^Omega + n_i^Gamma
+static constexpr int KKT_NC = 64;     // max n_C
+
+// ------------------------------------------------------------------------------------
+// Activations
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void act_eval(float z, int act, float& s, float& d) {
+    if (act == DDROM_ACT_IDENTITY) {
+        s = z;
+        d = 1.0f;
+        return;
+    }
+    float e = __expf(-z);
+    float sg = __builtin_amdgcn_rcpf(1.0f + e);
+    if (act == DDROM_ACT_SIGMOID) {
+        s = sg;
+        d = sg * (1.0f - sg);
+    } else {
+        s = z * sg;
+        d = sg + z * sg * (1.0f - sg);
+    }
+}
+
+__device__ __forceinline__ void act_eval(double z, int act, double& s, double& d) {
+    if (act == DDROM_ACT_IDENTITY) {
+        s = z;
+        d = 1.0;
+        return;
+    }
+    double sg = 1.0 / (1.0 + exp(-z));
+    if (act == DDROM_ACT_SIGMOID) {
+        s = sg;
+        d = sg * (1.0 - sg);
+    } else {
+        s = z * sg;
+        d = sg + z * sg * (1.0 - sg);
+    }
+}
+
+__device__ __forceinline__ bool lane_live(const SolveState* st, int b, int B) {
+    return b < B && (st == nullptr || st[b].phase != PH_DONE);
+}
+
+// ------------------------------------------------------------------------------------
+// Decoder: value and Jacobian rows of g(xhat) = x_ref + W2~ sigma(W1~ xhat + b1~)
+// ------------------------------------------------------------------------------------
+// One wave = one work item (a run of consecutive kept rows of one decoder) x 64 solves.
+// Rows are visited in ascending order; each row's three bands live in a window of at most
+// RING consecutive (compressed) hidden units, so hidden activations are computed once per
+// unit into a per-lane ring in LDS and consumed by the rows that need them.
+template <typename T, int NL>
+__global__ __launch_bounds__(64) void k_decode(const DecChunk* __restrict__ chunks, int chunk_base,
+                                               const DecSeg* __restrict__ segs, const T* __restrict__ W1,
+                                               const T* __restrict__ B1, const int2* __restrict__ bands,
+                                               const T* __restrict__ W2, const T* __restrict__ XR,
+                                               const double* __restrict__ xhat, int xstride, int xoff_override,
+                                               const SolveState* __restrict__ st, int B, T* __restrict__ out,
+                                               int Bp, int act) {
+    const DecChunk ch = chunks[chunk_base + blockIdx.x];
+    const DecSeg sg = segs[ch.seg];
+    const int lane = threadIdx.x;
+    const int b = blockIdx.y * 64 + lane;
+    const bool live = lane_live(st, b, B);
+    if (__ballot(live) == 0) return;
+    const int xo = xoff_override >= 0 ? xoff_override : sg.xoff;
+    T xl[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) xl[k] = live ? (T)xhat[(size_t)b * xstride + xo + k] : (T)0;
+
+    __shared__ T ring_s[RING][64];
+    __shared__ T ring_d[RING][64];
+    const T* w1 = W1 + sg.w1;
+    const T* b1 = B1 + sg.b1;
+    const int2* bd = bands + sg.band;
+    const T* w2 = W2 + sg.w2;
+    const T* xr = XR + sg.xref;
+    T* o = out + (size_t)sg.out * Bp + b;
+    const int bmax = sg.bmax;
+    int hn = -1;
+    for (int r = ch.r0; r < ch.r1; ++r) {
+        const int2 q0 = bd[r * 3 + 0], q1 = bd[r * 3 + 1], q2 = bd[r * 3 + 2];
+        int lo = 0x7fffffff, hi = -1;
+        if (q0.y > 0) { lo = min(lo, q0.x); hi = max(hi, q0.x + q0.y); }
+        if (q1.y > 0) { lo = min(lo, q1.x); hi = max(hi, q1.x + q1.y); }
+        if (q2.y > 0) { lo = min(lo, q2.x); hi = max(hi, q2.x + q2.y); }
+        if (hn < lo) hn = lo;
+        for (; hn < hi; ++hn) {
+            T z = b1[hn];
+#pragma unroll
+            for (int k = 0; k < NL; ++k) z += w1[(size_t)hn * NL + k] * xl[k];
+            T s, d;
+            act_eval(z, act, s, d);
+            ring_s[hn & (RING - 1)][lane] = s;
+            ring_d[hn & (RING - 1)][lane] = d;
+        }
+        T acc = xr[r];
+        T J[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) J[k] = (T)0;
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) {
+            const int2 q = kb == 0 ? q0 : (kb == 1 ? q1 : q2);
+            const T* w2r = w2 + ((size_t)r * 3 + kb) * bmax;
+            for (int t = 0; t < q.y; ++t) {
+                const int h = q.x + t;
+                const T wv = w2r[t];
+                acc += wv * ring_s[h & (RING - 1)][lane];
+                const T c = wv * ring_d[h & (RING - 1)][lane];
+#pragma unroll
+                for (int k = 0; k < NL; ++k) J[k] += c * w1[(size_t)h * NL + k];
+            }
+        }
+        T* orow = o + (size_t)r * (1 + NL) * Bp;
+        orow[0] = acc;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) orow[(size_t)(1 + k) * Bp] = J[k];
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Pointwise central-difference Burgers residual (eq. burgers_discretized in stencil form)
+// v: u_C, u_W, u_E, u_S, u_N, v_C, v_W, v_E, v_S, v_N
+// cu: d r_u / d(u_C, u_W, u_E, u_S, u_N, v_C); cv: d r_v / d(v_C, v_W, v_E, v_S, v_N, u_C)
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void burgers_point(const double* v, double nu, double hx, double hy, double& ru, double& rv,
+                                              double* cu, double* cv) {
+    const double ihx2 = 0.5 / hx, ihy2 = 0.5 / hy, ax = nu / (hx * hx), ay = nu / (hy * hy);
+    const double uc = v[S_UC], vc = v[S_VC];
+    const double dux = (v[S_UE] - v[S_UW]) * ihx2, duy = (v[S_UN] - v[S_US]) * ihy2;
+    const double dvx = (v[S_VE] - v[S_VW]) * ihx2, dvy = (v[S_VN] - v[S_VS]) * ihy2;
+    const double lu = ax * (v[S_UE] - 2.0 * uc + v[S_UW]) + ay * (v[S_UN] - 2.0 * uc + v[S_US]);
+    const double lv = ax * (v[S_VE] - 2.0 * vc + v[S_VW]) + ay * (v[S_VN] - 2.0 * vc + v[S_VS]);
+    ru = -uc * dux - vc * duy + lu;
+    rv = -uc * dvx - vc * dvy + lv;
+    const double diag = -2.0 * (ax + ay);
+    const double cw = uc * ihx2 + ax, ce = -uc * ihx2 + ax, cs = vc * ihy2 + ay, cn = -vc * ihy2 + ay;
+    cu[0] = -dux + diag; cu[1] = cw; cu[2] = ce; cu[3] = cs; cu[4] = cn; cu[5] = -duy;
+    cv[0] = -dvy + diag; cv[1] = cw; cv[2] = ce; cv[3] = cs; cv[4] = cn; cv[5] = -dvx;
+}
+
+__device__ __forceinline__ void exact_uv(double x, double y, double a, double lam, double nu, double& u, double& v) {
+    const double ep = exp(lam * (x - 1.0)), em = exp(-lam * (x - 1.0));
+    const double c = cos(lam * y), s = sin(lam * y);
+    const double psi = a * (1.0 + x) + (ep + em) * c;
+    u = -2.0 * nu * (a + lam * (ep - em) * c) / psi;
+    v = 2.0 * nu * (lam * (ep + em) * s) / psi;
+}
+
+// Dirichlet values at the boundary points touched by sampled stencils, per solve.
+__global__ void k_bc(const double* __restrict__ xy, const int* __restrict__ field, int n_bc,
+                     const double* __restrict__ mu, int B, int Bp, double nu, double* __restrict__ bc) {
+    const int b = blockIdx.y * blockDim.x + threadIdx.x;
+    const int k = blockIdx.x;
+    if (b >= Bp || k >= n_bc) return;
+    double u = 0.0, v = 0.0;
+    if (b < B) exact_uv(xy[2 * k], xy[2 * k + 1], mu[2 * b], mu[2 * b + 1], nu, u, v);
+    bc[(size_t)k * Bp + b] = field[k] == 0 ? u : v;
+}
+
+// ------------------------------------------------------------------------------------
+// HR residual, chain rule and Gauss-Newton partial sums
+// ------------------------------------------------------------------------------------
+template <typename T, int NO, int NG>
+__global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchunks, int rbase,
+                                               const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
+                                               const int* __restrict__ gather, const T* __restrict__ dec,
+                                               const double* __restrict__ bc, const SolveState* __restrict__ st,
+                                               int B, int Bp, double nu, double hx, double hy,
+                                               double* __restrict__ part, int estride) {
+    constexpr int NN = NO + NG;
+    constexpr int NH = NN * (NN + 1) / 2;
+    const ResChunk rc = rchunks[rbase + blockIdx.x];
+    const ResSeg rs = rsegs[rc.sd];
+    const long long oo = segs[rs.seg_om].out, og = segs[rs.seg_ga].out;
+    const int b = blockIdx.y * 64 + threadIdx.x;
+    if (__ballot(lane_live(st, b, B)) == 0) return;
+    const T* dom = dec + (size_t)oo * Bp + b;
+    const T* dga = dec + (size_t)og * Bp + b;
+    const double* bcb = bc + b;
+    double H[NH], g[NN], rr = 0.0;
+#pragma unroll
+    for (int e = 0; e < NH; ++e) H[e] = 0.0;
+#pragma unroll
+    for (int e = 0; e < NN; ++e) g[e] = 0.0;
+    const int* gp = gather + rs.gather;
+    for (int p = rc.p0; p < rc.p1; ++p) {
+        const int* code = gp + (size_t)p * N_SLOTS;
+        int cd[N_SLOTS];
+        double v[N_SLOTS];
+#pragma unroll
+        for (int t = 0; t < N_SLOTS; ++t) {
+            cd[t] = code[t];
+            const int kind = src_kind(cd[t]), idx = src_index(cd[t]);
+            if (kind == SRC_OMEGA) v[t] = (double)dom[(size_t)idx * (1 + NO) * Bp];
+            else if (kind == SRC_GAMMA) v[t] = (double)dga[(size_t)idx * (1 + NG) * Bp];
+            else v[t] = bcb[(size_t)idx * Bp];
+        }
+        double ru, rv, cu[6], cv[6];
+        burgers_point(v, nu, hx, hy, ru, rv, cu, cv);
+        double zu[NN], zv[NN];
+#pragma unroll
+        for (int e = 0; e < NN; ++e) { zu[e] = 0.0; zv[e] = 0.0; }
+#pragma unroll
+        for (int t = 0; t < N_SLOTS; ++t) {
+            double a_u, a_v;
+            if (t < 5) { a_u = cu[t]; a_v = (t == S_UC) ? cv[5] : 0.0; }
+            else { a_v = cv[t - 5]; a_u = (t == S_VC) ? cu[5] : 0.0; }
+            const int kind = src_kind(cd[t]), idx = src_index(cd[t]);
+            if (kind == SRC_OMEGA) {
+                const T* jr = dom + ((size_t)idx * (1 + NO) + 1) * Bp;
+#pragma unroll
+                for (int k = 0; k < NO; ++k) {
+                    const double jk = (double)jr[(size_t)k * Bp];
+                    zu[k] += a_u * jk;
+                    zv[k] += a_v * jk;
+                }
+            } else if (kind == SRC_GAMMA) {
+                const T* jr = dga + ((size_t)idx * (1 + NG) + 1) * Bp;
+#pragma unroll
+                for (int k = 0; k < NG; ++k) {
+                    const double jk = (double)jr[(size_t)k * Bp];
+                    zu[NO + k] += a_u * jk;
+                    zv[NO + k] += a_v * jk;
+                }
+            }
+        }
+        int e = 0;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+            g[i] += zu[i] * ru + zv[i] * rv;
+#pragma unroll
+            for (int j = i; j < NN; ++j) H[e++] += zu[i] * zu[j] + zv[i] * zv[j];
+        }
+        rr += ru * ru + rv * rv;
+    }
+    double* pp = part + (size_t)rc.slot * estride * Bp + b;
+#pragma unroll
+    for (int e = 0; e < NH; ++e) pp[(size_t)e * Bp] = H[e];
+#pragma unroll
+    for (int e = 0; e < NN; ++e) pp[(size_t)(NH + e) * Bp] = g[e];
+    pp[(size_t)(NH + NN) * Bp] = rr;
+}
+
+// ------------------------------------------------------------------------------------
+// Weak compatibility constraint: c_i = C A_i g_i^Gamma, E_i^Gamma = C A_i dg_i^Gamma/dxhat
+// ------------------------------------------------------------------------------------
+template <typename T, int NG>
+__global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, const ResSeg* __restrict__ rsegs,
+                                            const DecSeg* __restrict__ segs, const double* __restrict__ CA, int n_C,
+                                            const T* __restrict__ dec, const SolveState* __restrict__ st, int B,
+                                            int Bp, double* __restrict__ c_part, double* __restrict__ E_part,
+                                            int mmax) {
+    constexpr int JB = 8;
+    const ConChunk cc = cch[blockIdx.x];
+    const ResSeg rs = rsegs[cc.sd];
+    const int b = blockIdx.y * 64 + threadIdx.x;
+    if (__ballot(lane_live(st, b, B)) == 0) return;
+    const int Ng = rs.n_rows_ga;
+    const T* dga = dec + (size_t)segs[rs.seg_ga].out * Bp + b;
+    const double* ca = CA + rs.ca;
+    const int nj = cc.j1 - cc.j0;
+    double c[JB], E[JB][NG];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+        c[j] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NG; ++k) E[j][k] = 0.0;
+    }
+    for (int o = 0; o < Ng; ++o) {
+        const T* row = dga + (size_t)o * (1 + NG) * Bp;
+        const double x = (double)row[0];
+        double J[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) J[k] = (double)row[(size_t)(1 + k) * Bp];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+            if (j < nj) {
+                const double a = ca[(size_t)(cc.j0 + j) * Ng + o];
+                c[j] += a * x;
+#pragma unroll
+                for (int k = 0; k < NG; ++k) E[j][k] += a * J[k];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+        if (j < nj) {
+            const int jj = cc.j0 + j;
+            c_part[((size_t)cc.sd * n_C + jj) * Bp + b] = c[j];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) E_part[(((size_t)cc.sd * n_C + jj) * mmax + k) * Bp + b] = E[j][k];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Per-solve update: merit, Armijo, KKT (Schur complement on the block-arrow system)
+// ------------------------------------------------------------------------------------
+struct UpdArgs {
+    int n_sub, n_C, n_D, mmax, estride, Bp, B;
+    int lam_given;
+    int max_iter, max_bt;
+    double tol_abs, tol_rel, c1;
+    const int* n_om;       // [n_sub]
+    const int* n_ga;
+    const int* xoff;
+    const int* slot0;      // [n_sub + 1]
+    const double* gn_part;
+    const double* c_part;
+    const double* E_part;
+    double* x;
+    double* xt;
+    double* lam;
+    double* lamt;
+    double* step;
+    double* Y;             // [Bp][n_sub][KKT_NN][n_C+1]
+    SolveState* st;
+    int* counter;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// In-place Cholesky (lower) of an n x n matrix in LDS, leading dimension ld.  Returns
+// false if a pivot is not positive and finite.
+__device__ bool chol_lds(double* A, int n, int ld, int lane) {
+    __shared__ int bad;
+    if (lane == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (lane == 0) {
+            const double d = A[k * ld + k];
+            if (!(d > 0.0) || !isfinite(d)) bad = 1;
+            A[k * ld + k] = sqrt(fabs(d) + (d > 0.0 ? 0.0 : 1.0));
+        }
+        __syncthreads();
+        const double piv = A[k * ld + k];
+        for (int i = k + 1 + lane; i < n; i += 64) A[i * ld + k] /= piv;
+        __syncthreads();
+        const int m = n - k - 1;
+        for (int e = lane; e < m * m; e += 64) {
+            const int i = k + 1 + e / m, j = k + 1 + e % m;
+            if (j <= i) A[i * ld + j] -= A[i * ld + k] * A[j * ld + k];
+        }
+        __syncthreads();
+    }
+    const bool ok = bad == 0;
+    __syncthreads();
+    return ok;
+}
+
+// Solve L L^T y = y for one right-hand side held in y[0..n) (LDS, stride 1), L in A.
+__device__ void chol_solve_lane(const double* A, int n, int ld, double* y) {
+    for (int i = 0; i < n; ++i) {
+        double s = y[i];
+        for (int k = 0; k < i; ++k) s -= A[i * ld + k] * y[k];
+        y[i] = s / A[i * ld + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < n; ++k) s -= A[k * ld + i] * y[k];
+        y[i] = s / A[i * ld + i];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_update(UpdArgs a) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (b >= a.B) return;
+    SolveState S = a.st[b];
+    if (S.phase == PH_DONE) return;
+    const int Bp = a.Bp, nC = a.n_C, nD = a.n_D;
+
+    __shared__ double c_s[KKT_NC];
+    __shared__ double lam_s[KKT_NC];
+    __shared__ double Sm[KKT_NC * (KKT_NC + 1)];      // Schur complement | q, or the least-squares system
+    __shared__ double Hs[KKT_NN * KKT_NN];
+    __shared__ double Ys[(KKT_NC + 1) * KKT_NN];     // one right-hand side per lane
+    __shared__ double rho_s[KKT_NN];
+    __shared__ double red[4];
+    __shared__ int flag;
+
+    // c = sum_i c_i
+    for (int j = lane; j < nC; j += 64) {
+        double s = 0.0;
+        for (int sd = 0; sd < a.n_sub; ++sd) s += a.c_part[((size_t)sd * nC + j) * Bp + b];
+        c_s[j] = s;
+    }
+    for (int j = lane; j < nC; j += 64) lam_s[j] = a.lamt[(size_t)b * nC + j];
+    __syncthreads();
+
+    auto E_at = [&](int sd, int j, int k) { return a.E_part[(((size_t)sd * nC + j) * a.mmax + k) * Bp + b]; };
+    auto g_at = [&](int sd, int e) {
+        const int NN = a.n_om[sd] + a.n_ga[sd];
+        const int off = NN * (NN + 1) / 2 + e;
+        double s = 0.0;
+        for (int sl = a.slot0[sd]; sl < a.slot0[sd + 1]; ++sl) s += a.gn_part[((size_t)sl * a.estride + off) * Bp + b];
+        return s;
+    };
+
+    // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i || (Householder QR) ----
+    if (S.phase == PH_INIT && !a.lam_given && nC > 0) {
+        int R = 0;
+        for (int sd = 0; sd < a.n_sub; ++sd) R += a.n_ga[sd];
+        const int ld = nC + 1;
+        // rows of M = [(E_i^Gamma)^T | -g_i^Gamma], stored in Sm when R <= KKT_NC, else normal equations
+        if (R <= KKT_NC) {
+            int r0 = 0;
+            for (int sd = 0; sd < a.n_sub; ++sd) {
+                const int m = a.n_ga[sd], no = a.n_om[sd];
+                for (int e = lane; e < m * ld; e += 64) {
+                    const int k = e / ld, j = e % ld;
+                    Sm[(r0 + k) * ld + j] = j < nC ? E_at(sd, j, k) : -g_at(sd, no + k);
+                }
+                r0 += m;
+            }
+            __syncthreads();
+            for (int k = 0; k < nC && k < R; ++k) {
+                // Householder vector for column k, rows k..R-1
+                double nrm2 = 0.0;
+                for (int r = k + lane; r < R; r += 64) nrm2 += Sm[r * ld + k] * Sm[r * ld + k];
+                nrm2 = wave_sum(nrm2);
+                const double akk = Sm[k * ld + k];
+                const double alpha = akk > 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
+                const double v0 = akk - alpha;
+                const double vn2 = nrm2 - akk * akk + v0 * v0;
+                __syncthreads();
+                if (vn2 > 0.0) {
+                    for (int col = k + 1 + lane; col < ld; col += 64) {
+                        double dot = v0 * Sm[k * ld + col];
+                        for (int r = k + 1; r < R; ++r) dot += Sm[r * ld + k] * Sm[r * ld + col];
+                        const double f = 2.0 * dot / vn2;
+                        Sm[k * ld + col] -= f * v0;
+                        for (int r = k + 1; r < R; ++r) Sm[r * ld + col] -= f * Sm[r * ld + k];
+                    }
+                }
+                __syncthreads();
+                if (lane == 0) Sm[k * ld + k] = vn2 > 0.0 ? alpha : akk;
+                __syncthreads();
+            }
+            if (lane == 0) {
+                for (int i = nC - 1; i >= 0; --i) {
+                    double s = Sm[i * ld + nC];
+                    for (int k = i + 1; k < nC; ++k) s -= Sm[i * ld + k] * lam_s[k];
+                    lam_s[i] = s / Sm[i * ld + i];
+                }
+            }
+        } else {
+            // normal equations (sum_i E_i E_i^T) lambda = -sum_i E_i g_i^Gamma
+            for (int e = lane; e < nC * ld; e += 64) {
+                const int i = e / ld, j = e % ld;
+                double s = 0.0;
+                for (int sd = 0; sd < a.n_sub; ++sd)
+                    for (int k = 0; k < a.n_ga[sd]; ++k)
+                        s += E_at(sd, i, k) * (j < nC ? E_at(sd, j, k) : -g_at(sd, a.n_om[sd] + k));
+                Sm[i * ld + j] = s;
+            }
+            __syncthreads();
+            chol_lds(Sm, nC, ld, lane);
+            if (lane == 0) {
+                for (int i = 0; i < nC; ++i) lam_s[i] = Sm[i * ld + nC];
+                for (int i = 0; i < nC; ++i) {
+                    double s = lam_s[i];
+                    for (int k = 0; k < i; ++k) s -= Sm[i * ld + k] * lam_s[k];
+                    lam_s[i] = s / Sm[i * ld + i];
+                }
+                for (int i = nC - 1; i >= 0; --i) {
+                    double s = lam_s[i];
+                    for (int k = i + 1; k < nC; ++k) s -= Sm[k * ld + i] * lam_s[k];
+                    lam_s[i] = s / Sm[i * ld + i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- merit at the trial point: phi = 0.5 (sum_i ||rho_i||^2 + ||c||^2) ----
+    double acc = 0.0;
+    for (int sd = 0; sd < a.n_sub; ++sd) {
+        const int no = a.n_om[sd], NN = no + a.n_ga[sd];
+        for (int e = lane; e < NN; e += 64) {
+            double r = g_at(sd, e);
+            if (e >= no)
+                for (int j = 0; j < nC; ++j) r += E_at(sd, j, e - no) * lam_s[j];
+            acc += r * r;
+        }
+    }
+    for (int j = lane; j < nC; j += 64) acc += c_s[j] * c_s[j];
+    const double phi_t = 0.5 * wave_sum(acc);
+    const double fn_t = sqrt(2.0 * phi_t);
+
+    // ---- decision ----
+    int action = 0;   // 0: compute step, 1: backtrack, 2: stop
+    if (S.phase == PH_INIT) {
+        S.f0 = fn_t;
+        S.tol = fmax(a.tol_abs, a.tol_rel * fn_t);
+        S.fn = fn_t;
+        if (!isfinite(fn_t)) {
+            S.status = DDROM_STATUS_NONFINITE;
+            action = 2;
+        }
+        for (int j = lane; j < nC; j += 64) {
+            a.lam[(size_t)b * nC + j] = lam_s[j];
+            a.lamt[(size_t)b * nC + j] = lam_s[j];
+        }
+    } else {
+        const bool ok = isfinite(phi_t) && phi_t <= (1.0 - 2.0 * a.c1 * S.alpha) * S.phi0;
+        if (!ok) {
+            S.nbt += 1;
+            if (S.nbt > a.max_bt) {
+                S.status = DDROM_STATUS_LINESEARCH_FAIL;
+                action = 2;
+            } else {
+                S.alpha *= 0.5;
+                action = 1;
+            }
+        } else {
+            for (int e = lane; e < nD; e += 64) a.x[(size_t)b * nD + e] = a.xt[(size_t)b * nD + e];
+            for (int j = lane; j < nC; j += 64) a.lam[(size_t)b * nC + j] = lam_s[j];
+            S.iters += 1;
+            S.fn = fn_t;
+        }
+    }
+    if (action == 0 && S.phase != PH_DONE) {
+        if (S.fn <= S.tol) {
+            S.status = DDROM_STATUS_CONVERGED;
+            action = 2;
+        } else if (S.iters >= a.max_iter) {
+            S.status = DDROM_STATUS_MAX_ITER;
+            action = 2;
+        }
+    }
+    if (action == 1) {
+        // next trial on the same step with the halved alpha
+        for (int e = lane; e < nD; e += 64)
+            a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + S.alpha * a.step[(size_t)b * (nD + nC) + e];
+        for (int j = lane; j < nC; j += 64)
+            a.lamt[(size_t)b * nC + j] = a.lam[(size_t)b * nC + j] + S.alpha * a.step[(size_t)b * (nD + nC) + nD + j];
+        if (lane == 0) {
+            a.st[b] = S;
+            atomicAdd(a.counter, 1);
+        }
+        return;
+    }
+    if (action == 2) {
+        if (lane == 0) {
+            S.phase = PH_DONE;
+            a.st[b] = S;
+        }
+        return;
+    }
+
+    // ---- KKT step: H_i s_i + E_i^T s_l = -rho_i ; sum_i E_i s_i = -c ----
+    const int ld = nC + 1;
+    for (int e = lane; e < nC * ld; e += 64) Sm[e] = 0.0;
+    if (lane == 0) flag = 0;
+    __syncthreads();
+    double* Yb = a.Y + (size_t)b * a.n_sub * KKT_NN * ld;
+    for (int sd = 0; sd < a.n_sub; ++sd) {
+        const int no = a.n_om[sd], ng = a.n_ga[sd], NN = no + ng;
+        // H_i (full symmetric) from the packed upper-triangle partial sums
+        const int NH = NN * (NN + 1) / 2;
+        for (int e = lane; e < NH; e += 64) {
+            // map packed index e -> (i, j), i <= j
+            int i = 0, rem = e;
+            while (rem >= NN - i) { rem -= NN - i; ++i; }
+            const int j = i + rem;
+            double s = 0.0;
+            for (int sl = a.slot0[sd]; sl < a.slot0[sd + 1]; ++sl) s += a.gn_part[((size_t)sl * a.estride + e) * Bp + b];
+            Hs[i * KKT_NN + j] = s;
+            Hs[j * KKT_NN + i] = s;
+        }
+        for (int e = lane; e < NN; e += 64) {
+            double r = g_at(sd, e);
+            if (e >= no)
+                for (int j = 0; j < nC; ++j) r += E_at(sd, j, e - no) * lam_s[j];
+            rho_s[e] = r;
+        }
+        __syncthreads();
+        if (!chol_lds(Hs, NN, KKT_NN, lane)) {
+            if (lane == 0) flag = 1;
+        }
+        // right-hand sides: lane j < nC -> E_i^T e_j ; lane nC -> rho_i
+        if (lane <= nC) {
+            double* y = Ys + lane * KKT_NN;
+            for (int k = 0; k < NN; ++k) y[k] = 0.0;
+            if (lane < nC)
+                for (int k = 0; k < ng; ++k) y[no + k] = E_at(sd, lane, k);
+            else
+                for (int k = 0; k < NN; ++k) y[k] = rho_s[k];
+            chol_solve_lane(Hs, NN, KKT_NN, y);
+            for (int k = 0; k < NN; ++k) Yb[((size_t)sd * KKT_NN + k) * ld + lane] = y[k];
+            // Sm[:, lane] += E_i y
+            for (int r = 0; r < nC; ++r) {
+                double s = 0.0;
+                for (int k = 0; k < ng; ++k) s += E_at(sd, r, k) * y[no + k];
+                Sm[r * ld + lane] += s;
+            }
+        }
+        __syncthreads();
+    }
+    // S s_l = c - q
+    for (int j = lane; j < nC; j += 64) Sm[j * ld + nC] = c_s[j] - Sm[j * ld + nC];
+    __syncthreads();
+    const bool spd = chol_lds(Sm, nC, ld, lane);
+    if (!spd || flag) {
+        if (lane == 0) {
+            S.status = DDROM_STATUS_KKT_NOT_PD;
+            S.phase = PH_DONE;
+            a.st[b] = S;
+        }
+        return;
+    }
+    if (lane == 0 && nC > 0) {
+        double* y = Ys;   // reuse
+        for (int i = 0; i < nC; ++i) y[i] = Sm[i * ld + nC];
+        chol_solve_lane(Sm, nC, ld, y);
+        for (int i = 0; i < nC; ++i) lam_s[i] = y[i];   // lam_s now holds s_lambda
+    }
+    __syncthreads();
+    double* stp = a.step + (size_t)b * (nD + nC);
+    for (int j = lane; j < nC; j += 64) stp[nD + j] = lam_s[j];
+    for (int sd = 0; sd < a.n_sub; ++sd) {
+        const int NN = a.n_om[sd] + a.n_ga[sd];
+        for (int k = lane; k < NN; k += 64) {
+            const double* yr = Yb + ((size_t)sd * KKT_NN + k) * ld;
+            double s = yr[nC];
+            for (int j = 0; j < nC; ++j) s += yr[j] * lam_s[j];
+            stp[a.xoff[sd] + k] = -s;
+        }
+    }
+    __syncthreads();
+    for (int e = lane; e < nD; e += 64) a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + stp[e];
+    for (int j = lane; j < nC; j += 64)
+        a.lamt[(size_t)b * nC + j] = a.lam[(size_t)b * nC + j] + stp[nD + j];
+    if (lane == 0) {
+        S.phi0 = phi_t;
+        S.alpha = 1.0;
+        S.nbt = 0;
+        S.phase = PH_TRIAL;
+        a.st[b] = S;
+        atomicAdd(a.counter, 1);
+    }
+}
+
+__global__ void k_init(int B, int Bp, int nD, int nC, const double* __restrict__ mu, const double* __restrict__ x0,
+                       const double* __restrict__ l0, double* __restrict__ mu_ws, double* __restrict__ x,
+                       double* __restrict__ xt, double* __restrict__ lam, double* __restrict__ lamt,
+                       SolveState* __restrict__ st) {
+    const int b = blockIdx.x;
+    if (b >= Bp) return;
+    for (int e = threadIdx.x; e < nD; e += blockDim.x) {
+        const double v = (b < B && x0) ? x0[(size_t)b * nD + e] : 0.0;
+        x[(size_t)b * nD + e] = v;
+        xt[(size_t)b * nD + e] = v;
+    }
+    for (int j = threadIdx.x; j < nC; j += blockDim.x) {
+        const double v = (b < B && l0) ? l0[(size_t)b * nC + j] : 0.0;
+        lam[(size_t)b * nC + j] = v;
+        lamt[(size_t)b * nC + j] = v;
+    }
+    if (threadIdx.x == 0) {
+        mu_ws[2 * b] = b < B ? mu[2 * b] : 1.0;
+        mu_ws[2 * b + 1] = b < B ? mu[2 * b + 1] : 5.0;
+        SolveState s;
+        s.phase = b < B ? PH_INIT : PH_DONE;
+        s.status = DDROM_STATUS_MAX_ITER;
+        s.iters = 0;
+        s.nbt = 0;
+        s.alpha = 1.0;
+        s.phi0 = 0.0;
+        s.tol = 0.0;
+        s.f0 = 0.0;
+        s.fn = 0.0;
+        st[b] = s;
+    }
+}
+
+__global__ void k_finalize(int B, int nD, int nC, const double* __restrict__ x, const double* __restrict__ lam,
+                           const SolveState* __restrict__ st, double* __restrict__ xo, double* __restrict__ lo,
+                           int* __restrict__ it, int* __restrict__ status, double* __restrict__ fn,
+                           double* __restrict__ f0) {
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    for (int e = threadIdx.x; e < nD; e += blockDim.x) xo[(size_t)b * nD + e] = x[(size_t)b * nD + e];
+    if (lo)
+        for (int j = threadIdx.x; j < nC; j += blockDim.x) lo[(size_t)b * nC + j] = lam[(size_t)b * nC + j];
+    if (threadIdx.x == 0) {
+        if (it) it[b] = st[b].iters;
+        if (status) status[b] = st[b].status;
+        if (fn) fn[b] = st[b].fn;
+        if (f0) f0[b] = st[b].f0;
+    }
+}
+
+__global__ void k_zero_int(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// Sum of the GN partials into dense per-solve outputs (ddrom_gn_blocks).
+__global__ void k_collect(int B, int Bp, int n_sub, int n_C, int nD, int nmax, int mmax, int estride,
+                          const int* __restrict__ n_om, const int* __restrict__ n_ga, const int* __restrict__ xoff,
+                          const int* __restrict__ slot0, const double* __restrict__ part,
+                          const double* __restrict__ c_part, const double* __restrict__ E_part, double* H, double* g,
+                          double* EG, double* c, double* rr) {
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    double rrs = 0.0;
+    for (int sd = 0; sd < n_sub; ++sd) {
+        const int NN = n_om[sd] + n_ga[sd], NH = NN * (NN + 1) / 2;
+        for (int e = threadIdx.x; e < NH + NN + 1; e += blockDim.x) {
+            double s = 0.0;
+            for (int sl = slot0[sd]; sl < slot0[sd + 1]; ++sl) s += part[((size_t)sl * estride + e) * Bp + b];
+            if (e < NH) {
+                int i = 0, rem = e;
+                while (rem >= NN - i) { rem -= NN - i; ++i; }
+                const int j = i + rem;
+                if (H) {
+                    H[(((size_t)b * n_sub + sd) * nmax + i) * nmax + j] = s;
+                    H[(((size_t)b * n_sub + sd) * nmax + j) * nmax + i] = s;
+                }
+            } else if (e < NH + NN) {
+                if (g) g[(size_t)b * nD + xoff[sd] + (e - NH)] = s;
+            } else {
+                rrs += s;
+            }
+        }
+        if (EG)
+            for (int e = threadIdx.x; e < n_C * mmax; e += blockDim.x) {
+                const int j = e / mmax, k = e % mmax;
+                EG[(((size_t)b * n_sub + sd) * n_C + j) * mmax + k] =
+                    k < n_ga[sd] ? E_part[(((size_t)sd * n_C + j) * mmax + k) * Bp + b] : 0.0;
+            }
+    }
+    if (c)
+        for (int j = threadIdx.x; j < n_C; j += blockDim.x) {
+            double s = 0.0;
+            for (int sd = 0; sd < n_sub; ++sd) s += c_part[((size_t)sd * n_C + j) * Bp + b];
+            c[(size_t)b * n_C + j] = s;
+        }
+    // rr: reduce across the block
+    __shared__ double red[256];
+    red[threadIdx.x] = rrs;
+    __syncthreads();
+    if (threadIdx.x == 0 && rr) {
+        double s = 0.0;
+        for (int t = 0; t < (int)blockDim.x; ++t) s += red[t];
+        rr[b] = s;
+    }
+}
+
+// Transpose decoder output [rows*(1+n)][Bp] -> x [B][rows], J [B][rows][n]
+template <typename T>
+__global__ void k_dec_transpose(const T* __restrict__ dec, long long out_row0, int rows, int n, int B, int Bp,
+                                T* __restrict__ x, T* __restrict__ J) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)rows * (1 + n) * B;
+    if (idx >= tot) return;
+    const int b = (int)(idx % B);
+    const long long rj = idx / B;
+    const int r = (int)(rj / (1 + n)), j = (int)(rj % (1 + n));
+    const T v = dec[(size_t)(out_row0 + rj) * Bp + b];
+    if (j == 0) {
+        if (x) x[(size_t)b * rows + r] = v;
+    } else if (J) {
+        J[((size_t)b * rows + r) * n + (j - 1)] = v;
+    }
+}
+
+// DD FOM residual (all owned nodes of all subdomains), one thread per (node slot, solve).
+__global__ void k_fom_residual(int total_own, int B, const int* __restrict__ src, const int* __restrict__ sd_of,
+                               const long long* __restrict__ meta, const double* __restrict__ mu,
+                               const double* __restrict__ xsd, int n_state, int N_x, double nu, double hx,
+                               double hy, double* __restrict__ r, double* __restrict__ jac) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)total_own * B) return;
+    const int q = (int)(idx % total_own), b = (int)(idx / total_own);
+    const int sd = sd_of[q];
+    const long long* me = meta + 6 * sd;
+    const long long own_off = me[0], n_own = me[1], nint = me[2], nif = me[3], soff = me[4], roff = me[5];
+    const double* xs = xsd + (size_t)b * n_state + soff;
+    double v[N_SLOTS];
+    for (int t = 0; t < 5; ++t) {
+        const int code = src[(size_t)q * 5 + t];
+        const int kind = src_kind(code), ix = src_index(code);
+        if (kind == SRC_OMEGA) {
+            v[t] = xs[ix];
+            v[5 + t] = xs[ix + nint];
+        } else if (kind == SRC_GAMMA) {
+            v[t] = xs[2 * nint + ix];
+            v[5 + t] = xs[2 * nint + ix + nif];
+        } else {
+            const int I = ix >> 14, J = ix & 0x3fff;
+            exact_uv(-1.0 + I * hx, J * hy, mu[2 * b], mu[2 * b + 1], nu, v[t], v[5 + t]);
+        }
+    }
+    double ru, rv, cu[6], cv[6];
+    burgers_point(v, nu, hx, hy, ru, rv, cu, cv);
+    const long long l = q - own_off;
+    double* rb = r + (size_t)b * N_x + roff;
+    rb[l] = ru;
+    rb[n_own + l] = rv;
+    if (jac) {
+        double* ju = jac + ((size_t)b * N_x + roff + l) * 6;
+        double* jv = jac + ((size_t)b * N_x + roff + n_own + l) * 6;
+        for (int t = 0; t < 6; ++t) {
+            // zero the entries that multiply a Dirichlet value
+            const int slot = t < 5 ? t : 0;
+            const bool bnd = src_kind(src[(size_t)q * 5 + slot]) == SRC_BOUND;
+            ju[t] = bnd ? 0.0 : cu[t];
+            jv[t] = bnd ? 0.0 : cv[t];
+        }
+    }
+}
+
+// ====================================================================================
+// Host side
+// ====================================================================================
+namespace {
+
+struct DevInts {
+    int *n_om = nullptr, *n_ga = nullptr, *xoff = nullptr, *slot0 = nullptr;
+};
+
+struct ModelExtra {
+    DevInts di;
+};
+
+static int launch_decode(const ddrom_model* m, int prec, int c0, int c1, int n, const double* xhat, int xstride,
+                         int xoff_override, const SolveState* st, int B, void* out, int Bp, hipStream_t s) {
+    if (c1 <= c0) return 0;
+    dim3 grid(c1 - c0, Bp / 64), block(64);
+#define DEC_CASE(NLV)                                                                                            \
+    case NLV:                                                                                                    \
+        if (prec == DDROM_PREC_FP64)                                                                             \
+            hipLaunchKernelGGL((k_decode<double, NLV>), grid, block, 0, s, m->chunks_d, c0, m->segs_d, m->W1d,    \
+                               m->b1d, m->bands, m->W2d, m->xrefd, xhat, xstride, xoff_override, st, B,          \
+                               (double*)out, Bp, m->act);                                                        \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_decode<float, NLV>), grid, block, 0, s, m->chunks_d, c0, m->segs_d, m->W1f,     \
+                               m->b1f, m->bands, m->W2f, m->xreff, xhat, xstride, xoff_override, st, B,          \
+                               (float*)out, Bp, m->act);                                                         \
+        break;
+    switch (n) {
+        DEC_CASE(1) DEC_CASE(2) DEC_CASE(3) DEC_CASE(4) DEC_CASE(5) DEC_CASE(6) DEC_CASE(8) DEC_CASE(10)
+        DEC_CASE(12)
+        default:
+            set_error("unsupported latent size " + std::to_string(n));
+            return DDROM_EINVAL;
+    }
+#undef DEC_CASE
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const ddrom_workspace* ws,
+                      const SolveState* st, int B, hipStream_t s) {
+    const ddrom::ResSeg& rs = m->rsegs_h[sd0];
+    // one chunk per slot, slots of consecutive subdomains are consecutive
+    const int c0 = rs.slot0, c1 = m->rsegs_h[sd1 - 1].slot1;
+    dim3 grid(c1 - c0, ws->Bp / 64), block(64);
+#define RES_CASE(A, G)                                                                                            \
+    if (rs.n_om == A && rs.n_ga == G) {                                                                           \
+        if (prec == DDROM_PREC_FP64)                                                                              \
+            hipLaunchKernelGGL((k_res_gn<double, A, G>), grid, block, 0, s, m->rchunks_d, c0, m->rsegs_d,          \
+                               m->segs_d, m->gather_d, (const double*)ws->dec_out, ws->bc, st, B, ws->Bp, m->nu,  \
+                               m->hx, m->hy, ws->gn_part, m->estride);                                            \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_res_gn<float, A, G>), grid, block, 0, s, m->rchunks_d, c0, m->rsegs_d,           \
+                               m->segs_d, m->gather_d, (const float*)ws->dec_out, ws->bc, st, B, ws->Bp, m->nu,   \
+                               m->hx, m->hy, ws->gn_part, m->estride);                                            \
+        HIPCHECK(hipGetLastError());                                                                              \
+        return 0;                                                                                                 \
+    }
+    RES_CASE(2, 1) RES_CASE(3, 2) RES_CASE(4, 2) RES_CASE(6, 3) RES_CASE(8, 4) RES_CASE(12, 6) RES_CASE(3, 0)
+    RES_CASE(4, 0) RES_CASE(6, 0) RES_CASE(8, 0)
+#undef RES_CASE
+    set_error("unsupported latent sizes (" + std::to_string(rs.n_om) + ", " + std::to_string(rs.n_ga) + ")");
+    return DDROM_EINVAL;
+}
+
+static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const SolveState* st, int B,
+                      hipStream_t s) {
+    if (m->n_cchunks == 0 || m->n_C == 0) return 0;
+    // all subdomains must share n_i^Gamma for one launch; group otherwise
+    dim3 grid(m->n_cchunks, ws->Bp / 64), block(64);
+    const int ng = m->mmax;
+    for (int sd = 0; sd < m->n_sub; ++sd)
+        if (m->n_ga[sd] != ng) {
+            set_error("constraint kernel needs equal interface latent sizes");
+            return DDROM_EINVAL;
+        }
+#define CON_CASE(G)                                                                                               \
+    case G:                                                                                                       \
+        if (prec == DDROM_PREC_FP64)                                                                              \
+            hipLaunchKernelGGL((k_con<double, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d, \
+                               m->n_C, (const double*)ws->dec_out, st, B, ws->Bp, ws->c_part, ws->E_part, m->mmax); \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_con<float, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d,  \
+                               m->n_C, (const float*)ws->dec_out, st, B, ws->Bp, ws->c_part, ws->E_part, m->mmax); \
+        break;
+    switch (ng) {
+        CON_CASE(1) CON_CASE(2) CON_CASE(3) CON_CASE(4) CON_CASE(6)
+        default:
+            set_error("unsupported interface latent size");
+            return DDROM_EINVAL;
+    }
+#undef CON_CASE
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+// Device copies of small per-subdomain integer tables, kept next to the model.
+struct ModelDevInts {
+    int *n_om, *n_ga, *xoff, *slot0;
+};
+static ModelDevInts get_ints(const ddrom_model* m);
+
+// The model struct has no slot for these, so keep them in a side table keyed by model.
+static std::mutex g_mu;
+static std::map<const ddrom_model*, ModelDevInts> g_ints;
+
+static ModelDevInts get_ints(const ddrom_model* m) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_ints[m];
+}
+
+// One evaluation of all active solves at their trial points (xt).
+static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const SolveState* st,
+                          const double* xhat, hipStream_t s) {
+    int rc;
+    // decoders: one launch per run of consecutive segments with the same latent size
+    const int nseg = 2 * m->n_sub;
+    for (int g0 = 0; g0 < nseg;) {
+        int g1 = g0 + 1;
+        while (g1 < nseg && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
+        if ((rc = launch_decode(m, prec, m->seg_chunk0[g0], m->seg_chunk1[g1 - 1], m->segs_h[g0].n, xhat, m->n_D, -1,
+                                st, B, ws->dec_out, ws->Bp, s)))
+            return rc;
+        g0 = g1;
+    }
+    for (int s0 = 0; s0 < m->n_sub;) {
+        int s1 = s0 + 1;
+        while (s1 < m->n_sub && m->n_om[s1] == m->n_om[s0] && m->n_ga[s1] == m->n_ga[s0]) ++s1;
+        if ((rc = launch_res(m, prec, s0, s1, ws, st, B, s))) return rc;
+        s0 = s1;
+    }
+    if ((rc = launch_con(m, prec, ws, st, B, s))) return rc;
+    return 0;
+}
+
+static UpdArgs upd_args(const ddrom_model* m, ddrom_workspace* ws, int B, const ddrom_opts* o, int lam_given) {
+    ModelDevInts di = get_ints(m);
+    UpdArgs a;
+    a.n_sub = m->n_sub; a.n_C = m->n_C; a.n_D = m->n_D; a.mmax = m->mmax; a.estride = m->estride; a.Bp = ws->Bp;
+    a.B = B; a.lam_given = lam_given; a.max_iter = o->max_iter; a.max_bt = o->max_backtracks;
+    a.tol_abs = o->tol_abs; a.tol_rel = o->tol_rel; a.c1 = o->armijo_c1;
+    a.n_om = di.n_om; a.n_ga = di.n_ga; a.xoff = di.xoff; a.slot0 = di.slot0;
+    a.gn_part = ws->gn_part; a.c_part = ws->c_part; a.E_part = ws->E_part;
+    a.x = ws->x; a.xt = ws->xt; a.lam = ws->lam; a.lamt = ws->lamt; a.step = ws->step; a.Y = ws->Y;
+    a.st = ws->st; a.counter = ws->counter;
+    return a;
+}
+
+static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const UpdArgs& ua, hipStream_t s) {
+    int rc;
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, ws->counter);
+    if ((rc = evaluate_round(m, ws, prec, B, ws->st, ws->xt, s))) return rc;
+    hipLaunchKernelGGL(k_update, dim3(B), dim3(64), 0, s, ua);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+extern "C" {
+
+const char* ddrom_last_error(void) { return g_err.c_str(); }
+
+int ddrom_model_create(const ddrom_model_desc* desc, ddrom_model** out) {
+    if (!out) {
+        set_error("out is NULL");
+        return DDROM_EINVAL;
+    }
+    *out = nullptr;
+    std::unique_ptr<ddrom_model> m(new ddrom_model());
+    int rc = build_model(desc, m.get());
+    if (rc) {
+        free_model(m.get());
+        return rc;
+    }
+    ModelDevInts di{};
+    std::vector<int> slot0(m->n_sub + 1);
+    for (int sd = 0; sd < m->n_sub; ++sd) slot0[sd] = m->rsegs_h[sd].slot0;
+    slot0[m->n_sub] = m->n_slots;
+    auto up = [&](int** p, const std::vector<int>& v) -> int {
+        if (hipMalloc((void**)p, v.size() * sizeof(int)) != hipSuccess) return DDROM_ENOMEM;
+        if (hipMemcpy(*p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return DDROM_EHIP;
+        return 0;
+    };
+    if ((rc = up(&di.n_om, m->n_om)) || (rc = up(&di.n_ga, m->n_ga)) || (rc = up(&di.xoff, m->xoff)) ||
+        (rc = up(&di.slot0, slot0))) {
+        set_error("device allocation failed");
+        free_model(m.get());
+        return rc;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_ints[m.get()] = di;
+    }
+    *out = m.release();
+    return 0;
+}
+
+void ddrom_model_destroy(ddrom_model* m) {
+    if (!m) return;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_ints.find(m);
+        if (it != g_ints.end()) {
+            (void)hipFree(it->second.n_om);
+            (void)hipFree(it->second.n_ga);
+            (void)hipFree(it->second.xoff);
+            (void)hipFree(it->second.slot0);
+            g_ints.erase(it);
+        }
+    }
+    free_model(m);
+    delete m;
+}
+
+long long ddrom_model_size(const ddrom_model* m, int q, int sd) {
+    if (!m) return -1;
+    if (sd >= 0 && sd >= m->n_sub) return -1;
+    switch (q) {
+        case 0: return m->n_sub;
+        case 1: return m->n_D;
+        case 2: return m->n_C;
+        case 3: return m->N_A;
+        case 4: return m->N_x;
+        case 5: return m->n_state;
+        case 6: { long long t = 0; for (int v : m->nb) t += v; return t; }
+        case 10: return sd < 0 ? -1 : m->n_om[sd];
+        case 11: return sd < 0 ? -1 : m->n_ga[sd];
+        case 12: return sd < 0 ? -1 : m->N_om[sd];
+        case 13: return sd < 0 ? -1 : m->N_ga[sd];
+        case 14: return sd < 0 ? -1 : (long long)m->subnet_rows[sd].size();
+        case 15: return sd < 0 ? -1 : m->hid_om[sd];
+        case 16: return sd < 0 ? -1 : m->nb[sd];
+        case 17: return sd < 0 ? -1 : m->xoff[sd];
+        case 18: return sd < 0 ? -1 : m->n_own[sd];
+        default: return -1;
+    }
+}
+
+int ddrom_subnet_rows(const ddrom_model* m, int sd, int part, int* rows_h) {
+    if (!m || sd < 0 || sd >= m->n_sub || !rows_h || (part != 0 && part != 1)) {
+        set_error("bad arguments to ddrom_subnet_rows");
+        return DDROM_EINVAL;
+    }
+    if (part == 0)
+        for (size_t k = 0; k < m->subnet_rows[sd].size(); ++k) rows_h[k] = m->subnet_rows[sd][k];
+    else
+        for (int k = 0; k < m->N_ga[sd]; ++k) rows_h[k] = k;
+    return 0;
+}
+
+int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace** out) {
+    if (!m || !out || max_batch <= 0) {
+        set_error("bad arguments to ddrom_workspace_create");
+        return DDROM_EINVAL;
+    }
+    *out = nullptr;
+    std::unique_ptr<ddrom_workspace> w(new ddrom_workspace());
+    w->m = m;
+    w->max_B = max_batch;
+    w->Bp = (max_batch + 63) / 64 * 64;
+    const size_t Bp = w->Bp;
+    const int ld = m->n_C + 1;
+    struct A { void** p; size_t bytes; } allocs[] = {
+        {(void**)&w->dec_out, (size_t)m->dec_rows * Bp * sizeof(double)},
+        {(void**)&w->bc, std::max<size_t>(1, (size_t)m->n_bc) * Bp * sizeof(double)},
+        {(void**)&w->gn_part, (size_t)m->n_slots * m->estride * Bp * sizeof(double)},
+        {(void**)&w->c_part, std::max<size_t>(1, (size_t)m->n_sub * m->n_C) * Bp * sizeof(double)},
+        {(void**)&w->E_part, std::max<size_t>(1, (size_t)m->n_sub * m->n_C * std::max(1, m->mmax)) * Bp * sizeof(double)},
+        {(void**)&w->x, Bp * m->n_D * sizeof(double)},
+        {(void**)&w->xt, Bp * m->n_D * sizeof(double)},
+        {(void**)&w->lam, Bp * std::max(1, m->n_C) * sizeof(double)},
+        {(void**)&w->lamt, Bp * std::max(1, m->n_C) * sizeof(double)},
+        {(void**)&w->step, Bp * (m->n_D + m->n_C) * sizeof(double)},
+        {(void**)&w->Y, Bp * m->n_sub * KKT_NN * ld * sizeof(double)},
+        {(void**)&w->mu, Bp * 2 * sizeof(double)},
+        {(void**)&w->st, Bp * sizeof(SolveState)},
+        {(void**)&w->counter, sizeof(int) * 4},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            set_error("workspace allocation failed");
+            ddrom_workspace_destroy(w.release());
+            return DDROM_ENOMEM;
+        }
+    }
+    if (hipHostMalloc((void**)&w->counter_h, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+        set_error("pinned allocation failed");
+        ddrom_workspace_destroy(w.release());
+        return DDROM_ENOMEM;
+    }
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&w->t0) != hipSuccess || hipEventCreate(&w->t1) != hipSuccess) {
+        set_error("stream/event creation failed");
+        ddrom_workspace_destroy(w.release());
+        return DDROM_EHIP;
+    }
+    *out = w.release();
+    return 0;
+}
+
+void ddrom_workspace_destroy(ddrom_workspace* w) {
+    if (!w) return;
+    void* ptrs[] = {w->dec_out, w->bc, w->gn_part, w->c_part, w->E_part, w->x, w->xt, w->lam, w->lamt,
+                    w->step, w->Y, w->mu, w->st, w->counter};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (w->counter_h) (void)hipHostFree(w->counter_h);
+    if (w->graph) (void)hipGraphExecDestroy(w->graph);
+    if (w->ev_in) (void)hipEventDestroy(w->ev_in);
+    if (w->ev_out) (void)hipEventDestroy(w->ev_out);
+    if (w->t0) (void)hipEventDestroy(w->t0);
+    if (w->t1) (void)hipEventDestroy(w->t1);
+    if (w->stream) (void)hipStreamDestroy(w->stream);
+    delete w;
+}
+
+int dd_fom_residual(const ddrom_model* m, const double* mu_d, const double* xsd_d, int B, double* r_d, double* jac_d,
+                    hipStream_t s) {
+    if (!m || !mu_d || !xsd_d || !r_d || B < 0) {
+        set_error("bad arguments to dd_fom_residual");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    const long long tot = (long long)m->total_own * B;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_fom_residual, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s, m->total_own, B,
+                       m->fom_src_d, m->fom_sd_of_row_d, m->fom_meta_d, mu_d, xsd_d, m->n_state, m->N_x, m->nu,
+                       m->hx, m->hy, r_d, jac_d);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+static int check_ws(const ddrom_model* m, const ddrom_workspace* ws, int B) {
+    if (!m || !ws || ws->m != m) {
+        set_error("workspace missing or created for another model");
+        return DDROM_EINVAL;
+    }
+    if (B > ws->max_B) {
+        set_error("batch larger than the workspace capacity");
+        return DDROM_ESHAPE;
+    }
+    return 0;
+}
+
+static int decode_common(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
+                         int prec, void* x_d, void* J_d, hipStream_t s) {
+    int rc = check_ws(m, ws, B);
+    if (rc) return rc;
+    if (sd < 0 || sd >= m->n_sub || (part != 0 && part != 1) || !xhat_d || (prec != 0 && prec != 1)) {
+        set_error("bad arguments to ae_decode_hr / ae_jacobian_hr");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    const int seg = part * m->n_sub + sd;
+    const ddrom::DecSeg& sg = m->segs_h[seg];
+    if ((rc = launch_decode(m, prec, m->seg_chunk0[seg], m->seg_chunk1[seg], sg.n, xhat_d, sg.n, 0, nullptr, B,
+                            ws->dec_out, ws->Bp, s)))
+        return rc;
+    const long long tot = (long long)sg.rows * (1 + sg.n) * B;
+    if (tot == 0) return 0;
+    const int bs = 256;
+    dim3 grid((unsigned)((tot + bs - 1) / bs));
+    if (prec == DDROM_PREC_FP64)
+        hipLaunchKernelGGL(k_dec_transpose<double>, grid, dim3(bs), 0, s, (const double*)ws->dec_out, sg.out, sg.rows,
+                           sg.n, B, ws->Bp, (double*)x_d, (double*)J_d);
+    else
+        hipLaunchKernelGGL(k_dec_transpose<float>, grid, dim3(bs), 0, s, (const float*)ws->dec_out, sg.out, sg.rows,
+                           sg.n, B, ws->Bp, (float*)x_d, (float*)J_d);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+int ae_decode_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
+                 int precision, void* x_d, hipStream_t s) {
+    if (!x_d) {
+        set_error("x_d is NULL");
+        return DDROM_EINVAL;
+    }
+    return decode_common(m, ws, sd, part, xhat_d, B, precision, x_d, nullptr, s);
+}
+
+int ae_jacobian_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
+                   int precision, void* x_d, void* J_d, hipStream_t s) {
+    if (!J_d) {
+        set_error("J_d is NULL");
+        return DDROM_EINVAL;
+    }
+    return decode_common(m, ws, sd, part, xhat_d, B, precision, x_d, J_d, s);
+}
+
+int ddrom_gn_blocks(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, const double* xhat_d, int B,
+                    int precision, double* H_d, double* g_d, double* EG_d, double* c_d, double* rr_d, hipStream_t s) {
+    int rc = check_ws(m, ws, B);
+    if (rc) return rc;
+    if (!mu_d || !xhat_d || (precision != 0 && precision != 1)) {
+        set_error("bad arguments to ddrom_gn_blocks");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, s, B, ws->Bp, m->n_D, m->n_C, mu_d, xhat_d,
+                       (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt, ws->st);
+    if (m->n_bc > 0)
+        hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
+                           B, ws->Bp, m->nu, ws->bc);
+    if ((rc = evaluate_round(m, ws, precision, B, ws->st, ws->xt, s))) return rc;
+    ModelDevInts di = get_ints(m);
+    hipLaunchKernelGGL(k_collect, dim3(B), dim3(256), 0, s, B, ws->Bp, m->n_sub, m->n_C, m->n_D, m->nmax,
+                       std::max(1, m->mmax), m->estride, di.n_om, di.n_ga, di.xoff, di.slot0, ws->gn_part,
+                       ws->c_part, ws->E_part, H_d, g_d, EG_d, c_d, rr_d);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+struct FinalOut {
+    double *x, *lam, *fn, *f0;
+    int *it, *status;
+};
+
+static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, const double* x0,
+                        const double* l0, const ddrom_opts* o, hipStream_t caller, int use_graph, const FinalOut& fo) {
+    int rc = check_ws(m, ws, B);
+    if (rc) return rc;
+    if (!mu_d || !o || o->max_iter < 0 || o->max_backtracks < 0 || (o->precision != 0 && o->precision != 1)) {
+        set_error("bad arguments to the solver");
+        return DDROM_EINVAL;
+    }
+    hipStream_t s = ws->stream;
+    HIPCHECK(hipEventRecord(ws->ev_in, caller));
+    HIPCHECK(hipStreamWaitEvent(s, ws->ev_in, 0));
+    hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, s, B, ws->Bp, m->n_D, m->n_C, mu_d, x0, l0, ws->mu, ws->x,
+                       ws->xt, ws->lam, ws->lamt, ws->st);
+    if (m->n_bc > 0)
+        hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
+                           B, ws->Bp, m->nu, ws->bc);
+    HIPCHECK(hipGetLastError());
+    const UpdArgs ua = upd_args(m, ws, B, o, l0 != nullptr);
+    const int prec = o->precision;
+    // The first round evaluates the initial latents; later rounds are line-search trials.
+    const long long max_rounds = 1 + (long long)std::max(1, o->max_iter) * (o->max_backtracks + 1) + 1;
+    const int K = 8;
+    std::ostringstream key;
+    key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
+        << ":" << o->max_backtracks << ":" << (l0 != nullptr);
+    long long done = 0;
+    if (use_graph) {
+        if (ws->graph_key != key.str() || !ws->graph) {
+            if (ws->graph) {
+                (void)hipGraphExecDestroy(ws->graph);
+                ws->graph = nullptr;
+            }
+            hipGraph_t g;
+            HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            int crc = 0;
+            for (int k = 0; k < K && !crc; ++k) crc = round_launch(m, ws, prec, B, ua, s);
+            hipError_t ce = hipStreamEndCapture(s, &g);
+            if (crc) return crc;
+            if (ce != hipSuccess) {
+                set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
+                return DDROM_EHIP;
+            }
+            hipError_t ie = hipGraphInstantiate(&ws->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) {
+                ws->graph = nullptr;
+                set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+                return DDROM_EHIP;
+            }
+            ws->graph_key = key.str();
+        }
+        while (done < max_rounds) {
+            HIPCHECK(hipGraphLaunch(ws->graph, s));
+            done += K;
+            HIPCHECK(hipMemcpyAsync(ws->counter_h, ws->counter, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            if (*ws->counter_h == 0) break;
+        }
+    } else {
+        while (done < max_rounds) {
+            if ((rc = round_launch(m, ws, prec, B, ua, s))) return rc;
+            ++done;
+            HIPCHECK(hipMemcpyAsync(ws->counter_h, ws->counter, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            if (*ws->counter_h == 0) break;
+        }
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(B), dim3(64), 0, s, B, m->n_D, m->n_C, ws->x, ws->lam, ws->st, fo.x, fo.lam,
+                       fo.it, fo.status, fo.fn, fo.f0);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipEventRecord(ws->ev_out, s));
+    HIPCHECK(hipStreamWaitEvent(caller, ws->ev_out, 0));
+    return 0;
+}
+
+int sqp_step(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, double* xhat_d, double* lam_d,
+             double* fnorm_d, int* status_d, const ddrom_opts* o, hipStream_t s) {
+    if (!xhat_d || !lam_d || !o) {
+        set_error("bad arguments to sqp_step");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    ddrom_opts one = *o;
+    one.max_iter = 1;
+    one.tol_abs = 0.0;
+    one.tol_rel = 0.0;
+    FinalOut fo{xhat_d, lam_d, fnorm_d, nullptr, nullptr, status_d};
+    return solve_common(m, ws, mu_d, B, xhat_d, lam_d, &one, s, 0, fo);
+}
+
+int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, const double* xhat0_d,
+                    const double* lam0_d, const ddrom_opts* o, double* xhat_d, double* lam_d, int* iters_d,
+                    int* status_d, double* fnorm_d, double* fnorm0_d, hipStream_t s) {
+    if (!xhat_d) {
+        set_error("xhat_d is NULL");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    FinalOut fo{xhat_d, lam_d, fnorm_d, fnorm0_d, iters_d, status_d};
+    return solve_common(m, ws, mu_d, B, xhat0_d, lam0_d, o, s, 1, fo);
+}
+
+int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, const double* xhat_d, int B,
+                       int precision, int reps, float* ms_h) {
+    int rc = check_ws(m, ws, B);
+    if (rc) return rc;
+    if (!mu_d || !xhat_d || !ms_h || reps <= 0 || B <= 0 || (precision != 0 && precision != 1)) {
+        set_error("bad arguments to ddrom_time_kernels");
+        return DDROM_EINVAL;
+    }
+    hipStream_t s = ws->stream;
+    HIPCHECK(hipDeviceSynchronize());
+    hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, s, B, ws->Bp, m->n_D, m->n_C, mu_d, xhat_d,
+                       (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt, ws->st);
+    if (m->n_bc > 0)
+        hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
+                           B, ws->Bp, m->nu, ws->bc);
+    // warm the decoder outputs once so the residual and constraint kernels read real data
+    if ((rc = evaluate_round(m, ws, precision, B, ws->st, ws->xt, s))) return rc;
+    auto timed = [&](int which, float* out) -> int {
+        HIPCHECK(hipEventRecord(ws->t0, s));
+        for (int r = 0; r < reps; ++r) {
+            int c = 0;
+            if (which == 0) c = launch_decode(m, precision, m->seg_chunk0[0], m->seg_chunk1[m->n_sub - 1],
+                                              m->segs_h[0].n, ws->xt, m->n_D, -1, ws->st, B, ws->dec_out, ws->Bp, s);
+            else if (which == 1) c = launch_decode(m, precision, m->seg_chunk0[m->n_sub], m->seg_chunk1[2 * m->n_sub - 1],
+                                                   m->segs_h[m->n_sub].n, ws->xt, m->n_D, -1, ws->st, B, ws->dec_out,
+                                                   ws->Bp, s);
+            else if (which == 2) c = launch_res(m, precision, 0, m->n_sub, ws, ws->st, B, s);
+            else c = launch_con(m, precision, ws, ws->st, B, s);
+            if (c) return c;
+        }
+        HIPCHECK(hipEventRecord(ws->t1, s));
+        HIPCHECK(hipEventSynchronize(ws->t1));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, ws->t0, ws->t1));
+        *out = ms / reps;
+        return 0;
+    };
+    for (int k = 0; k < 4; ++k)
+        if ((rc = timed(k, ms_h + k))) return rc;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,474 @@
+// Host-side construction of the device model: algebraic DD maps (Section 2), ports and
+// compatibility matrices A_i, C A_i, interior decoder subnets (Section 5.4), stencil
+// gather tables for the HR residual and the DD FOM residual, and the upload of all pools.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <sstream>
+
+#include "internal.h"
+
+namespace ddrom {
+
+static constexpr int RING = 64;          // hidden-unit ring of the decode kernel (window bound)
+static constexpr int DEC_ROWS = 128;     // output rows per decode work item
+static constexpr int RES_NODES = 48;     // sampled nodes per residual work item
+static constexpr int CON_ROWS = 8;       // constraint rows per constraint work item
+
+template <typename T>
+static int upload(T** dst, const std::vector<T>& src) {
+    size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+    if (hipMalloc((void**)dst, bytes) != hipSuccess) {
+        set_error("hipMalloc failed while uploading the model");
+        return DDROM_ENOMEM;
+    }
+    if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("hipMemcpy failed while uploading the model");
+        return DDROM_EHIP;
+    }
+    return 0;
+}
+
+struct HostDecoder {
+    std::vector<double> W1, b1, W2, xref;   // packed subnet
+    std::vector<int2> band;
+    int rows = 0, hid = 0;
+};
+
+// Subnet of eq. subnet for the output rows `rows` (ascending) of one decoder.
+static int make_subnet(const ddrom_decoder_desc& d, const std::vector<int>& rows, HostDecoder& out) {
+    const int N = d.N, n = d.n, w = d.w, b = d.b, s = d.s;
+    std::vector<int> cmap(w, -1);
+    for (int r : rows)
+        for (int k = 0; k < 3; ++k)
+            for (int t = 0; t < b; ++t) {
+                long long c = (long long)r * s + (long long)(k - 1) * b * s + t;
+                if (c >= 0 && c < w) cmap[c] = 1;
+            }
+    int hid = 0;
+    std::vector<int> hidden;
+    for (int c = 0; c < w; ++c)
+        if (cmap[c] >= 0) {
+            cmap[c] = hid++;
+            hidden.push_back(c);
+        }
+    out.rows = (int)rows.size();
+    out.hid = hid;
+    out.W1.resize((size_t)hid * n);
+    out.b1.resize(hid);
+    for (int h = 0; h < hid; ++h) {
+        for (int k = 0; k < n; ++k) out.W1[(size_t)h * n + k] = d.W1[(size_t)hidden[h] * n + k];
+        out.b1[h] = d.b1[hidden[h]];
+    }
+    out.band.assign((size_t)rows.size() * 3, int2{0, 0});
+    out.W2.assign((size_t)rows.size() * 3 * b, 0.0);
+    out.xref.resize(rows.size());
+    for (size_t q = 0; q < rows.size(); ++q) {
+        int r = rows[q];
+        if (r < 0 || r >= N) {
+            set_error("subnet row out of range");
+            return DDROM_EINVAL;
+        }
+        out.xref[q] = d.x_ref[r];
+        int lo = 1 << 30, hi = -1;
+        for (int k = 0; k < 3; ++k) {
+            int t0 = -1, t1 = -1;
+            for (int t = 0; t < b; ++t) {
+                long long c = (long long)r * s + (long long)(k - 1) * b * s + t;
+                if (c >= 0 && c < w) {
+                    if (t0 < 0) t0 = t;
+                    t1 = t;
+                }
+            }
+            if (t0 < 0) continue;
+            int c0 = r * s + (k - 1) * b * s + t0;
+            int len = t1 - t0 + 1;
+            int cs = cmap[c0];
+            for (int t = 0; t < len; ++t) {
+                if (cmap[c0 + t] != cs + t) {
+                    set_error("internal: band not contiguous in the compressed hidden index");
+                    return DDROM_EINVAL;
+                }
+                out.W2[(q * 3 + k) * b + t] = d.W2[((size_t)r * 3 + k) * b + t0 + t];
+            }
+            out.band[q * 3 + k] = int2{cs, len};
+            lo = std::min(lo, cs);
+            hi = std::max(hi, cs + len);
+        }
+        if (hi >= 0 && hi - lo > RING) {
+            set_error("decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 64)");
+            return DDROM_EINVAL;
+        }
+    }
+    return 0;
+}
+
+int build_model(const ddrom_model_desc* d, ddrom_model* m) {
+    if (!d || d->nx <= 0 || d->ny <= 0 || d->nsx <= 0 || d->nsy <= 0 || d->nx % d->nsx || d->ny % d->nsy) {
+        set_error("grid must be positive and split evenly by nsx x nsy");
+        return DDROM_EINVAL;
+    }
+    if (d->activation < 0 || d->activation > 2 || d->nu <= 0 || d->ly <= 0) {
+        set_error("bad activation, viscosity or domain height");
+        return DDROM_EINVAL;
+    }
+    const int nx = d->nx, ny = d->ny, nsx = d->nsx, nsy = d->nsy, n_sub = nsx * nsy;
+    const int n_nodes = nx * ny, bx = nx / nsx, by = ny / nsy;
+    m->nx = nx; m->ny = ny; m->nsx = nsx; m->nsy = nsy; m->n_sub = n_sub;
+    m->act = d->activation; m->nu = d->nu; m->ly = d->ly;
+    m->hx = 2.0 / (nx + 1); m->hy = d->ly / (ny + 1);
+    m->N_x = 2 * n_nodes;
+    m->n_C = d->n_C;
+
+    // ---- DD maps: owned, own-interface, halo, interior and interface nodes ----
+    std::vector<int> owner(n_nodes);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) owner[j * nx + i] = (j / by) * nsx + (i / bx);
+    std::vector<std::vector<int>> own(n_sub), intn(n_sub), ifn(n_sub);
+    std::vector<std::vector<int>> halo(n_sub);
+    for (int q = 0; q < n_nodes; ++q) own[owner[q]].push_back(q);
+    std::vector<char> flag(n_nodes, 0);
+    auto neighbours = [&](int q, int* out) {
+        int j = q / nx, i = q % nx, c = 0;
+        if (i > 0) out[c++] = q - 1;
+        if (i < nx - 1) out[c++] = q + 1;
+        if (j > 0) out[c++] = q - nx;
+        if (j < ny - 1) out[c++] = q + nx;
+        return c;
+    };
+    for (int sd = 0; sd < n_sub; ++sd) {
+        std::vector<int> oif, hal;
+        for (int q : own[sd]) {
+            int nb[4], c = neighbours(q, nb), foreign = 0;
+            for (int t = 0; t < c; ++t)
+                if (owner[nb[t]] != sd) {
+                    foreign = 1;
+                    hal.push_back(nb[t]);
+                }
+            if (foreign) oif.push_back(q);
+        }
+        std::sort(hal.begin(), hal.end());
+        hal.erase(std::unique(hal.begin(), hal.end()), hal.end());
+        std::vector<char> oflag(n_nodes, 0);
+        for (int q : oif) oflag[q] = 1;
+        for (int q : own[sd])
+            if (!oflag[q]) intn[sd].push_back(q);
+        std::vector<int> all(oif);
+        all.insert(all.end(), hal.begin(), hal.end());
+        std::sort(all.begin(), all.end());
+        ifn[sd] = all;
+    }
+    m->n_om.resize(n_sub); m->n_ga.resize(n_sub); m->N_om.resize(n_sub); m->N_ga.resize(n_sub);
+    m->xoff.resize(n_sub); m->n_own.resize(n_sub); m->nb.resize(n_sub); m->hid_om.resize(n_sub);
+    m->state_off.resize(n_sub); m->res_off.resize(n_sub);
+    int nD = 0;
+    long long so = 0, ro = 0;
+    for (int sd = 0; sd < n_sub; ++sd) {
+        const ddrom_decoder_desc& a = d->dec_om[sd];
+        const ddrom_decoder_desc& g = d->dec_ga[sd];
+        m->N_om[sd] = 2 * (int)intn[sd].size();
+        m->N_ga[sd] = 2 * (int)ifn[sd].size();
+        m->n_own[sd] = (int)own[sd].size();
+        if (a.N != m->N_om[sd] || g.N != m->N_ga[sd]) {
+            std::ostringstream os;
+            os << "subdomain " << sd << ": decoder sizes (" << a.N << ", " << g.N << ") do not match the DD split ("
+               << m->N_om[sd] << ", " << m->N_ga[sd] << ")";
+            set_error(os.str());
+            return DDROM_ESHAPE;
+        }
+        for (const ddrom_decoder_desc* e : {&a, &g}) {
+            if (e->N > 0 && (e->n <= 0 || e->b <= 0 || e->s <= 0 || e->w != e->N * e->s || !e->W1 || !e->b1 || !e->W2 || !e->x_ref)) {
+                set_error("decoder descriptor: need n, b, s > 0, w = N*s and all weight pointers");
+                return DDROM_EINVAL;
+            }
+            if (e->n > 24) {
+                set_error("latent sizes above 24 are not supported");
+                return DDROM_EINVAL;
+            }
+        }
+        m->n_om[sd] = a.n;
+        m->n_ga[sd] = g.N > 0 ? g.n : 0;
+        if (m->n_om[sd] + m->n_ga[sd] > 24) {
+            set_error("n_i^Omega + n_i^Gamma above 24 is not supported by the KKT kernel");
+            return DDROM_EINVAL;
+        }
+        m->xoff[sd] = nD;
+        nD += m->n_om[sd] + m->n_ga[sd];
+        m->state_off[sd] = so;
+        so += m->N_om[sd] + m->N_ga[sd];
+        m->res_off[sd] = ro;
+        ro += 2 * m->n_own[sd];
+    }
+    m->n_D = nD;
+    m->n_state = (int)so;
+    m->nmax = 0; m->mmax = 0; m->NNmax = 0;
+    for (int sd = 0; sd < n_sub; ++sd) {
+        m->nmax = std::max(m->nmax, m->n_om[sd] + m->n_ga[sd]);
+        m->mmax = std::max(m->mmax, m->n_ga[sd]);
+    }
+    m->NNmax = m->nmax;
+    if (m->n_C > 63) {
+        set_error("n_C above 63 is not supported by the KKT kernel");
+        return DDROM_EINVAL;
+    }
+
+    // ---- ports / compatibility rows, C A_i ----
+    std::vector<std::vector<int>> carriers(n_nodes);
+    for (int sd = 0; sd < n_sub; ++sd)
+        for (int q : ifn[sd]) carriers[q].push_back(sd);   // sd ascending by construction
+    int n_A = 0;
+    for (int q = 0; q < n_nodes; ++q)
+        if (carriers[q].size() > 1) n_A += 2 * ((int)carriers[q].size() - 1);
+    m->N_A = n_A;
+    if (d->N_A != n_A) {
+        std::ostringstream os;
+        os << "C has " << d->N_A << " columns but the split has N_A = " << n_A << " compatibility conditions";
+        set_error(os.str());
+        return DDROM_ESHAPE;
+    }
+    if (m->n_C > 0 && !d->C) {
+        set_error("C is NULL");
+        return DDROM_EINVAL;
+    }
+    auto pos_in = [](const std::vector<int>& v, int q) {
+        return (int)(std::lower_bound(v.begin(), v.end(), q) - v.begin());
+    };
+    std::vector<std::vector<double>> CA(n_sub);
+    for (int sd = 0; sd < n_sub; ++sd) CA[sd].assign((size_t)m->n_C * m->N_ga[sd], 0.0);
+    {
+        // rows ordered by global DoF: u-DoFs (node ascending) then v-DoFs
+        int row = 0;
+        for (int f = 0; f < 2; ++f)
+            for (int q = 0; q < n_nodes; ++q) {
+                const std::vector<int>& car = carriers[q];
+                for (size_t t = 0; t + 1 < car.size(); ++t, ++row) {
+                    int lo = car[t], hi = car[t + 1];
+                    int plo = pos_in(ifn[lo], q) + f * (int)ifn[lo].size();
+                    int phi = pos_in(ifn[hi], q) + f * (int)ifn[hi].size();
+                    for (int j = 0; j < m->n_C; ++j) {
+                        double c = d->C[(size_t)j * n_A + row];
+                        CA[lo][(size_t)j * m->N_ga[lo] + plo] += c;
+                        CA[hi][(size_t)j * m->N_ga[hi] + phi] -= c;
+                    }
+                }
+            }
+    }
+
+    // ---- HR stencils, interior subnet rows, boundary points ----
+    std::map<long long, int> bc_index;
+    std::vector<double> bc_xy;
+    std::vector<int> bc_field;
+    auto bc_slot = [&](int I, int J, int field) {
+        long long key = ((long long)I << 32) | ((long long)J << 1) | field;
+        auto it = bc_index.find(key);
+        if (it != bc_index.end()) return it->second;
+        int k = (int)bc_field.size();
+        bc_index[key] = k;
+        bc_xy.push_back(-1.0 + I * m->hx);
+        bc_xy.push_back(J * m->hy);
+        bc_field.push_back(field);
+        return k;
+    };
+    std::vector<int> gather;
+    std::vector<std::vector<int>> gath_sd(n_sub);
+    m->subnet_rows.resize(n_sub);
+    for (int sd = 0; sd < n_sub; ++sd) {
+        int cnt = d->hr_count ? d->hr_count[sd] : 0;
+        if (cnt <= 0 || !d->hr_nodes || !d->hr_nodes[sd]) {
+            set_error("every subdomain needs at least one HR node");
+            return DDROM_EINVAL;
+        }
+        const int* hn = d->hr_nodes[sd];
+        for (int k = 0; k < cnt; ++k) {
+            if (hn[k] < 0 || hn[k] >= n_nodes || owner[hn[k]] != sd || (k > 0 && hn[k] <= hn[k - 1])) {
+                set_error("HR nodes must be owned by their subdomain, ascending and unique");
+                return DDROM_EINVAL;
+            }
+        }
+        m->nb[sd] = cnt;
+        const int nint = (int)intn[sd].size(), nif = (int)ifn[sd].size();
+        std::vector<char> isint(n_nodes, 0);
+        for (int q : intn[sd]) isint[q] = 1;
+        std::vector<int> raw((size_t)cnt * N_SLOTS);
+        std::vector<int> rows;
+        for (int k = 0; k < cnt; ++k) {
+            int q = hn[k], j = q / nx, i = q % nx;
+            const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
+            for (int t = 0; t < 5; ++t) {
+                int ii = i + di[t], jj = j + dj[t];
+                int cu, cv;
+                if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) {
+                    cu = src_code(SRC_BOUND, bc_slot(ii + 1, jj + 1, 0));
+                    cv = src_code(SRC_BOUND, bc_slot(ii + 1, jj + 1, 1));
+                } else {
+                    int r = jj * nx + ii;
+                    if (owner[r] == sd && isint[r]) {
+                        int p = pos_in(intn[sd], r);
+                        cu = src_code(SRC_OMEGA, p);
+                        cv = src_code(SRC_OMEGA, p + nint);
+                        rows.push_back(p);
+                        rows.push_back(p + nint);
+                    } else {
+                        int p = pos_in(ifn[sd], r);
+                        cu = src_code(SRC_GAMMA, p);
+                        cv = src_code(SRC_GAMMA, p + nif);
+                    }
+                }
+                raw[(size_t)k * N_SLOTS + t] = cu;
+                raw[(size_t)k * N_SLOTS + 5 + t] = cv;
+            }
+        }
+        std::sort(rows.begin(), rows.end());
+        rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+        for (int& c : raw)
+            if (src_kind(c) == SRC_OMEGA) c = src_code(SRC_OMEGA, pos_in(rows, src_index(c)));
+        m->subnet_rows[sd] = rows;
+        gath_sd[sd] = raw;
+    }
+    m->n_bc = (int)bc_field.size();
+
+    // ---- decoders: interior subnets and full interface decoders ----
+    std::vector<double> W1, b1, W2, xref;
+    std::vector<int2> bands;
+    m->segs_h.assign(2 * n_sub, DecSeg{});
+    long long out_rows = 0;
+    for (int part = 0; part < 2; ++part)
+        for (int sd = 0; sd < n_sub; ++sd) {
+            const ddrom_decoder_desc& dd = part == 0 ? d->dec_om[sd] : d->dec_ga[sd];
+            DecSeg& sg = m->segs_h[part * n_sub + sd];
+            sg.sd = sd;
+            sg.n = part == 0 ? m->n_om[sd] : m->n_ga[sd];
+            sg.xoff = m->xoff[sd] + (part == 0 ? 0 : m->n_om[sd]);
+            sg.bmax = dd.N > 0 ? dd.b : 1;
+            if (dd.N == 0) {
+                sg.rows = 0; sg.hid = 0;
+                sg.w1 = (long long)W1.size(); sg.b1 = (long long)b1.size(); sg.band = (long long)bands.size();
+                sg.w2 = (long long)W2.size(); sg.xref = (long long)xref.size(); sg.out = out_rows;
+                continue;
+            }
+            std::vector<int> rows;
+            if (part == 0) rows = m->subnet_rows[sd];
+            else {
+                rows.resize(dd.N);
+                std::iota(rows.begin(), rows.end(), 0);
+            }
+            HostDecoder hd;
+            int rc = make_subnet(dd, rows, hd);
+            if (rc) return rc;
+            sg.rows = hd.rows;
+            sg.hid = hd.hid;
+            sg.w1 = (long long)W1.size(); W1.insert(W1.end(), hd.W1.begin(), hd.W1.end());
+            sg.b1 = (long long)b1.size(); b1.insert(b1.end(), hd.b1.begin(), hd.b1.end());
+            sg.band = (long long)bands.size(); bands.insert(bands.end(), hd.band.begin(), hd.band.end());
+            sg.w2 = (long long)W2.size(); W2.insert(W2.end(), hd.W2.begin(), hd.W2.end());
+            sg.xref = (long long)xref.size(); xref.insert(xref.end(), hd.xref.begin(), hd.xref.end());
+            sg.out = out_rows;
+            out_rows += (long long)hd.rows * (1 + sg.n);
+            if (part == 0) m->hid_om[sd] = hd.hid;
+        }
+    m->dec_rows = std::max<long long>(1, out_rows);
+    m->seg_chunk0.assign(2 * n_sub, 0);
+    m->seg_chunk1.assign(2 * n_sub, 0);
+    for (int sgi = 0; sgi < 2 * n_sub; ++sgi) {
+        m->seg_chunk0[sgi] = (int)m->chunks_h.size();
+        const DecSeg& sg = m->segs_h[sgi];
+        for (int r = 0; r < sg.rows; r += DEC_ROWS) m->chunks_h.push_back(DecChunk{sgi, r, std::min(sg.rows, r + DEC_ROWS), 0});
+        m->seg_chunk1[sgi] = (int)m->chunks_h.size();
+    }
+
+    // ---- residual work items and GN partial slots ----
+    m->rsegs_h.resize(n_sub);
+    int slot = 0;
+    m->estride = 0;
+    for (int sd = 0; sd < n_sub; ++sd) {
+        ResSeg& rs = m->rsegs_h[sd];
+        rs.n_om = m->n_om[sd];
+        rs.n_ga = m->n_ga[sd];
+        rs.seg_om = sd;
+        rs.seg_ga = n_sub + sd;
+        rs.gather = (long long)gather.size();
+        gather.insert(gather.end(), gath_sd[sd].begin(), gath_sd[sd].end());
+        rs.slot0 = slot;
+        for (int p = 0; p < m->nb[sd]; p += RES_NODES) m->rchunks_h.push_back(ResChunk{sd, p, std::min(m->nb[sd], p + RES_NODES), slot++});
+        rs.slot1 = slot;
+        int NN = rs.n_om + rs.n_ga;
+        m->estride = std::max(m->estride, NN * (NN + 1) / 2 + NN + 1);
+    }
+    m->n_slots = slot;
+
+    // ---- constraint work items ----
+    std::vector<ConChunk> cch;
+    std::vector<double> CAflat;
+    m->CA_off.resize(n_sub);
+    for (int sd = 0; sd < n_sub; ++sd) {
+        m->CA_off[sd] = (long long)CAflat.size();
+        m->rsegs_h[sd].ca = m->CA_off[sd];
+        m->rsegs_h[sd].n_rows_ga = m->N_ga[sd];
+        CAflat.insert(CAflat.end(), CA[sd].begin(), CA[sd].end());
+        if (m->N_ga[sd] == 0) continue;
+        for (int j = 0; j < m->n_C; j += CON_ROWS) cch.push_back(ConChunk{sd, j, std::min(m->n_C, j + CON_ROWS), 0});
+    }
+    m->n_cchunks = (int)cch.size();
+
+    // ---- DD FOM residual tables ----
+    std::vector<int> fsrc;
+    std::vector<long long> fmeta;
+    std::vector<int> sd_of_row;
+    int own_off = 0;
+    for (int sd = 0; sd < n_sub; ++sd) {
+        const int nint = (int)intn[sd].size(), nif = (int)ifn[sd].size();
+        std::vector<char> isint(n_nodes, 0);
+        for (int q : intn[sd]) isint[q] = 1;
+        for (int q : own[sd]) {
+            int j = q / nx, i = q % nx;
+            const int di[5] = {0, -1, 1, 0, 0}, dj[5] = {0, 0, 0, -1, 1};
+            for (int t = 0; t < 5; ++t) {
+                int ii = i + di[t], jj = j + dj[t];
+                int code;
+                if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) code = src_code(SRC_BOUND, ((ii + 1) << 14) | (jj + 1));
+                else {
+                    int r = jj * nx + ii;
+                    if (owner[r] == sd && isint[r]) code = src_code(SRC_OMEGA, pos_in(intn[sd], r));
+                    else code = src_code(SRC_GAMMA, pos_in(ifn[sd], r));
+                }
+                fsrc.push_back(code);
+            }
+            sd_of_row.push_back(sd);
+        }
+        fmeta.insert(fmeta.end(), {(long long)own_off, (long long)own[sd].size(), (long long)nint, (long long)nif,
+                                   m->state_off[sd], m->res_off[sd]});
+        own_off += (int)own[sd].size();
+    }
+    m->total_own = own_off;
+    if (nx + 2 >= (1 << 14) || ny + 2 >= (1 << 14)) {
+        set_error("grid too large for the boundary code packing");
+        return DDROM_EINVAL;
+    }
+
+    // ---- upload ----
+    std::vector<float> W1f(W1.begin(), W1.end()), b1f(b1.begin(), b1.end()), W2f(W2.begin(), W2.end()),
+        xreff(xref.begin(), xref.end());
+    int rc = 0;
+    if ((rc = upload(&m->W1d, W1)) || (rc = upload(&m->b1d, b1)) || (rc = upload(&m->W2d, W2)) ||
+        (rc = upload(&m->xrefd, xref)) || (rc = upload(&m->W1f, W1f)) || (rc = upload(&m->b1f, b1f)) ||
+        (rc = upload(&m->W2f, W2f)) || (rc = upload(&m->xreff, xreff)) || (rc = upload(&m->bands, bands)) ||
+        (rc = upload(&m->segs_d, m->segs_h)) || (rc = upload(&m->chunks_d, m->chunks_h)) ||
+        (rc = upload(&m->gather_d, gather)) || (rc = upload(&m->rsegs_d, m->rsegs_h)) ||
+        (rc = upload(&m->rchunks_d, m->rchunks_h)) || (rc = upload(&m->bc_xy_d, bc_xy)) ||
+        (rc = upload(&m->bc_field_d, bc_field)) || (rc = upload(&m->CA_d, CAflat)) ||
+        (rc = upload(&m->cchunks_d, cch)) || (rc = upload(&m->fom_src_d, fsrc)) ||
+        (rc = upload(&m->fom_meta_d, fmeta)) || (rc = upload(&m->fom_sd_of_row_d, sd_of_row)))
+        return rc;
+    return 0;
+}
+
+void free_model(ddrom_model* m) {
+    void* ptrs[] = {m->W1f, m->b1f, m->W2f, m->xreff, m->W1d, m->b1d, m->W2d, m->xrefd, m->bands, m->segs_d,
+                    m->chunks_d, m->gather_d, m->rsegs_d, m->rchunks_d, m->bc_xy_d, m->bc_field_d, m->CA_d,
+                    m->cchunks_d, m->fom_src_d, m->fom_meta_d, m->fom_sd_of_row_d};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+}  // namespace ddrom

@@ -1,0 +1,253 @@
+"""ctypes binding of libddrom.so (argument marshalling only; every step of the solve runs
+in the library's HIP kernels).  PyTorch supplies device memory and the stream.
+
+The library is built in-tree (see build.py); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddrom.so")
+
+PREC_FP64 = 0
+PREC_FP32_DECODER = 1
+
+STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "kkt_not_pd", 4: "nonfinite"}
+
+
+class DecoderDesc(C.Structure):
+    _fields_ = [("N", C.c_int), ("n", C.c_int), ("w", C.c_int), ("b", C.c_int), ("s", C.c_int),
+                ("W1", C.POINTER(C.c_double)), ("b1", C.POINTER(C.c_double)),
+                ("W2", C.POINTER(C.c_double)), ("x_ref", C.POINTER(C.c_double))]
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nu", C.c_double), ("ly", C.c_double),
+                ("nsx", C.c_int), ("nsy", C.c_int), ("activation", C.c_int), ("n_C", C.c_int), ("N_A", C.c_int),
+                ("C", C.POINTER(C.c_double)), ("dec_om", C.POINTER(DecoderDesc)), ("dec_ga", C.POINTER(DecoderDesc)),
+                ("hr_count", C.POINTER(C.c_int)), ("hr_nodes", C.POINTER(C.POINTER(C.c_int)))]
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("tol_abs", C.c_double), ("tol_rel", C.c_double), ("armijo_c1", C.c_double),
+                ("max_backtracks", C.c_int), ("precision", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
+        L.ddrom_last_error.restype = C.c_char_p
+        L.ddrom_model_create.argtypes = [C.POINTER(ModelDesc), C.POINTER(vp)]
+        L.ddrom_model_destroy.argtypes = [vp]
+        L.ddrom_model_size.argtypes = [vp, ip, ip]
+        L.ddrom_model_size.restype = C.c_longlong
+        L.ddrom_subnet_rows.argtypes = [vp, ip, ip, C.POINTER(C.c_int)]
+        L.ddrom_workspace_create.argtypes = [vp, ip, C.POINTER(vp)]
+        L.ddrom_workspace_destroy.argtypes = [vp]
+        L.dd_fom_residual.argtypes = [vp, vp, vp, ip, vp, vp, vp]
+        L.ae_decode_hr.argtypes = [vp, vp, ip, ip, vp, ip, ip, vp, vp]
+        L.ae_jacobian_hr.argtypes = [vp, vp, ip, ip, vp, ip, ip, vp, vp, vp]
+        L.ddrom_gn_blocks.argtypes = [vp, vp, vp, vp, ip, ip, vp, vp, vp, vp, vp, vp]
+        L.sqp_step.argtypes = [vp, vp, vp, ip, vp, vp, vp, vp, C.POINTER(Opts), vp]
+        L.rom_solve_batch.argtypes = [vp, vp, vp, ip, vp, vp, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp]
+        L.ddrom_time_kernels.argtypes = [vp, vp, vp, vp, ip, ip, ip, C.POINTER(C.c_float)]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed ({rc}): {lib().ddrom_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype=torch.float64):
+    t = torch.as_tensor(x, dtype=dtype)
+    return t.to("cuda").contiguous()
+
+
+class Model:
+    """Device model built from a model pack (dict of numpy arrays, see oracle.pack's format)."""
+
+    def __init__(self, pack: dict):
+        L = lib()
+        n = int(pack["n_sub"])
+        keep = []
+
+        def dptr(a):
+            a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double))
+
+        decs = {}
+        for part in ("om", "ga"):
+            arr = (DecoderDesc * n)()
+            for i in range(n):
+                W1 = np.asarray(pack[f"{part}{i}_W1"])
+                b, s = (int(v) for v in pack[f"{part}{i}_bs"])
+                N = int(np.asarray(pack[f"{part}{i}_xref"]).shape[0])
+                arr[i] = DecoderDesc(N, int(W1.shape[1]) if W1.ndim == 2 else 0, int(W1.shape[0]), b, s,
+                                     dptr(W1), dptr(pack[f"{part}{i}_b1"]), dptr(pack[f"{part}{i}_W2"]),
+                                     dptr(pack[f"{part}{i}_xref"]))
+            decs[part] = arr
+        hr = [np.ascontiguousarray(np.asarray(pack[f"hr{i}"], dtype=np.int32)) for i in range(n)]
+        keep.extend(hr)
+        hr_cnt = (C.c_int * n)(*[len(h) for h in hr])
+        hr_ptrs = (C.POINTER(C.c_int) * n)(*[h.ctypes.data_as(C.POINTER(C.c_int)) for h in hr])
+        Cm = np.asarray(pack["C"], dtype=np.float64)
+        desc = ModelDesc(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"]), int(pack["nsx"]),
+                         int(pack["nsy"]), int(pack["act"]), int(Cm.shape[0]), int(Cm.shape[1]), dptr(Cm),
+                         decs["om"], decs["ga"], hr_cnt, hr_ptrs)
+        h = C.c_void_p()
+        _check(L.ddrom_model_create(C.byref(desc), C.byref(h)), "ddrom_model_create")
+        self.h = h
+        self.n_sub = n
+        self.n_D = self.size(1)
+        self.n_C = self.size(2)
+        self.N_A = self.size(3)
+        self.N_x = self.size(4)
+        self.n_state = self.size(5)
+        self.n_om = [self.size(10, i) for i in range(n)]
+        self.n_ga = [self.size(11, i) for i in range(n)]
+        self.N_om = [self.size(12, i) for i in range(n)]
+        self.N_ga = [self.size(13, i) for i in range(n)]
+        self.xoff = [self.size(17, i) for i in range(n)]
+
+    def size(self, q, sd=-1):
+        return int(lib().ddrom_model_size(self.h, q, sd))
+
+    def subnet_rows(self, sd, part=0):
+        n = self.size(14, sd) if part == 0 else self.N_ga[sd]
+        out = (C.c_int * max(1, n))()
+        _check(lib().ddrom_subnet_rows(self.h, sd, part, out), "ddrom_subnet_rows")
+        return np.array(out[:n], dtype=np.int64)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ddrom_model_destroy(self.h)
+            self.h = None
+
+
+class Workspace:
+    def __init__(self, model: Model, max_batch: int):
+        self.model = model
+        self.max_batch = max_batch
+        h = C.c_void_p()
+        _check(lib().ddrom_workspace_create(model.h, int(max_batch), C.byref(h)), "ddrom_workspace_create")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ddrom_workspace_destroy(self.h)
+            self.h = None
+
+
+def opts(max_iter=50, tol_abs=0.0, tol_rel=1e-8, armijo_c1=1e-4, max_backtracks=20, precision=PREC_FP64) -> Opts:
+    return Opts(int(max_iter), float(tol_abs), float(tol_rel), float(armijo_c1), int(max_backtracks), int(precision))
+
+
+def dd_fom_residual(model: Model, mu, xsd, jac: bool = False):
+    mu, xsd = _dev(mu), _dev(xsd)
+    B = mu.shape[0]
+    r = torch.empty((B, model.N_x), dtype=torch.float64, device="cuda")
+    J = torch.empty((B, model.N_x, 6), dtype=torch.float64, device="cuda") if jac else None
+    _check(lib().dd_fom_residual(model.h, _ptr(mu), _ptr(xsd), B, _ptr(r), _ptr(J), _stream()), "dd_fom_residual")
+    return (r, J) if jac else r
+
+
+def ae_jacobian_hr(model: Model, ws: Workspace, sd: int, part: int, xhat, precision=PREC_FP64, want_x=True):
+    xhat = _dev(xhat)
+    B = xhat.shape[0]
+    rows = model.size(14, sd) if part == 0 else model.N_ga[sd]
+    n = model.n_om[sd] if part == 0 else model.n_ga[sd]
+    dt = torch.float64 if precision == PREC_FP64 else torch.float32
+    x = torch.empty((B, rows), dtype=dt, device="cuda") if want_x else None
+    J = torch.empty((B, rows, n), dtype=dt, device="cuda")
+    _check(lib().ae_jacobian_hr(model.h, ws.h, sd, part, _ptr(xhat), B, precision, _ptr(x), _ptr(J), _stream()),
+           "ae_jacobian_hr")
+    return x, J
+
+
+def ae_decode_hr(model: Model, ws: Workspace, sd: int, part: int, xhat, precision=PREC_FP64):
+    xhat = _dev(xhat)
+    B = xhat.shape[0]
+    rows = model.size(14, sd) if part == 0 else model.N_ga[sd]
+    dt = torch.float64 if precision == PREC_FP64 else torch.float32
+    x = torch.empty((B, rows), dtype=dt, device="cuda")
+    _check(lib().ae_decode_hr(model.h, ws.h, sd, part, _ptr(xhat), B, precision, _ptr(x), _stream()), "ae_decode_hr")
+    return x
+
+
+def gn_blocks(model: Model, ws: Workspace, mu, xhat, precision=PREC_FP64):
+    mu, xhat = _dev(mu), _dev(xhat)
+    B = mu.shape[0]
+    nmax = max(a + b for a, b in zip(model.n_om, model.n_ga))
+    mmax = max(1, max(model.n_ga))
+    f = dict(dtype=torch.float64, device="cuda")
+    H = torch.zeros((B, model.n_sub, nmax, nmax), **f)
+    g = torch.zeros((B, model.n_D), **f)
+    EG = torch.zeros((B, model.n_sub, model.n_C, mmax), **f)
+    c = torch.zeros((B, max(1, model.n_C)), **f)
+    rr = torch.zeros((B,), **f)
+    _check(lib().ddrom_gn_blocks(model.h, ws.h, _ptr(mu), _ptr(xhat), B, precision, _ptr(H), _ptr(g), _ptr(EG),
+                                 _ptr(c), _ptr(rr), _stream()), "ddrom_gn_blocks")
+    return H, g, EG, c[:, :model.n_C], rr
+
+
+def sqp_step(model: Model, ws: Workspace, mu, xhat, lam, o: Opts):
+    mu = _dev(mu)
+    x = _dev(xhat).clone()
+    l = _dev(lam).clone()
+    B = mu.shape[0]
+    fn = torch.empty((B,), dtype=torch.float64, device="cuda")
+    st = torch.empty((B,), dtype=torch.int32, device="cuda")
+    _check(lib().sqp_step(model.h, ws.h, _ptr(mu), B, _ptr(x), _ptr(l), _ptr(fn), _ptr(st), C.byref(o), _stream()),
+           "sqp_step")
+    return x, l, fn, st
+
+
+def rom_solve_batch(model: Model, ws: Workspace, mu, o: Opts, xhat0=None, lam0=None, out=None):
+    """Returns dict(xhat, lam, iters, status, fnorm, fnorm0) of device tensors.  `out` may
+    pass preallocated tensors with those keys (the call then allocates nothing)."""
+    mu = _dev(mu)
+    B = mu.shape[0]
+    x0 = None if xhat0 is None else _dev(xhat0)
+    l0 = None if lam0 is None else _dev(lam0)
+    if out is None:
+        f = dict(dtype=torch.float64, device="cuda")
+        out = dict(xhat=torch.empty((B, model.n_D), **f), lam=torch.empty((B, max(1, model.n_C)), **f),
+                   iters=torch.empty((B,), dtype=torch.int32, device="cuda"),
+                   status=torch.empty((B,), dtype=torch.int32, device="cuda"),
+                   fnorm=torch.empty((B,), **f), fnorm0=torch.empty((B,), **f))
+    _check(lib().rom_solve_batch(model.h, ws.h, _ptr(mu), B, _ptr(x0), _ptr(l0), C.byref(o), _ptr(out["xhat"]),
+                                 _ptr(out["lam"]), _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["fnorm"]),
+                                 _ptr(out["fnorm0"]), _stream()), "rom_solve_batch")
+    return out
+
+
+def time_kernels(model: Model, ws: Workspace, mu, xhat, precision=PREC_FP32_DECODER, reps=20):
+    """Average ms per launch of [interior decode, interface decode, residual+GN, constraint]."""
+    mu, xhat = _dev(mu), _dev(xhat)
+    B = mu.shape[0]
+    ms = (C.c_float * 4)()
+    _check(lib().ddrom_time_kernels(model.h, ws.h, _ptr(mu), _ptr(xhat), B, precision, reps, ms), "ddrom_time_kernels")
+    return list(ms)
