@@ -1,0 +1,196 @@
+"""Benchmark: batched HR DD NM-ROM solves/sec on one MI355X.
+
+Workload (default): steady 2D Burgers on a 240x240 interior grid, 4x4 subdomains,
+latents (n^Omega, n^Gamma) = (8, 4), decoder width 2x DoFs, three-band mask with b = 9,
+HR on 10% of each subdomain's nodes, 512 held-out (a, lambda) drawn uniformly, zero
+start, FP32 decoders with FP64 residual / Gauss-Newton blocks / KKT / line search.
+One step = one rom_solve_batch call over the 512 parameters (all solver rounds, replayed
+from a captured HIP graph).  value = solves per second over the timed steps.
+
+The model pack (trained decoders, HR nodes, C) is read from models/<config>.npz, which the
+offline pipeline writes (python -m oracle.build_model <config>).
+
+Also reported: the dominant kernel's roofline figures (HIP-event timed launches on the
+library's stream), plain per-solve GPU SQP (B = 1, FP64, sequential calls) and the CPU
+oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HR DD NM-ROM solves/sec on 1 MI355X vs plain SQP at fixed rel. error vs FOM"
+PEAK_FP32_TFLOPS = 78.6     # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+CONFIGS = {
+    "cfg1": dict(batch=512, seed=1, precision=1, tol_rel=1e-6, max_iter=60,
+                 workload="Burgers 240x240, 4x4 subdomains, latent (8,4), width 2x, band 9, HR 10%, "
+                          "512 held-out (a,lambda), FP32 decoder + FP64 KKT"),
+    "cfg0": dict(batch=1, seed=0, precision=0, tol_rel=1e-8, max_iter=60,
+                 workload="Burgers 36x36, 2x2 subdomains, latent (6,3), width 3x, band 5, HR 20%, "
+                          "1 held-out (a,lambda), FP64"),
+}
+
+
+def decoder_work(model, B):
+    """Algorithmic FLOPs and bytes of one interior-decoder launch over B solves.
+    Per solve and subdomain: 2 n |I_h| (hidden pre-activations) + sum over kept rows of
+    q_r (3 + 2 n) (value FMA, sigma' scaling, n Jacobian FMAs per band entry); activations'
+    transcendentals are not counted.  Bytes (FP32): subnet weights read once, FP64 latents
+    read, value + Jacobian rows written."""
+    flops = 0.0
+    wbytes = 0.0
+    obytes = 0.0
+    for i in range(model.n_sub):
+        n = model.n_om[i]
+        H = model.size(15, i)
+        O = model.size(14, i)
+        q = model.size(19, i)
+        flops += 2.0 * n * H + q * (3.0 + 2.0 * n)
+        wbytes += 4.0 * (H * n + H + q + O) + 8.0 * 3 * O
+        obytes += 4.0 * O * (1 + n)
+    return flops * B, wbytes + B * (obytes + 8.0 * model.n_D)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cfg1")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--plain", type=int, default=8, help="parameters for the plain per-solve GPU SQP leg")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(parameter solves would shard across GPUs with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2305_15163_amd as dr
+    import seeded_inputs as si
+
+    cfg = CONFIGS[a.config]
+    path = os.path.join(ROOT, "models", f"{a.config}.npz")
+    if not os.path.exists(path):
+        print(f"missing model pack {path}; build it with: python -m oracle.build_model {a.config}", file=sys.stderr)
+        sys.exit(1)
+    pack = dict(np.load(path, allow_pickle=False))
+    torch.cuda.set_device(0)
+    print(f"[bench] loading model {path}", file=sys.stderr, flush=True)
+    model = dr.Model(pack)
+    B = cfg["batch"]
+    ws = dr.Workspace(model, B)
+    mu_h = si.heldout_mu(B, cfg["seed"])
+    mu = torch.as_tensor(mu_h, device="cuda")
+    o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"])
+    f = dict(dtype=torch.float64, device="cuda")
+    out = dict(xhat=torch.empty((B, model.n_D), **f), lam=torch.empty((B, max(1, model.n_C)), **f),
+               iters=torch.empty((B,), dtype=torch.int32, device="cuda"),
+               status=torch.empty((B,), dtype=torch.int32, device="cuda"),
+               fnorm=torch.empty((B,), **f), fnorm0=torch.empty((B,), **f))
+
+    for w in range(a.warmup):
+        dr.rom_solve_batch(model, ws, mu, o, out=out)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        dr.rom_solve_batch(model, ws, mu, o, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] timed {a.steps} steps in {dt:.3f}s", file=sys.stderr, flush=True)
+    value = B * a.steps / dt
+    iters = out["iters"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    xb = out["xhat"].cpu().numpy()
+
+    # dominant kernel: interior decoder subnets, every solve live
+    ms = dr.time_kernels(model, ws, mu, torch.zeros((B, model.n_D), **f), precision=cfg["precision"], reps=20)
+    flops, bytes_ = decoder_work(model, B)
+    if cfg["precision"] == 1:
+        roof = {"bound": "alu", "kernel": "k_decode<float,8> (interior subnets)", "achieved": flops / (ms[0] * 1e-3) / 1e12,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "alu", "kernel": "k_decode<double,n> (interior subnets)", "achieved": flops / (ms[0] * 1e-3) / 1e12,
+                "peak": 78.6, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["algorithmic_bytes_per_launch"] = bytes_
+    roof["hbm_GBs_if_algorithmic"] = bytes_ / (ms[0] * 1e-3) / 1e9
+    roof["ms_per_launch"] = {"decode_interior": ms[0], "decode_interface": ms[1], "residual_gn": ms[2], "constraint": ms[3]}
+    print(f"[bench] kernel ms {ms}", file=sys.stderr, flush=True)
+
+    # plain per-solve GPU SQP: B = 1, FP64, zero start, sequential host calls
+    plain = None
+    a.plain = min(a.plain, B)
+    if a.plain > 0:
+        ws1 = dr.Workspace(model, 1)
+        o1 = dr.opts(max_iter=cfg["max_iter"], tol_rel=1e-8, precision=0)
+        dr.rom_solve_batch(model, ws1, mu[:1], o1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        px = []
+        for b in range(a.plain):
+            r = dr.rom_solve_batch(model, ws1, mu[b:b + 1], o1)
+            px.append(r["xhat"])
+        torch.cuda.synchronize()
+        pt = time.perf_counter() - t1
+        plain = {"solves_per_s": a.plain / pt, "n": a.plain, "precision": "f64", "batch": 1}
+        px = torch.cat(px).cpu().numpy()
+        print(f"[bench] plain per-solve SQP {plain['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if cfg["precision"] == 1 else "f64", "data": "synthetic",
+        "config": {"workload": cfg["workload"], "batch": B, "subdomains": model.n_sub, "n_D": model.n_D,
+                   "n_C": model.n_C, "stop": f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
+                                             f"or line-search stagnation"},
+        "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+        "status_counts": {dr.STATUS[k]: int((status == k).sum()) for k in np.unique(status)},
+        "roofline": roof,
+        "plain_sqp": plain,
+        "speedup_vs_plain": (value / plain["solves_per_s"]) if plain else None,
+    }
+
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle.burgers import solve_fom
+        from oracle.pack import load_pack
+        from oracle.rom import SQPOptions, relative_error, sqp_solve
+        om = load_pack(pack)
+        with threadpool_limits(limits=1):
+            t2 = time.perf_counter()
+            n_cpu = 0
+            while True:
+                sqp_solve(om, mu_h[n_cpu], opts=SQPOptions(max_iter=cfg["max_iter"], tol_abs=0.0, tol_rel=1e-8))
+                n_cpu += 1
+                if time.perf_counter() - t2 > 10.0 or n_cpu >= B:
+                    break
+            ct = time.perf_counter() - t2
+            line["cpu_baseline"] = {"value": n_cpu / ct, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                    "sample": f"{n_cpu} of the {B} parameters, FP64 oracle SQP (dense KKT), "
+                                              f"relative KKT tolerance 1e-8, BLAS limited to 1 thread"}
+            # error against the FOM on a few parameters: batched (this run) and plain SQP
+            errs, perrs = [], []
+            for b in range(min(2, B)):
+                xf = solve_fom(om.fom, mu_h[b]).x
+                errs.append(relative_error(om, xb[b], xf))
+                if plain is not None and b < len(px):
+                    perrs.append(relative_error(om, px[b], xf))
+            line["rel_err_vs_fom"] = {"batched": errs, "plain_sqp": perrs, "n": len(errs)}
+        print(f"[bench] cpu leg {n_cpu} solves in {ct:.1f}s", file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,7 +108,9 @@ void ddrom_model_destroy(ddrom_model* m);
 /* Sizes: query = 0 n_sub, 1 n_D, 2 n_C, 3 N_A, 4 N_x (= 2 nx ny), 5 sum_i (N_i^Omega + N_i^Gamma),
  * 6 total HR nodes.  Per subdomain (sd >= 0): 10 n_i^Omega, 11 n_i^Gamma, 12 N_i^Omega,
  * 13 N_i^Gamma, 14 |I_o| of the interior subnet, 15 |I_h| of the interior subnet,
- * 16 HR nodes, 17 offset of xhat_i^Omega in xhat, 18 own nodes. */
+ * 16 HR nodes, 17 offset of xhat_i^Omega in xhat, 18 own nodes, 19 mask entries of the kept
+ * interior rows, 20 mask entries of the interface decoder, 21 hidden units of the interface
+ * decoder. */
 long long ddrom_model_size(const ddrom_model* m, int query, int sd);
 
 /* Subnet output rows I_o (local indices into x_i^Omega, ascending) of subdomain sd's

@@ -37,10 +37,30 @@ struct DecSeg {
     long long out;  // first Bp-row of the output: row r, column j (0 value, 1+k Jacobian) at (out + r*(1+n) + j)*Bp
 };
 
+// Dynamic LDS layout of one decode work item (byte offsets, 16-byte aligned regions):
+// staged W1~ rows [span][nl], biases [span], W2~ values [rows][3][bmax], x_ref [rows],
+// band descriptors [rows][3] (int2), then one hidden-activation ring per wave.
+struct DecLds {
+    size_t w1, b1, w2, xr, bd, ring, total;
+};
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
+__host__ __device__ inline DecLds dec_lds(int span, int rows, int nl, int bmax, int esz, int waves, int rk) {
+    DecLds L;
+    L.w1 = 0;
+    L.b1 = al16(L.w1 + (size_t)span * nl * esz);
+    L.w2 = al16(L.b1 + (size_t)span * esz);
+    L.xr = al16(L.w2 + (size_t)rows * 3 * bmax * esz);
+    L.bd = al16(L.xr + (size_t)rows * esz);
+    L.ring = al16(L.bd + (size_t)rows * 3 * 8);
+    L.total = L.ring + (size_t)waves * 48 * 64 * esz * rk;
+    return L;
+}
+
 struct DecChunk {
     int seg;
-    int r0, r1;
-    int pad;
+    int r0, r1;         // kept rows [r0, r1) of the segment
+    int h_lo, h_hi;     // compressed hidden units read by those rows
+    int pad[3];
 };
 
 // A contiguous range of sampled nodes of one subdomain (one residual/GN work item).
@@ -54,16 +74,19 @@ struct ResSeg {
     int n_om, n_ga;
     int seg_om, seg_ga;     // decoder segment ids
     long long gather;       // offset into the gather pool [nb][N_SLOTS]
-    long long ca;           // offset of C A_i [n_C][N_i^Gamma] in the CA pool
+    long long ca;           // offset of (C A_i)^T [N_i^Gamma][ca_ld] in the CA pool
     int slot0, slot1;       // GN partial slots of this subdomain
     int n_rows_ga;          // N_i^Gamma
+    int cpart0, cpart1;     // constraint partial-sum slots of this subdomain
     int pad;
 };
 
 struct ConChunk {
     int sd;
     int j0, j1;             // constraint rows
-    int pad;
+    int o0, o1;             // interface rows summed by this work item
+    int part;               // constraint partial-sum slot
+    int pad[2];
 };
 
 }  // namespace ddrom
@@ -73,6 +96,7 @@ struct ddrom_model {
     double nu, ly, hx, hy;
     int nmax, mmax, NNmax, estride;     // max latent sizes, GN partial stride
     std::vector<int> n_om, n_ga, N_om, N_ga, xoff, n_own, nb, hid_om;
+    std::vector<long long> band_nnz;            // valid band entries over kept rows, per decoder segment
     std::vector<std::vector<int>> subnet_rows;   // I_o per subdomain (interior local indices)
     std::vector<long long> state_off;            // offset of [x_i^Omega; x_i^Gamma] inside the DD state vector
     std::vector<long long> res_off;              // offset of r_i inside the DD residual vector
@@ -104,6 +128,9 @@ struct ddrom_model {
     std::vector<long long> CA_off;
     ddrom::ConChunk* cchunks_d = nullptr;
     int n_cchunks = 0;
+    int n_cparts = 0;
+    int ca_ld = 0;                               // row stride of (C A_i)^T (n_C rounded up to 8)
+    std::vector<long long> seg_stage_f32, seg_stage_f64;   // largest staged bytes of a chunk, per segment
 
     // DD FOM residual: per subdomain, per owned node, 5 stencil sources (C, W, E, S, N)
     int* fom_src_d = nullptr;                    // code: kind<<28 | node position; boundary: (I<<14)|J
@@ -126,8 +153,9 @@ struct ddrom_workspace {
     void* dec_out = nullptr;        // decoder values + Jacobians, [dec_rows][Bp] (float or double)
     double* bc = nullptr;           // [n_bc][Bp]
     double* gn_part = nullptr;      // [n_slots][estride][Bp]
-    double* c_part = nullptr;       // [n_sub][n_C][Bp]
-    double* E_part = nullptr;       // [n_sub][n_C][mmax][Bp]
+    double* c_part = nullptr;       // [n_cparts][n_C][Bp]
+    double* E_part = nullptr;       // [n_cparts][n_C][mmax][Bp]
+    long long zero_row = 0;         // first Bp-row of an all-zero block at the end of dec_out
     double* x = nullptr;            // accepted latents  [Bp][n_D]
     double* xt = nullptr;           // trial latents     [Bp][n_D]
     double* lam = nullptr;          // [Bp][n_C]

@@ -45,8 +45,9 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 static constexpr int RING = 64;
 static constexpr int PH_INIT = 0, PH_TRIAL = 1, PH_DONE = 2;
-static constexpr int KKT_NN = 24;     // max n_i^Omega + n_i^Gamma
-static constexpr int KKT_NC = 64;     // max n_C
+static constexpr int KKT_NN = 20;     // max n_i^Omega + n_i^Gamma
+static constexpr int KKT_MG = 12;     // max n_i^Gamma
+static constexpr int KKT_NC = 64;     // n_C < KKT_NC
 
 // ------------------------------------------------------------------------------------
 // Activations
@@ -91,76 +92,136 @@ __device__ __forceinline__ bool lane_live(const SolveState* st, int b, int B) {
 // ------------------------------------------------------------------------------------
 // Decoder: value and Jacobian rows of g(xhat) = x_ref + W2~ sigma(W1~ xhat + b1~)
 // ------------------------------------------------------------------------------------
-// One wave = one work item (a run of consecutive kept rows of one decoder) x 64 solves.
-// Rows are visited in ascending order; each row's three bands live in a window of at most
-// RING consecutive (compressed) hidden units, so hidden activations are computed once per
-// unit into a per-lane ring in LDS and consumed by the rows that need them.
-template <typename T, int NL>
-__global__ __launch_bounds__(64) void k_decode(const DecChunk* __restrict__ chunks, int chunk_base,
-                                               const DecSeg* __restrict__ segs, const T* __restrict__ W1,
-                                               const T* __restrict__ B1, const int2* __restrict__ bands,
-                                               const T* __restrict__ W2, const T* __restrict__ XR,
-                                               const double* __restrict__ xhat, int xstride, int xoff_override,
-                                               const SolveState* __restrict__ st, int B, T* __restrict__ out,
-                                               int Bp, int act) {
+// A workgroup of WAVES waves takes one work item (a run of consecutive kept rows of one
+// decoder) for WAVES x 64 solves, one solve per lane.  The weights the rows read (W1~ rows
+// and biases of their hidden units, W2~ band values, x_ref, band descriptors) are staged
+// once in LDS with coalesced loads and read back as wave-wide broadcasts.  Rows are visited
+// in ascending order; each row's three bands lie in a window of at most RING consecutive
+// compressed hidden units, so every hidden activation is computed once per lane into a
+// per-lane ring in LDS and consumed by the rows that need it.  For the sigmoid the ring
+// holds s = sigma(z) and sigma' = s - s^2 is formed on use; the swish keeps (value, sigma').
+constexpr int DEC_RING = 48;
+
+template <typename T, int ACT>
+struct RingSlots { static constexpr int K = (ACT == DDROM_ACT_SWISH) ? 2 : 1; };
+
+template <typename T>
+__device__ __forceinline__ T sig_fast(T z);
+template <>
+__device__ __forceinline__ float sig_fast<float>(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+template <>
+__device__ __forceinline__ double sig_fast<double>(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+// TAG only renames the instantiation (0: solver rounds, 1: standalone timing launches) so that
+// profiler summaries separate the two; the code is identical.
+template <typename T, int NL, int ACT, int WAVES, int TAG>
+__global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restrict__ chunks, int chunk_base,
+                                                       const DecSeg* __restrict__ segs, const T* __restrict__ W1,
+                                                       const T* __restrict__ B1, const int2* __restrict__ bands,
+                                                       const T* __restrict__ W2, const T* __restrict__ XR,
+                                                       const double* __restrict__ xhat, int xstride, int xoff_override,
+                                                       const SolveState* __restrict__ st, int B,
+                                                       T* __restrict__ out, int Bp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int RK = RingSlots<T, ACT>::K;
     const DecChunk ch = chunks[chunk_base + blockIdx.x];
     const DecSeg sg = segs[ch.seg];
-    const int lane = threadIdx.x;
-    const int b = blockIdx.y * 64 + lane;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = (blockIdx.y * WAVES + wave) * 64 + lane;
     const bool live = lane_live(st, b, B);
-    if (__ballot(live) == 0) return;
+    if (!__syncthreads_or(live)) return;
+
+    const int nrows = ch.r1 - ch.r0, span = ch.h_hi - ch.h_lo, bmax = sg.bmax;
+    const DecLds L = dec_lds(span, nrows, NL, bmax, (int)sizeof(T), WAVES, RK);
+    T* sW1 = reinterpret_cast<T*>(smem + L.w1);          // [span][NL]
+    T* sB1 = reinterpret_cast<T*>(smem + L.b1);          // [span]
+    T* sW2 = reinterpret_cast<T*>(smem + L.w2);          // [nrows][3][bmax]
+    T* sXR = reinterpret_cast<T*>(smem + L.xr);          // [nrows]
+    int2* sBd = reinterpret_cast<int2*>(smem + L.bd);    // [nrows][3]
+    T* ring = reinterpret_cast<T*>(smem + L.ring) + (size_t)wave * DEC_RING * 64 * RK;
+    {
+        const T* gW1 = W1 + sg.w1 + (size_t)ch.h_lo * NL;
+        for (int i = tid; i < span * NL; i += 64 * WAVES) sW1[i] = gW1[i];
+        const T* gB1 = B1 + sg.b1 + ch.h_lo;
+        for (int i = tid; i < span; i += 64 * WAVES) sB1[i] = gB1[i];
+        const T* gW2 = W2 + sg.w2 + (size_t)ch.r0 * 3 * bmax;
+        for (int i = tid; i < nrows * 3 * bmax; i += 64 * WAVES) sW2[i] = gW2[i];
+        const T* gXR = XR + sg.xref + ch.r0;
+        for (int i = tid; i < nrows; i += 64 * WAVES) sXR[i] = gXR[i];
+        const int2* gBd = bands + sg.band + (size_t)ch.r0 * 3;
+        for (int i = tid; i < nrows * 3; i += 64 * WAVES) {
+            int2 q = gBd[i];
+            q.x -= ch.h_lo;
+            sBd[i] = q;
+        }
+    }
     const int xo = xoff_override >= 0 ? xoff_override : sg.xoff;
     T xl[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) xl[k] = live ? (T)xhat[(size_t)b * xstride + xo + k] : (T)0;
+    __syncthreads();
 
-    __shared__ T ring_s[RING][64];
-    __shared__ T ring_d[RING][64];
-    const T* w1 = W1 + sg.w1;
-    const T* b1 = B1 + sg.b1;
-    const int2* bd = bands + sg.band;
-    const T* w2 = W2 + sg.w2;
-    const T* xr = XR + sg.xref;
-    T* o = out + (size_t)sg.out * Bp + b;
-    const int bmax = sg.bmax;
-    int hn = -1;
-    for (int r = ch.r0; r < ch.r1; ++r) {
-        const int2 q0 = bd[r * 3 + 0], q1 = bd[r * 3 + 1], q2 = bd[r * 3 + 2];
+    T* o = out + ((size_t)sg.out + (size_t)ch.r0 * (1 + NL)) * Bp + b;
+    int hn = -1;     // next hidden unit (relative to h_lo) to compute
+    int hslot = 0;   // its ring slot
+    for (int r = 0; r < nrows; ++r) {
+        const int2 q0 = sBd[r * 3 + 0], q1 = sBd[r * 3 + 1], q2 = sBd[r * 3 + 2];
         int lo = 0x7fffffff, hi = -1;
         if (q0.y > 0) { lo = min(lo, q0.x); hi = max(hi, q0.x + q0.y); }
         if (q1.y > 0) { lo = min(lo, q1.x); hi = max(hi, q1.x + q1.y); }
         if (q2.y > 0) { lo = min(lo, q2.x); hi = max(hi, q2.x + q2.y); }
-        if (hn < lo) hn = lo;
-        for (; hn < hi; ++hn) {
-            T z = b1[hn];
-#pragma unroll
-            for (int k = 0; k < NL; ++k) z += w1[(size_t)hn * NL + k] * xl[k];
-            T s, d;
-            act_eval(z, act, s, d);
-            ring_s[hn & (RING - 1)][lane] = s;
-            ring_d[hn & (RING - 1)][lane] = d;
+        if (hn < lo) {
+            hn = lo;
+            hslot = lo % DEC_RING;
         }
-        T acc = xr[r];
+        for (; hn < hi; ++hn) {
+            const T* w = sW1 + (size_t)hn * NL;
+            T z = sB1[hn];
+#pragma unroll
+            for (int k = 0; k < NL; ++k) z += w[k] * xl[k];
+            T* rs = ring + (size_t)hslot * 64 * RK + lane;
+            if (ACT == DDROM_ACT_SIGMOID) {
+                rs[0] = sig_fast<T>(z);
+            } else if (ACT == DDROM_ACT_SWISH) {
+                const T sg_ = sig_fast<T>(z);
+                rs[0] = z * sg_;
+                rs[64] = sg_ + z * sg_ * ((T)1 - sg_);
+            } else {
+                rs[0] = z;
+            }
+            hslot = hslot + 1 == DEC_RING ? 0 : hslot + 1;
+        }
+        T acc = sXR[r];
         T J[NL];
 #pragma unroll
         for (int k = 0; k < NL; ++k) J[k] = (T)0;
 #pragma unroll
         for (int kb = 0; kb < 3; ++kb) {
             const int2 q = kb == 0 ? q0 : (kb == 1 ? q1 : q2);
-            const T* w2r = w2 + ((size_t)r * 3 + kb) * bmax;
+            const T* w2r = sW2 + ((size_t)r * 3 + kb) * bmax;
+            int slot = q.x % DEC_RING;
             for (int t = 0; t < q.y; ++t) {
-                const int h = q.x + t;
                 const T wv = w2r[t];
-                acc += wv * ring_s[h & (RING - 1)][lane];
-                const T c = wv * ring_d[h & (RING - 1)][lane];
+                const T* rs = ring + (size_t)slot * 64 * RK + lane;
+                const T a = rs[0];
+                T d;
+                if (ACT == DDROM_ACT_SIGMOID) d = a - a * a;
+                else if (ACT == DDROM_ACT_SWISH) d = rs[64];
+                else d = (T)1;
+                acc += wv * a;
+                const T c = wv * d;
+                const T* w = sW1 + (size_t)(q.x + t) * NL;
 #pragma unroll
-                for (int k = 0; k < NL; ++k) J[k] += c * w1[(size_t)h * NL + k];
+                for (int k = 0; k < NL; ++k) J[k] += c * w[k];
+                slot = slot + 1 == DEC_RING ? 0 : slot + 1;
             }
         }
-        T* orow = o + (size_t)r * (1 + NL) * Bp;
-        orow[0] = acc;
+        if (b < Bp) {   // waves past the padded batch (small B) compute but never store
+            T* orow = o + (size_t)r * (1 + NL) * Bp;
+            orow[0] = acc;
 #pragma unroll
-        for (int k = 0; k < NL; ++k) orow[(size_t)(1 + k) * Bp] = J[k];
+            for (int k = 0; k < NL; ++k) orow[(size_t)(1 + k) * Bp] = J[k];
+        }
     }
 }
 
@@ -207,13 +268,18 @@ __global__ void k_bc(const double* __restrict__ xy, const int* __restrict__ fiel
 // ------------------------------------------------------------------------------------
 // HR residual, chain rule and Gauss-Newton partial sums
 // ------------------------------------------------------------------------------------
+// One wave = a run of sampled nodes of one subdomain x 64 solves.  For each node the ten
+// stencil DoFs are gathered without branches: every slot reads a value and NO Jacobian
+// entries from the decoder output (boundary slots read an all-zero block and take their
+// value from the per-solve Dirichlet buffer), so all loads of a node are in flight together;
+// the uniform source kind then selects which Jacobian columns each slot feeds.
 template <typename T, int NO, int NG>
 __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchunks, int rbase,
                                                const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
                                                const int* __restrict__ gather, const T* __restrict__ dec,
                                                const double* __restrict__ bc, const SolveState* __restrict__ st,
                                                int B, int Bp, double nu, double hx, double hy,
-                                               double* __restrict__ part, int estride) {
+                                               double* __restrict__ part, int estride, long long zero_row) {
     constexpr int NN = NO + NG;
     constexpr int NH = NN * (NN + 1) / 2;
     const ResChunk rc = rchunks[rbase + blockIdx.x];
@@ -223,6 +289,7 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
     if (__ballot(lane_live(st, b, B)) == 0) return;
     const T* dom = dec + (size_t)oo * Bp + b;
     const T* dga = dec + (size_t)og * Bp + b;
+    const T* dz = dec + (size_t)zero_row * Bp + b;
     const double* bcb = bc + b;
     double H[NH], g[NN], rr = 0.0;
 #pragma unroll
@@ -232,15 +299,21 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
     const int* gp = gather + rs.gather;
     for (int p = rc.p0; p < rc.p1; ++p) {
         const int* code = gp + (size_t)p * N_SLOTS;
-        int cd[N_SLOTS];
+        int kind[N_SLOTS];
         double v[N_SLOTS];
+        T jv[N_SLOTS][NO];
 #pragma unroll
         for (int t = 0; t < N_SLOTS; ++t) {
-            cd[t] = code[t];
-            const int kind = src_kind(cd[t]), idx = src_index(cd[t]);
-            if (kind == SRC_OMEGA) v[t] = (double)dom[(size_t)idx * (1 + NO) * Bp];
-            else if (kind == SRC_GAMMA) v[t] = (double)dga[(size_t)idx * (1 + NG) * Bp];
-            else v[t] = bcb[(size_t)idx * Bp];
+            const int cd = code[t];
+            kind[t] = src_kind(cd);
+            const int idx = src_index(cd);
+            const T* base = kind[t] == SRC_OMEGA ? dom + (size_t)idx * (1 + NO) * Bp
+                          : (kind[t] == SRC_GAMMA ? dga + (size_t)idx * (1 + NG) * Bp : dz);
+            const double bv = bcb[(size_t)(kind[t] == SRC_BOUND ? idx : 0) * Bp];
+            const T dv = base[0];
+            v[t] = kind[t] == SRC_BOUND ? bv : (double)dv;
+#pragma unroll
+            for (int k = 0; k < NO; ++k) jv[t][k] = base[(size_t)(1 + k) * Bp];
         }
         double ru, rv, cu[6], cv[6];
         burgers_point(v, nu, hx, hy, ru, rv, cu, cv);
@@ -252,23 +325,18 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
             double a_u, a_v;
             if (t < 5) { a_u = cu[t]; a_v = (t == S_UC) ? cv[5] : 0.0; }
             else { a_v = cv[t - 5]; a_u = (t == S_VC) ? cu[5] : 0.0; }
-            const int kind = src_kind(cd[t]), idx = src_index(cd[t]);
-            if (kind == SRC_OMEGA) {
-                const T* jr = dom + ((size_t)idx * (1 + NO) + 1) * Bp;
+            const bool om = kind[t] == SRC_OMEGA, ga = kind[t] == SRC_GAMMA;
 #pragma unroll
-                for (int k = 0; k < NO; ++k) {
-                    const double jk = (double)jr[(size_t)k * Bp];
-                    zu[k] += a_u * jk;
-                    zv[k] += a_v * jk;
-                }
-            } else if (kind == SRC_GAMMA) {
-                const T* jr = dga + ((size_t)idx * (1 + NG) + 1) * Bp;
+            for (int k = 0; k < NO; ++k) {
+                const double jk = (double)jv[t][k];
+                zu[k] += om ? a_u * jk : 0.0;
+                zv[k] += om ? a_v * jk : 0.0;
+            }
 #pragma unroll
-                for (int k = 0; k < NG; ++k) {
-                    const double jk = (double)jr[(size_t)k * Bp];
-                    zu[NO + k] += a_u * jk;
-                    zv[NO + k] += a_v * jk;
-                }
+            for (int k = 0; k < NG; ++k) {
+                const double jk = (double)jv[t][k];
+                zu[NO + k] += ga ? a_u * jk : 0.0;
+                zv[NO + k] += ga ? a_v * jk : 0.0;
             }
         }
         int e = 0;
@@ -291,20 +359,22 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
 // ------------------------------------------------------------------------------------
 // Weak compatibility constraint: c_i = C A_i g_i^Gamma, E_i^Gamma = C A_i dg_i^Gamma/dxhat
 // ------------------------------------------------------------------------------------
+// One wave = (subdomain, 8 constraint rows, a run of interface rows) x 64 solves; (C A_i)^T
+// is stored row-major with stride ca_ld so the 8 multipliers of an interface row are one
+// contiguous scalar load.  Partial sums over interface-row runs go to separate slots.
 template <typename T, int NG>
 __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, const ResSeg* __restrict__ rsegs,
                                             const DecSeg* __restrict__ segs, const double* __restrict__ CA, int n_C,
-                                            const T* __restrict__ dec, const SolveState* __restrict__ st, int B,
-                                            int Bp, double* __restrict__ c_part, double* __restrict__ E_part,
+                                            int ca_ld, const T* __restrict__ dec, const SolveState* __restrict__ st,
+                                            int B, int Bp, double* __restrict__ c_part, double* __restrict__ E_part,
                                             int mmax) {
     constexpr int JB = 8;
     const ConChunk cc = cch[blockIdx.x];
     const ResSeg rs = rsegs[cc.sd];
     const int b = blockIdx.y * 64 + threadIdx.x;
     if (__ballot(lane_live(st, b, B)) == 0) return;
-    const int Ng = rs.n_rows_ga;
     const T* dga = dec + (size_t)segs[rs.seg_ga].out * Bp + b;
-    const double* ca = CA + rs.ca;
+    const double* ca = CA + rs.ca + cc.j0;
     const int nj = cc.j1 - cc.j0;
     double c[JB], E[JB][NG];
 #pragma unroll
@@ -313,29 +383,29 @@ __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, co
 #pragma unroll
         for (int k = 0; k < NG; ++k) E[j][k] = 0.0;
     }
-    for (int o = 0; o < Ng; ++o) {
+#pragma unroll 2
+    for (int o = cc.o0; o < cc.o1; ++o) {
         const T* row = dga + (size_t)o * (1 + NG) * Bp;
         const double x = (double)row[0];
         double J[NG];
 #pragma unroll
         for (int k = 0; k < NG; ++k) J[k] = (double)row[(size_t)(1 + k) * Bp];
+        const double* a = ca + (size_t)o * ca_ld;
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
-            if (j < nj) {
-                const double a = ca[(size_t)(cc.j0 + j) * Ng + o];
-                c[j] += a * x;
+            const double aj = a[j];     // slots j >= nj hold zeros (padding of ca_ld) or are discarded
+            c[j] += aj * x;
 #pragma unroll
-                for (int k = 0; k < NG; ++k) E[j][k] += a * J[k];
-            }
+            for (int k = 0; k < NG; ++k) E[j][k] += aj * J[k];
         }
     }
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
         if (j < nj) {
             const int jj = cc.j0 + j;
-            c_part[((size_t)cc.sd * n_C + jj) * Bp + b] = c[j];
+            c_part[((size_t)cc.part * n_C + jj) * Bp + b] = c[j];
 #pragma unroll
-            for (int k = 0; k < NG; ++k) E_part[(((size_t)cc.sd * n_C + jj) * mmax + k) * Bp + b] = E[j][k];
+            for (int k = 0; k < NG; ++k) E_part[(((size_t)cc.part * n_C + jj) * mmax + k) * Bp + b] = E[j][k];
         }
     }
 }
@@ -352,6 +422,8 @@ struct UpdArgs {
     const int* n_ga;
     const int* xoff;
     const int* slot0;      // [n_sub + 1]
+    const int* cpart0;     // [n_sub + 1] constraint partial slots per subdomain
+    int n_cparts;
     const double* gn_part;
     const double* c_part;
     const double* E_part;
@@ -412,6 +484,61 @@ __device__ void chol_solve_lane(const double* A, int n, int ld, double* y) {
     }
 }
 
+// Gaussian elimination with partial pivoting on the augmented n x (n+1) system in LDS
+// (leading dimension ld); on success the solution is left in rhs_out[0..n).  Returns false
+// on a zero or non-finite pivot.
+__device__ bool lu_solve_lds(double* A, int n, int ld, int lane, double* rhs_out) {
+    __shared__ int piv_row;
+    __shared__ int bad_lu;
+    if (lane == 0) bad_lu = 0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        // pivot search (wave reduction on |A[i][k]|, ties to the lower row)
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + lane; i < n; i += 64) {
+            const double v = fabs(A[i * ld + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (lane == 0) {
+            piv_row = bi;
+            if (!(best > 0.0) || !isfinite(best)) bad_lu = 1;
+        }
+        __syncthreads();
+        const int pr = piv_row;
+        if (pr != k)
+            for (int j = lane; j <= n; j += 64) {
+                const double t = A[k * ld + j];
+                A[k * ld + j] = A[pr * ld + j];
+                A[pr * ld + j] = t;
+            }
+        __syncthreads();
+        const double pv = A[k * ld + k];
+        const int m = n - k - 1;
+        if (pv != 0.0)
+            for (int e = lane; e < m * (m + 1); e += 64) {
+                const int i = k + 1 + e / (m + 1), j = k + 1 + e % (m + 1);
+                A[i * ld + j] -= A[i * ld + k] / pv * A[k * ld + j];
+            }
+        __syncthreads();
+    }
+    const bool ok = bad_lu == 0;
+    if (ok && lane == 0) {
+        for (int i = n - 1; i >= 0; --i) {
+            double s = A[i * ld + n];
+            for (int k = i + 1; k < n; ++k) s -= A[i * ld + k] * rhs_out[k];
+            rhs_out[i] = s / A[i * ld + i];
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
 __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
     const int b = blockIdx.x;
     const int lane = threadIdx.x;
@@ -425,20 +552,30 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
     __shared__ double Sm[KKT_NC * (KKT_NC + 1)];      // Schur complement | q, or the least-squares system
     __shared__ double Hs[KKT_NN * KKT_NN];
     __shared__ double Ys[(KKT_NC + 1) * KKT_NN];     // one right-hand side per lane
+    __shared__ double Es[KKT_NC * KKT_MG];           // E_i^Gamma of the current subdomain
     __shared__ double rho_s[KKT_NN];
-    __shared__ double red[4];
     __shared__ int flag;
 
-    // c = sum_i c_i
+    // c = sum over all constraint partial slots
     for (int j = lane; j < nC; j += 64) {
         double s = 0.0;
-        for (int sd = 0; sd < a.n_sub; ++sd) s += a.c_part[((size_t)sd * nC + j) * Bp + b];
+        for (int p = 0; p < a.n_cparts; ++p) s += a.c_part[((size_t)p * nC + j) * Bp + b];
         c_s[j] = s;
     }
     for (int j = lane; j < nC; j += 64) lam_s[j] = a.lamt[(size_t)b * nC + j];
-    __syncthreads();
 
-    auto E_at = [&](int sd, int j, int k) { return a.E_part[(((size_t)sd * nC + j) * a.mmax + k) * Bp + b]; };
+    // E_i^Gamma (n_C x n_i^Gamma) of subdomain sd into Es (sum over its partial slots)
+    auto load_E = [&](int sd) {
+        const int ng = a.n_ga[sd];
+        __syncthreads();
+        for (int e = lane; e < nC * ng; e += 64) {
+            const int j = e / ng, k = e % ng;
+            double s = 0.0;
+            for (int p = a.cpart0[sd]; p < a.cpart0[sd + 1]; ++p) s += a.E_part[(((size_t)p * nC + j) * a.mmax + k) * Bp + b];
+            Es[j * KKT_MG + k] = s;
+        }
+        __syncthreads();
+    };
     auto g_at = [&](int sd, int e) {
         const int NN = a.n_om[sd] + a.n_ga[sd];
         const int off = NN * (NN + 1) / 2 + e;
@@ -446,26 +583,27 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
         for (int sl = a.slot0[sd]; sl < a.slot0[sd + 1]; ++sl) s += a.gn_part[((size_t)sl * a.estride + off) * Bp + b];
         return s;
     };
+    __syncthreads();
 
-    // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i || (Householder QR) ----
+    // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i || ----
     if (S.phase == PH_INIT && !a.lam_given && nC > 0) {
         int R = 0;
         for (int sd = 0; sd < a.n_sub; ++sd) R += a.n_ga[sd];
         const int ld = nC + 1;
-        // rows of M = [(E_i^Gamma)^T | -g_i^Gamma], stored in Sm when R <= KKT_NC, else normal equations
         if (R <= KKT_NC) {
+            // Householder QR of M = [(E_i^Gamma)^T | -g_i^Gamma] stacked over subdomains
             int r0 = 0;
             for (int sd = 0; sd < a.n_sub; ++sd) {
                 const int m = a.n_ga[sd], no = a.n_om[sd];
+                load_E(sd);
                 for (int e = lane; e < m * ld; e += 64) {
                     const int k = e / ld, j = e % ld;
-                    Sm[(r0 + k) * ld + j] = j < nC ? E_at(sd, j, k) : -g_at(sd, no + k);
+                    Sm[(r0 + k) * ld + j] = j < nC ? Es[j * KKT_MG + k] : -g_at(sd, no + k);
                 }
                 r0 += m;
             }
             __syncthreads();
             for (int k = 0; k < nC && k < R; ++k) {
-                // Householder vector for column k, rows k..R-1
                 double nrm2 = 0.0;
                 for (int r = k + lane; r < R; r += 64) nrm2 += Sm[r * ld + k] * Sm[r * ld + k];
                 nrm2 = wave_sum(nrm2);
@@ -496,28 +634,26 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
             }
         } else {
             // normal equations (sum_i E_i E_i^T) lambda = -sum_i E_i g_i^Gamma
-            for (int e = lane; e < nC * ld; e += 64) {
-                const int i = e / ld, j = e % ld;
-                double s = 0.0;
-                for (int sd = 0; sd < a.n_sub; ++sd)
-                    for (int k = 0; k < a.n_ga[sd]; ++k)
-                        s += E_at(sd, i, k) * (j < nC ? E_at(sd, j, k) : -g_at(sd, a.n_om[sd] + k));
-                Sm[i * ld + j] = s;
+            for (int e = lane; e < nC * ld; e += 64) Sm[e] = 0.0;
+            for (int sd = 0; sd < a.n_sub; ++sd) {
+                const int m = a.n_ga[sd], no = a.n_om[sd];
+                load_E(sd);
+                if (lane < m) rho_s[lane] = g_at(sd, no + lane);
+                __syncthreads();
+                for (int e = lane; e < nC * ld; e += 64) {
+                    const int i = e / ld, j = e % ld;
+                    double s = 0.0;
+                    for (int k = 0; k < m; ++k) s += Es[i * KKT_MG + k] * (j < nC ? Es[j * KKT_MG + k] : -rho_s[k]);
+                    Sm[e] += s;
+                }
             }
             __syncthreads();
             chol_lds(Sm, nC, ld, lane);
             if (lane == 0) {
-                for (int i = 0; i < nC; ++i) lam_s[i] = Sm[i * ld + nC];
-                for (int i = 0; i < nC; ++i) {
-                    double s = lam_s[i];
-                    for (int k = 0; k < i; ++k) s -= Sm[i * ld + k] * lam_s[k];
-                    lam_s[i] = s / Sm[i * ld + i];
-                }
-                for (int i = nC - 1; i >= 0; --i) {
-                    double s = lam_s[i];
-                    for (int k = i + 1; k < nC; ++k) s -= Sm[k * ld + i] * lam_s[k];
-                    lam_s[i] = s / Sm[i * ld + i];
-                }
+                double* y = Ys;
+                for (int i = 0; i < nC; ++i) y[i] = Sm[i * ld + nC];
+                chol_solve_lane(Sm, nC, ld, y);
+                for (int i = 0; i < nC; ++i) lam_s[i] = y[i];
             }
         }
         __syncthreads();
@@ -527,10 +663,11 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
     double acc = 0.0;
     for (int sd = 0; sd < a.n_sub; ++sd) {
         const int no = a.n_om[sd], NN = no + a.n_ga[sd];
+        load_E(sd);
         for (int e = lane; e < NN; e += 64) {
             double r = g_at(sd, e);
             if (e >= no)
-                for (int j = 0; j < nC; ++j) r += E_at(sd, j, e - no) * lam_s[j];
+                for (int j = 0; j < nC; ++j) r += Es[j * KKT_MG + (e - no)] * lam_s[j];
             acc += r * r;
         }
     }
@@ -570,7 +707,7 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
             S.fn = fn_t;
         }
     }
-    if (action == 0 && S.phase != PH_DONE) {
+    if (action == 0) {
         if (S.fn <= S.tol) {
             S.status = DDROM_STATUS_CONVERGED;
             action = 2;
@@ -580,7 +717,6 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
         }
     }
     if (action == 1) {
-        // next trial on the same step with the halved alpha
         for (int e = lane; e < nD; e += 64)
             a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + S.alpha * a.step[(size_t)b * (nD + nC) + e];
         for (int j = lane; j < nC; j += 64)
@@ -599,7 +735,7 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
         return;
     }
 
-    // ---- KKT step: H_i s_i + E_i^T s_l = -rho_i ; sum_i E_i s_i = -c ----
+    // ---- KKT step: H_i s_i + E_i^T s_l = -rho_i ; sum_i E_i s_i = -c (Schur complement) ----
     const int ld = nC + 1;
     for (int e = lane; e < nC * ld; e += 64) Sm[e] = 0.0;
     if (lane == 0) flag = 0;
@@ -607,10 +743,9 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
     double* Yb = a.Y + (size_t)b * a.n_sub * KKT_NN * ld;
     for (int sd = 0; sd < a.n_sub; ++sd) {
         const int no = a.n_om[sd], ng = a.n_ga[sd], NN = no + ng;
-        // H_i (full symmetric) from the packed upper-triangle partial sums
         const int NH = NN * (NN + 1) / 2;
+        load_E(sd);
         for (int e = lane; e < NH; e += 64) {
-            // map packed index e -> (i, j), i <= j
             int i = 0, rem = e;
             while (rem >= NN - i) { rem -= NN - i; ++i; }
             const int j = i + rem;
@@ -622,7 +757,7 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
         for (int e = lane; e < NN; e += 64) {
             double r = g_at(sd, e);
             if (e >= no)
-                for (int j = 0; j < nC; ++j) r += E_at(sd, j, e - no) * lam_s[j];
+                for (int j = 0; j < nC; ++j) r += Es[j * KKT_MG + (e - no)] * lam_s[j];
             rho_s[e] = r;
         }
         __syncthreads();
@@ -634,7 +769,7 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
             double* y = Ys + lane * KKT_NN;
             for (int k = 0; k < NN; ++k) y[k] = 0.0;
             if (lane < nC)
-                for (int k = 0; k < ng; ++k) y[no + k] = E_at(sd, lane, k);
+                for (int k = 0; k < ng; ++k) y[no + k] = Es[lane * KKT_MG + k];
             else
                 for (int k = 0; k < NN; ++k) y[k] = rho_s[k];
             chol_solve_lane(Hs, NN, KKT_NN, y);
@@ -642,7 +777,7 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
             // Sm[:, lane] += E_i y
             for (int r = 0; r < nC; ++r) {
                 double s = 0.0;
-                for (int k = 0; k < ng; ++k) s += E_at(sd, r, k) * y[no + k];
+                for (int k = 0; k < ng; ++k) s += Es[r * KKT_MG + k] * y[no + k];
                 Sm[r * ld + lane] += s;
             }
         }
@@ -651,8 +786,10 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
     // S s_l = c - q
     for (int j = lane; j < nC; j += 64) Sm[j * ld + nC] = c_s[j] - Sm[j * ld + nC];
     __syncthreads();
-    const bool spd = chol_lds(Sm, nC, ld, lane);
-    if (!spd || flag) {
+    // S is symmetric positive definite in exact arithmetic when the H_i are; it can be badly
+    // conditioned, so it is solved by elimination with partial pivoting (lam_s <- s_lambda).
+    const bool sok = nC == 0 || lu_solve_lds(Sm, nC, ld, lane, lam_s);
+    if (!sok || flag) {
         if (lane == 0) {
             S.status = DDROM_STATUS_KKT_NOT_PD;
             S.phase = PH_DONE;
@@ -660,13 +797,6 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
         }
         return;
     }
-    if (lane == 0 && nC > 0) {
-        double* y = Ys;   // reuse
-        for (int i = 0; i < nC; ++i) y[i] = Sm[i * ld + nC];
-        chol_solve_lane(Sm, nC, ld, y);
-        for (int i = 0; i < nC; ++i) lam_s[i] = y[i];   // lam_s now holds s_lambda
-    }
-    __syncthreads();
     double* stp = a.step + (size_t)b * (nD + nC);
     for (int j = lane; j < nC; j += 64) stp[nD + j] = lam_s[j];
     for (int sd = 0; sd < a.n_sub; ++sd) {
@@ -749,7 +879,8 @@ __global__ void k_zero_int(int* p) {
 // Sum of the GN partials into dense per-solve outputs (ddrom_gn_blocks).
 __global__ void k_collect(int B, int Bp, int n_sub, int n_C, int nD, int nmax, int mmax, int estride,
                           const int* __restrict__ n_om, const int* __restrict__ n_ga, const int* __restrict__ xoff,
-                          const int* __restrict__ slot0, const double* __restrict__ part,
+                          const int* __restrict__ slot0, const int* __restrict__ cpart0, int n_cparts,
+                          const double* __restrict__ part,
                           const double* __restrict__ c_part, const double* __restrict__ E_part, double* H, double* g,
                           double* EG, double* c, double* rr) {
     const int b = blockIdx.x;
@@ -777,14 +908,16 @@ __global__ void k_collect(int B, int Bp, int n_sub, int n_C, int nD, int nmax, i
         if (EG)
             for (int e = threadIdx.x; e < n_C * mmax; e += blockDim.x) {
                 const int j = e / mmax, k = e % mmax;
-                EG[(((size_t)b * n_sub + sd) * n_C + j) * mmax + k] =
-                    k < n_ga[sd] ? E_part[(((size_t)sd * n_C + j) * mmax + k) * Bp + b] : 0.0;
+                double sum = 0.0;
+                if (k < n_ga[sd])
+                    for (int p = cpart0[sd]; p < cpart0[sd + 1]; ++p) sum += E_part[(((size_t)p * n_C + j) * mmax + k) * Bp + b];
+                EG[(((size_t)b * n_sub + sd) * n_C + j) * mmax + k] = sum;
             }
     }
     if (c)
         for (int j = threadIdx.x; j < n_C; j += blockDim.x) {
             double s = 0.0;
-            for (int sd = 0; sd < n_sub; ++sd) s += c_part[((size_t)sd * n_C + j) * Bp + b];
+            for (int p = 0; p < n_cparts; ++p) s += c_part[((size_t)p * n_C + j) * Bp + b];
             c[(size_t)b * n_C + j] = s;
         }
     // rr: reduce across the block
@@ -867,37 +1000,48 @@ __global__ void k_fom_residual(int total_own, int B, const int* __restrict__ src
 // ====================================================================================
 namespace {
 
-struct DevInts {
-    int *n_om = nullptr, *n_ga = nullptr, *xoff = nullptr, *slot0 = nullptr;
-};
-
-struct ModelExtra {
-    DevInts di;
-};
-
-static int launch_decode(const ddrom_model* m, int prec, int c0, int c1, int n, const double* xhat, int xstride,
+template <int TAG>
+static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const double* xhat, int xstride,
                          int xoff_override, const SolveState* st, int B, void* out, int Bp, hipStream_t s) {
+    const int c0 = m->seg_chunk0[g0], c1 = m->seg_chunk1[g1 - 1];
     if (c1 <= c0) return 0;
-    dim3 grid(c1 - c0, Bp / 64), block(64);
-#define DEC_CASE(NLV)                                                                                            \
-    case NLV:                                                                                                    \
-        if (prec == DDROM_PREC_FP64)                                                                             \
-            hipLaunchKernelGGL((k_decode<double, NLV>), grid, block, 0, s, m->chunks_d, c0, m->segs_d, m->W1d,    \
-                               m->b1d, m->bands, m->W2d, m->xrefd, xhat, xstride, xoff_override, st, B,          \
-                               (double*)out, Bp, m->act);                                                        \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_decode<float, NLV>), grid, block, 0, s, m->chunks_d, c0, m->segs_d, m->W1f,     \
-                               m->b1f, m->bands, m->W2f, m->xreff, xhat, xstride, xoff_override, st, B,          \
-                               (float*)out, Bp, m->act);                                                         \
+    const int n = m->segs_h[g0].n;
+    long long stage = 0;
+    for (int g = g0; g < g1; ++g) stage = std::max(stage, prec == DDROM_PREC_FP64 ? m->seg_stage_f64[g] : m->seg_stage_f32[g]);
+    const int act = m->act;
+    const int rk = act == DDROM_ACT_SWISH ? 2 : 1;
+    const int waves = prec == DDROM_PREC_FP64 ? 1 : (act == DDROM_ACT_SWISH ? 2 : 4);
+    const int esz = prec == DDROM_PREC_FP64 ? 8 : 4;
+    DecLds L;
+    L.total = (size_t)stage + (size_t)waves * DEC_RING * 64 * esz * rk;
+    if (L.total > 65536) {
+        set_error("decode work item exceeds 64 KiB of LDS");
+        return DDROM_EINVAL;
+    }
+    dim3 grid(c1 - c0, (Bp + 64 * waves - 1) / (64 * waves)), block(64 * waves);
+    const unsigned lds = (unsigned)L.total;
+#define DEC_LAUNCH(T, NLV, ACTV, WV, W1p, B1p, W2p, XRp)                                                          \
+    hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG>), grid, block, lds, s, m->chunks_d, c0, m->segs_d, W1p,     \
+                       B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, st, B, (T*)out, Bp)
+#define DEC_ACT(NLV, ACTV)                                                                                        \
+    if (prec == DDROM_PREC_FP64) DEC_LAUNCH(double, NLV, ACTV, 1, m->W1d, m->b1d, m->W2d, m->xrefd);            \
+    else if (ACTV == DDROM_ACT_SWISH) DEC_LAUNCH(float, NLV, ACTV, 2, m->W1f, m->b1f, m->W2f, m->xreff);         \
+    else DEC_LAUNCH(float, NLV, ACTV, 4, m->W1f, m->b1f, m->W2f, m->xreff);
+#define DEC_CASE(NLV)                                                                                             \
+    case NLV:                                                                                                     \
+        if (act == DDROM_ACT_SIGMOID) { DEC_ACT(NLV, DDROM_ACT_SIGMOID) }                                       \
+        else if (act == DDROM_ACT_SWISH) { DEC_ACT(NLV, DDROM_ACT_SWISH) }                                       \
+        else { DEC_ACT(NLV, DDROM_ACT_IDENTITY) }                                                                 \
         break;
     switch (n) {
-        DEC_CASE(1) DEC_CASE(2) DEC_CASE(3) DEC_CASE(4) DEC_CASE(5) DEC_CASE(6) DEC_CASE(8) DEC_CASE(10)
-        DEC_CASE(12)
+        DEC_CASE(2) DEC_CASE(3) DEC_CASE(4) DEC_CASE(6) DEC_CASE(8) DEC_CASE(12)
         default:
             set_error("unsupported latent size " + std::to_string(n));
             return DDROM_EINVAL;
     }
 #undef DEC_CASE
+#undef DEC_ACT
+#undef DEC_LAUNCH
     HIPCHECK(hipGetLastError());
     return 0;
 }
@@ -913,16 +1057,16 @@ static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const dd
         if (prec == DDROM_PREC_FP64)                                                                              \
             hipLaunchKernelGGL((k_res_gn<double, A, G>), grid, block, 0, s, m->rchunks_d, c0, m->rsegs_d,          \
                                m->segs_d, m->gather_d, (const double*)ws->dec_out, ws->bc, st, B, ws->Bp, m->nu,  \
-                               m->hx, m->hy, ws->gn_part, m->estride);                                            \
+                               m->hx, m->hy, ws->gn_part, m->estride, ws->zero_row);                              \
         else                                                                                                      \
             hipLaunchKernelGGL((k_res_gn<float, A, G>), grid, block, 0, s, m->rchunks_d, c0, m->rsegs_d,           \
                                m->segs_d, m->gather_d, (const float*)ws->dec_out, ws->bc, st, B, ws->Bp, m->nu,   \
-                               m->hx, m->hy, ws->gn_part, m->estride);                                            \
+                               m->hx, m->hy, ws->gn_part, m->estride, ws->zero_row);                              \
         HIPCHECK(hipGetLastError());                                                                              \
         return 0;                                                                                                 \
     }
-    RES_CASE(2, 1) RES_CASE(3, 2) RES_CASE(4, 2) RES_CASE(6, 3) RES_CASE(8, 4) RES_CASE(12, 6) RES_CASE(3, 0)
-    RES_CASE(4, 0) RES_CASE(6, 0) RES_CASE(8, 0)
+    RES_CASE(2, 1) RES_CASE(3, 2) RES_CASE(4, 2) RES_CASE(6, 3) RES_CASE(8, 4) RES_CASE(12, 6) RES_CASE(4, 0)
+    RES_CASE(6, 0) RES_CASE(8, 0)
 #undef RES_CASE
     set_error("unsupported latent sizes (" + std::to_string(rs.n_om) + ", " + std::to_string(rs.n_ga) + ")");
     return DDROM_EINVAL;
@@ -931,7 +1075,6 @@ static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const dd
 static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const SolveState* st, int B,
                       hipStream_t s) {
     if (m->n_cchunks == 0 || m->n_C == 0) return 0;
-    // all subdomains must share n_i^Gamma for one launch; group otherwise
     dim3 grid(m->n_cchunks, ws->Bp / 64), block(64);
     const int ng = m->mmax;
     for (int sd = 0; sd < m->n_sub; ++sd)
@@ -943,10 +1086,12 @@ static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws,
     case G:                                                                                                       \
         if (prec == DDROM_PREC_FP64)                                                                              \
             hipLaunchKernelGGL((k_con<double, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d, \
-                               m->n_C, (const double*)ws->dec_out, st, B, ws->Bp, ws->c_part, ws->E_part, m->mmax); \
+                               m->n_C, m->ca_ld, (const double*)ws->dec_out, st, B, ws->Bp, ws->c_part,           \
+                               ws->E_part, m->mmax);                                                              \
         else                                                                                                      \
             hipLaunchKernelGGL((k_con<float, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d,  \
-                               m->n_C, (const float*)ws->dec_out, st, B, ws->Bp, ws->c_part, ws->E_part, m->mmax); \
+                               m->n_C, m->ca_ld, (const float*)ws->dec_out, st, B, ws->Bp, ws->c_part,            \
+                               ws->E_part, m->mmax);                                                              \
         break;
     switch (ng) {
         CON_CASE(1) CON_CASE(2) CON_CASE(3) CON_CASE(4) CON_CASE(6)
@@ -963,7 +1108,7 @@ static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws,
 
 // Device copies of small per-subdomain integer tables, kept next to the model.
 struct ModelDevInts {
-    int *n_om, *n_ga, *xoff, *slot0;
+    int *n_om, *n_ga, *xoff, *slot0, *cpart0;
 };
 static ModelDevInts get_ints(const ddrom_model* m);
 
@@ -985,8 +1130,7 @@ static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, i
     for (int g0 = 0; g0 < nseg;) {
         int g1 = g0 + 1;
         while (g1 < nseg && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
-        if ((rc = launch_decode(m, prec, m->seg_chunk0[g0], m->seg_chunk1[g1 - 1], m->segs_h[g0].n, xhat, m->n_D, -1,
-                                st, B, ws->dec_out, ws->Bp, s)))
+        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, st, B, ws->dec_out, ws->Bp, s)))
             return rc;
         g0 = g1;
     }
@@ -1007,6 +1151,7 @@ static UpdArgs upd_args(const ddrom_model* m, ddrom_workspace* ws, int B, const 
     a.B = B; a.lam_given = lam_given; a.max_iter = o->max_iter; a.max_bt = o->max_backtracks;
     a.tol_abs = o->tol_abs; a.tol_rel = o->tol_rel; a.c1 = o->armijo_c1;
     a.n_om = di.n_om; a.n_ga = di.n_ga; a.xoff = di.xoff; a.slot0 = di.slot0;
+    a.cpart0 = di.cpart0; a.n_cparts = m->n_cparts;
     a.gn_part = ws->gn_part; a.c_part = ws->c_part; a.E_part = ws->E_part;
     a.x = ws->x; a.xt = ws->xt; a.lam = ws->lam; a.lamt = ws->lamt; a.step = ws->step; a.Y = ws->Y;
     a.st = ws->st; a.counter = ws->counter;
@@ -1042,13 +1187,16 @@ int ddrom_model_create(const ddrom_model_desc* desc, ddrom_model** out) {
     std::vector<int> slot0(m->n_sub + 1);
     for (int sd = 0; sd < m->n_sub; ++sd) slot0[sd] = m->rsegs_h[sd].slot0;
     slot0[m->n_sub] = m->n_slots;
+    std::vector<int> cpart0(m->n_sub + 1);
+    for (int sd = 0; sd < m->n_sub; ++sd) cpart0[sd] = m->rsegs_h[sd].cpart0;
+    cpart0[m->n_sub] = m->n_cparts;
     auto up = [&](int** p, const std::vector<int>& v) -> int {
         if (hipMalloc((void**)p, v.size() * sizeof(int)) != hipSuccess) return DDROM_ENOMEM;
         if (hipMemcpy(*p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return DDROM_EHIP;
         return 0;
     };
     if ((rc = up(&di.n_om, m->n_om)) || (rc = up(&di.n_ga, m->n_ga)) || (rc = up(&di.xoff, m->xoff)) ||
-        (rc = up(&di.slot0, slot0))) {
+        (rc = up(&di.slot0, slot0)) || (rc = up(&di.cpart0, cpart0))) {
         set_error("device allocation failed");
         free_model(m.get());
         return rc;
@@ -1071,6 +1219,7 @@ void ddrom_model_destroy(ddrom_model* m) {
             (void)hipFree(it->second.n_ga);
             (void)hipFree(it->second.xoff);
             (void)hipFree(it->second.slot0);
+            (void)hipFree(it->second.cpart0);
             g_ints.erase(it);
         }
     }
@@ -1098,6 +1247,9 @@ long long ddrom_model_size(const ddrom_model* m, int q, int sd) {
         case 16: return sd < 0 ? -1 : m->nb[sd];
         case 17: return sd < 0 ? -1 : m->xoff[sd];
         case 18: return sd < 0 ? -1 : m->n_own[sd];
+        case 19: return sd < 0 ? -1 : m->band_nnz[sd];
+        case 20: return sd < 0 ? -1 : m->band_nnz[m->n_sub + sd];
+        case 21: return sd < 0 ? -1 : m->segs_h[m->n_sub + sd].hid;
         default: return -1;
     }
 }
@@ -1127,11 +1279,11 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
     const size_t Bp = w->Bp;
     const int ld = m->n_C + 1;
     struct A { void** p; size_t bytes; } allocs[] = {
-        {(void**)&w->dec_out, (size_t)m->dec_rows * Bp * sizeof(double)},
+        {(void**)&w->dec_out, (size_t)(m->dec_rows + 1 + m->nmax) * Bp * sizeof(double)},
         {(void**)&w->bc, std::max<size_t>(1, (size_t)m->n_bc) * Bp * sizeof(double)},
         {(void**)&w->gn_part, (size_t)m->n_slots * m->estride * Bp * sizeof(double)},
-        {(void**)&w->c_part, std::max<size_t>(1, (size_t)m->n_sub * m->n_C) * Bp * sizeof(double)},
-        {(void**)&w->E_part, std::max<size_t>(1, (size_t)m->n_sub * m->n_C * std::max(1, m->mmax)) * Bp * sizeof(double)},
+        {(void**)&w->c_part, std::max<size_t>(1, (size_t)m->n_cparts * m->n_C) * Bp * sizeof(double)},
+        {(void**)&w->E_part, std::max<size_t>(1, (size_t)m->n_cparts * m->n_C * std::max(1, m->mmax)) * Bp * sizeof(double)},
         {(void**)&w->x, Bp * m->n_D * sizeof(double)},
         {(void**)&w->xt, Bp * m->n_D * sizeof(double)},
         {(void**)&w->lam, Bp * std::max(1, m->n_C) * sizeof(double)},
@@ -1148,6 +1300,13 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
             ddrom_workspace_destroy(w.release());
             return DDROM_ENOMEM;
         }
+    }
+    // all-zero block after the decoder outputs (read by boundary stencil slots)
+    w->zero_row = m->dec_rows;
+    if (hipMemset(w->dec_out, 0, (size_t)(m->dec_rows + 1 + m->nmax) * Bp * sizeof(double)) != hipSuccess) {
+        set_error("workspace clear failed");
+        ddrom_workspace_destroy(w.release());
+        return DDROM_EHIP;
     }
     if (hipHostMalloc((void**)&w->counter_h, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
         set_error("pinned allocation failed");
@@ -1221,8 +1380,7 @@ static int decode_common(const ddrom_model* m, ddrom_workspace* ws, int sd, int 
     if (B == 0) return 0;
     const int seg = part * m->n_sub + sd;
     const ddrom::DecSeg& sg = m->segs_h[seg];
-    if ((rc = launch_decode(m, prec, m->seg_chunk0[seg], m->seg_chunk1[seg], sg.n, xhat_d, sg.n, 0, nullptr, B,
-                            ws->dec_out, ws->Bp, s)))
+    if ((rc = launch_decode<0>(m, prec, seg, seg + 1, xhat_d, sg.n, 0, nullptr, B, ws->dec_out, ws->Bp, s)))
         return rc;
     const long long tot = (long long)sg.rows * (1 + sg.n) * B;
     if (tot == 0) return 0;
@@ -1273,7 +1431,7 @@ int ddrom_gn_blocks(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
     if ((rc = evaluate_round(m, ws, precision, B, ws->st, ws->xt, s))) return rc;
     ModelDevInts di = get_ints(m);
     hipLaunchKernelGGL(k_collect, dim3(B), dim3(256), 0, s, B, ws->Bp, m->n_sub, m->n_C, m->n_D, m->nmax,
-                       std::max(1, m->mmax), m->estride, di.n_om, di.n_ga, di.xoff, di.slot0, ws->gn_part,
+                       std::max(1, m->mmax), m->estride, di.n_om, di.n_ga, di.xoff, di.slot0, di.cpart0, m->n_cparts, ws->gn_part,
                        ws->c_part, ws->E_part, H_d, g_d, EG_d, c_d, rr_d);
     HIPCHECK(hipGetLastError());
     return 0;
@@ -1361,11 +1519,11 @@ static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double*
 
 int sqp_step(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, double* xhat_d, double* lam_d,
              double* fnorm_d, int* status_d, const ddrom_opts* o, hipStream_t s) {
+    if (B == 0) return 0;
     if (!xhat_d || !lam_d || !o) {
         set_error("bad arguments to sqp_step");
         return DDROM_EINVAL;
     }
-    if (B == 0) return 0;
     ddrom_opts one = *o;
     one.max_iter = 1;
     one.tol_abs = 0.0;
@@ -1377,11 +1535,11 @@ int sqp_step(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int 
 int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, const double* xhat0_d,
                     const double* lam0_d, const ddrom_opts* o, double* xhat_d, double* lam_d, int* iters_d,
                     int* status_d, double* fnorm_d, double* fnorm0_d, hipStream_t s) {
+    if (B == 0) return 0;
     if (!xhat_d) {
         set_error("xhat_d is NULL");
         return DDROM_EINVAL;
     }
-    if (B == 0) return 0;
     FinalOut fo{xhat_d, lam_d, fnorm_d, fnorm0_d, iters_d, status_d};
     return solve_common(m, ws, mu_d, B, xhat0_d, lam0_d, o, s, 1, fo);
 }
@@ -1407,11 +1565,10 @@ int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* 
         HIPCHECK(hipEventRecord(ws->t0, s));
         for (int r = 0; r < reps; ++r) {
             int c = 0;
-            if (which == 0) c = launch_decode(m, precision, m->seg_chunk0[0], m->seg_chunk1[m->n_sub - 1],
-                                              m->segs_h[0].n, ws->xt, m->n_D, -1, ws->st, B, ws->dec_out, ws->Bp, s);
-            else if (which == 1) c = launch_decode(m, precision, m->seg_chunk0[m->n_sub], m->seg_chunk1[2 * m->n_sub - 1],
-                                                   m->segs_h[m->n_sub].n, ws->xt, m->n_D, -1, ws->st, B, ws->dec_out,
-                                                   ws->Bp, s);
+            if (which == 0) c = launch_decode<1>(m, precision, 0, m->n_sub, ws->xt, m->n_D, -1, ws->st, B, ws->dec_out,
+                                                 ws->Bp, s);
+            else if (which == 1) c = launch_decode<1>(m, precision, m->n_sub, 2 * m->n_sub, ws->xt, m->n_D, -1, ws->st,
+                                                      B, ws->dec_out, ws->Bp, s);
             else if (which == 2) c = launch_res(m, precision, 0, m->n_sub, ws, ws->st, B, s);
             else c = launch_con(m, precision, ws, ws->st, B, s);
             if (c) return c;

@@ -11,10 +11,12 @@
 
 namespace ddrom {
 
-static constexpr int RING = 64;          // hidden-unit ring of the decode kernel (window bound)
-static constexpr int DEC_ROWS = 128;     // output rows per decode work item
-static constexpr int RES_NODES = 48;     // sampled nodes per residual work item
+static constexpr int RING = 48;          // hidden-unit ring of the decode kernel (window bound)
+static constexpr int DEC_ROWS = 96;      // max output rows per decode work item
+static constexpr int DEC_STAGE = 15360;  // bytes of FP32 weights staged in LDS per decode work item
+static constexpr int RES_NODES = 24;     // sampled nodes per residual work item
 static constexpr int CON_ROWS = 8;       // constraint rows per constraint work item
+static constexpr int CON_OROWS = 256;    // interface rows per constraint work item
 
 template <typename T>
 static int upload(T** dst, const std::vector<T>& src) {
@@ -97,7 +99,7 @@ static int make_subnet(const ddrom_decoder_desc& d, const std::vector<int>& rows
             hi = std::max(hi, cs + len);
         }
         if (hi >= 0 && hi - lo > RING) {
-            set_error("decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 64)");
+            set_error("decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 48)");
             return DDROM_EINVAL;
         }
     }
@@ -189,8 +191,8 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         }
         m->n_om[sd] = a.n;
         m->n_ga[sd] = g.N > 0 ? g.n : 0;
-        if (m->n_om[sd] + m->n_ga[sd] > 24) {
-            set_error("n_i^Omega + n_i^Gamma above 24 is not supported by the KKT kernel");
+        if (m->n_om[sd] + m->n_ga[sd] > 20 || m->n_ga[sd] > 12) {
+            set_error("n_i^Omega + n_i^Gamma above 20 or n_i^Gamma above 12 is not supported by the KKT kernel");
             return DDROM_EINVAL;
         }
         m->xoff[sd] = nD;
@@ -332,6 +334,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     std::vector<double> W1, b1, W2, xref;
     std::vector<int2> bands;
     m->segs_h.assign(2 * n_sub, DecSeg{});
+    m->band_nnz.assign(2 * n_sub, 0);
     long long out_rows = 0;
     for (int part = 0; part < 2; ++part)
         for (int sd = 0; sd < n_sub; ++sd) {
@@ -365,15 +368,53 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             sg.xref = (long long)xref.size(); xref.insert(xref.end(), hd.xref.begin(), hd.xref.end());
             sg.out = out_rows;
             out_rows += (long long)hd.rows * (1 + sg.n);
+            {
+                long long nnz = 0;
+                for (const int2& q : hd.band) nnz += q.y;
+                m->band_nnz[part * n_sub + sd] = nnz;
+            }
             if (part == 0) m->hid_om[sd] = hd.hid;
         }
     m->dec_rows = std::max<long long>(1, out_rows);
+    // Decode work items: runs of consecutive kept rows whose staged weights (W1~ rows and
+    // biases of the hidden units they read, their W2~ values, x_ref, band descriptors) fit
+    // in DEC_STAGE bytes of FP32.
     m->seg_chunk0.assign(2 * n_sub, 0);
     m->seg_chunk1.assign(2 * n_sub, 0);
+    m->seg_stage_f32.assign(2 * n_sub, 0);
+    m->seg_stage_f64.assign(2 * n_sub, 0);
     for (int sgi = 0; sgi < 2 * n_sub; ++sgi) {
         m->seg_chunk0[sgi] = (int)m->chunks_h.size();
         const DecSeg& sg = m->segs_h[sgi];
-        for (int r = 0; r < sg.rows; r += DEC_ROWS) m->chunks_h.push_back(DecChunk{sgi, r, std::min(sg.rows, r + DEC_ROWS), 0});
+        const int2* bd = bands.data() + sg.band;
+        auto row_lo = [&](int r) {
+            int lo = 1 << 30;
+            for (int k = 0; k < 3; ++k)
+                if (bd[r * 3 + k].y > 0) lo = std::min(lo, bd[r * 3 + k].x);
+            return lo;
+        };
+        auto row_hi = [&](int r) {
+            int hi = 0;
+            for (int k = 0; k < 3; ++k)
+                if (bd[r * 3 + k].y > 0) hi = std::max(hi, bd[r * 3 + k].x + bd[r * 3 + k].y);
+            return hi;
+        };
+        int r = 0;
+        while (r < sg.rows) {
+            int lo = row_lo(r), hi = row_hi(r), e = r + 1;
+            while (e < sg.rows && e - r < DEC_ROWS) {
+                int nhi = std::max(hi, row_hi(e));
+                long long bytes = 4LL * ((long long)(nhi - lo) * (sg.n + 1) + (long long)(e + 1 - r) * (3 * sg.bmax + 1)) +
+                                  24LL * (e + 1 - r);
+                if (bytes > DEC_STAGE) break;
+                hi = nhi;
+                ++e;
+            }
+            m->chunks_h.push_back(DecChunk{sgi, r, e, lo, hi, {0, 0, 0}});
+            m->seg_stage_f32[sgi] = std::max<long long>(m->seg_stage_f32[sgi], (long long)dec_lds(hi - lo, e - r, sg.n, sg.bmax, 4, 0, 1).ring);
+            m->seg_stage_f64[sgi] = std::max<long long>(m->seg_stage_f64[sgi], (long long)dec_lds(hi - lo, e - r, sg.n, sg.bmax, 8, 0, 1).ring);
+            r = e;
+        }
         m->seg_chunk1[sgi] = (int)m->chunks_h.size();
     }
 
@@ -401,15 +442,27 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     std::vector<ConChunk> cch;
     std::vector<double> CAflat;
     m->CA_off.resize(n_sub);
+    m->ca_ld = (m->n_C + 7) / 8 * 8;
+    int cpart = 0;
     for (int sd = 0; sd < n_sub; ++sd) {
+        const int Ng = m->N_ga[sd];
         m->CA_off[sd] = (long long)CAflat.size();
         m->rsegs_h[sd].ca = m->CA_off[sd];
-        m->rsegs_h[sd].n_rows_ga = m->N_ga[sd];
-        CAflat.insert(CAflat.end(), CA[sd].begin(), CA[sd].end());
-        if (m->N_ga[sd] == 0) continue;
-        for (int j = 0; j < m->n_C; j += CON_ROWS) cch.push_back(ConChunk{sd, j, std::min(m->n_C, j + CON_ROWS), 0});
+        m->rsegs_h[sd].n_rows_ga = Ng;
+        // (C A_i)^T, rows of length ca_ld so that a work item's 8 multipliers are contiguous
+        std::vector<double> t((size_t)Ng * m->ca_ld, 0.0);
+        for (int j = 0; j < m->n_C; ++j)
+            for (int o = 0; o < Ng; ++o) t[(size_t)o * m->ca_ld + j] = CA[sd][(size_t)j * Ng + o];
+        CAflat.insert(CAflat.end(), t.begin(), t.end());
+        m->rsegs_h[sd].cpart0 = cpart;
+        if (Ng > 0 && m->n_C > 0)
+            for (int o = 0; o < Ng; o += CON_OROWS, ++cpart)
+                for (int j = 0; j < m->n_C; j += CON_ROWS)
+                    cch.push_back(ConChunk{sd, j, std::min(m->n_C, j + CON_ROWS), o, std::min(Ng, o + CON_OROWS), cpart, {0, 0}});
+        m->rsegs_h[sd].cpart1 = cpart;
     }
     m->n_cchunks = (int)cch.size();
+    m->n_cparts = cpart;
 
     // ---- DD FOM residual tables ----
     std::vector<int> fsrc;
