@@ -168,7 +168,9 @@ struct ddrom_workspace {
     int* counter_h = nullptr;       // pinned host mirror
     // private stream (default priority) on which solves run and graphs are captured
     hipStream_t stream = nullptr;
+    hipStream_t stream2 = nullptr;  // interface decoders + constraint run here, forked from `stream`
     hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_ga = nullptr, ev_con = nullptr;
     // cached graph of solver rounds
     hipGraphExec_t graph = nullptr;
     std::string graph_key;

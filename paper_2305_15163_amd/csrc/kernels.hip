@@ -162,35 +162,42 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     __syncthreads();
 
     T* o = out + ((size_t)sg.out + (size_t)ch.r0 * (1 + NL)) * Bp + b;
-    int hn = -1;     // next hidden unit (relative to h_lo) to compute
-    int hslot = 0;   // its ring slot
+    // Units [vlo, vhi) (relative to h_lo) are valid in the ring; vhi - vlo <= DEC_RING.  Rows
+    // ascend, so windows mostly slide right, but near the first rows of a decoder a clipped
+    // band can start below the previous row's window: missing units are then computed on
+    // whichever side they lie.
+    int vlo = 0, vhi = 0;
+    auto hidden = [&](int h) {
+        const T* w = sW1 + (size_t)h * NL;
+        T z = sB1[h];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) z += w[k] * xl[k];
+        T* rs = ring + (size_t)(h % DEC_RING) * 64 * RK + lane;
+        if (ACT == DDROM_ACT_SIGMOID) {
+            rs[0] = sig_fast<T>(z);
+        } else if (ACT == DDROM_ACT_SWISH) {
+            const T sg_ = sig_fast<T>(z);
+            rs[0] = z * sg_;
+            rs[64] = sg_ + z * sg_ * ((T)1 - sg_);
+        } else {
+            rs[0] = z;
+        }
+    };
     for (int r = 0; r < nrows; ++r) {
         const int2 q0 = sBd[r * 3 + 0], q1 = sBd[r * 3 + 1], q2 = sBd[r * 3 + 2];
         int lo = 0x7fffffff, hi = -1;
         if (q0.y > 0) { lo = min(lo, q0.x); hi = max(hi, q0.x + q0.y); }
         if (q1.y > 0) { lo = min(lo, q1.x); hi = max(hi, q1.x + q1.y); }
         if (q2.y > 0) { lo = min(lo, q2.x); hi = max(hi, q2.x + q2.y); }
-        if (hn < lo) {
-            hn = lo;
-            hslot = lo % DEC_RING;
+        if (lo >= vhi || hi <= vlo) {      // disjoint from the valid range: start afresh
+            vlo = lo;
+            vhi = lo;
         }
-        for (; hn < hi; ++hn) {
-            const T* w = sW1 + (size_t)hn * NL;
-            T z = sB1[hn];
-#pragma unroll
-            for (int k = 0; k < NL; ++k) z += w[k] * xl[k];
-            T* rs = ring + (size_t)hslot * 64 * RK + lane;
-            if (ACT == DDROM_ACT_SIGMOID) {
-                rs[0] = sig_fast<T>(z);
-            } else if (ACT == DDROM_ACT_SWISH) {
-                const T sg_ = sig_fast<T>(z);
-                rs[0] = z * sg_;
-                rs[64] = sg_ + z * sg_ * ((T)1 - sg_);
-            } else {
-                rs[0] = z;
-            }
-            hslot = hslot + 1 == DEC_RING ? 0 : hslot + 1;
-        }
+        for (int h = lo; h < vlo; ++h) hidden(h);
+        vlo = min(vlo, lo);
+        for (int h = vhi; h < hi; ++h) hidden(h);
+        vhi = max(vhi, hi);
+        vlo = max(vlo, vhi - DEC_RING);
         T acc = sXR[r];
         T J[NL];
 #pragma unroll
@@ -273,6 +280,78 @@ __global__ void k_bc(const double* __restrict__ xy, const int* __restrict__ fiel
 // entries from the decoder output (boundary slots read an all-zero block and take their
 // value from the per-solve Dirichlet buffer), so all loads of a node are in flight together;
 // the uniform source kind then selects which Jacobian columns each slot feeds.
+template <typename T, int NO>
+struct NodeLoads {
+    int kind[N_SLOTS];
+    double v[N_SLOTS];
+    T jv[N_SLOTS][NO];
+};
+
+template <typename T, int NO, int NG>
+__device__ __forceinline__ void load_node(const int* __restrict__ code, const T* dom, const T* dga, const T* dz,
+                                          const double* bcb, int Bp, NodeLoads<T, NO>& L) {
+#pragma unroll
+    for (int t = 0; t < N_SLOTS; ++t) {
+        const int cd = code[t];
+        L.kind[t] = src_kind(cd);
+        const int idx = src_index(cd);
+        const T* base = L.kind[t] == SRC_OMEGA ? dom + (size_t)idx * (1 + NO) * Bp
+                      : (L.kind[t] == SRC_GAMMA ? dga + (size_t)idx * (1 + NG) * Bp : dz);
+        const double bv = bcb[(size_t)(L.kind[t] == SRC_BOUND ? idx : 0) * Bp];
+        const T dv = base[0];
+        L.v[t] = L.kind[t] == SRC_BOUND ? bv : (double)dv;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) L.jv[t][k] = base[(size_t)(1 + k) * Bp];
+    }
+}
+
+template <typename T, int NO, int NG>
+__device__ __forceinline__ void accumulate_node(const NodeLoads<T, NO>& L, double nu, double hx, double hy,
+                                                double* H, double* g, double& rr) {
+    constexpr int NN = NO + NG;
+    double ru, rv, cu[6], cv[6];
+    burgers_point(L.v, nu, hx, hy, ru, rv, cu, cv);
+    double zu[NN], zv[NN];
+#pragma unroll
+    for (int e = 0; e < NN; ++e) { zu[e] = 0.0; zv[e] = 0.0; }
+#pragma unroll
+    for (int t = 0; t < N_SLOTS; ++t) {
+        double a_u, a_v;
+        if (t < 5) { a_u = cu[t]; a_v = (t == S_UC) ? cv[5] : 0.0; }
+        else { a_v = cv[t - 5]; a_u = (t == S_VC) ? cu[5] : 0.0; }
+        // the kind is wave-uniform: scalar branches, all loads already issued
+        if (L.kind[t] == SRC_OMEGA) {
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                const double jk = (double)L.jv[t][k];
+                zu[k] += a_u * jk;
+                zv[k] += a_v * jk;
+            }
+        } else if (L.kind[t] == SRC_GAMMA) {
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                const double jk = (double)L.jv[t][k];
+                zu[NO + k] += a_u * jk;
+                zv[NO + k] += a_v * jk;
+            }
+        }
+    }
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+        g[i] += zu[i] * ru + zv[i] * rv;
+#pragma unroll
+        for (int j = i; j < NN; ++j) H[e++] += zu[i] * zu[j] + zv[i] * zv[j];
+    }
+    rr += ru * ru + rv * rv;
+}
+
+// One wave = a run of sampled nodes of one subdomain x 64 solves.  For each node the ten
+// stencil DoFs are gathered without branches: every slot reads a value and NO Jacobian
+// entries from the decoder output (boundary slots read an all-zero block and take their
+// value from the per-solve Dirichlet buffer), so all loads of a node are in flight together,
+// and the next node's loads are issued before the current node is accumulated.  The
+// uniform source kind then selects which Jacobian columns each slot feeds.
 template <typename T, int NO, int NG>
 __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchunks, int rbase,
                                                const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
@@ -298,55 +377,9 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
     for (int e = 0; e < NN; ++e) g[e] = 0.0;
     const int* gp = gather + rs.gather;
     for (int p = rc.p0; p < rc.p1; ++p) {
-        const int* code = gp + (size_t)p * N_SLOTS;
-        int kind[N_SLOTS];
-        double v[N_SLOTS];
-        T jv[N_SLOTS][NO];
-#pragma unroll
-        for (int t = 0; t < N_SLOTS; ++t) {
-            const int cd = code[t];
-            kind[t] = src_kind(cd);
-            const int idx = src_index(cd);
-            const T* base = kind[t] == SRC_OMEGA ? dom + (size_t)idx * (1 + NO) * Bp
-                          : (kind[t] == SRC_GAMMA ? dga + (size_t)idx * (1 + NG) * Bp : dz);
-            const double bv = bcb[(size_t)(kind[t] == SRC_BOUND ? idx : 0) * Bp];
-            const T dv = base[0];
-            v[t] = kind[t] == SRC_BOUND ? bv : (double)dv;
-#pragma unroll
-            for (int k = 0; k < NO; ++k) jv[t][k] = base[(size_t)(1 + k) * Bp];
-        }
-        double ru, rv, cu[6], cv[6];
-        burgers_point(v, nu, hx, hy, ru, rv, cu, cv);
-        double zu[NN], zv[NN];
-#pragma unroll
-        for (int e = 0; e < NN; ++e) { zu[e] = 0.0; zv[e] = 0.0; }
-#pragma unroll
-        for (int t = 0; t < N_SLOTS; ++t) {
-            double a_u, a_v;
-            if (t < 5) { a_u = cu[t]; a_v = (t == S_UC) ? cv[5] : 0.0; }
-            else { a_v = cv[t - 5]; a_u = (t == S_VC) ? cu[5] : 0.0; }
-            const bool om = kind[t] == SRC_OMEGA, ga = kind[t] == SRC_GAMMA;
-#pragma unroll
-            for (int k = 0; k < NO; ++k) {
-                const double jk = (double)jv[t][k];
-                zu[k] += om ? a_u * jk : 0.0;
-                zv[k] += om ? a_v * jk : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < NG; ++k) {
-                const double jk = (double)jv[t][k];
-                zu[NO + k] += ga ? a_u * jk : 0.0;
-                zv[NO + k] += ga ? a_v * jk : 0.0;
-            }
-        }
-        int e = 0;
-#pragma unroll
-        for (int i = 0; i < NN; ++i) {
-            g[i] += zu[i] * ru + zv[i] * rv;
-#pragma unroll
-            for (int j = i; j < NN; ++j) H[e++] += zu[i] * zu[j] + zv[i] * zv[j];
-        }
-        rr += ru * ru + rv * rv;
+        NodeLoads<T, NO> A;
+        load_node<T, NO, NG>(gp + (size_t)p * N_SLOTS, dom, dga, dz, bcb, Bp, A);
+        accumulate_node<T, NO, NG>(A, nu, hx, hy, H, g, rr);
     }
     double* pp = part + (size_t)rc.slot * estride * Bp + b;
 #pragma unroll
@@ -1121,26 +1154,39 @@ static ModelDevInts get_ints(const ddrom_model* m) {
     return g_ints[m];
 }
 
-// One evaluation of all active solves at their trial points (xt).
+// One evaluation of all active solves at their trial points (xt).  The interface decoders
+// and the constraint sums run on a second stream forked from `s` (they depend only on the
+// interface latents), overlapping the interior decoders and the residual kernel.
 static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const SolveState* st,
                           const double* xhat, hipStream_t s) {
     int rc;
-    // decoders: one launch per run of consecutive segments with the same latent size
-    const int nseg = 2 * m->n_sub;
-    for (int g0 = 0; g0 < nseg;) {
+    const int n = m->n_sub;
+    hipStream_t s2 = ws->stream2;
+    HIPCHECK(hipEventRecord(ws->ev_fork, s));
+    HIPCHECK(hipStreamWaitEvent(s2, ws->ev_fork, 0));
+    for (int g0 = n; g0 < 2 * n;) {
         int g1 = g0 + 1;
-        while (g1 < nseg && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
-        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, st, B, ws->dec_out, ws->Bp, s)))
-            return rc;
+        while (g1 < 2 * n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
+        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, st, B, ws->dec_out, ws->Bp, s2))) return rc;
         g0 = g1;
     }
-    for (int s0 = 0; s0 < m->n_sub;) {
+    HIPCHECK(hipEventRecord(ws->ev_ga, s2));
+    if ((rc = launch_con(m, prec, ws, st, B, s2))) return rc;
+    HIPCHECK(hipEventRecord(ws->ev_con, s2));
+    for (int g0 = 0; g0 < n;) {
+        int g1 = g0 + 1;
+        while (g1 < n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
+        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, st, B, ws->dec_out, ws->Bp, s))) return rc;
+        g0 = g1;
+    }
+    HIPCHECK(hipStreamWaitEvent(s, ws->ev_ga, 0));
+    for (int s0 = 0; s0 < n;) {
         int s1 = s0 + 1;
-        while (s1 < m->n_sub && m->n_om[s1] == m->n_om[s0] && m->n_ga[s1] == m->n_ga[s0]) ++s1;
+        while (s1 < n && m->n_om[s1] == m->n_om[s0] && m->n_ga[s1] == m->n_ga[s0]) ++s1;
         if ((rc = launch_res(m, prec, s0, s1, ws, st, B, s))) return rc;
         s0 = s1;
     }
-    if ((rc = launch_con(m, prec, ws, st, B, s))) return rc;
+    HIPCHECK(hipStreamWaitEvent(s, ws->ev_con, 0));
     return 0;
 }
 
@@ -1314,6 +1360,10 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
         return DDROM_ENOMEM;
     }
     if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&w->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_ga, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_con, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&w->t0) != hipSuccess || hipEventCreate(&w->t1) != hipSuccess) {
@@ -1337,7 +1387,11 @@ void ddrom_workspace_destroy(ddrom_workspace* w) {
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);
     if (w->t0) (void)hipEventDestroy(w->t0);
     if (w->t1) (void)hipEventDestroy(w->t1);
+    if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
+    if (w->ev_ga) (void)hipEventDestroy(w->ev_ga);
+    if (w->ev_con) (void)hipEventDestroy(w->ev_con);
     if (w->stream) (void)hipStreamDestroy(w->stream);
+    if (w->stream2) (void)hipStreamDestroy(w->stream2);
     delete w;
 }
 

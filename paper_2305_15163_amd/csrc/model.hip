@@ -12,7 +12,7 @@
 namespace ddrom {
 
 static constexpr int RING = 48;          // hidden-unit ring of the decode kernel (window bound)
-static constexpr int DEC_ROWS = 96;      // max output rows per decode work item
+static constexpr int DEC_ROWS = 48;      // max output rows per decode work item
 static constexpr int DEC_STAGE = 15360;  // bytes of FP32 weights staged in LDS per decode work item
 static constexpr int RES_NODES = 24;     // sampled nodes per residual work item
 static constexpr int CON_ROWS = 8;       // constraint rows per constraint work item
@@ -401,13 +401,28 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         };
         int r = 0;
         while (r < sg.rows) {
+            // The span is the union of the rows' windows (near the first rows a clipped band -1
+            // can start below the first row's lowest band).  The kernel's ring holds the units
+            // [vlo, vhi) with vhi - vlo <= RING; a row that would need a wider valid range starts
+            // a new work item.
             int lo = row_lo(r), hi = row_hi(r), e = r + 1;
+            int vlo = lo, vhi = hi;
             while (e < sg.rows && e - r < DEC_ROWS) {
-                int nhi = std::max(hi, row_hi(e));
-                long long bytes = 4LL * ((long long)(nhi - lo) * (sg.n + 1) + (long long)(e + 1 - r) * (3 * sg.bmax + 1)) +
+                const int rl = row_lo(e), rh = row_hi(e);
+                int nvlo = vlo, nvhi = vhi;
+                if (rl >= nvhi || rh <= nvlo) nvlo = nvhi = rl;
+                nvlo = std::min(nvlo, rl);
+                nvhi = std::max(nvhi, rh);
+                if (nvhi - rl > RING) break;
+                nvlo = std::max(nvlo, nvhi - RING);
+                int nlo = std::min(lo, rl), nhi = std::max(hi, rh);
+                long long bytes = 4LL * ((long long)(nhi - nlo) * (sg.n + 1) + (long long)(e + 1 - r) * (3 * sg.bmax + 1)) +
                                   24LL * (e + 1 - r);
                 if (bytes > DEC_STAGE) break;
+                lo = nlo;
                 hi = nhi;
+                vlo = nvlo;
+                vhi = nvhi;
                 ++e;
             }
             m->chunks_h.push_back(DecChunk{sgi, r, e, lo, hi, {0, 0, 0}});
