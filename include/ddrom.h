@@ -40,6 +40,7 @@ extern "C" {
 #define DDROM_STATUS_LINESEARCH_FAIL 2
 #define DDROM_STATUS_KKT_NOT_PD 3     /* Lemma 1 hypotheses fail: an H_i or the Schur complement is not positive definite */
 #define DDROM_STATUS_NONFINITE 4
+#define DDROM_STATUS_STALLED 5        /* Armijo failed with ||F|| <= stall_tol ||F_0||: the arithmetic's noise floor */
 
 #define DDROM_ACT_SIGMOID 0
 #define DDROM_ACT_SWISH 1
@@ -94,6 +95,8 @@ typedef struct {
     double armijo_c1;       /* accept alpha when phi(alpha) <= (1 - 2 c1 alpha) phi(0) */
     int max_backtracks;     /* halvings of alpha before LINESEARCH_FAIL */
     int precision;          /* DDROM_PREC_* */
+    double stall_tol;       /* 0 disables; else an Armijo failure with ||F|| <= stall_tol ||F_0|| stops the
+                               solve with DDROM_STATUS_STALLED (meant for the FP32-decoder mode) */
 } ddrom_opts;
 
 const char* ddrom_last_error(void);

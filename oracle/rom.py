@@ -32,7 +32,7 @@ from .autoencoder import Decoder, decode_jacobian, decode
 from .burgers import BurgersFOM, Grid
 from .ddmaps import DDMaps, build_dd, subdomain_residual_jac
 
-CONVERGED, MAX_ITER, LINESEARCH_FAIL, KKT_NOT_PD, NONFINITE = 0, 1, 2, 3, 4
+CONVERGED, MAX_ITER, LINESEARCH_FAIL, KKT_NOT_PD, NONFINITE, STALLED = 0, 1, 2, 3, 4, 5
 
 
 @dataclass
@@ -181,6 +181,7 @@ class SQPOptions:
     tol_rel: float = 0.0
     c1: float = 1e-4
     max_backtracks: int = 20
+    stall_tol: float = 0.0    # > 0: an Armijo failure with ||F|| <= stall_tol ||F_0|| stops with STALLED
 
 
 @dataclass
@@ -195,7 +196,7 @@ class SQPResult:
     history: list = field(default_factory=list)
 
 
-def sqp_step(model: ROMModel, mu, xhat, lam, opts: SQPOptions, ev: Evaluation | None = None):
+def sqp_step(model: ROMModel, mu, xhat, lam, opts: SQPOptions, ev: Evaluation | None = None, f0: float = np.inf):
     """One Lagrange-Gauss-Newton SQP iteration from (xhat, lambda): KKT step, then
     Armijo backtracking.  Returns (xhat+, lambda+, ev+, ||F+||, status, n_evals, alpha);
     status is -1 for an accepted step."""
@@ -216,6 +217,8 @@ def sqp_step(model: ROMModel, mu, xhat, lam, opts: SQPOptions, ev: Evaluation | 
             pass
         elif phi <= (1.0 - 2.0 * opts.c1 * alpha) * phi0:
             return xt, lt, evt, np.sqrt(2.0 * phi), -1, nb + 1, alpha
+        if np.sqrt(2.0 * phi0) <= opts.stall_tol * f0:
+            return xhat, lam, ev, np.sqrt(2.0 * phi0), STALLED, nb + 1, 0.0
         alpha *= 0.5
     return xhat, lam, ev, np.sqrt(2.0 * phi0), LINESEARCH_FAIL, opts.max_backtracks + 1, 0.0
 
@@ -235,7 +238,7 @@ def sqp_solve(model: ROMModel, mu, xhat0: np.ndarray | None = None, lam0: np.nda
     for k in range(opts.max_iter):
         if fn <= tol:
             return SQPResult(x, lam, CONVERGED, k, fn, f0, n_eval, hist)
-        x, lam, ev, fn, st, ne, _ = sqp_step(model, mu, x, lam, opts, ev)
+        x, lam, ev, fn, st, ne, _ = sqp_step(model, mu, x, lam, opts, ev, f0)
         n_eval += ne
         hist.append(fn)
         if st >= 0:

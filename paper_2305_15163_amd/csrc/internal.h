@@ -163,6 +163,8 @@ struct ddrom_workspace {
     double* step = nullptr;         // [Bp][n_D + n_C]
     double* Y = nullptr;            // KKT scratch [Bp][n_sub][NNmax][n_C + 1]
     double* mu = nullptr;           // [Bp][2]
+    double* RB = nullptr;           // per-solve reduced blocks [Bp][RS]
+    int rs = 0, RS = 0;             // per-subdomain block size, per-solve stride
     SolveState* st = nullptr;       // [Bp]
     int* counter = nullptr;         // active-solve counter (device)
     int* counter_h = nullptr;       // pinned host mirror

@@ -446,11 +446,95 @@ __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, co
 // ------------------------------------------------------------------------------------
 // Per-solve update: merit, Armijo, KKT (Schur complement on the block-arrow system)
 // ------------------------------------------------------------------------------------
+// ------------------------------------------------------------------------------------
+// Sum of the partial slots into one contiguous block per solve
+// ------------------------------------------------------------------------------------
+// Lanes are solves, so the partial sums are read coalesced; a 32-entry LDS tile is then
+// written out transposed, so that each solve's block [H packed | g | rr | E] per subdomain,
+// followed by c, is contiguous for the per-solve update wave.
+__global__ __launch_bounds__(64) void k_reduce(int n_sub, int n_C, int mmax, int estride, int rs, int RS, int Bp,
+                                               int B, const int* __restrict__ n_om, const int* __restrict__ n_ga,
+                                               const int* __restrict__ slot0, const int* __restrict__ cpart0,
+                                               int n_cparts, const double* __restrict__ gn_part,
+                                               const double* __restrict__ c_part, const double* __restrict__ E_part,
+                                               const SolveState* __restrict__ st, double* __restrict__ RB) {
+    __shared__ double tile[32][65];
+    const int sd = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int b0 = blockIdx.z * 64, b = b0 + lane;
+    if (__ballot(lane_live(st, b, B)) == 0) return;
+    int n_e, ne_gn = 0, ng = 0;
+    size_t dst0;
+    if (sd < n_sub) {
+        const int NN = n_om[sd] + n_ga[sd];
+        ne_gn = NN * (NN + 1) / 2 + NN + 1;
+        ng = n_ga[sd];
+        n_e = estride + n_C * mmax;
+        dst0 = (size_t)sd * rs;
+    } else {
+        n_e = n_C;
+        dst0 = (size_t)n_sub * rs;
+    }
+    const int e0 = blockIdx.y * 32;
+    if (e0 >= n_e) return;
+    const int cnt = min(32, n_e - e0);
+    // 32 independent accumulators; loads are unconditional (indices clamped into the buffer)
+    // and masked afterwards, so every load of a slot is in flight before any add waits
+    double acc[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+    if (sd < n_sub) {
+        if (e0 < estride) {
+            for (int sl = slot0[sd]; sl < slot0[sd + 1]; ++sl) {
+                const double* src = gn_part + (size_t)sl * estride * Bp + b;
+                double v[32];
+#pragma unroll
+                for (int j = 0; j < 32; ++j) v[j] = src[(size_t)min(e0 + j, estride - 1) * Bp];
+#pragma unroll
+                for (int j = 0; j < 32; ++j) acc[j] += (e0 + j < ne_gn) ? v[j] : 0.0;
+            }
+        }
+        if (e0 + 32 > estride) {
+            for (int p = cpart0[sd]; p < cpart0[sd + 1]; ++p) {
+                const double* src = E_part + (size_t)p * n_C * mmax * Bp + b;
+                double v[32];
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    const int q = min(max(e0 + j - estride, 0), n_C * mmax - 1);
+                    v[j] = src[(size_t)q * Bp];
+                }
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    const int q = e0 + j - estride;
+                    acc[j] += (q >= 0 && q < n_C * mmax && (q % mmax) < ng) ? v[j] : 0.0;
+                }
+            }
+        }
+    } else {
+        for (int p = 0; p < n_cparts; ++p) {
+            const double* src = c_part + (size_t)p * n_C * Bp + b;
+            double v[32];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) v[j] = src[(size_t)min(e0 + j, n_C - 1) * Bp];
+#pragma unroll
+            for (int j = 0; j < 32; ++j) acc[j] += (e0 + j < n_C) ? v[j] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) tile[j][lane] = acc[j];
+    __syncthreads();
+    for (int q = lane; q < 64 * 32; q += 64) {
+        const int sv = q >> 5, j = q & 31;
+        if (j < cnt) RB[(size_t)(b0 + sv) * RS + dst0 + e0 + j] = tile[j][sv];
+    }
+}
+
 struct UpdArgs {
     int n_sub, n_C, n_D, mmax, estride, Bp, B;
     int lam_given;
     int max_iter, max_bt;
-    double tol_abs, tol_rel, c1;
+    int NNmax, qr_rows;
+    double tol_abs, tol_rel, c1, stall_tol;
     const int* n_om;       // [n_sub]
     const int* n_ga;
     const int* xoff;
@@ -460,6 +544,8 @@ struct UpdArgs {
     const double* gn_part;
     const double* c_part;
     const double* E_part;
+    const double* RB;      // per-solve reduced blocks [Bp][RS]
+    int rs, RS;
     double* x;
     double* xt;
     double* lam;
@@ -475,240 +561,178 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// In-place Cholesky (lower) of an n x n matrix in LDS, leading dimension ld.  Returns
-// false if a pivot is not positive and finite.
-__device__ bool chol_lds(double* A, int n, int ld, int lane) {
-    __shared__ int bad;
-    if (lane == 0) bad = 0;
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (lane == 0) {
-            const double d = A[k * ld + k];
-            if (!(d > 0.0) || !isfinite(d)) bad = 1;
-            A[k * ld + k] = sqrt(fabs(d) + (d > 0.0 ? 0.0 : 1.0));
-        }
-        __syncthreads();
-        const double piv = A[k * ld + k];
-        for (int i = k + 1 + lane; i < n; i += 64) A[i * ld + k] /= piv;
-        __syncthreads();
-        const int m = n - k - 1;
-        for (int e = lane; e < m * m; e += 64) {
-            const int i = k + 1 + e / m, j = k + 1 + e % m;
-            if (j <= i) A[i * ld + j] -= A[i * ld + k] * A[j * ld + k];
-        }
-        __syncthreads();
-    }
-    const bool ok = bad == 0;
-    __syncthreads();
-    return ok;
+// ------------------------------------------------------------------------------------
+// Per-solve update (one workgroup of nw waves per solve)
+// ------------------------------------------------------------------------------------
+// Block-arrow KKT (eq. sqp_system) by the Schur complement.  E_i = [0, Ehat_i] has only the m
+// interface columns, so only W_i = H_i^{-1} [0; I_m] (m right-hand sides) and t_i = H_i^{-1} rho_i
+// are needed:  S = sum_i Ehat_i (W_i)_Gamma Ehat_i^T,  S s_lambda = c - sum_i Ehat_i (t_i)_Gamma,
+// s_i = -(t_i + W_i Ehat_i^T s_lambda).  The waves of the workgroup factor different subdomains
+// concurrently (Cholesky of H_i padded to the largest block size, so all waves run the same
+// barriers); S is accumulated in a fixed order and solved by elimination with partial pivoting.
+struct UpdLds {
+    int c, lam, sl, S, work, wt, red, total;   // offsets in doubles
+};
+__host__ __device__ inline UpdLds upd_lds(int nC, int nw, int NNM, int mg, int nh_pad, int qr_rows) {
+    UpdLds L;
+    L.c = 0;
+    L.lam = L.c + 64;
+    L.sl = L.lam + 64;
+    L.S = L.sl + 64;
+    L.work = L.S + nC * (nC + 1);
+    const int per_sd = nw * (nh_pad + 2 * nC * (mg + 1));
+    const int qr = qr_rows * (nC + 1);
+    L.wt = L.work + (per_sd > qr ? per_sd : qr);
+    L.red = L.wt + nw * NNM * (mg + 1);
+    L.total = L.red + 32;
+    return L;
 }
 
-// Solve L L^T y = y for one right-hand side held in y[0..n) (LDS, stride 1), L in A.
-__device__ void chol_solve_lane(const double* A, int n, int ld, double* y) {
-    for (int i = 0; i < n; ++i) {
-        double s = y[i];
-        for (int k = 0; k < i; ++k) s -= A[i * ld + k] * y[k];
-        y[i] = s / A[i * ld + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-        double s = y[i];
-        for (int k = i + 1; k < n; ++k) s -= A[k * ld + i] * y[k];
-        y[i] = s / A[i * ld + i];
-    }
+__device__ __forceinline__ int packed_idx(int i, int j, int n) {   // i <= j, upper triangle row-major
+    return i * n - i * (i - 1) / 2 + (j - i);
 }
 
-// Gaussian elimination with partial pivoting on the augmented n x (n+1) system in LDS
-// (leading dimension ld); on success the solution is left in rhs_out[0..n).  Returns false
-// on a zero or non-finite pivot.
-__device__ bool lu_solve_lds(double* A, int n, int ld, int lane, double* rhs_out) {
-    __shared__ int piv_row;
-    __shared__ int bad_lu;
-    if (lane == 0) bad_lu = 0;
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        // pivot search (wave reduction on |A[i][k]|, ties to the lower row)
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + lane; i < n; i += 64) {
-            const double v = fabs(A[i * ld + k]);
-            if (v > best) { best = v; bi = i; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (lane == 0) {
-            piv_row = bi;
-            if (!(best > 0.0) || !isfinite(best)) bad_lu = 1;
-        }
-        __syncthreads();
-        const int pr = piv_row;
-        if (pr != k)
-            for (int j = lane; j <= n; j += 64) {
-                const double t = A[k * ld + j];
-                A[k * ld + j] = A[pr * ld + j];
-                A[pr * ld + j] = t;
-            }
-        __syncthreads();
-        const double pv = A[k * ld + k];
-        const int m = n - k - 1;
-        if (pv != 0.0)
-            for (int e = lane; e < m * (m + 1); e += 64) {
-                const int i = k + 1 + e / (m + 1), j = k + 1 + e % (m + 1);
-                A[i * ld + j] -= A[i * ld + k] / pv * A[k * ld + j];
-            }
-        __syncthreads();
-    }
-    const bool ok = bad_lu == 0;
-    if (ok && lane == 0) {
-        for (int i = n - 1; i >= 0; --i) {
-            double s = A[i * ld + n];
-            for (int k = i + 1; k < n; ++k) s -= A[i * ld + k] * rhs_out[k];
-            rhs_out[i] = s / A[i * ld + i];
-        }
-    }
-    __syncthreads();
-    return ok;
-}
-
-__global__ __launch_bounds__(64) void k_update(UpdArgs a) {
+__global__ void k_update(UpdArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* sm = reinterpret_cast<double*>(smem_raw);
+    __shared__ int flag_bad, piv_row;
     const int b = blockIdx.x;
-    const int lane = threadIdx.x;
     if (b >= a.B) return;
     SolveState S = a.st[b];
     if (S.phase == PH_DONE) return;
-    const int Bp = a.Bp, nC = a.n_C, nD = a.n_D;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nth = blockDim.x, nw = nth >> 6;
+    const int nC = a.n_C, nD = a.n_D, NNM = a.NNmax, mg = a.mmax, nhp = NNM * (NNM + 1) / 2;
+    const UpdLds L = upd_lds(nC, nw, NNM, mg, nhp, a.qr_rows);
+    double* c_s = sm + L.c;
+    double* lam_s = sm + L.lam;
+    double* sl_s = sm + L.sl;
+    double* Sm = sm + L.S;
+    double* work = sm + L.work;
+    double* Wt = sm + L.wt + (size_t)wave * NNM * (mg + 1);
+    double* red = sm + L.red;
+    const double* rb = a.RB + (size_t)b * a.RS;
+    const int ld = nC + 1;
 
-    __shared__ double c_s[KKT_NC];
-    __shared__ double lam_s[KKT_NC];
-    __shared__ double Sm[KKT_NC * (KKT_NC + 1)];      // Schur complement | q, or the least-squares system
-    __shared__ double Hs[KKT_NN * KKT_NN];
-    __shared__ double Ys[(KKT_NC + 1) * KKT_NN];     // one right-hand side per lane
-    __shared__ double Es[KKT_NC * KKT_MG];           // E_i^Gamma of the current subdomain
-    __shared__ double rho_s[KKT_NN];
-    __shared__ int flag;
-
-    // c = sum over all constraint partial slots
-    for (int j = lane; j < nC; j += 64) {
-        double s = 0.0;
-        for (int p = 0; p < a.n_cparts; ++p) s += a.c_part[((size_t)p * nC + j) * Bp + b];
-        c_s[j] = s;
+    for (int j = tid; j < nC; j += nth) {
+        c_s[j] = rb[(size_t)a.n_sub * a.rs + j];
+        lam_s[j] = a.lamt[(size_t)b * nC + j];
     }
-    for (int j = lane; j < nC; j += 64) lam_s[j] = a.lamt[(size_t)b * nC + j];
-
-    // E_i^Gamma (n_C x n_i^Gamma) of subdomain sd into Es (sum over its partial slots)
-    auto load_E = [&](int sd) {
-        const int ng = a.n_ga[sd];
-        __syncthreads();
-        for (int e = lane; e < nC * ng; e += 64) {
-            const int j = e / ng, k = e % ng;
-            double s = 0.0;
-            for (int p = a.cpart0[sd]; p < a.cpart0[sd + 1]; ++p) s += a.E_part[(((size_t)p * nC + j) * a.mmax + k) * Bp + b];
-            Es[j * KKT_MG + k] = s;
-        }
-        __syncthreads();
-    };
-    auto g_at = [&](int sd, int e) {
-        const int NN = a.n_om[sd] + a.n_ga[sd];
-        const int off = NN * (NN + 1) / 2 + e;
-        double s = 0.0;
-        for (int sl = a.slot0[sd]; sl < a.slot0[sd + 1]; ++sl) s += a.gn_part[((size_t)sl * a.estride + off) * Bp + b];
-        return s;
-    };
+    if (tid == 0) flag_bad = 0;
     __syncthreads();
 
-    // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i || ----
+    auto Eg = [&](int sd, int j, int k) { return rb[(size_t)sd * a.rs + a.estride + j * mg + k]; };
+    auto gv = [&](int sd, int e) {
+        const int NN = a.n_om[sd] + a.n_ga[sd];
+        return rb[(size_t)sd * a.rs + NN * (NN + 1) / 2 + e];
+    };
+
+    // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i || (wave 0) ----
     if (S.phase == PH_INIT && !a.lam_given && nC > 0) {
         int R = 0;
         for (int sd = 0; sd < a.n_sub; ++sd) R += a.n_ga[sd];
-        const int ld = nC + 1;
-        if (R <= KKT_NC) {
-            // Householder QR of M = [(E_i^Gamma)^T | -g_i^Gamma] stacked over subdomains
-            int r0 = 0;
-            for (int sd = 0; sd < a.n_sub; ++sd) {
-                const int m = a.n_ga[sd], no = a.n_om[sd];
-                load_E(sd);
-                for (int e = lane; e < m * ld; e += 64) {
-                    const int k = e / ld, j = e % ld;
-                    Sm[(r0 + k) * ld + j] = j < nC ? Es[j * KKT_MG + k] : -g_at(sd, no + k);
+        double* M = work;
+        if (R <= a.qr_rows) {
+            if (wave == 0) {
+                int r0 = 0;
+                for (int sd = 0; sd < a.n_sub; ++sd) {
+                    const int m = a.n_ga[sd], no = a.n_om[sd];
+                    for (int e = lane; e < m * ld; e += 64) {
+                        const int k = e / ld, j = e % ld;
+                        M[(r0 + k) * ld + j] = j < nC ? Eg(sd, j, k) : -gv(sd, no + k);
+                    }
+                    r0 += m;
                 }
-                r0 += m;
             }
             __syncthreads();
             for (int k = 0; k < nC && k < R; ++k) {
-                double nrm2 = 0.0;
-                for (int r = k + lane; r < R; r += 64) nrm2 += Sm[r * ld + k] * Sm[r * ld + k];
-                nrm2 = wave_sum(nrm2);
-                const double akk = Sm[k * ld + k];
-                const double alpha = akk > 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
-                const double v0 = akk - alpha;
-                const double vn2 = nrm2 - akk * akk + v0 * v0;
+                double nrm2 = 0.0, akk = 0.0, alpha = 0.0, v0 = 0.0, vn2 = 0.0;
+                if (wave == 0) {
+                    for (int r = k + lane; r < R; r += 64) nrm2 += M[r * ld + k] * M[r * ld + k];
+                    nrm2 = wave_sum(nrm2);
+                    akk = M[k * ld + k];
+                    alpha = akk > 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
+                    v0 = akk - alpha;
+                    vn2 = nrm2 - akk * akk + v0 * v0;
+                }
                 __syncthreads();
-                if (vn2 > 0.0) {
+                if (wave == 0 && vn2 > 0.0) {
                     for (int col = k + 1 + lane; col < ld; col += 64) {
-                        double dot = v0 * Sm[k * ld + col];
-                        for (int r = k + 1; r < R; ++r) dot += Sm[r * ld + k] * Sm[r * ld + col];
+                        double dot = v0 * M[k * ld + col];
+                        for (int r = k + 1; r < R; ++r) dot += M[r * ld + k] * M[r * ld + col];
                         const double f = 2.0 * dot / vn2;
-                        Sm[k * ld + col] -= f * v0;
-                        for (int r = k + 1; r < R; ++r) Sm[r * ld + col] -= f * Sm[r * ld + k];
+                        M[k * ld + col] -= f * v0;
+                        for (int r = k + 1; r < R; ++r) M[r * ld + col] -= f * M[r * ld + k];
                     }
                 }
                 __syncthreads();
-                if (lane == 0) Sm[k * ld + k] = vn2 > 0.0 ? alpha : akk;
+                if (tid == 0) M[k * ld + k] = vn2 > 0.0 ? alpha : akk;
                 __syncthreads();
             }
-            if (lane == 0) {
+            if (tid == 0) {
                 for (int i = nC - 1; i >= 0; --i) {
-                    double s = Sm[i * ld + nC];
-                    for (int k = i + 1; k < nC; ++k) s -= Sm[i * ld + k] * lam_s[k];
-                    lam_s[i] = s / Sm[i * ld + i];
+                    double s = M[i * ld + nC];
+                    for (int k = i + 1; k < nC; ++k) s -= M[i * ld + k] * lam_s[k];
+                    lam_s[i] = s / M[i * ld + i];
                 }
             }
         } else {
-            // normal equations (sum_i E_i E_i^T) lambda = -sum_i E_i g_i^Gamma
-            for (int e = lane; e < nC * ld; e += 64) Sm[e] = 0.0;
-            for (int sd = 0; sd < a.n_sub; ++sd) {
-                const int m = a.n_ga[sd], no = a.n_om[sd];
-                load_E(sd);
-                if (lane < m) rho_s[lane] = g_at(sd, no + lane);
-                __syncthreads();
-                for (int e = lane; e < nC * ld; e += 64) {
-                    const int i = e / ld, j = e % ld;
-                    double s = 0.0;
-                    for (int k = 0; k < m; ++k) s += Es[i * KKT_MG + k] * (j < nC ? Es[j * KKT_MG + k] : -rho_s[k]);
-                    Sm[e] += s;
-                }
+            // normal equations (sum_i E_i E_i^T) lambda = -sum_i E_i g_i^Gamma, Cholesky by thread 0
+            for (int e = tid; e < nC * ld; e += nth) {
+                const int i = e / ld, j = e % ld;
+                double s = 0.0;
+                for (int sd = 0; sd < a.n_sub; ++sd)
+                    for (int k = 0; k < a.n_ga[sd]; ++k) s += Eg(sd, i, k) * (j < nC ? Eg(sd, j, k) : -gv(sd, a.n_om[sd] + k));
+                M[e] = s;
             }
             __syncthreads();
-            chol_lds(Sm, nC, ld, lane);
-            if (lane == 0) {
-                double* y = Ys;
-                for (int i = 0; i < nC; ++i) y[i] = Sm[i * ld + nC];
-                chol_solve_lane(Sm, nC, ld, y);
-                for (int i = 0; i < nC; ++i) lam_s[i] = y[i];
+            if (tid == 0) {
+                for (int k = 0; k < nC; ++k) {
+                    const double d = M[k * ld + k];
+                    const double l = sqrt(d > 0.0 ? d : 1.0);
+                    M[k * ld + k] = l;
+                    for (int i = k + 1; i < nC; ++i) M[i * ld + k] /= l;
+                    for (int i = k + 1; i < nC; ++i)
+                        for (int j = k + 1; j <= i; ++j) M[i * ld + j] -= M[i * ld + k] * M[j * ld + k];
+                }
+                for (int i = 0; i < nC; ++i) {
+                    double s = M[i * ld + nC];
+                    for (int k = 0; k < i; ++k) s -= M[i * ld + k] * lam_s[k];
+                    lam_s[i] = s / M[i * ld + i];
+                }
+                for (int i = nC - 1; i >= 0; --i) {
+                    double s = lam_s[i];
+                    for (int k = i + 1; k < nC; ++k) s -= M[k * ld + i] * lam_s[k];
+                    lam_s[i] = s / M[i * ld + i];
+                }
             }
         }
         __syncthreads();
     }
 
     // ---- merit at the trial point: phi = 0.5 (sum_i ||rho_i||^2 + ||c||^2) ----
-    double acc = 0.0;
-    for (int sd = 0; sd < a.n_sub; ++sd) {
-        const int no = a.n_om[sd], NN = no + a.n_ga[sd];
-        load_E(sd);
-        for (int e = lane; e < NN; e += 64) {
-            double r = g_at(sd, e);
-            if (e >= no)
-                for (int j = 0; j < nC; ++j) r += Es[j * KKT_MG + (e - no)] * lam_s[j];
-            acc += r * r;
+    {
+        double acc = 0.0;
+        for (int sd = wave; sd < a.n_sub; sd += nw) {
+            const int no = a.n_om[sd], NN = no + a.n_ga[sd];
+            for (int e = lane; e < NN; e += 64) {
+                double r = gv(sd, e);
+                if (e >= no)
+                    for (int j = 0; j < nC; ++j) r += Eg(sd, j, e - no) * lam_s[j];
+                acc += r * r;
+            }
         }
+        if (wave == 0)
+            for (int j = lane; j < nC; j += 64) acc += c_s[j] * c_s[j];
+        acc = wave_sum(acc);
+        if (lane == 0) red[wave] = acc;
+        __syncthreads();
     }
-    for (int j = lane; j < nC; j += 64) acc += c_s[j] * c_s[j];
-    const double phi_t = 0.5 * wave_sum(acc);
+    double phi_t = 0.0;
+    for (int w = 0; w < nw; ++w) phi_t += red[w];
+    phi_t *= 0.5;
     const double fn_t = sqrt(2.0 * phi_t);
 
-    // ---- decision ----
+    // ---- decision (every thread evaluates it identically) ----
     int action = 0;   // 0: compute step, 1: backtrack, 2: stop
     if (S.phase == PH_INIT) {
         S.f0 = fn_t;
@@ -718,13 +742,16 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
             S.status = DDROM_STATUS_NONFINITE;
             action = 2;
         }
-        for (int j = lane; j < nC; j += 64) {
+        for (int j = tid; j < nC; j += nth) {
             a.lam[(size_t)b * nC + j] = lam_s[j];
             a.lamt[(size_t)b * nC + j] = lam_s[j];
         }
     } else {
         const bool ok = isfinite(phi_t) && phi_t <= (1.0 - 2.0 * a.c1 * S.alpha) * S.phi0;
-        if (!ok) {
+        if (!ok && S.fn <= a.stall_tol * S.f0) {
+            S.status = DDROM_STATUS_STALLED;
+            action = 2;
+        } else if (!ok) {
             S.nbt += 1;
             if (S.nbt > a.max_bt) {
                 S.status = DDROM_STATUS_LINESEARCH_FAIL;
@@ -734,8 +761,8 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
                 action = 1;
             }
         } else {
-            for (int e = lane; e < nD; e += 64) a.x[(size_t)b * nD + e] = a.xt[(size_t)b * nD + e];
-            for (int j = lane; j < nC; j += 64) a.lam[(size_t)b * nC + j] = lam_s[j];
+            for (int e = tid; e < nD; e += nth) a.x[(size_t)b * nD + e] = a.xt[(size_t)b * nD + e];
+            for (int j = tid; j < nC; j += nth) a.lam[(size_t)b * nC + j] = lam_s[j];
             S.iters += 1;
             S.fn = fn_t;
         }
@@ -750,102 +777,209 @@ __global__ __launch_bounds__(64) void k_update(UpdArgs a) {
         }
     }
     if (action == 1) {
-        for (int e = lane; e < nD; e += 64)
+        for (int e = tid; e < nD; e += nth)
             a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + S.alpha * a.step[(size_t)b * (nD + nC) + e];
-        for (int j = lane; j < nC; j += 64)
+        for (int j = tid; j < nC; j += nth)
             a.lamt[(size_t)b * nC + j] = a.lam[(size_t)b * nC + j] + S.alpha * a.step[(size_t)b * (nD + nC) + nD + j];
-        if (lane == 0) {
+        if (tid == 0) {
             a.st[b] = S;
             atomicAdd(a.counter, 1);
         }
         return;
     }
     if (action == 2) {
-        if (lane == 0) {
+        if (tid == 0) {
             S.phase = PH_DONE;
             a.st[b] = S;
         }
         return;
     }
 
-    // ---- KKT step: H_i s_i + E_i^T s_l = -rho_i ; sum_i E_i s_i = -c (Schur complement) ----
-    const int ld = nC + 1;
-    for (int e = lane; e < nC * ld; e += 64) Sm[e] = 0.0;
-    if (lane == 0) flag = 0;
+    // ---- KKT step ----
+    for (int e = tid; e < nC * ld; e += nth) Sm[e] = 0.0;
+    const size_t ystride = (size_t)NNM * (mg + 1);
+    double* Yb = a.Y + (size_t)b * a.n_sub * ystride;
+    double* Hp = work + (size_t)wave * (nhp + 2 * nC * (mg + 1));   // packed Cholesky factor of this wave's H_i
+    double* Pw = Hp + nhp;                                           // [nC][m+1]: Ehat_i (W_i)_Gamma | Ehat_i (t_i)_Gamma
+    double* Ew = Pw + nC * (mg + 1);                                 // [nC][m]: Ehat_i
     __syncthreads();
-    double* Yb = a.Y + (size_t)b * a.n_sub * KKT_NN * ld;
-    for (int sd = 0; sd < a.n_sub; ++sd) {
-        const int no = a.n_om[sd], ng = a.n_ga[sd], NN = no + ng;
-        const int NH = NN * (NN + 1) / 2;
-        load_E(sd);
-        for (int e = lane; e < NH; e += 64) {
+    for (int pass = 0; pass * nw < a.n_sub; ++pass) {
+        const int sd = pass * nw + wave;
+        const bool act = sd < a.n_sub;
+        const int no = act ? a.n_om[sd] : 0, ng = act ? a.n_ga[sd] : 0, NN = no + ng;
+        // H_i packed (padded to NNM with identity), Ehat_i, rho_i
+        for (int e = lane; e < nhp; e += 64) {
             int i = 0, rem = e;
-            while (rem >= NN - i) { rem -= NN - i; ++i; }
+            while (rem >= NNM - i) { rem -= NNM - i; ++i; }
             const int j = i + rem;
-            double s = 0.0;
-            for (int sl = a.slot0[sd]; sl < a.slot0[sd + 1]; ++sl) s += a.gn_part[((size_t)sl * a.estride + e) * Bp + b];
-            Hs[i * KKT_NN + j] = s;
-            Hs[j * KKT_NN + i] = s;
+            double v;
+            if (act && i < NN && j < NN) v = rb[(size_t)sd * a.rs + packed_idx(i, j, NN)];
+            else v = (i == j) ? 1.0 : 0.0;
+            Hp[e] = v;
         }
-        for (int e = lane; e < NN; e += 64) {
-            double r = g_at(sd, e);
-            if (e >= no)
-                for (int j = 0; j < nC; ++j) r += Es[j * KKT_MG + (e - no)] * lam_s[j];
-            rho_s[e] = r;
+        for (int e = lane; e < nC * mg; e += 64) {
+            const int j = e / mg, k = e % mg;
+            Ew[e] = (act && k < ng) ? Eg(sd, j, k) : 0.0;
         }
         __syncthreads();
-        if (!chol_lds(Hs, NN, KKT_NN, lane)) {
-            if (lane == 0) flag = 1;
+        // right-hand sides in Wt: column l < m -> e_{no+l}; column m -> rho_i
+        for (int e = lane; e < NNM * (mg + 1); e += 64) {
+            const int k = e / (mg + 1), l = e % (mg + 1);
+            double v = 0.0;
+            if (act && k < NN) {
+                if (l < mg) v = (l < ng && k == no + l) ? 1.0 : 0.0;
+                else {
+                    v = gv(sd, k);
+                    if (k >= no)
+                        for (int j = 0; j < nC; ++j) v += Ew[j * mg + (k - no)] * lam_s[j];
+                }
+            }
+            Wt[e] = v;
         }
-        // right-hand sides: lane j < nC -> E_i^T e_j ; lane nC -> rho_i
-        if (lane <= nC) {
-            double* y = Ys + lane * KKT_NN;
-            for (int k = 0; k < NN; ++k) y[k] = 0.0;
-            if (lane < nC)
-                for (int k = 0; k < ng; ++k) y[no + k] = Es[lane * KKT_MG + k];
-            else
-                for (int k = 0; k < NN; ++k) y[k] = rho_s[k];
-            chol_solve_lane(Hs, NN, KKT_NN, y);
-            for (int k = 0; k < NN; ++k) Yb[((size_t)sd * KKT_NN + k) * ld + lane] = y[k];
-            // Sm[:, lane] += E_i y
-            for (int r = 0; r < nC; ++r) {
-                double s = 0.0;
-                for (int k = 0; k < ng; ++k) s += Es[r * KKT_MG + k] * y[no + k];
-                Sm[r * ld + lane] += s;
+        // Cholesky of the padded block, all waves in step (same NNM)
+        for (int k = 0; k < NNM; ++k) {
+            if (lane == 0) {
+                const int kk = packed_idx(k, k, NNM);
+                const double d = Hp[kk];
+                if (act && (!(d > 0.0) || !isfinite(d))) flag_bad = 1;
+                Hp[kk] = sqrt(d > 0.0 ? d : 1.0);
+            }
+            __syncthreads();
+            const double piv = Hp[packed_idx(k, k, NNM)];
+            for (int j = k + 1 + lane; j < NNM; j += 64) Hp[packed_idx(k, j, NNM)] /= piv;
+            __syncthreads();
+            const int m2 = NNM - k - 1;
+            for (int e = lane; e < m2 * m2; e += 64) {
+                const int i = k + 1 + e / m2, j = k + 1 + e % m2;
+                if (j >= i) Hp[packed_idx(i, j, NNM)] -= Hp[packed_idx(k, i, NNM)] * Hp[packed_idx(k, j, NNM)];
+            }
+            __syncthreads();
+        }
+        // (Hp now holds U with H = U^T U.)  Each lane l <= m solves its column.
+        if (lane <= mg) {
+            double* y = Wt + lane;   // column lane, stride mg+1
+            for (int i = 0; i < NNM; ++i) {
+                double s = y[i * (mg + 1)];
+                for (int k = 0; k < i; ++k) s -= Hp[packed_idx(k, i, NNM)] * y[k * (mg + 1)];
+                y[i * (mg + 1)] = s / Hp[packed_idx(i, i, NNM)];
+            }
+            for (int i = NNM - 1; i >= 0; --i) {
+                double s = y[i * (mg + 1)];
+                for (int k = i + 1; k < NNM; ++k) s -= Hp[packed_idx(i, k, NNM)] * y[k * (mg + 1)];
+                y[i * (mg + 1)] = s / Hp[packed_idx(i, i, NNM)];
             }
         }
         __syncthreads();
+        if (act)
+            for (int e = lane; e < NNM * (mg + 1); e += 64) Yb[(size_t)sd * ystride + e] = Wt[e];
+        // Pw = Ehat_i [ (W_i)_Gamma | (t_i)_Gamma ]
+        for (int e = lane; e < nC * (mg + 1); e += 64) {
+            const int j = e / (mg + 1), l = e % (mg + 1);
+            double s = 0.0;
+            if (act && (l < ng || l == mg))
+                for (int k = 0; k < ng; ++k) s += Ew[j * mg + k] * Wt[(no + k) * (mg + 1) + l];
+            Pw[e] = s;
+        }
+        __syncthreads();
+        // S += sum over this pass's subdomains (fixed order), q in column nC
+        const int nact = min(nw, a.n_sub - pass * nw);
+        for (int e = tid; e < nC * ld; e += nth) {
+            const int i = e / ld, j = e % ld;
+            double s = 0.0;
+            for (int w = 0; w < nact; ++w) {
+                const double* P = work + (size_t)w * (nhp + 2 * nC * (mg + 1)) + nhp;
+                const double* E = P + nC * (mg + 1);
+                if (j < nC)
+                    for (int l = 0; l < mg; ++l) s += P[i * (mg + 1) + l] * E[j * mg + l];
+                else
+                    s += P[i * (mg + 1) + mg];
+            }
+            Sm[e] += s;
+        }
+        __syncthreads();
     }
-    // S s_l = c - q
-    for (int j = lane; j < nC; j += 64) Sm[j * ld + nC] = c_s[j] - Sm[j * ld + nC];
+    for (int j = tid; j < nC; j += nth) Sm[j * ld + nC] = c_s[j] - Sm[j * ld + nC];
     __syncthreads();
-    // S is symmetric positive definite in exact arithmetic when the H_i are; it can be badly
-    // conditioned, so it is solved by elimination with partial pivoting (lam_s <- s_lambda).
-    const bool sok = nC == 0 || lu_solve_lds(Sm, nC, ld, lane, lam_s);
-    if (!sok || flag) {
-        if (lane == 0) {
+    // elimination with partial pivoting on [S | c - q]
+    for (int k = 0; k < nC; ++k) {
+        if (wave == 0) {
+            double best = -1.0;
+            int bi = k;
+            for (int i = k + lane; i < nC; i += 64) {
+                const double v = fabs(Sm[i * ld + k]);
+                if (v > best) { best = v; bi = i; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (lane == 0) {
+                piv_row = bi;
+                if (!(best > 0.0) || !isfinite(best)) flag_bad = 1;
+            }
+        }
+        __syncthreads();
+        const int pr = piv_row;
+        if (pr != k)
+            for (int j = tid; j <= nC; j += nth) {
+                const double t = Sm[k * ld + j];
+                Sm[k * ld + j] = Sm[pr * ld + j];
+                Sm[pr * ld + j] = t;
+            }
+        __syncthreads();
+        const double pv = Sm[k * ld + k];
+        const int m2 = nC - k - 1;
+        if (pv != 0.0)
+            for (int e = tid; e < m2 * (m2 + 1); e += nth) {
+                const int i = k + 1 + e / (m2 + 1), j = k + 1 + e % (m2 + 1);
+                Sm[i * ld + j] -= Sm[i * ld + k] / pv * Sm[k * ld + j];
+            }
+        __syncthreads();
+    }
+    if (flag_bad) {
+        if (tid == 0) {
             S.status = DDROM_STATUS_KKT_NOT_PD;
             S.phase = PH_DONE;
             a.st[b] = S;
         }
         return;
     }
+    if (tid == 0)
+        for (int i = nC - 1; i >= 0; --i) {
+            double s = Sm[i * ld + nC];
+            for (int k = i + 1; k < nC; ++k) s -= Sm[i * ld + k] * sl_s[k];
+            sl_s[i] = s / Sm[i * ld + i];
+        }
+    __syncthreads();
+    // s_i = -(t_i + W_i Ehat_i^T s_lambda)
     double* stp = a.step + (size_t)b * (nD + nC);
-    for (int j = lane; j < nC; j += 64) stp[nD + j] = lam_s[j];
-    for (int sd = 0; sd < a.n_sub; ++sd) {
-        const int NN = a.n_om[sd] + a.n_ga[sd];
+    for (int j = tid; j < nC; j += nth) stp[nD + j] = sl_s[j];
+    double* u_s = work + (size_t)wave * 64;   // this wave's Ehat_i^T s_lambda (the work area is free now)
+    for (int sd = wave; sd < a.n_sub; sd += nw) {
+        const int no = a.n_om[sd], ng = a.n_ga[sd], NN = no + ng;
+        const double* Y = Yb + (size_t)sd * ystride;
+        if (lane < ng) {
+            double u = 0.0;
+            for (int j = 0; j < nC; ++j) u += Eg(sd, j, lane) * sl_s[j];
+            u_s[lane] = u;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int k = lane; k < NN; k += 64) {
-            const double* yr = Yb + ((size_t)sd * KKT_NN + k) * ld;
-            double s = yr[nC];
-            for (int j = 0; j < nC; ++j) s += yr[j] * lam_s[j];
+            double s = Y[k * (mg + 1) + mg];
+            for (int l = 0; l < ng; ++l) s += Y[k * (mg + 1) + l] * u_s[l];
             stp[a.xoff[sd] + k] = -s;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
-    for (int e = lane; e < nD; e += 64) a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + stp[e];
-    for (int j = lane; j < nC; j += 64)
-        a.lamt[(size_t)b * nC + j] = a.lam[(size_t)b * nC + j] + stp[nD + j];
-    if (lane == 0) {
+    for (int e = tid; e < nD; e += nth) a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + stp[e];
+    for (int j = tid; j < nC; j += nth) a.lamt[(size_t)b * nC + j] = a.lam[(size_t)b * nC + j] + stp[nD + j];
+    if (tid == 0) {
         S.phi0 = phi_t;
         S.alpha = 1.0;
         S.nbt = 0;
@@ -1195,10 +1329,12 @@ static UpdArgs upd_args(const ddrom_model* m, ddrom_workspace* ws, int B, const 
     UpdArgs a;
     a.n_sub = m->n_sub; a.n_C = m->n_C; a.n_D = m->n_D; a.mmax = m->mmax; a.estride = m->estride; a.Bp = ws->Bp;
     a.B = B; a.lam_given = lam_given; a.max_iter = o->max_iter; a.max_bt = o->max_backtracks;
-    a.tol_abs = o->tol_abs; a.tol_rel = o->tol_rel; a.c1 = o->armijo_c1;
+    a.tol_abs = o->tol_abs; a.tol_rel = o->tol_rel; a.c1 = o->armijo_c1; a.stall_tol = o->stall_tol;
     a.n_om = di.n_om; a.n_ga = di.n_ga; a.xoff = di.xoff; a.slot0 = di.slot0;
     a.cpart0 = di.cpart0; a.n_cparts = m->n_cparts;
     a.gn_part = ws->gn_part; a.c_part = ws->c_part; a.E_part = ws->E_part;
+    a.RB = ws->RB; a.rs = ws->rs; a.RS = ws->RS;
+    a.NNmax = m->NNmax; a.qr_rows = 64;
     a.x = ws->x; a.xt = ws->xt; a.lam = ws->lam; a.lamt = ws->lamt; a.step = ws->step; a.Y = ws->Y;
     a.st = ws->st; a.counter = ws->counter;
     return a;
@@ -1208,7 +1344,15 @@ static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int
     int rc;
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, ws->counter);
     if ((rc = evaluate_round(m, ws, prec, B, ws->st, ws->xt, s))) return rc;
-    hipLaunchKernelGGL(k_update, dim3(B), dim3(64), 0, s, ua);
+    const int n_etiles = (m->estride + m->n_C * std::max(1, m->mmax) + 31) / 32;
+    hipLaunchKernelGGL(k_reduce, dim3(m->n_sub + 1, n_etiles, ws->Bp / 64), dim3(64), 0, s, m->n_sub, m->n_C, std::max(1, m->mmax),
+                       m->estride, ws->rs, ws->RS, ws->Bp, B, ua.n_om, ua.n_ga, ua.slot0, ua.cpart0, m->n_cparts,
+                       ws->gn_part, ws->c_part, ws->E_part, ws->st, ws->RB);
+    int nw = std::max(1, std::min(16, m->n_sub));
+    const int nhp = m->NNmax * (m->NNmax + 1) / 2;
+    while (nw > 1 && upd_lds(m->n_C, nw, m->NNmax, std::max(1, m->mmax), nhp, 64).total * 8 > 60 * 1024) --nw;
+    const size_t ulds = (size_t)upd_lds(m->n_C, nw, m->NNmax, std::max(1, m->mmax), nhp, 64).total * 8;
+    hipLaunchKernelGGL(k_update, dim3(B), dim3(64 * nw), ulds, s, ua);
     HIPCHECK(hipGetLastError());
     return 0;
 }
@@ -1322,6 +1466,8 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
     w->m = m;
     w->max_B = max_batch;
     w->Bp = (max_batch + 63) / 64 * 64;
+    w->rs = m->estride + m->n_C * std::max(1, m->mmax);
+    w->RS = m->n_sub * w->rs + std::max(1, m->n_C);
     const size_t Bp = w->Bp;
     const int ld = m->n_C + 1;
     struct A { void** p; size_t bytes; } allocs[] = {
@@ -1335,8 +1481,9 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
         {(void**)&w->lam, Bp * std::max(1, m->n_C) * sizeof(double)},
         {(void**)&w->lamt, Bp * std::max(1, m->n_C) * sizeof(double)},
         {(void**)&w->step, Bp * (m->n_D + m->n_C) * sizeof(double)},
-        {(void**)&w->Y, Bp * m->n_sub * KKT_NN * ld * sizeof(double)},
+        {(void**)&w->Y, Bp * m->n_sub * (size_t)m->NNmax * (std::max(1, m->mmax) + 1) * sizeof(double)},
         {(void**)&w->mu, Bp * 2 * sizeof(double)},
+        {(void**)&w->RB, Bp * (size_t)(m->n_sub * (m->estride + m->n_C * std::max(1, m->mmax)) + std::max(1, m->n_C)) * sizeof(double)},
         {(void**)&w->st, Bp * sizeof(SolveState)},
         {(void**)&w->counter, sizeof(int) * 4},
     };
@@ -1378,7 +1525,7 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
 void ddrom_workspace_destroy(ddrom_workspace* w) {
     if (!w) return;
     void* ptrs[] = {w->dec_out, w->bc, w->gn_part, w->c_part, w->E_part, w->x, w->xt, w->lam, w->lamt,
-                    w->step, w->Y, w->mu, w->st, w->counter};
+                    w->step, w->Y, w->mu, w->st, w->counter, w->RB};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->counter_h) (void)hipHostFree(w->counter_h);
@@ -1520,7 +1667,7 @@ static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double*
     const int K = 8;
     std::ostringstream key;
     key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
-        << ":" << o->max_backtracks << ":" << (l0 != nullptr);
+        << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << (l0 != nullptr);
     long long done = 0;
     if (use_graph) {
         if (ws->graph_key != key.str() || !ws->graph) {

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libddrom.so")
 PREC_FP64 = 0
 PREC_FP32_DECODER = 1
 
-STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "kkt_not_pd", 4: "nonfinite"}
+STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "kkt_not_pd", 4: "nonfinite", 5: "stalled"}
 
 
 class DecoderDesc(C.Structure):
@@ -35,7 +35,7 @@ class ModelDesc(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol_abs", C.c_double), ("tol_rel", C.c_double), ("armijo_c1", C.c_double),
-                ("max_backtracks", C.c_int), ("precision", C.c_int)]
+                ("max_backtracks", C.c_int), ("precision", C.c_int), ("stall_tol", C.c_double)]
 
 
 _lib = None
@@ -161,8 +161,10 @@ class Workspace:
             self.h = None
 
 
-def opts(max_iter=50, tol_abs=0.0, tol_rel=1e-8, armijo_c1=1e-4, max_backtracks=20, precision=PREC_FP64) -> Opts:
-    return Opts(int(max_iter), float(tol_abs), float(tol_rel), float(armijo_c1), int(max_backtracks), int(precision))
+def opts(max_iter=50, tol_abs=0.0, tol_rel=1e-8, armijo_c1=1e-4, max_backtracks=20, precision=PREC_FP64,
+         stall_tol=0.0) -> Opts:
+    return Opts(int(max_iter), float(tol_abs), float(tol_rel), float(armijo_c1), int(max_backtracks), int(precision),
+                float(stall_tol))
 
 
 def dd_fom_residual(model: Model, mu, xsd, jac: bool = False):
