@@ -26,14 +26,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "HR DD NM-ROM solves/sec on 1 MI355X vs plain SQP at fixed rel. error vs FOM"
-PEAK_FP32_TFLOPS = 78.6     # non-packed FP32 FMA: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # published FP32 vector peak (packed FP32 issue)
+PEAK_FP32_UNPACKED_TFLOPS = 78.6  # one FP32 FMA per lane per clock: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 CONFIGS = {
-    "cfg1": dict(batch=512, seed=1, precision=1, tol_rel=1e-6, max_iter=60,
+    "cfg1": dict(batch=512, seed=1, precision=1, tol_rel=1e-6, stall_tol=1e-5, max_iter=60,
                  workload="Burgers 240x240, 4x4 subdomains, latent (8,4), width 2x, band 9, HR 10%, "
                           "512 held-out (a,lambda), FP32 decoder + FP64 KKT"),
-    "cfg0": dict(batch=1, seed=0, precision=0, tol_rel=1e-8, max_iter=60,
+    "cfg0": dict(batch=1, seed=0, precision=0, tol_rel=1e-8, stall_tol=0.0, max_iter=60,
                  workload="Burgers 36x36, 2x2 subdomains, latent (6,3), width 3x, band 5, HR 20%, "
                           "1 held-out (a,lambda), FP64"),
 }
@@ -90,7 +92,8 @@ def main():
     ws = dr.Workspace(model, B)
     mu_h = si.heldout_mu(B, cfg["seed"])
     mu = torch.as_tensor(mu_h, device="cuda")
-    o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"])
+    o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"],
+                stall_tol=cfg["stall_tol"])
     f = dict(dtype=torch.float64, device="cuda")
     out = dict(xhat=torch.empty((B, model.n_D), **f), lam=torch.empty((B, max(1, model.n_C)), **f),
                iters=torch.empty((B,), dtype=torch.int32, device="cuda"),
@@ -116,13 +119,16 @@ def main():
     # dominant kernel: interior decoder subnets, every solve live
     ms = dr.time_kernels(model, ws, mu, torch.zeros((B, model.n_D), **f), precision=cfg["precision"], reps=20)
     flops, bytes_ = decoder_work(model, B)
+    achieved = flops / (ms[0] * 1e-3) / 1e12
     if cfg["precision"] == 1:
-        roof = {"bound": "alu", "kernel": "k_decode<float,8> (interior subnets)", "achieved": flops / (ms[0] * 1e-3) / 1e12,
-                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "kernel": "k_decode<float,8,...> (interior subnets, all solves live)",
+                "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS}
     else:
-        roof = {"bound": "alu", "kernel": "k_decode<double,n> (interior subnets)", "achieved": flops / (ms[0] * 1e-3) / 1e12,
-                "peak": 78.6, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+        roof = {"bound": "alu", "kernel": "k_decode<double,...> (interior subnets, all solves live)",
+                "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VECTOR_TFLOPS}
     roof["traffic"] = None
     roof["algorithmic_bytes_per_launch"] = bytes_
     roof["hbm_GBs_if_algorithmic"] = bytes_ / (ms[0] * 1e-3) / 1e9
@@ -154,7 +160,7 @@ def main():
         "dtype": "f32+f64" if cfg["precision"] == 1 else "f64", "data": "synthetic",
         "config": {"workload": cfg["workload"], "batch": B, "subdomains": model.n_sub, "n_D": model.n_D,
                    "n_C": model.n_C, "stop": f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
-                                             f"or line-search stagnation"},
+                                             f"or line-search stagnation below {cfg['stall_tol']:g} ||F0||"},
         "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
         "status_counts": {dr.STATUS[k]: int((status == k).sum()) for k in np.unique(status)},
         "roofline": roof,
