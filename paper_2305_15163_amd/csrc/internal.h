@@ -161,12 +161,12 @@ struct ddrom_workspace {
     double* lam = nullptr;          // [Bp][n_C]
     double* lamt = nullptr;
     double* step = nullptr;         // [Bp][n_D + n_C]
-    double* Y = nullptr;            // KKT scratch [Bp][n_sub][NNmax][n_C + 1]
+    int* live = nullptr;            // [Bp] original index of each still-running solve, ascending
     double* mu = nullptr;           // [Bp][2]
     double* RB = nullptr;           // per-solve reduced blocks [Bp][RS]
     int rs = 0, RS = 0;             // per-subdomain block size, per-solve stride
     SolveState* st = nullptr;       // [Bp]
-    int* counter = nullptr;         // active-solve counter (device)
+    int* counter = nullptr;         // [0]: number of running solves (length of `live`)
     int* counter_h = nullptr;       // pinned host mirror
     // private stream (default priority) on which solves run and graphs are captured
     hipStream_t stream = nullptr;

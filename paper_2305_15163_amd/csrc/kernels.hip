@@ -11,8 +11,10 @@
 //   k_res_gn   HR Burgers residual at the sampled nodes, Z R_i by the chain rule, and the
 //              Gauss-Newton blocks H_i = (Z R_i)^T Z R_i, g_i = (Z R_i)^T Z r_i (partial sums)
 //   k_con      weak constraint sum_i C A_i g_i^Gamma and E_i^Gamma = C A_i dg_i^Gamma/dxhat
-//   k_update   one wave per solve: merit, Armijo test, KKT solve by Schur complement on the
-//              block-arrow system (eq. sqp_system), next trial point
+//   k_reduce   sums the partial slots of each solve into one contiguous record
+//   k_update   one workgroup per solve: merit, Armijo test, KKT solve by Schur complement on
+//              the block-arrow system (eq. sqp_system), next trial point
+//   k_compact  list of the solves still running; the next round's kernels run over it only
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,8 +87,14 @@ __device__ __forceinline__ void act_eval(double z, int act, double& s, double& d
     }
 }
 
-__device__ __forceinline__ bool lane_live(const SolveState* st, int b, int B) {
-    return b < B && (st == nullptr || st[b].phase != PH_DONE);
+// Solve slots.  Batch kernels run over slots j = 0, 1, ...: during a solve, slot j holds the
+// j-th still-running solve (live[j], ascending) and only the first *n_live slots are in use,
+// so a round costs in proportion to the running solves; per-round buffers (decoder output,
+// partial sums, reduced blocks) are indexed by slot, per-solve state by the solve index.
+// Without a live list (live == nullptr) slot j is solve j and all B slots are in use.
+__device__ __forceinline__ int live_count(const int* n_live, int B) { return n_live ? *n_live : B; }
+__device__ __forceinline__ int slot_solve(const int* live, int j, int nl) {
+    return j < nl ? (live ? live[j] : j) : 0;
 }
 
 // ------------------------------------------------------------------------------------
@@ -120,16 +128,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
                                                        const T* __restrict__ B1, const int2* __restrict__ bands,
                                                        const T* __restrict__ W2, const T* __restrict__ XR,
                                                        const double* __restrict__ xhat, int xstride, int xoff_override,
-                                                       const SolveState* __restrict__ st, int B,
-                                                       T* __restrict__ out, int Bp) {
+                                                       const int* __restrict__ live, const int* __restrict__ n_live,
+                                                       int B, T* __restrict__ out, int Bp) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RK = RingSlots<T, ACT>::K;
     const DecChunk ch = chunks[chunk_base + blockIdx.x];
     const DecSeg sg = segs[ch.seg];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int b = (blockIdx.y * WAVES + wave) * 64 + lane;
-    const bool live = lane_live(st, b, B);
-    if (!__syncthreads_or(live)) return;
+    const int nl = live_count(n_live, B);
+    if ((int)blockIdx.y * WAVES * 64 >= nl) return;     // every slot of this workgroup is idle
+    const int j = (blockIdx.y * WAVES + wave) * 64 + lane;
+    const bool act = j < nl;
+    const int b = slot_solve(live, j, nl);
 
     const int nrows = ch.r1 - ch.r0, span = ch.h_hi - ch.h_lo, bmax = sg.bmax;
     const DecLds L = dec_lds(span, nrows, NL, bmax, (int)sizeof(T), WAVES, RK);
@@ -158,10 +168,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     const int xo = xoff_override >= 0 ? xoff_override : sg.xoff;
     T xl[NL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) xl[k] = live ? (T)xhat[(size_t)b * xstride + xo + k] : (T)0;
+    for (int k = 0; k < NL; ++k) xl[k] = act ? (T)xhat[(size_t)b * xstride + xo + k] : (T)0;
     __syncthreads();
 
-    T* o = out + ((size_t)sg.out + (size_t)ch.r0 * (1 + NL)) * Bp + b;
+    T* o = out + ((size_t)sg.out + (size_t)ch.r0 * (1 + NL)) * Bp + j;
     // Units [vlo, vhi) (relative to h_lo) are valid in the ring; vhi - vlo <= DEC_RING.  Rows
     // ascend, so windows mostly slide right, but near the first rows of a decoder a clipped
     // band can start below the previous row's window: missing units are then computed on
@@ -223,7 +233,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
                 slot = slot + 1 == DEC_RING ? 0 : slot + 1;
             }
         }
-        if (b < Bp) {   // waves past the padded batch (small B) compute but never store
+        if (j < Bp) {   // waves past the padded batch (small B) compute but never store
             T* orow = o + (size_t)r * (1 + NL) * Bp;
             orow[0] = acc;
 #pragma unroll
@@ -356,20 +366,21 @@ template <typename T, int NO, int NG>
 __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchunks, int rbase,
                                                const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
                                                const int* __restrict__ gather, const T* __restrict__ dec,
-                                               const double* __restrict__ bc, const SolveState* __restrict__ st,
-                                               int B, int Bp, double nu, double hx, double hy,
+                                               const double* __restrict__ bc, const int* __restrict__ live,
+                                               const int* __restrict__ n_live, int B, int Bp, double nu, double hx, double hy,
                                                double* __restrict__ part, int estride, long long zero_row) {
     constexpr int NN = NO + NG;
     constexpr int NH = NN * (NN + 1) / 2;
     const ResChunk rc = rchunks[rbase + blockIdx.x];
     const ResSeg rs = rsegs[rc.sd];
     const long long oo = segs[rs.seg_om].out, og = segs[rs.seg_ga].out;
-    const int b = blockIdx.y * 64 + threadIdx.x;
-    if (__ballot(lane_live(st, b, B)) == 0) return;
-    const T* dom = dec + (size_t)oo * Bp + b;
-    const T* dga = dec + (size_t)og * Bp + b;
-    const T* dz = dec + (size_t)zero_row * Bp + b;
-    const double* bcb = bc + b;
+    const int nl = live_count(n_live, B);
+    if ((int)blockIdx.y * 64 >= nl) return;
+    const int j = blockIdx.y * 64 + threadIdx.x;
+    const T* dom = dec + (size_t)oo * Bp + j;
+    const T* dga = dec + (size_t)og * Bp + j;
+    const T* dz = dec + (size_t)zero_row * Bp + j;
+    const double* bcb = bc + slot_solve(live, j, nl);   // Dirichlet data are per solve
     double H[NH], g[NN], rr = 0.0;
 #pragma unroll
     for (int e = 0; e < NH; ++e) H[e] = 0.0;
@@ -381,7 +392,7 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
         load_node<T, NO, NG>(gp + (size_t)p * N_SLOTS, dom, dga, dz, bcb, Bp, A);
         accumulate_node<T, NO, NG>(A, nu, hx, hy, H, g, rr);
     }
-    double* pp = part + (size_t)rc.slot * estride * Bp + b;
+    double* pp = part + (size_t)rc.slot * estride * Bp + j;
 #pragma unroll
     for (int e = 0; e < NH; ++e) pp[(size_t)e * Bp] = H[e];
 #pragma unroll
@@ -398,14 +409,14 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
 template <typename T, int NG>
 __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, const ResSeg* __restrict__ rsegs,
                                             const DecSeg* __restrict__ segs, const double* __restrict__ CA, int n_C,
-                                            int ca_ld, const T* __restrict__ dec, const SolveState* __restrict__ st,
+                                            int ca_ld, const T* __restrict__ dec, const int* __restrict__ n_live,
                                             int B, int Bp, double* __restrict__ c_part, double* __restrict__ E_part,
                                             int mmax) {
     constexpr int JB = 8;
     const ConChunk cc = cch[blockIdx.x];
     const ResSeg rs = rsegs[cc.sd];
-    const int b = blockIdx.y * 64 + threadIdx.x;
-    if (__ballot(lane_live(st, b, B)) == 0) return;
+    if ((int)blockIdx.y * 64 >= live_count(n_live, B)) return;
+    const int b = blockIdx.y * 64 + threadIdx.x;   // slot
     const T* dga = dec + (size_t)segs[rs.seg_ga].out * Bp + b;
     const double* ca = CA + rs.ca + cc.j0;
     const int nj = cc.j1 - cc.j0;
@@ -457,12 +468,12 @@ __global__ __launch_bounds__(64) void k_reduce(int n_sub, int n_C, int mmax, int
                                                const int* __restrict__ slot0, const int* __restrict__ cpart0,
                                                int n_cparts, const double* __restrict__ gn_part,
                                                const double* __restrict__ c_part, const double* __restrict__ E_part,
-                                               const SolveState* __restrict__ st, double* __restrict__ RB) {
+                                               const int* __restrict__ n_live, double* __restrict__ RB) {
     __shared__ double tile[32][65];
     const int sd = blockIdx.x;
     const int lane = threadIdx.x;
-    const int b0 = blockIdx.z * 64, b = b0 + lane;
-    if (__ballot(lane_live(st, b, B)) == 0) return;
+    const int b0 = blockIdx.z * 64, b = b0 + lane;   // slots
+    if (b0 >= live_count(n_live, B)) return;
     int n_e, ne_gn = 0, ng = 0;
     size_t dst0;
     if (sd < n_sub) {
@@ -530,30 +541,23 @@ __global__ __launch_bounds__(64) void k_reduce(int n_sub, int n_C, int mmax, int
 }
 
 struct UpdArgs {
-    int n_sub, n_C, n_D, mmax, estride, Bp, B;
+    int n_sub, n_C, n_D, mg, estride, Bp, B;   // mg = max(1, largest n_i^Gamma): stride of the E blocks
     int lam_given;
     int max_iter, max_bt;
-    int NNmax, qr_rows;
     double tol_abs, tol_rel, c1, stall_tol;
     const int* n_om;       // [n_sub]
     const int* n_ga;
     const int* xoff;
-    const int* slot0;      // [n_sub + 1]
-    const int* cpart0;     // [n_sub + 1] constraint partial slots per subdomain
-    int n_cparts;
-    const double* gn_part;
-    const double* c_part;
-    const double* E_part;
-    const double* RB;      // per-solve reduced blocks [Bp][RS]
+    const double* RB;      // per-slot reduced blocks [Bp][RS]
     int rs, RS;
     double* x;
     double* xt;
     double* lam;
     double* lamt;
     double* step;
-    double* Y;             // [Bp][n_sub][KKT_NN][n_C+1]
     SolveState* st;
-    int* counter;
+    const int* live;       // slot -> solve
+    const int* n_live;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -561,168 +565,174 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// ------------------------------------------------------------------------------------
-// Per-solve update (one workgroup of nw waves per solve)
-// ------------------------------------------------------------------------------------
-// Block-arrow KKT (eq. sqp_system) by the Schur complement.  E_i = [0, Ehat_i] has only the m
-// interface columns, so only W_i = H_i^{-1} [0; I_m] (m right-hand sides) and t_i = H_i^{-1} rho_i
-// are needed:  S = sum_i Ehat_i (W_i)_Gamma Ehat_i^T,  S s_lambda = c - sum_i Ehat_i (t_i)_Gamma,
-// s_i = -(t_i + W_i Ehat_i^T s_lambda).  The waves of the workgroup factor different subdomains
-// concurrently (Cholesky of H_i padded to the largest block size, so all waves run the same
-// barriers); S is accumulated in a fixed order and solved by elimination with partial pivoting.
-struct UpdLds {
-    int c, lam, sl, S, work, wt, red, total;   // offsets in doubles
-};
-__host__ __device__ inline UpdLds upd_lds(int nC, int nw, int NNM, int mg, int nh_pad, int qr_rows) {
-    UpdLds L;
-    L.c = 0;
-    L.lam = L.c + 64;
-    L.sl = L.lam + 64;
-    L.S = L.sl + 64;
-    L.work = L.S + nC * (nC + 1);
-    const int per_sd = nw * (nh_pad + 2 * nC * (mg + 1));
-    const int qr = qr_rows * (nC + 1);
-    L.wt = L.work + (per_sd > qr ? per_sd : qr);
-    L.red = L.wt + nw * NNM * (mg + 1);
-    L.total = L.red + 32;
-    return L;
+// Value of v held by lane l (l wave-uniform).
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)u, l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ int packed_idx(int i, int j, int n) {   // i <= j, upper triangle row-major
     return i * n - i * (i - 1) / 2 + (j - i);
 }
 
-__global__ void k_update(UpdArgs a) {
+// LDS layout of the update kernel (offsets in doubles).
+struct UpdLds {
+    int lam, c, sl, red, E, P, q, rho, X, S, total;
+};
+__host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int MG) {
+    UpdLds L;
+    L.lam = 0;
+    L.c = L.lam + 64;
+    L.sl = L.c + 64;
+    L.red = L.sl + 64;
+    L.E = L.red + 16;                        // [n_sub][nC][mg]  Ehat_i
+    L.P = L.E + n_sub * nC * mg;             // [n_sub][nC][mg]  Ehat_i (W_i)_Gamma
+    L.q = L.P + n_sub * nC * mg;             // [n_sub][nC]      Ehat_i (t_i)_Gamma
+    L.rho = L.q + n_sub * nC;                // [n_sub][NN]      rho_i
+    L.X = L.rho + n_sub * NN;                // [n_sub][NN][MG+1]  [W_i | t_i]
+    L.S = L.X + n_sub * NN * (MG + 1);       // [nC][nC+1]       [S | right-hand side]
+    L.total = L.S + nC * (nC + 1);
+    return L;
+}
+
+// Dense n x n system [M | r] in LDS (row stride n + 1), solved by one wave: Gaussian
+// elimination with partial pivoting (rows in lanes), then back substitution.  The solution
+// goes to x.  Returns false if a pivot is zero or not finite.  n <= 64.
+__device__ bool wave_lu_solve(double* M, int n, double* x, int lane) {
+    const int ld = n + 1;
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        double best = (lane >= k && lane < n) ? fabs(M[lane * ld + k]) : -1.0;
+        int bi = lane;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        const int p = __builtin_amdgcn_readfirstlane(bi);
+        if (!(best > 0.0) || !isfinite(best)) ok = false;
+        if (p != k)
+            for (int jj = lane; jj <= n; jj += 64) {
+                const double t = M[k * ld + jj];
+                M[k * ld + jj] = M[p * ld + jj];
+                M[p * ld + jj] = t;
+            }
+        wave_sync_lds();
+        const double pv = M[k * ld + k];
+        if (lane > k && lane < n && pv != 0.0) {
+            const double f = M[lane * ld + k] / pv;
+            for (int jj = k + 1; jj <= n; ++jj) M[lane * ld + jj] -= f * M[k * ld + jj];
+        }
+        wave_sync_lds();
+    }
+    double r = lane < n ? M[lane * ld + n] : 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+        const double xi = lane_bcast(r, i) / M[i * ld + i];
+        if (lane == i) x[i] = xi;
+        if (lane < i) r -= M[lane * ld + i] * xi;
+    }
+    wave_sync_lds();
+    return ok;
+}
+
+// ------------------------------------------------------------------------------------
+// Per-solve update: merit, Armijo test, KKT step (one workgroup of NW waves per solve slot)
+// ------------------------------------------------------------------------------------
+// Block-arrow KKT (eq. sqp_system) by the Schur complement.  E_i = [0, Ehat_i] has only the m_i
+// interface columns, so only W_i = H_i^{-1} [0; I_m] (m right-hand sides) and t_i = H_i^{-1} rho_i
+// are needed:  S = sum_i Ehat_i (W_i)_Gamma Ehat_i^T,  S s_lambda = c - sum_i Ehat_i (t_i)_Gamma,
+// s_i = -(t_i + W_i Ehat_i^T s_lambda).
+// Each wave solves its subdomains' systems H_i [W_i | t_i] = [[0; I_m] | rho_i] in registers:
+// row r of the augmented block lives in lane r and pivot rows are broadcast lane to lane, so
+// these solves need no LDS traffic and no workgroup barrier.  S (a sum over subdomains in a
+// fixed order) and its pivoted solve then go through LDS.  NN >= n_i^Omega + n_i^Gamma and
+// MG >= n_i^Gamma bound every block (smaller blocks are padded with identity rows).
+template <int NN, int MG>
+__global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
-    __shared__ int flag_bad, piv_row;
-    const int b = blockIdx.x;
-    if (b >= a.B) return;
+    __shared__ int flag_bad;
+    const int slot = blockIdx.x;
+    const int nl = live_count(a.n_live, a.B);
+    if (slot >= nl) return;
+    const int b = slot_solve(a.live, slot, nl);
     SolveState S = a.st[b];
     if (S.phase == PH_DONE) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nth = blockDim.x, nw = nth >> 6;
-    const int nC = a.n_C, nD = a.n_D, NNM = a.NNmax, mg = a.mmax, nhp = NNM * (NNM + 1) / 2;
-    const UpdLds L = upd_lds(nC, nw, NNM, mg, nhp, a.qr_rows);
-    double* c_s = sm + L.c;
+    const int nC = a.n_C, nD = a.n_D, mg = a.mg, ns = a.n_sub;
+    const UpdLds L = upd_lds(ns, nC, mg, NN, MG);
     double* lam_s = sm + L.lam;
+    double* c_s = sm + L.c;
     double* sl_s = sm + L.sl;
-    double* Sm = sm + L.S;
-    double* work = sm + L.work;
-    double* Wt = sm + L.wt + (size_t)wave * NNM * (mg + 1);
     double* red = sm + L.red;
-    const double* rb = a.RB + (size_t)b * a.RS;
+    double* Es = sm + L.E;
+    double* Ps = sm + L.P;
+    double* qs = sm + L.q;
+    double* rho = sm + L.rho;
+    double* Xs = sm + L.X;
+    double* Sm = sm + L.S;
+    const double* rb = a.RB + (size_t)slot * a.RS;
     const int ld = nC + 1;
 
-    for (int j = tid; j < nC; j += nth) {
-        c_s[j] = rb[(size_t)a.n_sub * a.rs + j];
-        lam_s[j] = a.lamt[(size_t)b * nC + j];
+    for (int jj = tid; jj < nC; jj += nth) {
+        c_s[jj] = rb[(size_t)ns * a.rs + jj];
+        lam_s[jj] = a.lamt[(size_t)b * nC + jj];
+    }
+    for (int e = tid; e < ns * nC * mg; e += nth) {
+        const int sd = e / (nC * mg), r = e % (nC * mg);
+        Es[e] = rb[(size_t)sd * a.rs + a.estride + r];
     }
     if (tid == 0) flag_bad = 0;
     __syncthreads();
-
-    auto Eg = [&](int sd, int j, int k) { return rb[(size_t)sd * a.rs + a.estride + j * mg + k]; };
     auto gv = [&](int sd, int e) {
-        const int NN = a.n_om[sd] + a.n_ga[sd];
-        return rb[(size_t)sd * a.rs + NN * (NN + 1) / 2 + e];
+        const int NNi = a.n_om[sd] + a.n_ga[sd];
+        return rb[(size_t)sd * a.rs + NNi * (NNi + 1) / 2 + e];
     };
 
-    // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i || (wave 0) ----
+    // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i ||, by its normal
+    //      equations (sum_i Ehat_i Ehat_i^T) lambda = -sum_i Ehat_i g_i^Gamma ----
     if (S.phase == PH_INIT && !a.lam_given && nC > 0) {
-        int R = 0;
-        for (int sd = 0; sd < a.n_sub; ++sd) R += a.n_ga[sd];
-        double* M = work;
-        if (R <= a.qr_rows) {
-            if (wave == 0) {
-                int r0 = 0;
-                for (int sd = 0; sd < a.n_sub; ++sd) {
-                    const int m = a.n_ga[sd], no = a.n_om[sd];
-                    for (int e = lane; e < m * ld; e += 64) {
-                        const int k = e / ld, j = e % ld;
-                        M[(r0 + k) * ld + j] = j < nC ? Eg(sd, j, k) : -gv(sd, no + k);
-                    }
-                    r0 += m;
-                }
+        for (int e = tid; e < nC * ld; e += nth) {
+            const int i = e / ld, jj = e % ld;
+            double s = 0.0;
+            for (int sd = 0; sd < ns; ++sd) {
+                const int m = a.n_ga[sd], no = a.n_om[sd];
+                const double* E = Es + (size_t)sd * nC * mg;
+                for (int k = 0; k < m; ++k) s += E[i * mg + k] * (jj < nC ? E[jj * mg + k] : -gv(sd, no + k));
             }
-            __syncthreads();
-            for (int k = 0; k < nC && k < R; ++k) {
-                double nrm2 = 0.0, akk = 0.0, alpha = 0.0, v0 = 0.0, vn2 = 0.0;
-                if (wave == 0) {
-                    for (int r = k + lane; r < R; r += 64) nrm2 += M[r * ld + k] * M[r * ld + k];
-                    nrm2 = wave_sum(nrm2);
-                    akk = M[k * ld + k];
-                    alpha = akk > 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
-                    v0 = akk - alpha;
-                    vn2 = nrm2 - akk * akk + v0 * v0;
-                }
-                __syncthreads();
-                if (wave == 0 && vn2 > 0.0) {
-                    for (int col = k + 1 + lane; col < ld; col += 64) {
-                        double dot = v0 * M[k * ld + col];
-                        for (int r = k + 1; r < R; ++r) dot += M[r * ld + k] * M[r * ld + col];
-                        const double f = 2.0 * dot / vn2;
-                        M[k * ld + col] -= f * v0;
-                        for (int r = k + 1; r < R; ++r) M[r * ld + col] -= f * M[r * ld + k];
-                    }
-                }
-                __syncthreads();
-                if (tid == 0) M[k * ld + k] = vn2 > 0.0 ? alpha : akk;
-                __syncthreads();
-            }
-            if (tid == 0) {
-                for (int i = nC - 1; i >= 0; --i) {
-                    double s = M[i * ld + nC];
-                    for (int k = i + 1; k < nC; ++k) s -= M[i * ld + k] * lam_s[k];
-                    lam_s[i] = s / M[i * ld + i];
-                }
-            }
-        } else {
-            // normal equations (sum_i E_i E_i^T) lambda = -sum_i E_i g_i^Gamma, Cholesky by thread 0
-            for (int e = tid; e < nC * ld; e += nth) {
-                const int i = e / ld, j = e % ld;
-                double s = 0.0;
-                for (int sd = 0; sd < a.n_sub; ++sd)
-                    for (int k = 0; k < a.n_ga[sd]; ++k) s += Eg(sd, i, k) * (j < nC ? Eg(sd, j, k) : -gv(sd, a.n_om[sd] + k));
-                M[e] = s;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                for (int k = 0; k < nC; ++k) {
-                    const double d = M[k * ld + k];
-                    const double l = sqrt(d > 0.0 ? d : 1.0);
-                    M[k * ld + k] = l;
-                    for (int i = k + 1; i < nC; ++i) M[i * ld + k] /= l;
-                    for (int i = k + 1; i < nC; ++i)
-                        for (int j = k + 1; j <= i; ++j) M[i * ld + j] -= M[i * ld + k] * M[j * ld + k];
-                }
-                for (int i = 0; i < nC; ++i) {
-                    double s = M[i * ld + nC];
-                    for (int k = 0; k < i; ++k) s -= M[i * ld + k] * lam_s[k];
-                    lam_s[i] = s / M[i * ld + i];
-                }
-                for (int i = nC - 1; i >= 0; --i) {
-                    double s = lam_s[i];
-                    for (int k = i + 1; k < nC; ++k) s -= M[k * ld + i] * lam_s[k];
-                    lam_s[i] = s / M[i * ld + i];
-                }
-            }
+            Sm[e] = s;
         }
+        __syncthreads();
+        if (wave == 0) wave_lu_solve(Sm, nC, lam_s, lane);
         __syncthreads();
     }
 
-    // ---- merit at the trial point: phi = 0.5 (sum_i ||rho_i||^2 + ||c||^2) ----
+    // ---- merit at the trial point: phi = 0.5 (sum_i ||rho_i||^2 + ||c||^2), rho_i kept ----
     {
         double acc = 0.0;
-        for (int sd = wave; sd < a.n_sub; sd += nw) {
-            const int no = a.n_om[sd], NN = no + a.n_ga[sd];
-            for (int e = lane; e < NN; e += 64) {
-                double r = gv(sd, e);
-                if (e >= no)
-                    for (int j = 0; j < nC; ++j) r += Eg(sd, j, e - no) * lam_s[j];
-                acc += r * r;
+        for (int e = tid; e < ns * NN; e += nth) {
+            const int sd = e / NN, r = e % NN;
+            const int no = a.n_om[sd], NNi = no + a.n_ga[sd];
+            double v = 0.0;
+            if (r < NNi) {
+                v = gv(sd, r);
+                if (r >= no) {
+                    const double* E = Es + (size_t)sd * nC * mg + (r - no);
+                    for (int jj = 0; jj < nC; ++jj) v += E[jj * mg] * lam_s[jj];
+                }
             }
+            rho[e] = v;
+            acc += v * v;
         }
-        if (wave == 0)
-            for (int j = lane; j < nC; j += 64) acc += c_s[j] * c_s[j];
+        for (int jj = tid; jj < nC; jj += nth) acc += c_s[jj] * c_s[jj];
         acc = wave_sum(acc);
         if (lane == 0) red[wave] = acc;
         __syncthreads();
@@ -742,9 +752,9 @@ __global__ void k_update(UpdArgs a) {
             S.status = DDROM_STATUS_NONFINITE;
             action = 2;
         }
-        for (int j = tid; j < nC; j += nth) {
-            a.lam[(size_t)b * nC + j] = lam_s[j];
-            a.lamt[(size_t)b * nC + j] = lam_s[j];
+        for (int jj = tid; jj < nC; jj += nth) {
+            a.lam[(size_t)b * nC + jj] = lam_s[jj];
+            a.lamt[(size_t)b * nC + jj] = lam_s[jj];
         }
     } else {
         const bool ok = isfinite(phi_t) && phi_t <= (1.0 - 2.0 * a.c1 * S.alpha) * S.phi0;
@@ -762,7 +772,7 @@ __global__ void k_update(UpdArgs a) {
             }
         } else {
             for (int e = tid; e < nD; e += nth) a.x[(size_t)b * nD + e] = a.xt[(size_t)b * nD + e];
-            for (int j = tid; j < nC; j += nth) a.lam[(size_t)b * nC + j] = lam_s[j];
+            for (int jj = tid; jj < nC; jj += nth) a.lam[(size_t)b * nC + jj] = lam_s[jj];
             S.iters += 1;
             S.fn = fn_t;
         }
@@ -779,12 +789,9 @@ __global__ void k_update(UpdArgs a) {
     if (action == 1) {
         for (int e = tid; e < nD; e += nth)
             a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + S.alpha * a.step[(size_t)b * (nD + nC) + e];
-        for (int j = tid; j < nC; j += nth)
-            a.lamt[(size_t)b * nC + j] = a.lam[(size_t)b * nC + j] + S.alpha * a.step[(size_t)b * (nD + nC) + nD + j];
-        if (tid == 0) {
-            a.st[b] = S;
-            atomicAdd(a.counter, 1);
-        }
+        for (int jj = tid; jj < nC; jj += nth)
+            a.lamt[(size_t)b * nC + jj] = a.lam[(size_t)b * nC + jj] + S.alpha * a.step[(size_t)b * (nD + nC) + nD + jj];
+        if (tid == 0) a.st[b] = S;
         return;
     }
     if (action == 2) {
@@ -795,148 +802,72 @@ __global__ void k_update(UpdArgs a) {
         return;
     }
 
-    // ---- KKT step ----
-    for (int e = tid; e < nC * ld; e += nth) Sm[e] = 0.0;
-    const size_t ystride = (size_t)NNM * (mg + 1);
-    double* Yb = a.Y + (size_t)b * a.n_sub * ystride;
-    double* Hp = work + (size_t)wave * (nhp + 2 * nC * (mg + 1));   // packed Cholesky factor of this wave's H_i
-    double* Pw = Hp + nhp;                                           // [nC][m+1]: Ehat_i (W_i)_Gamma | Ehat_i (t_i)_Gamma
-    double* Ew = Pw + nC * (mg + 1);                                 // [nC][m]: Ehat_i
-    __syncthreads();
-    for (int pass = 0; pass * nw < a.n_sub; ++pass) {
-        const int sd = pass * nw + wave;
-        const bool act = sd < a.n_sub;
-        const int no = act ? a.n_om[sd] : 0, ng = act ? a.n_ga[sd] : 0, NN = no + ng;
-        // H_i packed (padded to NNM with identity), Ehat_i, rho_i
-        for (int e = lane; e < nhp; e += 64) {
-            int i = 0, rem = e;
-            while (rem >= NNM - i) { rem -= NNM - i; ++i; }
-            const int j = i + rem;
-            double v;
-            if (act && i < NN && j < NN) v = rb[(size_t)sd * a.rs + packed_idx(i, j, NN)];
-            else v = (i == j) ? 1.0 : 0.0;
-            Hp[e] = v;
+    // ---- per-subdomain solves H_i [W_i | t_i] = [[0; I_m] | rho_i], one wave per subdomain ----
+    constexpr int NA = NN + MG + 1;   // augmented row: NN entries of H_i, MG + 1 right-hand sides
+    for (int sd = wave; sd < ns; sd += nw) {
+        const int no = a.n_om[sd], ng = a.n_ga[sd], NNi = no + ng;
+        const double* hp = rb + (size_t)sd * a.rs;
+        const bool real_row = lane < NNi;
+        double A[NA];
+#pragma unroll
+        for (int c = 0; c < NN; ++c) {
+            double v = (lane == c) ? 1.0 : 0.0;
+            if (real_row && c < NNi) v = hp[lane <= c ? packed_idx(lane, c, NNi) : packed_idx(c, lane, NNi)];
+            A[c] = v;
         }
-        for (int e = lane; e < nC * mg; e += 64) {
-            const int j = e / mg, k = e % mg;
-            Ew[e] = (act && k < ng) ? Eg(sd, j, k) : 0.0;
+#pragma unroll
+        for (int l = 0; l < MG; ++l) A[NN + l] = (l < ng && lane == no + l) ? 1.0 : 0.0;
+        A[NN + MG] = (real_row && lane < NN) ? rho[sd * NN + lane] : 0.0;
+        // forward elimination without pivoting (H_i is symmetric positive definite; a
+        // non-positive pivot marks the block as not positive definite)
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < NN; ++k) {
+            const double piv = lane_bcast(A[k], k);
+            if (k < NNi && (!(piv > 0.0) || !isfinite(piv))) bad = true;
+            const double f = (lane > k) ? A[k] / piv : 0.0;
+#pragma unroll
+            for (int c = k + 1; c < NA; ++c) A[c] -= f * lane_bcast(A[c], k);
         }
-        __syncthreads();
-        // right-hand sides in Wt: column l < m -> e_{no+l}; column m -> rho_i
-        for (int e = lane; e < NNM * (mg + 1); e += 64) {
-            const int k = e / (mg + 1), l = e % (mg + 1);
-            double v = 0.0;
-            if (act && k < NN) {
-                if (l < mg) v = (l < ng && k == no + l) ? 1.0 : 0.0;
-                else {
-                    v = gv(sd, k);
-                    if (k >= no)
-                        for (int j = 0; j < nC; ++j) v += Ew[j * mg + (k - no)] * lam_s[j];
-                }
-            }
-            Wt[e] = v;
-        }
-        // Cholesky of the padded block, all waves in step (same NNM)
-        for (int k = 0; k < NNM; ++k) {
-            if (lane == 0) {
-                const int kk = packed_idx(k, k, NNM);
-                const double d = Hp[kk];
-                if (act && (!(d > 0.0) || !isfinite(d))) flag_bad = 1;
-                Hp[kk] = sqrt(d > 0.0 ? d : 1.0);
-            }
-            __syncthreads();
-            const double piv = Hp[packed_idx(k, k, NNM)];
-            for (int j = k + 1 + lane; j < NNM; j += 64) Hp[packed_idx(k, j, NNM)] /= piv;
-            __syncthreads();
-            const int m2 = NNM - k - 1;
-            for (int e = lane; e < m2 * m2; e += 64) {
-                const int i = k + 1 + e / m2, j = k + 1 + e % m2;
-                if (j >= i) Hp[packed_idx(i, j, NNM)] -= Hp[packed_idx(k, i, NNM)] * Hp[packed_idx(k, j, NNM)];
-            }
-            __syncthreads();
-        }
-        // (Hp now holds U with H = U^T U.)  Each lane l <= m solves its column.
-        if (lane <= mg) {
-            double* y = Wt + lane;   // column lane, stride mg+1
-            for (int i = 0; i < NNM; ++i) {
-                double s = y[i * (mg + 1)];
-                for (int k = 0; k < i; ++k) s -= Hp[packed_idx(k, i, NNM)] * y[k * (mg + 1)];
-                y[i * (mg + 1)] = s / Hp[packed_idx(i, i, NNM)];
-            }
-            for (int i = NNM - 1; i >= 0; --i) {
-                double s = y[i * (mg + 1)];
-                for (int k = i + 1; k < NNM; ++k) s -= Hp[packed_idx(i, k, NNM)] * y[k * (mg + 1)];
-                y[i * (mg + 1)] = s / Hp[packed_idx(i, i, NNM)];
+        // back substitution, column-oriented: x_k = A[k][rhs] / A[k][k], then rows above
+        double Xr[MG + 1];
+#pragma unroll
+        for (int l = 0; l <= MG; ++l) Xr[l] = 0.0;
+#pragma unroll
+        for (int k = NN - 1; k >= 0; --k) {
+            const double dk = lane_bcast(A[k], k);
+#pragma unroll
+            for (int l = 0; l <= MG; ++l) {
+                const double xk = lane_bcast(A[NN + l], k) / dk;
+                if (lane == k) Xr[l] = xk;
+                if (lane < k) A[NN + l] -= A[k] * xk;
             }
         }
-        __syncthreads();
-        if (act)
-            for (int e = lane; e < NNM * (mg + 1); e += 64) Yb[(size_t)sd * ystride + e] = Wt[e];
-        // Pw = Ehat_i [ (W_i)_Gamma | (t_i)_Gamma ]
-        for (int e = lane; e < nC * (mg + 1); e += 64) {
-            const int j = e / (mg + 1), l = e % (mg + 1);
-            double s = 0.0;
-            if (act && (l < ng || l == mg))
-                for (int k = 0; k < ng; ++k) s += Ew[j * mg + k] * Wt[(no + k) * (mg + 1) + l];
-            Pw[e] = s;
-        }
-        __syncthreads();
-        // S += sum over this pass's subdomains (fixed order), q in column nC
-        const int nact = min(nw, a.n_sub - pass * nw);
-        for (int e = tid; e < nC * ld; e += nth) {
-            const int i = e / ld, j = e % ld;
-            double s = 0.0;
-            for (int w = 0; w < nact; ++w) {
-                const double* P = work + (size_t)w * (nhp + 2 * nC * (mg + 1)) + nhp;
-                const double* E = P + nC * (mg + 1);
-                if (j < nC)
-                    for (int l = 0; l < mg; ++l) s += P[i * (mg + 1) + l] * E[j * mg + l];
-                else
-                    s += P[i * (mg + 1) + mg];
+        if (bad && lane == 0) flag_bad = 1;
+        if (lane < NN)
+#pragma unroll
+            for (int l = 0; l <= MG; ++l) Xs[((size_t)sd * NN + lane) * (MG + 1) + l] = Xr[l];
+        // P_i = Ehat_i (W_i)_Gamma, q_i = Ehat_i (t_i)_Gamma (constraint row jj in lane jj)
+        const double* E = Es + (size_t)sd * nC * mg;
+        double P[MG + 1];
+#pragma unroll
+        for (int l = 0; l <= MG; ++l) P[l] = 0.0;
+#pragma unroll
+        for (int k = 0; k < MG; ++k) {
+            if (k < ng) {
+                const double e = lane < nC ? E[lane * mg + k] : 0.0;
+#pragma unroll
+                for (int l = 0; l <= MG; ++l) P[l] += e * lane_bcast(Xr[l], no + k);
             }
-            Sm[e] += s;
         }
-        __syncthreads();
+        if (lane < nC) {
+#pragma unroll
+            for (int l = 0; l < MG; ++l)
+                if (l < mg) Ps[((size_t)sd * nC + lane) * mg + l] = l < ng ? P[l] : 0.0;
+            qs[(size_t)sd * nC + lane] = P[MG];
+        }
     }
-    for (int j = tid; j < nC; j += nth) Sm[j * ld + nC] = c_s[j] - Sm[j * ld + nC];
     __syncthreads();
-    // elimination with partial pivoting on [S | c - q]
-    for (int k = 0; k < nC; ++k) {
-        if (wave == 0) {
-            double best = -1.0;
-            int bi = k;
-            for (int i = k + lane; i < nC; i += 64) {
-                const double v = fabs(Sm[i * ld + k]);
-                if (v > best) { best = v; bi = i; }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            if (lane == 0) {
-                piv_row = bi;
-                if (!(best > 0.0) || !isfinite(best)) flag_bad = 1;
-            }
-        }
-        __syncthreads();
-        const int pr = piv_row;
-        if (pr != k)
-            for (int j = tid; j <= nC; j += nth) {
-                const double t = Sm[k * ld + j];
-                Sm[k * ld + j] = Sm[pr * ld + j];
-                Sm[pr * ld + j] = t;
-            }
-        __syncthreads();
-        const double pv = Sm[k * ld + k];
-        const int m2 = nC - k - 1;
-        if (pv != 0.0)
-            for (int e = tid; e < m2 * (m2 + 1); e += nth) {
-                const int i = k + 1 + e / (m2 + 1), j = k + 1 + e % (m2 + 1);
-                Sm[i * ld + j] -= Sm[i * ld + k] / pv * Sm[k * ld + j];
-            }
-        __syncthreads();
-    }
     if (flag_bad) {
         if (tid == 0) {
             S.status = DDROM_STATUS_KKT_NOT_PD;
@@ -945,48 +876,92 @@ __global__ void k_update(UpdArgs a) {
         }
         return;
     }
-    if (tid == 0)
-        for (int i = nC - 1; i >= 0; --i) {
-            double s = Sm[i * ld + nC];
-            for (int k = i + 1; k < nC; ++k) s -= Sm[i * ld + k] * sl_s[k];
-            sl_s[i] = s / Sm[i * ld + i];
-        }
-    __syncthreads();
-    // s_i = -(t_i + W_i Ehat_i^T s_lambda)
     double* stp = a.step + (size_t)b * (nD + nC);
-    for (int j = tid; j < nC; j += nth) stp[nD + j] = sl_s[j];
-    double* u_s = work + (size_t)wave * 64;   // this wave's Ehat_i^T s_lambda (the work area is free now)
-    for (int sd = wave; sd < a.n_sub; sd += nw) {
-        const int no = a.n_om[sd], ng = a.n_ga[sd], NN = no + ng;
-        const double* Y = Yb + (size_t)sd * ystride;
-        if (lane < ng) {
-            double u = 0.0;
-            for (int j = 0; j < nC; ++j) u += Eg(sd, j, lane) * sl_s[j];
-            u_s[lane] = u;
+    if (nC > 0) {
+        // [S | c - q] with S = sum_i P_i Ehat_i^T, summed over subdomains in a fixed order
+        for (int e = tid; e < nC * ld; e += nth) {
+            const int i = e / ld, jj = e % ld;
+            double s = 0.0;
+            if (jj < nC) {
+                for (int sd = 0; sd < ns; ++sd) {
+                    const double* P = Ps + ((size_t)sd * nC + i) * mg;
+                    const double* E = Es + ((size_t)sd * nC + jj) * mg;
+                    for (int l = 0; l < mg; ++l) s += P[l] * E[l];
+                }
+            } else {
+                for (int sd = 0; sd < ns; ++sd) s += qs[(size_t)sd * nC + i];
+                s = c_s[i] - s;
+            }
+            Sm[e] = s;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int k = lane; k < NN; k += 64) {
-            double s = Y[k * (mg + 1) + mg];
-            for (int l = 0; l < ng; ++l) s += Y[k * (mg + 1) + l] * u_s[l];
-            stp[a.xoff[sd] + k] = -s;
+        __syncthreads();
+        if (wave == 0 && !wave_lu_solve(Sm, nC, sl_s, lane) && lane == 0) flag_bad = 1;
+        __syncthreads();
+        if (flag_bad) {
+            if (tid == 0) {
+                S.status = DDROM_STATUS_KKT_NOT_PD;
+                S.phase = PH_DONE;
+                a.st[b] = S;
+            }
+            return;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // s_i = -(t_i + W_i u_i),  u_i = Ehat_i^T s_lambda
+    for (int e = tid; e < ns * NN; e += nth) {
+        const int sd = e / NN, r = e % NN;
+        const int ng = a.n_ga[sd], NNi = a.n_om[sd] + ng;
+        if (r >= NNi) continue;
+        const double* X = Xs + ((size_t)sd * NN + r) * (MG + 1);
+        const double* E = Es + (size_t)sd * nC * mg;
+        double s = X[MG];
+        for (int l = 0; l < ng; ++l) {
+            double u = 0.0;
+            for (int jj = 0; jj < nC; ++jj) u += E[jj * mg + l] * sl_s[jj];
+            s += X[l] * u;
+        }
+        stp[a.xoff[sd] + r] = -s;
+    }
+    for (int jj = tid; jj < nC; jj += nth) stp[nD + jj] = sl_s[jj];
     __syncthreads();
     for (int e = tid; e < nD; e += nth) a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e] + stp[e];
-    for (int j = tid; j < nC; j += nth) a.lamt[(size_t)b * nC + j] = a.lam[(size_t)b * nC + j] + stp[nD + j];
+    for (int jj = tid; jj < nC; jj += nth) a.lamt[(size_t)b * nC + jj] = a.lam[(size_t)b * nC + jj] + stp[nD + jj];
     if (tid == 0) {
         S.phi0 = phi_t;
         S.alpha = 1.0;
         S.nbt = 0;
         S.phase = PH_TRIAL;
         a.st[b] = S;
-        atomicAdd(a.counter, 1);
     }
+}
+
+// List of the still-running solves, ascending (one workgroup of 1024 threads), and its length
+// in n_live[0] (the host reads it to stop replaying rounds).
+__global__ __launch_bounds__(1024) void k_compact(int B, const SolveState* __restrict__ st, int* __restrict__ live,
+                                                  int* __restrict__ n_live) {
+    __shared__ int wcount[16];
+    __shared__ int base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) base = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < B; c0 += 1024) {
+        const int b = c0 + tid;
+        const bool run = b < B && st[b].phase != PH_DONE;
+        const unsigned long long m = __ballot(run);
+        const int below = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wcount[wave] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int w = 0; w < wave; ++w) off += wcount[w];
+        if (run) live[off + below] = b;
+        __syncthreads();
+        if (tid == 0) {
+            int t = base;
+            for (int w = 0; w < 16; ++w) t += wcount[w];
+            base = t;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) n_live[0] = base;
 }
 
 __global__ void k_init(int B, int Bp, int nD, int nC, const double* __restrict__ mu, const double* __restrict__ x0,
@@ -1037,10 +1012,6 @@ __global__ void k_finalize(int B, int nD, int nC, const double* __restrict__ x, 
         if (fn) fn[b] = st[b].fn;
         if (f0) f0[b] = st[b].f0;
     }
-}
-
-__global__ void k_zero_int(int* p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
 // Sum of the GN partials into dense per-solve outputs (ddrom_gn_blocks).
@@ -1169,7 +1140,8 @@ namespace {
 
 template <int TAG>
 static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const double* xhat, int xstride,
-                         int xoff_override, const SolveState* st, int B, void* out, int Bp, hipStream_t s) {
+                         int xoff_override, const int* live, const int* n_live, int B, void* out, int Bp,
+                         hipStream_t s) {
     const int c0 = m->seg_chunk0[g0], c1 = m->seg_chunk1[g1 - 1];
     if (c1 <= c0) return 0;
     const int n = m->segs_h[g0].n;
@@ -1189,7 +1161,7 @@ static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const d
     const unsigned lds = (unsigned)L.total;
 #define DEC_LAUNCH(T, NLV, ACTV, WV, W1p, B1p, W2p, XRp)                                                          \
     hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG>), grid, block, lds, s, m->chunks_d, c0, m->segs_d, W1p,     \
-                       B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, st, B, (T*)out, Bp)
+                       B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, live, n_live, B, (T*)out, Bp)
 #define DEC_ACT(NLV, ACTV)                                                                                        \
     if (prec == DDROM_PREC_FP64) DEC_LAUNCH(double, NLV, ACTV, 1, m->W1d, m->b1d, m->W2d, m->xrefd);            \
     else if (ACTV == DDROM_ACT_SWISH) DEC_LAUNCH(float, NLV, ACTV, 2, m->W1f, m->b1f, m->W2f, m->xreff);         \
@@ -1214,7 +1186,7 @@ static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const d
 }
 
 static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const ddrom_workspace* ws,
-                      const SolveState* st, int B, hipStream_t s) {
+                      const int* live, const int* n_live, int B, hipStream_t s) {
     const ddrom::ResSeg& rs = m->rsegs_h[sd0];
     // one chunk per slot, slots of consecutive subdomains are consecutive
     const int c0 = rs.slot0, c1 = m->rsegs_h[sd1 - 1].slot1;
@@ -1223,12 +1195,12 @@ static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const dd
     if (rs.n_om == A && rs.n_ga == G) {                                                                           \
         if (prec == DDROM_PREC_FP64)                                                                              \
             hipLaunchKernelGGL((k_res_gn<double, A, G>), grid, block, 0, s, m->rchunks_d, c0, m->rsegs_d,          \
-                               m->segs_d, m->gather_d, (const double*)ws->dec_out, ws->bc, st, B, ws->Bp, m->nu,  \
-                               m->hx, m->hy, ws->gn_part, m->estride, ws->zero_row);                              \
+                               m->segs_d, m->gather_d, (const double*)ws->dec_out, ws->bc, live, n_live, B, ws->Bp, \
+                               m->nu, m->hx, m->hy, ws->gn_part, m->estride, ws->zero_row);                       \
         else                                                                                                      \
             hipLaunchKernelGGL((k_res_gn<float, A, G>), grid, block, 0, s, m->rchunks_d, c0, m->rsegs_d,           \
-                               m->segs_d, m->gather_d, (const float*)ws->dec_out, ws->bc, st, B, ws->Bp, m->nu,   \
-                               m->hx, m->hy, ws->gn_part, m->estride, ws->zero_row);                              \
+                               m->segs_d, m->gather_d, (const float*)ws->dec_out, ws->bc, live, n_live, B, ws->Bp,  \
+                               m->nu, m->hx, m->hy, ws->gn_part, m->estride, ws->zero_row);                       \
         HIPCHECK(hipGetLastError());                                                                              \
         return 0;                                                                                                 \
     }
@@ -1239,7 +1211,7 @@ static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const dd
     return DDROM_EINVAL;
 }
 
-static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const SolveState* st, int B,
+static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const int* n_live, int B,
                       hipStream_t s) {
     if (m->n_cchunks == 0 || m->n_C == 0) return 0;
     dim3 grid(m->n_cchunks, ws->Bp / 64), block(64);
@@ -1253,11 +1225,11 @@ static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws,
     case G:                                                                                                       \
         if (prec == DDROM_PREC_FP64)                                                                              \
             hipLaunchKernelGGL((k_con<double, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d, \
-                               m->n_C, m->ca_ld, (const double*)ws->dec_out, st, B, ws->Bp, ws->c_part,           \
+                               m->n_C, m->ca_ld, (const double*)ws->dec_out, n_live, B, ws->Bp, ws->c_part,       \
                                ws->E_part, m->mmax);                                                              \
         else                                                                                                      \
             hipLaunchKernelGGL((k_con<float, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d,  \
-                               m->n_C, m->ca_ld, (const float*)ws->dec_out, st, B, ws->Bp, ws->c_part,            \
+                               m->n_C, m->ca_ld, (const float*)ws->dec_out, n_live, B, ws->Bp, ws->c_part,        \
                                ws->E_part, m->mmax);                                                              \
         break;
     switch (ng) {
@@ -1291,8 +1263,8 @@ static ModelDevInts get_ints(const ddrom_model* m) {
 // One evaluation of all active solves at their trial points (xt).  The interface decoders
 // and the constraint sums run on a second stream forked from `s` (they depend only on the
 // interface latents), overlapping the interior decoders and the residual kernel.
-static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const SolveState* st,
-                          const double* xhat, hipStream_t s) {
+static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const int* live,
+                          const int* n_live, const double* xhat, hipStream_t s) {
     int rc;
     const int n = m->n_sub;
     hipStream_t s2 = ws->stream2;
@@ -1301,23 +1273,25 @@ static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, i
     for (int g0 = n; g0 < 2 * n;) {
         int g1 = g0 + 1;
         while (g1 < 2 * n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
-        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, st, B, ws->dec_out, ws->Bp, s2))) return rc;
+        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, live, n_live, B, ws->dec_out, ws->Bp, s2)))
+            return rc;
         g0 = g1;
     }
     HIPCHECK(hipEventRecord(ws->ev_ga, s2));
-    if ((rc = launch_con(m, prec, ws, st, B, s2))) return rc;
+    if ((rc = launch_con(m, prec, ws, n_live, B, s2))) return rc;
     HIPCHECK(hipEventRecord(ws->ev_con, s2));
     for (int g0 = 0; g0 < n;) {
         int g1 = g0 + 1;
         while (g1 < n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
-        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, st, B, ws->dec_out, ws->Bp, s))) return rc;
+        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, live, n_live, B, ws->dec_out, ws->Bp, s)))
+            return rc;
         g0 = g1;
     }
     HIPCHECK(hipStreamWaitEvent(s, ws->ev_ga, 0));
     for (int s0 = 0; s0 < n;) {
         int s1 = s0 + 1;
         while (s1 < n && m->n_om[s1] == m->n_om[s0] && m->n_ga[s1] == m->n_ga[s0]) ++s1;
-        if ((rc = launch_res(m, prec, s0, s1, ws, st, B, s))) return rc;
+        if ((rc = launch_res(m, prec, s0, s1, ws, live, n_live, B, s))) return rc;
         s0 = s1;
     }
     HIPCHECK(hipStreamWaitEvent(s, ws->ev_con, 0));
@@ -1327,32 +1301,53 @@ static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, i
 static UpdArgs upd_args(const ddrom_model* m, ddrom_workspace* ws, int B, const ddrom_opts* o, int lam_given) {
     ModelDevInts di = get_ints(m);
     UpdArgs a;
-    a.n_sub = m->n_sub; a.n_C = m->n_C; a.n_D = m->n_D; a.mmax = m->mmax; a.estride = m->estride; a.Bp = ws->Bp;
-    a.B = B; a.lam_given = lam_given; a.max_iter = o->max_iter; a.max_bt = o->max_backtracks;
+    a.n_sub = m->n_sub; a.n_C = m->n_C; a.n_D = m->n_D; a.mg = std::max(1, m->mmax); a.estride = m->estride;
+    a.Bp = ws->Bp; a.B = B; a.lam_given = lam_given; a.max_iter = o->max_iter; a.max_bt = o->max_backtracks;
     a.tol_abs = o->tol_abs; a.tol_rel = o->tol_rel; a.c1 = o->armijo_c1; a.stall_tol = o->stall_tol;
-    a.n_om = di.n_om; a.n_ga = di.n_ga; a.xoff = di.xoff; a.slot0 = di.slot0;
-    a.cpart0 = di.cpart0; a.n_cparts = m->n_cparts;
-    a.gn_part = ws->gn_part; a.c_part = ws->c_part; a.E_part = ws->E_part;
+    a.n_om = di.n_om; a.n_ga = di.n_ga; a.xoff = di.xoff;
     a.RB = ws->RB; a.rs = ws->rs; a.RS = ws->RS;
-    a.NNmax = m->NNmax; a.qr_rows = 64;
-    a.x = ws->x; a.xt = ws->xt; a.lam = ws->lam; a.lamt = ws->lamt; a.step = ws->step; a.Y = ws->Y;
-    a.st = ws->st; a.counter = ws->counter;
+    a.x = ws->x; a.xt = ws->xt; a.lam = ws->lam; a.lamt = ws->lamt; a.step = ws->step;
+    a.st = ws->st; a.live = ws->live; a.n_live = ws->counter;
     return a;
+}
+
+// Block bounds (NN >= n_i^Omega + n_i^Gamma, MG >= n_i^Gamma) of the compiled update kernels.
+static const int kUpdShapes[][2] = {{3, 1}, {4, 0}, {5, 2}, {6, 0}, {6, 2}, {8, 0}, {9, 3}, {12, 4}, {18, 6}, {20, 12}};
+
+static int launch_update(const ddrom_model* m, const UpdArgs& ua, int B, hipStream_t s) {
+    int pick = -1;
+    for (int k = 0; k < (int)(sizeof(kUpdShapes) / sizeof(kUpdShapes[0])); ++k)
+        if (kUpdShapes[k][0] >= m->NNmax && kUpdShapes[k][1] >= m->mmax) { pick = k; break; }
+    if (pick < 0) {
+        set_error("subdomain block too large for the update kernel");
+        return DDROM_EINVAL;
+    }
+    const int NN = kUpdShapes[pick][0], MG = kUpdShapes[pick][1];
+    const size_t lds = (size_t)upd_lds(m->n_sub, m->n_C, std::max(1, m->mmax), NN, MG).total * sizeof(double);
+    if (lds > 65536) {
+        set_error("KKT update needs more than 64 KiB of LDS (too many subdomains or constraints)");
+        return DDROM_EINVAL;
+    }
+    const int nw = std::max(1, std::min(8, m->n_sub));
+#define UPD_CASE(A, G)                                                                                 \
+    if (NN == A && MG == G) hipLaunchKernelGGL((k_update<A, G>), dim3(B), dim3(64 * nw), lds, s, ua);
+    UPD_CASE(3, 1) UPD_CASE(4, 0) UPD_CASE(5, 2) UPD_CASE(6, 0) UPD_CASE(6, 2) UPD_CASE(8, 0) UPD_CASE(9, 3)
+    UPD_CASE(12, 4) UPD_CASE(18, 6) UPD_CASE(20, 12)
+#undef UPD_CASE
+    HIPCHECK(hipGetLastError());
+    return 0;
 }
 
 static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const UpdArgs& ua, hipStream_t s) {
     int rc;
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, ws->counter);
-    if ((rc = evaluate_round(m, ws, prec, B, ws->st, ws->xt, s))) return rc;
+    if ((rc = evaluate_round(m, ws, prec, B, ws->live, ws->counter, ws->xt, s))) return rc;
+    ModelDevInts di = get_ints(m);
     const int n_etiles = (m->estride + m->n_C * std::max(1, m->mmax) + 31) / 32;
-    hipLaunchKernelGGL(k_reduce, dim3(m->n_sub + 1, n_etiles, ws->Bp / 64), dim3(64), 0, s, m->n_sub, m->n_C, std::max(1, m->mmax),
-                       m->estride, ws->rs, ws->RS, ws->Bp, B, ua.n_om, ua.n_ga, ua.slot0, ua.cpart0, m->n_cparts,
-                       ws->gn_part, ws->c_part, ws->E_part, ws->st, ws->RB);
-    int nw = std::max(1, std::min(16, m->n_sub));
-    const int nhp = m->NNmax * (m->NNmax + 1) / 2;
-    while (nw > 1 && upd_lds(m->n_C, nw, m->NNmax, std::max(1, m->mmax), nhp, 64).total * 8 > 60 * 1024) --nw;
-    const size_t ulds = (size_t)upd_lds(m->n_C, nw, m->NNmax, std::max(1, m->mmax), nhp, 64).total * 8;
-    hipLaunchKernelGGL(k_update, dim3(B), dim3(64 * nw), ulds, s, ua);
+    hipLaunchKernelGGL(k_reduce, dim3(m->n_sub + 1, n_etiles, ws->Bp / 64), dim3(64), 0, s, m->n_sub, m->n_C,
+                       std::max(1, m->mmax), m->estride, ws->rs, ws->RS, ws->Bp, B, di.n_om, di.n_ga, di.slot0,
+                       di.cpart0, m->n_cparts, ws->gn_part, ws->c_part, ws->E_part, ws->counter, ws->RB);
+    if ((rc = launch_update(m, ua, B, s))) return rc;
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, B, ws->st, ws->live, ws->counter);
     HIPCHECK(hipGetLastError());
     return 0;
 }
@@ -1481,7 +1476,7 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
         {(void**)&w->lam, Bp * std::max(1, m->n_C) * sizeof(double)},
         {(void**)&w->lamt, Bp * std::max(1, m->n_C) * sizeof(double)},
         {(void**)&w->step, Bp * (m->n_D + m->n_C) * sizeof(double)},
-        {(void**)&w->Y, Bp * m->n_sub * (size_t)m->NNmax * (std::max(1, m->mmax) + 1) * sizeof(double)},
+        {(void**)&w->live, Bp * sizeof(int)},
         {(void**)&w->mu, Bp * 2 * sizeof(double)},
         {(void**)&w->RB, Bp * (size_t)(m->n_sub * (m->estride + m->n_C * std::max(1, m->mmax)) + std::max(1, m->n_C)) * sizeof(double)},
         {(void**)&w->st, Bp * sizeof(SolveState)},
@@ -1525,7 +1520,7 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
 void ddrom_workspace_destroy(ddrom_workspace* w) {
     if (!w) return;
     void* ptrs[] = {w->dec_out, w->bc, w->gn_part, w->c_part, w->E_part, w->x, w->xt, w->lam, w->lamt,
-                    w->step, w->Y, w->mu, w->st, w->counter, w->RB};
+                    w->step, w->live, w->mu, w->st, w->counter, w->RB};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->counter_h) (void)hipHostFree(w->counter_h);
@@ -1581,7 +1576,7 @@ static int decode_common(const ddrom_model* m, ddrom_workspace* ws, int sd, int 
     if (B == 0) return 0;
     const int seg = part * m->n_sub + sd;
     const ddrom::DecSeg& sg = m->segs_h[seg];
-    if ((rc = launch_decode<0>(m, prec, seg, seg + 1, xhat_d, sg.n, 0, nullptr, B, ws->dec_out, ws->Bp, s)))
+    if ((rc = launch_decode<0>(m, prec, seg, seg + 1, xhat_d, sg.n, 0, nullptr, nullptr, B, ws->dec_out, ws->Bp, s)))
         return rc;
     const long long tot = (long long)sg.rows * (1 + sg.n) * B;
     if (tot == 0) return 0;
@@ -1629,7 +1624,7 @@ int ddrom_gn_blocks(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
     if (m->n_bc > 0)
         hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
                            B, ws->Bp, m->nu, ws->bc);
-    if ((rc = evaluate_round(m, ws, precision, B, ws->st, ws->xt, s))) return rc;
+    if ((rc = evaluate_round(m, ws, precision, B, nullptr, nullptr, ws->xt, s))) return rc;
     ModelDevInts di = get_ints(m);
     hipLaunchKernelGGL(k_collect, dim3(B), dim3(256), 0, s, B, ws->Bp, m->n_sub, m->n_C, m->n_D, m->nmax,
                        std::max(1, m->mmax), m->estride, di.n_om, di.n_ga, di.xoff, di.slot0, di.cpart0, m->n_cparts, ws->gn_part,
@@ -1659,6 +1654,7 @@ static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double*
     if (m->n_bc > 0)
         hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
                            B, ws->Bp, m->nu, ws->bc);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, B, ws->st, ws->live, ws->counter);
     HIPCHECK(hipGetLastError());
     const UpdArgs ua = upd_args(m, ws, B, o, l0 != nullptr);
     const int prec = o->precision;
@@ -1761,17 +1757,17 @@ int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* 
         hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
                            B, ws->Bp, m->nu, ws->bc);
     // warm the decoder outputs once so the residual and constraint kernels read real data
-    if ((rc = evaluate_round(m, ws, precision, B, ws->st, ws->xt, s))) return rc;
+    if ((rc = evaluate_round(m, ws, precision, B, nullptr, nullptr, ws->xt, s))) return rc;
     auto timed = [&](int which, float* out) -> int {
         HIPCHECK(hipEventRecord(ws->t0, s));
         for (int r = 0; r < reps; ++r) {
             int c = 0;
-            if (which == 0) c = launch_decode<1>(m, precision, 0, m->n_sub, ws->xt, m->n_D, -1, ws->st, B, ws->dec_out,
-                                                 ws->Bp, s);
-            else if (which == 1) c = launch_decode<1>(m, precision, m->n_sub, 2 * m->n_sub, ws->xt, m->n_D, -1, ws->st,
-                                                      B, ws->dec_out, ws->Bp, s);
-            else if (which == 2) c = launch_res(m, precision, 0, m->n_sub, ws, ws->st, B, s);
-            else c = launch_con(m, precision, ws, ws->st, B, s);
+            if (which == 0) c = launch_decode<1>(m, precision, 0, m->n_sub, ws->xt, m->n_D, -1, nullptr, nullptr, B,
+                                                 ws->dec_out, ws->Bp, s);
+            else if (which == 1) c = launch_decode<1>(m, precision, m->n_sub, 2 * m->n_sub, ws->xt, m->n_D, -1,
+                                                      nullptr, nullptr, B, ws->dec_out, ws->Bp, s);
+            else if (which == 2) c = launch_res(m, precision, 0, m->n_sub, ws, nullptr, nullptr, B, s);
+            else c = launch_con(m, precision, ws, nullptr, B, s);
             if (c) return c;
         }
         HIPCHECK(hipEventRecord(ws->t1, s));
