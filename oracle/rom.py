@@ -224,12 +224,16 @@ def sqp_step(model: ROMModel, mu, xhat, lam, opts: SQPOptions, ev: Evaluation | 
 
 
 def sqp_solve(model: ROMModel, mu, xhat0: np.ndarray | None = None, lam0: np.ndarray | None = None,
-              opts: SQPOptions = SQPOptions()) -> SQPResult:
+              opts: SQPOptions = SQPOptions(), f_ref: float | None = None) -> SQPResult:
+    """SQP from (xhat0, lam0) (zero latents and the least-squares multiplier by default).
+    The relative tolerance and the stagnation test are taken relative to f_ref, by default
+    the first KKT residual norm of this start."""
     x = np.zeros(model.n_D) if xhat0 is None else np.array(xhat0, dtype=np.float64)
     ev = evaluate(model, mu, x)
     lam = initial_multiplier(model, ev) if lam0 is None else np.array(lam0, dtype=np.float64)
     F = kkt_rhs(model, ev, lam)
-    f0 = fn = float(np.linalg.norm(F))
+    fn = float(np.linalg.norm(F))
+    f0 = fn if f_ref is None else float(f_ref)
     n_eval = 1
     hist = [fn]
     if not np.isfinite(fn):
@@ -245,6 +249,27 @@ def sqp_solve(model: ROMModel, mu, xhat0: np.ndarray | None = None, lam0: np.nda
             return SQPResult(x, lam, st, k, fn, f0, n_eval, hist)
     status = CONVERGED if fn <= tol else MAX_ITER
     return SQPResult(x, lam, status, opts.max_iter, fn, f0, n_eval, hist)
+
+
+def sqp_solve_warm(model: ROMModel, mu, xhat0: np.ndarray, lam0: np.ndarray, opts: SQPOptions = SQPOptions()):
+    """SQP warm-started from a proposal (xhat0, lam0), with the zero start as fallback: the
+    zero start's first KKT residual norm f_zero (zero latents, least-squares multiplier) is
+    computed first; the proposal is used only if its own first norm is finite and not larger.
+    Tolerances are relative to f_zero either way.  Returns (result, used_fallback, f_zero,
+    f_proposal)."""
+    from .proposal import use_zero_start
+    x_z = np.zeros(model.n_D)
+    ev_z = evaluate(model, mu, x_z)
+    lam_z = initial_multiplier(model, ev_z)
+    f_zero = float(np.linalg.norm(kkt_rhs(model, ev_z, lam_z)))
+    ev_p = evaluate(model, mu, np.asarray(xhat0, dtype=np.float64))
+    f_prop = float(np.linalg.norm(kkt_rhs(model, ev_p, np.asarray(lam0, dtype=np.float64))))
+    fb = use_zero_start(f_prop, f_zero)
+    if fb:
+        res = sqp_solve(model, mu, x_z, lam_z, opts, f_ref=f_zero)
+    else:
+        res = sqp_solve(model, mu, xhat0, lam0, opts, f_ref=f_zero)
+    return res, fb, f_zero, f_prop
 
 
 # ----------------------------------------------------------------------------------

@@ -67,3 +67,26 @@ def spawn_seeds(seed: int, n: int) -> list[int]:
     """n independent child seeds derived from one seed (SeedSequence.spawn)."""
     ss = np.random.SeedSequence(int(seed))
     return [int(c.generate_state(1)[0]) for c in ss.spawn(n)]
+
+
+def mlp_init(sizes, seed: int) -> list:
+    """Glorot-uniform weights and zero biases of a dense network with layer widths `sizes`
+    (input first).  Returns [(W [out][in], b [out]), ...]; one spawned seed per layer."""
+    seeds = spawn_seeds(seed, len(sizes) - 1)
+    out = []
+    for k in range(len(sizes) - 1):
+        fi, fo = sizes[k], sizes[k + 1]
+        out.append((glorot_uniform(fi, fo, (fo, fi), rng(seeds[k])), np.zeros(fo)))
+    return out
+
+
+def train_split(n: int, frac_test: float, seed: int):
+    """Seeded permutation of range(n) split into (train, test) index arrays."""
+    p = rng(seed).permutation(n)
+    n_test = int(round(frac_test * n))
+    return np.sort(p[n_test:]), np.sort(p[:n_test])
+
+
+def epoch_order(n: int, seed: int, epoch: int) -> np.ndarray:
+    """Minibatch visiting order of one training epoch (a seeded permutation of range(n))."""
+    return np.random.Generator(np.random.PCG64([int(seed), int(epoch)])).permutation(n)
