@@ -2,13 +2,18 @@
 
 Workload (default): steady 2D Burgers on a 240x240 interior grid, 4x4 subdomains,
 latents (n^Omega, n^Gamma) = (8, 4), decoder width 2x DoFs, three-band mask with b = 9,
-HR on 10% of each subdomain's nodes, 512 held-out (a, lambda) drawn uniformly, zero
-start, FP32 decoders with FP64 residual / Gauss-Newton blocks / KKT / line search.
-One step = one rom_solve_batch call over the 512 parameters (all solver rounds, replayed
-from a captured HIP graph).  value = solves per second over the timed steps.
+HR on 10% of each subdomain's nodes, 512 held-out (a, lambda) drawn uniformly, FP32
+decoders with FP64 residual / Gauss-Newton blocks / KKT / line search.  Solves are
+warm-started from the learned proposal (2 -> 256 -> 256 -> 224 SiLU network trained on the
+method's own solves) with the zero start as fallback.
+One step = one rom_solve_warm call over the 512 parameters (proposal inference and all
+solver rounds, replayed from a captured HIP graph).  value = solves per second over the
+timed steps.  The zero-start batch (rom_solve_batch) is timed the same way beside it.
 
 The model pack (trained decoders, HR nodes, C) is read from models/<config>.npz, which the
-offline pipeline writes (python -m oracle.build_model <config>).
+offline pipeline writes (python -m oracle.build_model <config>); the proposal from
+models/<config>_mlp.npz (python -m paper_2305_15163_amd.train_proposal).  Without the
+proposal file the zero-start batch is the headline.
 
 Also reported: the dominant kernel's roofline figures (HIP-event timed launches on the
 library's stream), plain per-solve GPU SQP (B = 1, FP64, sequential calls) and the CPU
@@ -100,21 +105,45 @@ def main():
                status=torch.empty((B,), dtype=torch.int32, device="cuda"),
                fnorm=torch.empty((B,), **f), fnorm0=torch.empty((B,), **f))
 
-    for w in range(a.warmup):
+    out["fallback"] = torch.empty((B,), dtype=torch.int32, device="cuda")
+    ppath = os.path.join(ROOT, "models", f"{a.config}_mlp.npz")
+    prop = dr.Proposal.from_pack(dict(np.load(ppath, allow_pickle=False))) if os.path.exists(ppath) else None
+    if prop is None:
+        print(f"[bench] no proposal at {ppath}: zero start only", file=sys.stderr, flush=True)
+
+    def run_cold():
         dr.rom_solve_batch(model, ws, mu, o, out=out)
+
+    def run_warm():
+        dr.rom_solve_warm(model, ws, prop, mu, o, out=out)
+
+    def timed(fn, tag):
+        for w in range(a.warmup):
+            fn()
+            torch.cuda.synchronize()
+            print(f"[bench] {tag} warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        print(f"[bench] warmup {w + 1}/{a.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        dr.rom_solve_batch(model, ws, mu, o, out=out)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    print(f"[bench] timed {a.steps} steps in {dt:.3f}s", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        for k in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"[bench] {tag}: timed {a.steps} steps in {dt:.3f}s", file=sys.stderr, flush=True)
+        res = {k: v.cpu().numpy().copy() for k, v in out.items()}
+        return dt, res
+
+    dt_c, res_c = timed(run_cold, "zero start")
+    cold = {"solves_per_s": B * a.steps / dt_c, "ms_per_step": 1e3 * dt_c / a.steps,
+            "iters_mean": float(res_c["iters"].mean()), "iters_max": int(res_c["iters"].max()),
+            "status_counts": {dr.STATUS[k]: int((res_c["status"] == k).sum()) for k in np.unique(res_c["status"])}}
+    if prop is not None:
+        dt, res = timed(run_warm, "warm start")
+    else:
+        dt, res = dt_c, res_c
     value = B * a.steps / dt
-    iters = out["iters"].cpu().numpy()
-    status = out["status"].cpu().numpy()
-    xb = out["xhat"].cpu().numpy()
+    iters = res["iters"]
+    status = res["status"]
+    xb = res["xhat"]
 
     # dominant kernel: interior decoder subnets, every solve live
     ms = dr.time_kernels(model, ws, mu, torch.zeros((B, model.n_D), **f), precision=cfg["precision"], reps=20)
@@ -160,9 +189,12 @@ def main():
         "dtype": "f32+f64" if cfg["precision"] == 1 else "f64", "data": "synthetic",
         "config": {"workload": cfg["workload"], "batch": B, "subdomains": model.n_sub, "n_D": model.n_D,
                    "n_C": model.n_C, "stop": f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
-                                             f"or line-search stagnation below {cfg['stall_tol']:g} ||F0||"},
+                                             f"or line-search stagnation below {cfg['stall_tol']:g} ||F0||",
+                   "start": ("learned proposal, zero-start fallback" if prop is not None else "zero start")},
         "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
         "status_counts": {dr.STATUS[k]: int((status == k).sum()) for k in np.unique(status)},
+        "fallback_count": int(res["fallback"].sum()) if prop is not None else None,
+        "zero_start": cold,
         "roofline": roof,
         "plain_sqp": plain,
         "speedup_vs_plain": (value / plain["solves_per_s"]) if plain else None,
@@ -188,7 +220,7 @@ def main():
                                               f"relative KKT tolerance 1e-8, BLAS limited to 1 thread"}
             # error against the FOM on a few parameters: batched (this run) and plain SQP
             errs, perrs = [], []
-            for b in range(min(2, B)):
+            for b in range(min(3, B)):
                 xf = solve_fom(om.fom, mu_h[b]).x
                 errs.append(relative_error(om, xb[b], xf))
                 if plain is not None and b < len(px):

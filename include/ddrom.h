@@ -175,6 +175,62 @@ int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
                     double* xhat_d, double* lam_d, int* iters_d, int* status_d, double* fnorm_d,
                     double* fnorm0_d, hipStream_t s);
 
+/* ---- Learned initial iterate --------------------------------------------------------
+ * A dense network maps the Burgers parameters mu = (a, lambda) to a proposal for every
+ * subdomain's latents and the multipliers; it stands where the paper interpolates training
+ * solutions to start its online solves (Section 6).  Inputs (log10 a, lambda), each mapped
+ * affinely onto [-1, 1] over a in [1, 1e4], lambda in [5, 20]; layers W_k [out][in], b_k [out]
+ * with SiLU after every layer but the last; the outputs are standardised, so the proposal is
+ * y * out_std + out_mean: components [0, n_D) are xhat, the rest lambda.  FP32 arithmetic. */
+typedef struct ddrom_mlp ddrom_mlp;
+typedef struct ddrom_mlp_trainer ddrom_mlp_trainer;
+
+typedef struct {
+    int n_layers;               /* dense layers, 1..8 */
+    const int* sizes;           /* [n_layers + 1] widths, input first (2); hidden widths <= 512 */
+    const float* params;        /* host: W_0, b_0, W_1, b_1, ... packed, W_k row-major [out][in] */
+    const double* out_mean;     /* host [sizes[n_layers]] (unused by the trainer) */
+    const double* out_std;      /* host [sizes[n_layers]] (unused by the trainer) */
+    int n_D;                    /* leading outputs that are latents */
+} ddrom_mlp_desc;
+
+/* Device copy of a trained network (immutable after create). */
+int ddrom_mlp_create(const ddrom_mlp_desc* d, ddrom_mlp** out);
+void ddrom_mlp_destroy(ddrom_mlp* p);
+/* query 0: parameter count, 1: output width, 2: n_D; -1 on error. */
+long long ddrom_mlp_size(const ddrom_mlp* p, int query);
+
+/* Proposal for B parameters: mu_d [B][2] -> xhat0_d [B][n_D], lam0_d (nullable)
+ * [B][outputs - n_D], all FP64 device memory owned by the caller. */
+int mlp_proposal(const ddrom_mlp* p, const double* mu_d, int B, double* xhat0_d, double* lam0_d, hipStream_t s);
+
+/* Trainer: FP32 master weights initialised from d->params, Adam moments (beta 0.9, 0.999,
+ * eps 1e-8) and activation buffers for minibatches of up to max_batch rows. */
+int ddrom_mlp_trainer_create(const ddrom_mlp_desc* d, int max_batch, ddrom_mlp_trainer** out);
+void ddrom_mlp_trainer_destroy(ddrom_mlp_trainer* t);
+/* query 0: parameter count, 1: output width. */
+long long ddrom_mlp_trainer_size(const ddrom_mlp_trainer* t, int query);
+/* Copy the current weights (packed as in ddrom_mlp_desc) to device memory params_d. */
+int ddrom_mlp_trainer_params(const ddrom_mlp_trainer* t, float* params_d, hipStream_t s);
+
+/* One minibatch: rows_d [B] index the training set mu_d [N][2] (FP64) and standardised
+ * targets target_d [N][outputs] (FP32).  Forward, mean squared error over the B x outputs
+ * entries, gradient by back-propagation; grad_d (nullable, device [n_params]) receives the
+ * gradient; loss_d (nullable, device [1]) the loss before the update; update != 0 applies
+ * one Adam step with learning rate lr.  1 <= B <= max_batch. */
+int mlp_train_step(ddrom_mlp_trainer* t, const double* mu_d, const float* target_d, const int* rows_d, int B,
+                   float lr, int update, float* loss_d, float* grad_d, hipStream_t s);
+
+/* rom_solve_batch warm-started from the network's proposal, with the zero start (zero
+ * latents, least-squares multiplier) as fallback: each solve evaluates the zero start's first
+ * KKT residual norm f_zero, then the proposal's; the proposal is kept only if its norm is
+ * finite and not larger than f_zero.  Tolerances are relative to f_zero (fnorm0_d receives
+ * it).  fallback_d (nullable) [B]: 1 where the zero start was used.  Outputs as in
+ * rom_solve_batch. */
+int rom_solve_warm(const ddrom_model* m, ddrom_workspace* ws, const ddrom_mlp* p, const double* mu_d, int B,
+                   const ddrom_opts* o, double* xhat_d, double* lam_d, int* iters_d, int* status_d, double* fnorm_d,
+                   double* fnorm0_d, int* fallback_d, hipStream_t s);
+
 /* Measurement helper: average device time (ms) per launch of the four evaluation kernels
  * of one solver round, ms_h[0] interior decoder subnets, [1] interface decoders,
  * [2] HR residual + Gauss-Newton blocks, [3] weak constraint, each launched `reps` times

@@ -38,6 +38,15 @@ CONFIGS = {
     # 240x240 grid, 4x4, latent 8 -> (8,4), width 2x, band 9, HR 10%
     "cfg1": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID,
                  epochs=1000, batch=32, train_grid=(16, 16), hr_frac=0.10, seed=1),
+    # uneven batch: three models whose subdomains are all 60 x 60 nodes, with per-subdomain
+    # latent sizes drawn from {4, 6, 8, 12} (interface half of it) and HR fractions drawn
+    # from [5%, 25%]; a reduced training budget (8 x 8 parameter grid, 300 epochs)
+    "cfg2a": dict(nx=120, ny=120, nsx=2, nsy=2, n_om="draw", n_ga="half", b=9, s=2, act=ACT_SIGMOID,
+                  epochs=300, batch=16, train_grid=(8, 8), hr_frac=(0.05, 0.25), seed=21),
+    "cfg2b": dict(nx=240, ny=240, nsx=4, nsy=4, n_om="draw", n_ga="half", b=9, s=2, act=ACT_SIGMOID,
+                  epochs=300, batch=16, train_grid=(8, 8), hr_frac=(0.05, 0.25), seed=22),
+    "cfg2c": dict(nx=480, ny=480, nsx=8, nsy=8, n_om="draw", n_ga="half", b=9, s=2, act=ACT_SIGMOID,
+                  epochs=300, batch=16, train_grid=(8, 8), hr_frac=(0.05, 0.25), seed=23),
     # small configurations for tests
     "tiny": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID,
                  epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
@@ -76,6 +85,21 @@ def _train_job(args):
     return tag, dec, rep, time.time() - t0
 
 
+def per_subdomain_choices(cfg: dict, n_sub: int):
+    """Latent sizes and HR fractions per subdomain: fixed by the configuration, or drawn
+    (seeded) for the uneven batch: n^Omega uniform over {4, 6, 8, 12}, n^Gamma = n^Omega / 2,
+    HR fraction uniform over the given interval."""
+    g = si.rng(cfg["seed"] + 1000)
+    if cfg["n_om"] == "draw":
+        n_om = [int(v) for v in g.choice([4, 6, 8, 12], size=n_sub)]
+    else:
+        n_om = [int(cfg["n_om"])] * n_sub
+    n_ga = [v // 2 for v in n_om] if cfg["n_ga"] == "half" else [int(cfg["n_ga"])] * n_sub
+    hf = cfg["hr_frac"]
+    hr = list(g.uniform(hf[0], hf[1], size=n_sub)) if isinstance(hf, tuple) else [float(hf)] * n_sub
+    return n_om, n_ga, hr
+
+
 def build(name: str, workers: int = 8, verbose=True):
     cfg = CONFIGS[name]
     g = Grid(cfg["nx"], cfg["ny"])
@@ -87,11 +111,12 @@ def build(name: str, workers: int = 8, verbose=True):
         print(f"[{name}] {len(mus)} FOM snapshots, {len(Rsnap)} residual snapshots in {time.time() - t0:.1f}s", flush=True)
 
     seeds = si.spawn_seeds(cfg["seed"], 2 * dd.n_sub + 1)
+    n_om, n_ga, hr_frac = per_subdomain_choices(cfg, dd.n_sub)
     jobs = []
     for i, sd in enumerate(dd.subdomains):
-        jobs.append((X[:, sd.omega], len(sd.omega), cfg["n_om"], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i],
+        jobs.append((X[:, sd.omega], len(sd.omega), n_om[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i],
                      cfg["epochs"], cfg["batch"], ("om", i)))
-        jobs.append((X[:, sd.gamma], len(sd.gamma), cfg["n_ga"], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i + 1],
+        jobs.append((X[:, sd.gamma], len(sd.gamma), n_ga[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i + 1],
                      cfg["epochs"], cfg["batch"], ("ga", i)))
     jobs.sort(key=lambda j: -j[1])        # largest first
     t0 = time.time()
@@ -113,10 +138,10 @@ def build(name: str, workers: int = 8, verbose=True):
         Ri = Rsnap[:, sd.res_rows].T                      # N_i^r x n_snap
         Phi = pod_basis(Ri, 1e-10)
         n_own = len(sd.own_nodes)
-        k = int(round(cfg["hr_frac"] * n_own))
+        k = int(round(hr_frac[i] * n_own))
         loc = greedy_sample(Phi, n_own, k)
         hr_nodes.append(sd.own_nodes[loc])
-    n_C = sum(cfg["n_ga"] for _ in dd.subdomains) // 2
+    n_C = sum(n_ga) // 2
     C = si.gaussian_matrix(n_C, dd.n_A, seeds[-1])
     pack = dict(nx=g.nx, ny=g.ny, nu=g.nu, ly=g.ly, nsx=cfg["nsx"], nsy=cfg["nsy"], act=cfg["act"],
                 n_sub=dd.n_sub, C=C)

@@ -140,12 +140,20 @@ struct ddrom_model {
 };
 
 struct SolveState {
-    int phase;      // 0 initial evaluation, 1 line-search trial, 2 stopped
+    int phase;      // 0 initial evaluation, 1 line-search trial, 2 stopped, 3 zero start of a warm solve
     int status;
     int iters;
     int nbt;
+    int flags;      // SF_* bits
+    int pad;
     double alpha, phi0, tol, f0, fn;
+    double fz;      // first KKT residual norm of the zero start (warm solves)
 };
+// SolveState::flags
+constexpr int SF_WARM = 1;       // the proposal's first evaluation is pending comparison with fz
+constexpr int SF_FALLBACK = 2;   // the proposal was rejected; the solve runs from the zero start
+constexpr int SF_LAMFIX = 4;     // the initial multiplier is given (no least-squares start)
+constexpr int SF_REF = 8;        // tolerances are relative to fz
 
 struct ddrom_workspace {
     const ddrom_model* m = nullptr;

@@ -46,7 +46,7 @@ void set_error(const std::string& msg) { g_err = msg; }
     } while (0)
 
 static constexpr int RING = 64;
-static constexpr int PH_INIT = 0, PH_TRIAL = 1, PH_DONE = 2;
+static constexpr int PH_INIT = 0, PH_TRIAL = 1, PH_DONE = 2, PH_ZERO = 3;
 static constexpr int KKT_NN = 20;     // max n_i^Omega + n_i^Gamma
 static constexpr int KKT_MG = 12;     // max n_i^Gamma
 static constexpr int KKT_NC = 64;     // n_C < KKT_NC
@@ -699,7 +699,8 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
 
     // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i ||, by its normal
     //      equations (sum_i Ehat_i Ehat_i^T) lambda = -sum_i Ehat_i g_i^Gamma ----
-    if (S.phase == PH_INIT && !a.lam_given && nC > 0) {
+    const bool ls_start = S.phase == PH_ZERO || (S.phase == PH_INIT && !(S.flags & SF_LAMFIX));
+    if (ls_start && !a.lam_given && nC > 0) {
         for (int e = tid; e < nC * ld; e += nth) {
             const int i = e / ld, jj = e % ld;
             double s = 0.0;
@@ -744,9 +745,43 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
 
     // ---- decision (every thread evaluates it identically) ----
     int action = 0;   // 0: compute step, 1: backtrack, 2: stop
+    if (S.phase == PH_ZERO) {
+        // zero start of a warm solve: keep its norm and multiplier, then evaluate the proposal
+        // (held in x, lam); the multiplier waits in the step buffer's lambda part
+        double* stp = a.step + (size_t)b * (nD + nC);
+        for (int jj = tid; jj < nC; jj += nth) {
+            stp[nD + jj] = lam_s[jj];
+            a.lamt[(size_t)b * nC + jj] = a.lam[(size_t)b * nC + jj];
+        }
+        for (int e = tid; e < nD; e += nth) a.xt[(size_t)b * nD + e] = a.x[(size_t)b * nD + e];
+        if (tid == 0) {
+            S.fz = isfinite(fn_t) ? fn_t : INFINITY;
+            S.flags |= SF_WARM | SF_LAMFIX | SF_REF;
+            S.phase = PH_INIT;
+            a.st[b] = S;
+        }
+        return;
+    }
+    if (S.phase == PH_INIT && (S.flags & SF_WARM)) {
+        S.flags &= ~SF_WARM;
+        if (!(isfinite(fn_t) && fn_t <= S.fz)) {
+            // fallback: the proposal's first residual is larger than the zero start's
+            const double* stp = a.step + (size_t)b * (nD + nC);
+            for (int jj = tid; jj < nC; jj += nth) a.lamt[(size_t)b * nC + jj] = stp[nD + jj];
+            for (int e = tid; e < nD; e += nth) {   // both the accepted and the trial point restart at zero
+                a.x[(size_t)b * nD + e] = 0.0;
+                a.xt[(size_t)b * nD + e] = 0.0;
+            }
+            if (tid == 0) {
+                S.flags |= SF_FALLBACK;
+                a.st[b] = S;
+            }
+            return;
+        }
+    }
     if (S.phase == PH_INIT) {
-        S.f0 = fn_t;
-        S.tol = fmax(a.tol_abs, a.tol_rel * fn_t);
+        S.f0 = (S.flags & SF_REF) ? S.fz : fn_t;
+        S.tol = fmax(a.tol_abs, a.tol_rel * S.f0);
         S.fn = fn_t;
         if (!isfinite(fn_t)) {
             S.status = DDROM_STATUS_NONFINITE;
@@ -964,18 +999,27 @@ __global__ __launch_bounds__(1024) void k_compact(int B, const SolveState* __res
     if (tid == 0) n_live[0] = base;
 }
 
+// warm != 0: x and lam already hold a proposal; the first round evaluates the zero start.
 __global__ void k_init(int B, int Bp, int nD, int nC, const double* __restrict__ mu, const double* __restrict__ x0,
                        const double* __restrict__ l0, double* __restrict__ mu_ws, double* __restrict__ x,
                        double* __restrict__ xt, double* __restrict__ lam, double* __restrict__ lamt,
-                       SolveState* __restrict__ st) {
+                       SolveState* __restrict__ st, int warm) {
     const int b = blockIdx.x;
     if (b >= Bp) return;
     for (int e = threadIdx.x; e < nD; e += blockDim.x) {
+        if (warm) {
+            xt[(size_t)b * nD + e] = 0.0;
+            continue;
+        }
         const double v = (b < B && x0) ? x0[(size_t)b * nD + e] : 0.0;
         x[(size_t)b * nD + e] = v;
         xt[(size_t)b * nD + e] = v;
     }
     for (int j = threadIdx.x; j < nC; j += blockDim.x) {
+        if (warm) {
+            lamt[(size_t)b * nC + j] = 0.0;
+            continue;
+        }
         const double v = (b < B && l0) ? l0[(size_t)b * nC + j] : 0.0;
         lam[(size_t)b * nC + j] = v;
         lamt[(size_t)b * nC + j] = v;
@@ -984,7 +1028,10 @@ __global__ void k_init(int B, int Bp, int nD, int nC, const double* __restrict__
         mu_ws[2 * b] = b < B ? mu[2 * b] : 1.0;
         mu_ws[2 * b + 1] = b < B ? mu[2 * b + 1] : 5.0;
         SolveState s;
-        s.phase = b < B ? PH_INIT : PH_DONE;
+        s.phase = b < B ? (warm ? PH_ZERO : PH_INIT) : PH_DONE;
+        s.flags = 0;
+        s.pad = 0;
+        s.fz = 0.0;
         s.status = DDROM_STATUS_MAX_ITER;
         s.iters = 0;
         s.nbt = 0;
@@ -1000,7 +1047,7 @@ __global__ void k_init(int B, int Bp, int nD, int nC, const double* __restrict__
 __global__ void k_finalize(int B, int nD, int nC, const double* __restrict__ x, const double* __restrict__ lam,
                            const SolveState* __restrict__ st, double* __restrict__ xo, double* __restrict__ lo,
                            int* __restrict__ it, int* __restrict__ status, double* __restrict__ fn,
-                           double* __restrict__ f0) {
+                           double* __restrict__ f0, int* __restrict__ fallback) {
     const int b = blockIdx.x;
     if (b >= B) return;
     for (int e = threadIdx.x; e < nD; e += blockDim.x) xo[(size_t)b * nD + e] = x[(size_t)b * nD + e];
@@ -1011,6 +1058,7 @@ __global__ void k_finalize(int B, int nD, int nC, const double* __restrict__ x, 
         if (status) status[b] = st[b].status;
         if (fn) fn[b] = st[b].fn;
         if (f0) f0[b] = st[b].f0;
+        if (fallback) fallback[b] = (st[b].flags & SF_FALLBACK) ? 1 : 0;
     }
 }
 
@@ -1620,7 +1668,7 @@ int ddrom_gn_blocks(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
     }
     if (B == 0) return 0;
     hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, s, B, ws->Bp, m->n_D, m->n_C, mu_d, xhat_d,
-                       (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt, ws->st);
+                       (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt, ws->st, 0);
     if (m->n_bc > 0)
         hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
                            B, ws->Bp, m->nu, ws->bc);
@@ -1635,22 +1683,34 @@ int ddrom_gn_blocks(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
 
 struct FinalOut {
     double *x, *lam, *fn, *f0;
-    int *it, *status;
+    int *it, *status, *fallback;
 };
 
+// prop != nullptr: warm start from the network's proposal, the zero start as fallback.
 static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, const double* x0,
-                        const double* l0, const ddrom_opts* o, hipStream_t caller, int use_graph, const FinalOut& fo) {
+                        const double* l0, const ddrom_opts* o, hipStream_t caller, int use_graph, const FinalOut& fo,
+                        const ddrom_mlp* prop = nullptr) {
     int rc = check_ws(m, ws, B);
     if (rc) return rc;
     if (!mu_d || !o || o->max_iter < 0 || o->max_backtracks < 0 || (o->precision != 0 && o->precision != 1)) {
         set_error("bad arguments to the solver");
         return DDROM_EINVAL;
     }
+    const int warm = prop != nullptr;
+    if (warm && (ddrom_mlp_size(prop, 2) != m->n_D || ddrom_mlp_size(prop, 1) != (long long)m->n_D + m->n_C)) {
+        set_error("proposal network outputs do not match the model's latents and multipliers");
+        return DDROM_ESHAPE;
+    }
     hipStream_t s = ws->stream;
     HIPCHECK(hipEventRecord(ws->ev_in, caller));
     HIPCHECK(hipStreamWaitEvent(s, ws->ev_in, 0));
+    if (warm) {
+        if ((rc = mlp_proposal(prop, mu_d, B, ws->x, m->n_C > 0 ? ws->lam : nullptr, s))) return rc;
+        x0 = nullptr;
+        l0 = nullptr;
+    }
     hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, s, B, ws->Bp, m->n_D, m->n_C, mu_d, x0, l0, ws->mu, ws->x,
-                       ws->xt, ws->lam, ws->lamt, ws->st);
+                       ws->xt, ws->lam, ws->lamt, ws->st, warm);
     if (m->n_bc > 0)
         hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
                            B, ws->Bp, m->nu, ws->bc);
@@ -1658,12 +1718,13 @@ static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double*
     HIPCHECK(hipGetLastError());
     const UpdArgs ua = upd_args(m, ws, B, o, l0 != nullptr);
     const int prec = o->precision;
-    // The first round evaluates the initial latents; later rounds are line-search trials.
-    const long long max_rounds = 1 + (long long)std::max(1, o->max_iter) * (o->max_backtracks + 1) + 1;
+    // The first round evaluates the initial latents; later rounds are line-search trials
+    // (a warm solve first evaluates the zero start, then the proposal, maybe the zero start again).
+    const long long max_rounds = 1 + (long long)std::max(1, o->max_iter) * (o->max_backtracks + 1) + 1 + 2 * warm;
     const int K = 8;
     std::ostringstream key;
     key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
-        << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << (l0 != nullptr);
+        << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << (l0 != nullptr) << ":" << warm;
     long long done = 0;
     if (use_graph) {
         if (ws->graph_key != key.str() || !ws->graph) {
@@ -1707,7 +1768,7 @@ static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double*
         }
     }
     hipLaunchKernelGGL(k_finalize, dim3(B), dim3(64), 0, s, B, m->n_D, m->n_C, ws->x, ws->lam, ws->st, fo.x, fo.lam,
-                       fo.it, fo.status, fo.fn, fo.f0);
+                       fo.it, fo.status, fo.fn, fo.f0, fo.fallback);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipEventRecord(ws->ev_out, s));
     HIPCHECK(hipStreamWaitEvent(caller, ws->ev_out, 0));
@@ -1725,7 +1786,7 @@ int sqp_step(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int 
     one.max_iter = 1;
     one.tol_abs = 0.0;
     one.tol_rel = 0.0;
-    FinalOut fo{xhat_d, lam_d, fnorm_d, nullptr, nullptr, status_d};
+    FinalOut fo{xhat_d, lam_d, fnorm_d, nullptr, nullptr, status_d, nullptr};
     return solve_common(m, ws, mu_d, B, xhat_d, lam_d, &one, s, 0, fo);
 }
 
@@ -1737,8 +1798,20 @@ int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
         set_error("xhat_d is NULL");
         return DDROM_EINVAL;
     }
-    FinalOut fo{xhat_d, lam_d, fnorm_d, fnorm0_d, iters_d, status_d};
+    FinalOut fo{xhat_d, lam_d, fnorm_d, fnorm0_d, iters_d, status_d, nullptr};
     return solve_common(m, ws, mu_d, B, xhat0_d, lam0_d, o, s, 1, fo);
+}
+
+int rom_solve_warm(const ddrom_model* m, ddrom_workspace* ws, const ddrom_mlp* p, const double* mu_d, int B,
+                   const ddrom_opts* o, double* xhat_d, double* lam_d, int* iters_d, int* status_d, double* fnorm_d,
+                   double* fnorm0_d, int* fallback_d, hipStream_t s) {
+    if (B == 0) return 0;
+    if (!p || !xhat_d) {
+        set_error("bad arguments to rom_solve_warm");
+        return DDROM_EINVAL;
+    }
+    FinalOut fo{xhat_d, lam_d, fnorm_d, fnorm0_d, iters_d, status_d, fallback_d};
+    return solve_common(m, ws, mu_d, B, nullptr, nullptr, o, s, 1, fo, p);
 }
 
 int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, const double* xhat_d, int B,
@@ -1752,7 +1825,7 @@ int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* 
     hipStream_t s = ws->stream;
     HIPCHECK(hipDeviceSynchronize());
     hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, s, B, ws->Bp, m->n_D, m->n_C, mu_d, xhat_d,
-                       (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt, ws->st);
+                       (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt, ws->st, 0);
     if (m->n_bc > 0)
         hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, s, m->bc_xy_d, m->bc_field_d, m->n_bc, ws->mu,
                            B, ws->Bp, m->nu, ws->bc);

@@ -33,6 +33,11 @@ class ModelDesc(C.Structure):
                 ("hr_count", C.POINTER(C.c_int)), ("hr_nodes", C.POINTER(C.POINTER(C.c_int)))]
 
 
+class MlpDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int), ("sizes", C.POINTER(C.c_int)), ("params", C.POINTER(C.c_float)),
+                ("out_mean", C.POINTER(C.c_double)), ("out_std", C.POINTER(C.c_double)), ("n_D", C.c_int)]
+
+
 class Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol_abs", C.c_double), ("tol_rel", C.c_double), ("armijo_c1", C.c_double),
                 ("max_backtracks", C.c_int), ("precision", C.c_int), ("stall_tol", C.c_double)]
@@ -63,6 +68,18 @@ def lib():
         L.sqp_step.argtypes = [vp, vp, vp, ip, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rom_solve_batch.argtypes = [vp, vp, vp, ip, vp, vp, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp]
         L.ddrom_time_kernels.argtypes = [vp, vp, vp, vp, ip, ip, ip, C.POINTER(C.c_float)]
+        L.ddrom_mlp_create.argtypes = [C.POINTER(MlpDesc), C.POINTER(vp)]
+        L.ddrom_mlp_destroy.argtypes = [vp]
+        L.ddrom_mlp_size.argtypes = [vp, ip]
+        L.ddrom_mlp_size.restype = C.c_longlong
+        L.mlp_proposal.argtypes = [vp, vp, ip, vp, vp, vp]
+        L.ddrom_mlp_trainer_create.argtypes = [C.POINTER(MlpDesc), ip, C.POINTER(vp)]
+        L.ddrom_mlp_trainer_destroy.argtypes = [vp]
+        L.ddrom_mlp_trainer_size.argtypes = [vp, ip]
+        L.ddrom_mlp_trainer_size.restype = C.c_longlong
+        L.ddrom_mlp_trainer_params.argtypes = [vp, vp, vp]
+        L.mlp_train_step.argtypes = [vp, vp, vp, vp, ip, C.c_float, ip, vp, vp, vp]
+        L.rom_solve_warm.argtypes = [vp, vp, vp, vp, ip, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -253,3 +270,120 @@ def time_kernels(model: Model, ws: Workspace, mu, xhat, precision=PREC_FP32_DECO
     ms = (C.c_float * 4)()
     _check(lib().ddrom_time_kernels(model.h, ws.h, _ptr(mu), _ptr(xhat), B, precision, reps, ms), "ddrom_time_kernels")
     return list(ms)
+
+
+# ---- learned initial iterate ---------------------------------------------------------
+
+def pack_mlp_params(layers) -> np.ndarray:
+    """[(W [out][in], b [out]), ...] -> the packed FP32 parameter vector of ddrom_mlp_desc."""
+    return np.concatenate([np.concatenate([np.asarray(W, dtype=np.float32).ravel(), np.asarray(b, dtype=np.float32)])
+                           for W, b in layers])
+
+
+def unpack_mlp_params(flat, sizes) -> list:
+    flat = np.asarray(flat)
+    out, o = [], 0
+    for k in range(len(sizes) - 1):
+        fi, fo = sizes[k], sizes[k + 1]
+        W = flat[o:o + fi * fo].reshape(fo, fi)
+        o += fi * fo
+        b = flat[o:o + fo]
+        o += fo
+        out.append((W, b))
+    return out
+
+
+def _mlp_desc(sizes, params, out_mean, out_std, n_D, keep):
+    sz = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    pr = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    n_out = int(sz[-1])
+    mn = np.ascontiguousarray(np.zeros(n_out) if out_mean is None else np.asarray(out_mean, dtype=np.float64))
+    sd = np.ascontiguousarray(np.ones(n_out) if out_std is None else np.asarray(out_std, dtype=np.float64))
+    keep += [sz, pr, mn, sd]
+    return MlpDesc(len(sz) - 1, sz.ctypes.data_as(C.POINTER(C.c_int)), pr.ctypes.data_as(C.POINTER(C.c_float)),
+                   mn.ctypes.data_as(C.POINTER(C.c_double)), sd.ctypes.data_as(C.POINTER(C.c_double)), int(n_D))
+
+
+class Proposal:
+    """Device copy of a trained proposal network (see mlp_proposal in include/ddrom.h)."""
+
+    def __init__(self, sizes, params, out_mean, out_std, n_D: int):
+        keep = []
+        d = _mlp_desc(sizes, params, out_mean, out_std, n_D, keep)
+        h = C.c_void_p()
+        _check(lib().ddrom_mlp_create(C.byref(d), C.byref(h)), "ddrom_mlp_create")
+        self.h = h
+        self.sizes = [int(v) for v in sizes]
+        self.n_D = int(n_D)
+        self.n_out = self.sizes[-1]
+
+    @classmethod
+    def from_pack(cls, pk: dict):
+        return cls(pk["sizes"], pk["params"], pk["out_mean"], pk["out_std"], int(pk["n_D"]))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ddrom_mlp_destroy(self.h)
+            self.h = None
+
+
+class ProposalTrainer:
+    """FP32 trainer of the proposal network (forward, back-propagation and Adam in HIP)."""
+
+    def __init__(self, sizes, params, max_batch: int):
+        keep = []
+        d = _mlp_desc(sizes, params, None, None, 0, keep)
+        h = C.c_void_p()
+        _check(lib().ddrom_mlp_trainer_create(C.byref(d), int(max_batch), C.byref(h)), "ddrom_mlp_trainer_create")
+        self.h = h
+        self.sizes = [int(v) for v in sizes]
+        self.n_params = int(lib().ddrom_mlp_trainer_size(h, 0))
+        self.max_batch = int(max_batch)
+
+    def step(self, mu, target, rows, lr: float = 1e-3, update: bool = True, loss: bool = False, grad: bool = False):
+        """One minibatch; mu [N][2] FP64, target [N][out] FP32 (standardised), rows [B] int32,
+        all device tensors.  Returns (loss tensor or None, gradient tensor or None)."""
+        B = int(rows.shape[0])
+        lt = torch.empty((1,), dtype=torch.float32, device="cuda") if loss else None
+        gt = torch.empty((self.n_params,), dtype=torch.float32, device="cuda") if grad else None
+        _check(lib().mlp_train_step(self.h, _ptr(mu), _ptr(target), _ptr(rows), B, float(lr), int(bool(update)),
+                                    _ptr(lt), _ptr(gt), _stream()), "mlp_train_step")
+        return lt, gt
+
+    def params(self):
+        out = torch.empty((self.n_params,), dtype=torch.float32, device="cuda")
+        _check(lib().ddrom_mlp_trainer_params(self.h, _ptr(out), _stream()), "ddrom_mlp_trainer_params")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ddrom_mlp_trainer_destroy(self.h)
+            self.h = None
+
+
+def mlp_proposal(p: Proposal, mu):
+    """(xhat0 [B][n_D], lam0 [B][outputs - n_D]) proposed for parameters mu [B][2]."""
+    mu = _dev(mu)
+    B = mu.shape[0]
+    f = dict(dtype=torch.float64, device="cuda")
+    x0 = torch.empty((B, p.n_D), **f)
+    l0 = torch.empty((B, max(1, p.n_out - p.n_D)), **f)
+    _check(lib().mlp_proposal(p.h, _ptr(mu), B, _ptr(x0), _ptr(l0), _stream()), "mlp_proposal")
+    return x0, l0[:, :p.n_out - p.n_D]
+
+
+def rom_solve_warm(model: Model, ws: Workspace, p: Proposal, mu, o: Opts, out=None):
+    """rom_solve_batch warm-started from the proposal (zero start as fallback).  Returns
+    dict(xhat, lam, iters, status, fnorm, fnorm0, fallback) of device tensors."""
+    mu = _dev(mu)
+    B = mu.shape[0]
+    if out is None:
+        f = dict(dtype=torch.float64, device="cuda")
+        i32 = dict(dtype=torch.int32, device="cuda")
+        out = dict(xhat=torch.empty((B, model.n_D), **f), lam=torch.empty((B, max(1, model.n_C)), **f),
+                   iters=torch.empty((B,), **i32), status=torch.empty((B,), **i32),
+                   fnorm=torch.empty((B,), **f), fnorm0=torch.empty((B,), **f), fallback=torch.empty((B,), **i32))
+    _check(lib().rom_solve_warm(model.h, ws.h, p.h, _ptr(mu), B, C.byref(o), _ptr(out["xhat"]), _ptr(out["lam"]),
+                                _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["fnorm"]), _ptr(out["fnorm0"]),
+                                _ptr(out["fallback"]), _stream()), "rom_solve_warm")
+    return out

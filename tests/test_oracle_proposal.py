@@ -105,9 +105,10 @@ def test_warm_start_fallback_and_exact_proposal(tiny_pack):
     opts = SQPOptions(max_iter=50, tol_abs=0.0, tol_rel=1e-10)
     cold = sqp_solve(model, mu, opts=opts)
     assert cold.status == CONVERGED
-    # a wild proposal is rejected and the solve is the zero-start solve
-    bad_x = np.full(model.n_D, 40.0)
-    bad_l = np.full(model.n_C, 1e6)
+    # zero latents with a non-least-squares multiplier: same constraint value as the zero start,
+    # larger interface rows of rho (lambda_LS minimises them), so it is rejected
+    bad_x = np.zeros(model.n_D)
+    bad_l = np.full(model.n_C, 1e3)
     res, fb, f_zero, f_prop = sqp_solve_warm(model, mu, bad_x, bad_l, opts)
     assert fb and f_prop > f_zero
     assert res.iters == cold.iters and np.array_equal(res.xhat, cold.xhat)
