@@ -136,8 +136,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     const DecSeg sg = segs[ch.seg];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nl = live_count(n_live, B);
-    if ((int)blockIdx.y * WAVES * 64 >= nl) return;     // every slot of this workgroup is idle
-    const int j = (blockIdx.y * WAVES + wave) * 64 + lane;
+    const int j0 = (int)blockIdx.y * WAVES * 64;
+    if (j0 >= nl) return;     // every slot of this workgroup is idle
+    // When the running solves fill only one or two of the workgroup's 64-slot groups (the
+    // last rounds of a batch), the idle waves take a share of the rows instead: G slot
+    // groups x R row parts.  Each wave keeps its own activation ring.
+    const int live_groups = min(WAVES, (nl - j0 + 63) / 64);
+    const int R = live_groups == 1 ? WAVES : ((live_groups == 2 && WAVES % 2 == 0) ? WAVES / 2 : 1);
+    const int G = WAVES / R;
+    const int group = wave % G, part = wave / G;
+    const int j = (blockIdx.y * WAVES + group) * 64 + lane;
     const bool act = j < nl;
     const int b = slot_solve(live, j, nl);
 
@@ -193,7 +201,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
             rs[0] = z;
         }
     };
-    for (int r = 0; r < nrows; ++r) {
+    const int r_begin = nrows * part / R, r_end = nrows * (part + 1) / R;
+    for (int r = r_begin; r < r_end; ++r) {
         const int2 q0 = sBd[r * 3 + 0], q1 = sBd[r * 3 + 1], q2 = sBd[r * 3 + 2];
         int lo = 0x7fffffff, hi = -1;
         if (q0.y > 0) { lo = min(lo, q0.x); hi = max(hi, q0.x + q0.y); }
@@ -356,27 +365,37 @@ __device__ __forceinline__ void accumulate_node(const NodeLoads<T, NO>& L, doubl
     rr += ru * ru + rv * rv;
 }
 
-// One wave = a run of sampled nodes of one subdomain x 64 solves.  For each node the ten
-// stencil DoFs are gathered without branches: every slot reads a value and NO Jacobian
-// entries from the decoder output (boundary slots read an all-zero block and take their
-// value from the per-solve Dirichlet buffer), so all loads of a node are in flight together,
-// and the next node's loads are issued before the current node is accumulated.  The
-// uniform source kind then selects which Jacobian columns each slot feeds.
+// One workgroup = a run of sampled nodes of one subdomain x 64 solve slots.  Its four waves
+// take consecutive quarters of the node run (short dependent chains, also when few solves
+// run) and their partial sums are combined in LDS in a fixed order, so every solve's sums
+// are formed the same way whatever the batch.  For each node the ten stencil DoFs are
+// gathered without branches: every slot reads a value and NO Jacobian entries from the
+// decoder output (boundary slots read an all-zero block and take their value from the
+// per-solve Dirichlet buffer), so all loads of a node are in flight together.  The uniform
+// source kind then selects which Jacobian columns each slot feeds.
 template <typename T, int NO, int NG>
-__global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchunks, int rbase,
-                                               const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
-                                               const int* __restrict__ gather, const T* __restrict__ dec,
-                                               const double* __restrict__ bc, const int* __restrict__ live,
-                                               const int* __restrict__ n_live, int B, int Bp, double nu, double hx, double hy,
-                                               double* __restrict__ part, int estride, long long zero_row) {
+__global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rchunks, int rbase,
+                                                const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
+                                                const int* __restrict__ gather, const T* __restrict__ dec,
+                                                const double* __restrict__ bc, const int* __restrict__ live,
+                                                const int* __restrict__ n_live, int B, int Bp, double nu, double hx,
+                                                double hy, double* __restrict__ part, int estride,
+                                                long long zero_row) {
     constexpr int NN = NO + NG;
     constexpr int NH = NN * (NN + 1) / 2;
+    constexpr int NE = NH + NN + 1;
+    constexpr int CH = 16;
+    __shared__ double red[3][CH][64];
+    const int nl = live_count(n_live, B);
+    const int j0 = blockIdx.y * 64;
+    if (j0 >= nl) return;
     const ResChunk rc = rchunks[rbase + blockIdx.x];
     const ResSeg rs = rsegs[rc.sd];
     const long long oo = segs[rs.seg_om].out, og = segs[rs.seg_ga].out;
-    const int nl = live_count(n_live, B);
-    if ((int)blockIdx.y * 64 >= nl) return;
-    const int j = blockIdx.y * 64 + threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, prt = tid >> 6;
+    const int j = j0 + lane;
+    const int np = rc.p1 - rc.p0;
+    const int pb = rc.p0 + np * prt / 4, pe = rc.p0 + np * (prt + 1) / 4;
     const T* dom = dec + (size_t)oo * Bp + j;
     const T* dga = dec + (size_t)og * Bp + j;
     const T* dz = dec + (size_t)zero_row * Bp + j;
@@ -387,25 +406,33 @@ __global__ __launch_bounds__(64) void k_res_gn(const ResChunk* __restrict__ rchu
 #pragma unroll
     for (int e = 0; e < NN; ++e) g[e] = 0.0;
     const int* gp = gather + rs.gather;
-    for (int p = rc.p0; p < rc.p1; ++p) {
+    for (int p = pb; p < pe; ++p) {
         NodeLoads<T, NO> A;
         load_node<T, NO, NG>(gp + (size_t)p * N_SLOTS, dom, dga, dz, bcb, Bp, A);
         accumulate_node<T, NO, NG>(A, nu, hx, hy, H, g, rr);
     }
     double* pp = part + (size_t)rc.slot * estride * Bp + j;
+    auto val = [&](int e) { return e < NH ? H[e] : (e < NH + NN ? g[e - NH] : rr); };
 #pragma unroll
-    for (int e = 0; e < NH; ++e) pp[(size_t)e * Bp] = H[e];
+    for (int c0 = 0; c0 < NE; c0 += CH) {
+        if (prt > 0)
 #pragma unroll
-    for (int e = 0; e < NN; ++e) pp[(size_t)(NH + e) * Bp] = g[e];
-    pp[(size_t)(NH + NN) * Bp] = rr;
+            for (int e = c0; e < c0 + CH && e < NE; ++e) red[prt - 1][e - c0][lane] = val(e);
+        __syncthreads();
+        if (prt == 0)
+#pragma unroll
+            for (int e = c0; e < c0 + CH && e < NE; ++e)
+                pp[(size_t)e * Bp] = ((val(e) + red[0][e - c0][lane]) + red[1][e - c0][lane]) + red[2][e - c0][lane];
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------------------------
 // Weak compatibility constraint: c_i = C A_i g_i^Gamma, E_i^Gamma = C A_i dg_i^Gamma/dxhat
 // ------------------------------------------------------------------------------------
-// One wave = (subdomain, 8 constraint rows, a run of interface rows) x 64 solves; (C A_i)^T
-// is stored row-major with stride ca_ld so the 8 multipliers of an interface row are one
-// contiguous scalar load.  Partial sums over interface-row runs go to separate slots.
+// One wave = (subdomain, 8 constraint rows, a run of interface rows) x 64 solve slots;
+// (C A_i)^T is stored row-major with stride ca_ld so the 8 multipliers of an interface row
+// are one contiguous scalar load.  Partial sums over interface-row runs go to separate slots.
 template <typename T, int NG>
 __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, const ResSeg* __restrict__ rsegs,
                                             const DecSeg* __restrict__ segs, const double* __restrict__ CA, int n_C,
@@ -455,23 +482,24 @@ __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, co
 }
 
 // ------------------------------------------------------------------------------------
-// Per-solve update: merit, Armijo, KKT (Schur complement on the block-arrow system)
-// ------------------------------------------------------------------------------------
-// ------------------------------------------------------------------------------------
 // Sum of the partial slots into one contiguous block per solve
 // ------------------------------------------------------------------------------------
-// Lanes are solves, so the partial sums are read coalesced; a 32-entry LDS tile is then
-// written out transposed, so that each solve's block [H packed | g | rr | E] per subdomain,
-// followed by c, is contiguous for the per-solve update wave.
-__global__ __launch_bounds__(64) void k_reduce(int n_sub, int n_C, int mmax, int estride, int rs, int RS, int Bp,
-                                               int B, const int* __restrict__ n_om, const int* __restrict__ n_ga,
-                                               const int* __restrict__ slot0, const int* __restrict__ cpart0,
-                                               int n_cparts, const double* __restrict__ gn_part,
-                                               const double* __restrict__ c_part, const double* __restrict__ E_part,
-                                               const int* __restrict__ n_live, double* __restrict__ RB) {
-    __shared__ double tile[32][65];
+// Lanes are solve slots, so the partial sums are read coalesced.  The four waves of a
+// workgroup take every fourth partial slot (short dependent chains when few solves run) and
+// their sums are combined in LDS in a fixed order; a 16-entry LDS tile is then written out
+// transposed, so that each slot's block [H packed | g | rr | E] per subdomain, followed by c,
+// is contiguous for the update kernel.
+constexpr int RED_E = 16;
+__global__ __launch_bounds__(256) void k_reduce(int n_sub, int n_C, int mmax, int estride, int rs, int RS, int Bp,
+                                                int B, const int* __restrict__ n_om, const int* __restrict__ n_ga,
+                                                const int* __restrict__ slot0, const int* __restrict__ cpart0,
+                                                int n_cparts, const double* __restrict__ gn_part,
+                                                const double* __restrict__ c_part, const double* __restrict__ E_part,
+                                                const int* __restrict__ n_live, double* __restrict__ RB) {
+    __shared__ double wpart[3][RED_E][64];
+    __shared__ double tile[RED_E][65];
     const int sd = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int b0 = blockIdx.z * 64, b = b0 + lane;   // slots
     if (b0 >= live_count(n_live, B)) return;
     int n_e, ne_gn = 0, ng = 0;
@@ -486,56 +514,61 @@ __global__ __launch_bounds__(64) void k_reduce(int n_sub, int n_C, int mmax, int
         n_e = n_C;
         dst0 = (size_t)n_sub * rs;
     }
-    const int e0 = blockIdx.y * 32;
+    const int e0 = blockIdx.y * RED_E;
     if (e0 >= n_e) return;
-    const int cnt = min(32, n_e - e0);
-    // 32 independent accumulators; loads are unconditional (indices clamped into the buffer)
-    // and masked afterwards, so every load of a slot is in flight before any add waits
-    double acc[32];
+    const int cnt = min(RED_E, n_e - e0);
+    // loads are unconditional (indices clamped into the buffer) and masked afterwards, so
+    // every load of a slot is in flight before any add waits
+    double acc[RED_E];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+    for (int j = 0; j < RED_E; ++j) acc[j] = 0.0;
     if (sd < n_sub) {
         if (e0 < estride) {
-            for (int sl = slot0[sd]; sl < slot0[sd + 1]; ++sl) {
+            for (int sl = slot0[sd] + wave; sl < slot0[sd + 1]; sl += 4) {
                 const double* src = gn_part + (size_t)sl * estride * Bp + b;
-                double v[32];
+                double v[RED_E];
 #pragma unroll
-                for (int j = 0; j < 32; ++j) v[j] = src[(size_t)min(e0 + j, estride - 1) * Bp];
+                for (int j = 0; j < RED_E; ++j) v[j] = src[(size_t)min(e0 + j, estride - 1) * Bp];
 #pragma unroll
-                for (int j = 0; j < 32; ++j) acc[j] += (e0 + j < ne_gn) ? v[j] : 0.0;
+                for (int j = 0; j < RED_E; ++j) acc[j] += (e0 + j < ne_gn) ? v[j] : 0.0;
             }
         }
-        if (e0 + 32 > estride) {
-            for (int p = cpart0[sd]; p < cpart0[sd + 1]; ++p) {
+        if (e0 + RED_E > estride) {
+            for (int p = cpart0[sd] + wave; p < cpart0[sd + 1]; p += 4) {
                 const double* src = E_part + (size_t)p * n_C * mmax * Bp + b;
-                double v[32];
+                double v[RED_E];
 #pragma unroll
-                for (int j = 0; j < 32; ++j) {
+                for (int j = 0; j < RED_E; ++j) {
                     const int q = min(max(e0 + j - estride, 0), n_C * mmax - 1);
                     v[j] = src[(size_t)q * Bp];
                 }
 #pragma unroll
-                for (int j = 0; j < 32; ++j) {
+                for (int j = 0; j < RED_E; ++j) {
                     const int q = e0 + j - estride;
                     acc[j] += (q >= 0 && q < n_C * mmax && (q % mmax) < ng) ? v[j] : 0.0;
                 }
             }
         }
     } else {
-        for (int p = 0; p < n_cparts; ++p) {
+        for (int p = wave; p < n_cparts; p += 4) {
             const double* src = c_part + (size_t)p * n_C * Bp + b;
-            double v[32];
+            double v[RED_E];
 #pragma unroll
-            for (int j = 0; j < 32; ++j) v[j] = src[(size_t)min(e0 + j, n_C - 1) * Bp];
+            for (int j = 0; j < RED_E; ++j) v[j] = src[(size_t)min(e0 + j, n_C - 1) * Bp];
 #pragma unroll
-            for (int j = 0; j < 32; ++j) acc[j] += (e0 + j < n_C) ? v[j] : 0.0;
+            for (int j = 0; j < RED_E; ++j) acc[j] += (e0 + j < n_C) ? v[j] : 0.0;
         }
     }
+    if (wave > 0)
 #pragma unroll
-    for (int j = 0; j < 32; ++j) tile[j][lane] = acc[j];
+        for (int j = 0; j < RED_E; ++j) wpart[wave - 1][j][lane] = acc[j];
     __syncthreads();
-    for (int q = lane; q < 64 * 32; q += 64) {
-        const int sv = q >> 5, j = q & 31;
+    if (wave == 0)
+#pragma unroll
+        for (int j = 0; j < RED_E; ++j) tile[j][lane] = ((acc[j] + wpart[0][j][lane]) + wpart[1][j][lane]) + wpart[2][j][lane];
+    __syncthreads();
+    for (int q = tid; q < 64 * RED_E; q += 256) {
+        const int sv = q / RED_E, j = q % RED_E;
         if (j < cnt) RB[(size_t)(b0 + sv) * RS + dst0 + e0 + j] = tile[j][sv];
     }
 }
@@ -603,14 +636,25 @@ __host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int
     return L;
 }
 
-// Dense n x n system [M | r] in LDS (row stride n + 1), solved by one wave: Gaussian
-// elimination with partial pivoting (rows in lanes), then back substitution.  The solution
-// goes to x.  Returns false if a pivot is zero or not finite.  n <= 64.
-__device__ bool wave_lu_solve(double* M, int n, double* x, int lane) {
+// Dense n x n system [M | r] (in LDS, row stride n + 1) solved by one wave with row i in
+// lane i, held in registers: Gaussian elimination with partial pivoting in which the pivot
+// row is broadcast lane to lane and never moved (the pivot order is recorded), then back
+// substitution in reverse pivot order.  The solution goes to x (LDS, written by lane 0).
+// Sizes n <= NCP are padded with identity rows and columns.  Returns false if a pivot is
+// zero or not finite.
+template <int NCP>
+__device__ bool wave_lu_reg(const double* M, int n, double* x, int lane) {
     const int ld = n + 1;
+    double row[NCP + 1];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) row[c] = (lane < n && c < n) ? M[lane * ld + c] : (lane == c ? 1.0 : 0.0);
+    row[NCP] = lane < n ? M[lane * ld + n] : 0.0;
+    bool used = lane >= NCP;
     bool ok = true;
-    for (int k = 0; k < n; ++k) {
-        double best = (lane >= k && lane < n) ? fabs(M[lane * ld + k]) : -1.0;
+    int pk[NCP];
+#pragma unroll
+    for (int k = 0; k < NCP; ++k) {
+        double best = used ? -1.0 : fabs(row[k]);
         int bi = lane;
         for (int off = 32; off > 0; off >>= 1) {
             const double ob = __shfl_xor(best, off, 64);
@@ -618,29 +662,32 @@ __device__ bool wave_lu_solve(double* M, int n, double* x, int lane) {
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
         const int p = __builtin_amdgcn_readfirstlane(bi);
+        pk[k] = p;
         if (!(best > 0.0) || !isfinite(best)) ok = false;
-        if (p != k)
-            for (int jj = lane; jj <= n; jj += 64) {
-                const double t = M[k * ld + jj];
-                M[k * ld + jj] = M[p * ld + jj];
-                M[p * ld + jj] = t;
-            }
-        wave_sync_lds();
-        const double pv = M[k * ld + k];
-        if (lane > k && lane < n && pv != 0.0) {
-            const double f = M[lane * ld + k] / pv;
-            for (int jj = k + 1; jj <= n; ++jj) M[lane * ld + jj] -= f * M[k * ld + jj];
-        }
-        wave_sync_lds();
+        const double pv = lane_bcast(row[k], p);
+        const double f = (!used && lane != p) ? row[k] / pv : 0.0;
+        used = used || lane == p;
+#pragma unroll
+        for (int c = k + 1; c <= NCP; ++c) row[c] -= f * lane_bcast(row[c], p);
     }
-    double r = lane < n ? M[lane * ld + n] : 0.0;
-    for (int i = n - 1; i >= 0; --i) {
-        const double xi = lane_bcast(r, i) / M[i * ld + i];
-        if (lane == i) x[i] = xi;
-        if (lane < i) r -= M[lane * ld + i] * xi;
+    // Lanes pivoted after step k hold stale column-k entries, but their right-hand sides are
+    // no longer read once step k is reached.
+    double r = row[NCP];
+#pragma unroll
+    for (int k = NCP - 1; k >= 0; --k) {
+        const int p = pk[k];
+        const double xk = lane_bcast(r, p) / lane_bcast(row[k], p);
+        if (k < n && lane == 0) x[k] = xk;
+        r -= row[k] * xk;
     }
-    wave_sync_lds();
     return ok;
+}
+
+__device__ __noinline__ bool wave_lu_solve(const double* M, int n, double* x, int lane) {
+    if (n <= 8) return wave_lu_reg<8>(M, n, x, lane);
+    if (n <= 16) return wave_lu_reg<16>(M, n, x, lane);
+    if (n <= 32) return wave_lu_reg<32>(M, n, x, lane);
+    return wave_lu_reg<64>(M, n, x, lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -870,10 +917,10 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         for (int l = 0; l <= MG; ++l) Xr[l] = 0.0;
 #pragma unroll
         for (int k = NN - 1; k >= 0; --k) {
-            const double dk = lane_bcast(A[k], k);
+            const double rdk = 1.0 / lane_bcast(A[k], k);
 #pragma unroll
             for (int l = 0; l <= MG; ++l) {
-                const double xk = lane_bcast(A[NN + l], k) / dk;
+                const double xk = lane_bcast(A[NN + l], k) * rdk;
                 if (lane == k) Xr[l] = xk;
                 if (lane < k) A[NN + l] -= A[k] * xk;
             }
@@ -1238,7 +1285,7 @@ static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const dd
     const ddrom::ResSeg& rs = m->rsegs_h[sd0];
     // one chunk per slot, slots of consecutive subdomains are consecutive
     const int c0 = rs.slot0, c1 = m->rsegs_h[sd1 - 1].slot1;
-    dim3 grid(c1 - c0, ws->Bp / 64), block(64);
+    dim3 grid(c1 - c0, ws->Bp / 64), block(256);
 #define RES_CASE(A, G)                                                                                            \
     if (rs.n_om == A && rs.n_ga == G) {                                                                           \
         if (prec == DDROM_PREC_FP64)                                                                              \
@@ -1390,8 +1437,8 @@ static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int
     int rc;
     if ((rc = evaluate_round(m, ws, prec, B, ws->live, ws->counter, ws->xt, s))) return rc;
     ModelDevInts di = get_ints(m);
-    const int n_etiles = (m->estride + m->n_C * std::max(1, m->mmax) + 31) / 32;
-    hipLaunchKernelGGL(k_reduce, dim3(m->n_sub + 1, n_etiles, ws->Bp / 64), dim3(64), 0, s, m->n_sub, m->n_C,
+    const int n_etiles = (m->estride + m->n_C * std::max(1, m->mmax) + RED_E - 1) / RED_E;
+    hipLaunchKernelGGL(k_reduce, dim3(m->n_sub + 1, n_etiles, ws->Bp / 64), dim3(256), 0, s, m->n_sub, m->n_C,
                        std::max(1, m->mmax), m->estride, ws->rs, ws->RS, ws->Bp, B, di.n_om, di.n_ga, di.slot0,
                        di.cpart0, m->n_cparts, ws->gn_part, ws->c_part, ws->E_part, ws->counter, ws->RB);
     if ((rc = launch_update(m, ua, B, s))) return rc;
