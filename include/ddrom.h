@@ -231,6 +231,21 @@ int rom_solve_warm(const ddrom_model* m, ddrom_workspace* ws, const ddrom_mlp* p
                    const ddrom_opts* o, double* xhat_d, double* lam_d, int* iters_d, int* status_d, double* fnorm_d,
                    double* fnorm0_d, int* fallback_d, hipStream_t s);
 
+/* ---- After a solve ------------------------------------------------------------------
+ * Decoded subdomain states g_i(xhat_i) of B solves from their latents xhat_d [B][n_D] with the
+ * full interior and interface decoders (every row, values only): xsd_d [B][n_state] FP64 in the
+ * layout of dd_fom_residual ([x_1^Omega; x_1^Gamma; x_2^Omega; ...]).  The workspace allocates
+ * its n_state x max_batch state buffer on the first call of this or the next function. */
+int rom_decode_states(const ddrom_model* m, ddrom_workspace* ws, const double* xhat_d, int B, int precision,
+                      double* xsd_d, hipStream_t s);
+
+/* Relative error of the decoded states against FOM states (eq. relative_error, Section 6):
+ * err_d[b] = sqrt( (1/n_sub) sum_i ||x_FOM|_i - g_i(xhat_i)||^2 / ||x_FOM|_i||^2 ) where x_FOM|_i
+ * restricts xfom_d [B][N_x] (FP64, global order [u; v], x-fastest) to subdomain i's interior
+ * and interface DoFs.  Decodes in `precision`; sums in FP64. */
+int rom_relative_error(const ddrom_model* m, ddrom_workspace* ws, const double* xhat_d, int B, int precision,
+                       const double* xfom_d, double* err_d, hipStream_t s);
+
 /* Measurement helper: average device time (ms) per launch of the four evaluation kernels
  * of one solver round, ms_h[0] interior decoder subnets, [1] interface decoders,
  * [2] HR residual + Gauss-Newton blocks, [3] weak constraint, each launched `reps` times

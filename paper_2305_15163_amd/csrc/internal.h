@@ -105,7 +105,10 @@ struct ddrom_model {
     float *W1f = nullptr, *b1f = nullptr, *W2f = nullptr, *xreff = nullptr;
     double *W1d = nullptr, *b1d = nullptr, *W2d = nullptr, *xrefd = nullptr;
     int2* bands = nullptr;
-    std::vector<ddrom::DecSeg> segs_h;           // [0, n_sub): interior subnets; [n_sub, 2 n_sub): interface
+    // [0, n_sub): interior subnets; [n_sub, 2 n_sub): interface decoders (value + Jacobian rows
+    // in dec_out); [2 n_sub, 3 n_sub): full interior, [3 n_sub, 4 n_sub): full interface
+    // decoders (values only, rows of the DD state buffer)
+    std::vector<ddrom::DecSeg> segs_h;
     ddrom::DecSeg* segs_d = nullptr;
     std::vector<ddrom::DecChunk> chunks_h;       // sorted by segment
     ddrom::DecChunk* chunks_d = nullptr;
@@ -137,6 +140,7 @@ struct ddrom_model {
     long long* fom_meta_d = nullptr;             // per subdomain: [own_off, n_own, n_int_nodes, n_if_nodes, state_off, res_off]
     int total_own = 0;
     int* fom_sd_of_row_d = nullptr;              // owner subdomain of each flattened own-node slot
+    int* state_dof_d = nullptr;                  // [n_state] global DoF of each row of the DD state
 };
 
 struct SolveState {
@@ -170,6 +174,9 @@ struct ddrom_workspace {
     double* lamt = nullptr;
     double* step = nullptr;         // [Bp][n_D + n_C]
     int* live = nullptr;            // [Bp] original index of each still-running solve, ascending
+    void* state_out = nullptr;      // decoded DD states [n_state][Bp], allocated on first use
+    int state_prec = -1;            // precision state_out was allocated for
+    double* err_part = nullptr;     // [n_sub][2][Bp] error numerators / denominators
     double* mu = nullptr;           // [Bp][2]
     double* RB = nullptr;           // per-solve reduced blocks [Bp][RS]
     int rs = 0, RS = 0;             // per-subdomain block size, per-solve stride

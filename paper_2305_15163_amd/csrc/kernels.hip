@@ -121,8 +121,9 @@ template <>
 __device__ __forceinline__ double sig_fast<double>(double z) { return 1.0 / (1.0 + exp(-z)); }
 
 // TAG only renames the instantiation (0: solver rounds, 1: standalone timing launches) so that
-// profiler summaries separate the two; the code is identical.
-template <typename T, int NL, int ACT, int WAVES, int TAG>
+// profiler summaries separate the two; the code is identical.  VO = 1 evaluates values only
+// (decoded states after a solve): row r goes to Bp-row out + r.
+template <typename T, int NL, int ACT, int WAVES, int TAG, int VO = 0>
 __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restrict__ chunks, int chunk_base,
                                                        const DecSeg* __restrict__ segs, const T* __restrict__ W1,
                                                        const T* __restrict__ B1, const int2* __restrict__ bands,
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     for (int k = 0; k < NL; ++k) xl[k] = act ? (T)xhat[(size_t)b * xstride + xo + k] : (T)0;
     __syncthreads();
 
-    T* o = out + ((size_t)sg.out + (size_t)ch.r0 * (1 + NL)) * Bp + j;
+    T* o = out + ((size_t)sg.out + (size_t)ch.r0 * (VO ? 1 : 1 + NL)) * Bp + j;
     // Units [vlo, vhi) (relative to h_lo) are valid in the ring; vhi - vlo <= DEC_RING.  Rows
     // ascend, so windows mostly slide right, but near the first rows of a decoder a clipped
     // band can start below the previous row's window: missing units are then computed on
@@ -235,18 +236,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
                 else if (ACT == DDROM_ACT_SWISH) d = rs[64];
                 else d = (T)1;
                 acc += wv * a;
-                const T c = wv * d;
-                const T* w = sW1 + (size_t)(q.x + t) * NL;
+                if (!VO) {
+                    const T c = wv * d;
+                    const T* w = sW1 + (size_t)(q.x + t) * NL;
 #pragma unroll
-                for (int k = 0; k < NL; ++k) J[k] += c * w[k];
+                    for (int k = 0; k < NL; ++k) J[k] += c * w[k];
+                }
                 slot = slot + 1 == DEC_RING ? 0 : slot + 1;
             }
         }
         if (j < Bp) {   // waves past the padded batch (small B) compute but never store
-            T* orow = o + (size_t)r * (1 + NL) * Bp;
+            T* orow = o + (size_t)r * (VO ? 1 : 1 + NL) * Bp;
             orow[0] = acc;
+            if (!VO)
 #pragma unroll
-            for (int k = 0; k < NL; ++k) orow[(size_t)(1 + k) * Bp] = J[k];
+                for (int k = 0; k < NL; ++k) orow[(size_t)(1 + k) * Bp] = J[k];
         }
     }
 }
@@ -1228,12 +1232,68 @@ __global__ void k_fom_residual(int total_own, int B, const int* __restrict__ src
     }
 }
 
+// ------------------------------------------------------------------------------------
+// Decoded states and the relative error against FOM states (eq. relative_error)
+// ------------------------------------------------------------------------------------
+// States [n_state][Bp] -> caller layout [B][n_state] (FP64).
+template <typename T>
+__global__ void k_state_out(const T* __restrict__ st, int n_state, int B, int Bp, double* __restrict__ x) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)n_state * B) return;
+    const int b = (int)(e / n_state), r = (int)(e % n_state);
+    x[e] = (double)st[(size_t)r * Bp + b];
+}
+
+// Per subdomain and 64 solves: sum over the subdomain's state rows of (x_FOM - g)^2 and
+// x_FOM^2, the FOM state read at each row's global DoF.  Four waves take quarters of the rows
+// and are combined in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_err_part(const T* __restrict__ st, const int* __restrict__ dof,
+                                                  const long long* __restrict__ meta, int B, int Bp, int N_x,
+                                                  const double* __restrict__ xfom, double* __restrict__ part) {
+    __shared__ double red[3][2][64];
+    const int sd = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int b = blockIdx.y * 64 + lane;
+    const long long* me = meta + 6 * sd;
+    const long long r0 = me[4], nr = 2 * (me[2] + me[3]);   // state rows of [x^Omega; x^Gamma]
+    const long long rb = r0 + nr * w / 4, re = r0 + nr * (w + 1) / 4;
+    double num = 0.0, den = 0.0;
+    if (b < B) {
+        const double* xf = xfom + (size_t)b * N_x;
+        for (long long r = rb; r < re; ++r) {
+            const double t = xf[dof[r]];
+            const double d = t - (double)st[(size_t)r * Bp + b];
+            num += d * d;
+            den += t * t;
+        }
+    }
+    if (w > 0) {
+        red[w - 1][0][lane] = num;
+        red[w - 1][1][lane] = den;
+    }
+    __syncthreads();
+    if (w == 0 && b < B) {
+        num = ((num + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
+        den = ((den + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
+        part[((size_t)sd * 2 + 0) * Bp + b] = num;
+        part[((size_t)sd * 2 + 1) * Bp + b] = den;
+    }
+}
+
+__global__ void k_err_final(const double* __restrict__ part, int n_sub, int B, int Bp, double* __restrict__ err) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double t = 0.0;
+    for (int sd = 0; sd < n_sub; ++sd) t += part[((size_t)sd * 2) * Bp + b] / part[((size_t)sd * 2 + 1) * Bp + b];
+    err[b] = sqrt(t / n_sub);
+}
+
 // ====================================================================================
 // Host side
 // ====================================================================================
 namespace {
 
-template <int TAG>
+template <int TAG, int VO = 0>
 static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const double* xhat, int xstride,
                          int xoff_override, const int* live, const int* n_live, int B, void* out, int Bp,
                          hipStream_t s) {
@@ -1255,7 +1315,7 @@ static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const d
     dim3 grid(c1 - c0, (Bp + 64 * waves - 1) / (64 * waves)), block(64 * waves);
     const unsigned lds = (unsigned)L.total;
 #define DEC_LAUNCH(T, NLV, ACTV, WV, W1p, B1p, W2p, XRp)                                                          \
-    hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG>), grid, block, lds, s, m->chunks_d, c0, m->segs_d, W1p,     \
+    hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG, VO>), grid, block, lds, s, m->chunks_d, c0, m->segs_d, W1p, \
                        B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, live, n_live, B, (T*)out, Bp)
 #define DEC_ACT(NLV, ACTV)                                                                                        \
     if (prec == DDROM_PREC_FP64) DEC_LAUNCH(double, NLV, ACTV, 1, m->W1d, m->b1d, m->W2d, m->xrefd);            \
@@ -1619,6 +1679,8 @@ void ddrom_workspace_destroy(ddrom_workspace* w) {
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->counter_h) (void)hipHostFree(w->counter_h);
+    if (w->state_out) (void)hipFree(w->state_out);
+    if (w->err_part) (void)hipFree(w->err_part);
     if (w->graph) (void)hipGraphExecDestroy(w->graph);
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);
@@ -1859,6 +1921,72 @@ int rom_solve_warm(const ddrom_model* m, ddrom_workspace* ws, const ddrom_mlp* p
     }
     FinalOut fo{xhat_d, lam_d, fnorm_d, fnorm0_d, iters_d, status_d, fallback_d};
     return solve_common(m, ws, mu_d, B, nullptr, nullptr, o, s, 1, fo, p);
+}
+
+// Decoded DD states of B solves into ws->state_out (allocated on the first call).
+static int decode_states(const ddrom_model* m, ddrom_workspace* ws, const double* xhat_d, int B, int prec,
+                         hipStream_t s) {
+    if (!ws->state_out) {
+        if (hipMalloc(&ws->state_out, (size_t)m->n_state * ws->Bp * sizeof(double)) != hipSuccess ||
+            hipMalloc((void**)&ws->err_part, (size_t)m->n_sub * 2 * ws->Bp * sizeof(double)) != hipSuccess) {
+            set_error("state buffer allocation failed");
+            return DDROM_ENOMEM;
+        }
+    }
+    const int n = m->n_sub;
+    int rc;
+    for (int g0 = 2 * n; g0 < 4 * n;) {
+        int g1 = g0 + 1;
+        while (g1 < 4 * n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
+        if ((rc = launch_decode<0, 1>(m, prec, g0, g1, xhat_d, m->n_D, -1, nullptr, nullptr, B, ws->state_out, ws->Bp, s)))
+            return rc;
+        g0 = g1;
+    }
+    return 0;
+}
+
+int rom_decode_states(const ddrom_model* m, ddrom_workspace* ws, const double* xhat_d, int B, int precision,
+                      double* xsd_d, hipStream_t s) {
+    int rc = check_ws(m, ws, B);
+    if (rc) return rc;
+    if (B > 0 && (!xhat_d || !xsd_d || (precision != 0 && precision != 1))) {
+        set_error("bad arguments to rom_decode_states");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    if ((rc = decode_states(m, ws, xhat_d, B, precision, s))) return rc;
+    const long long tot = (long long)m->n_state * B;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    if (precision == DDROM_PREC_FP64)
+        hipLaunchKernelGGL(k_state_out<double>, grid, dim3(256), 0, s, (const double*)ws->state_out, m->n_state, B,
+                           ws->Bp, xsd_d);
+    else
+        hipLaunchKernelGGL(k_state_out<float>, grid, dim3(256), 0, s, (const float*)ws->state_out, m->n_state, B,
+                           ws->Bp, xsd_d);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+int rom_relative_error(const ddrom_model* m, ddrom_workspace* ws, const double* xhat_d, int B, int precision,
+                       const double* xfom_d, double* err_d, hipStream_t s) {
+    int rc = check_ws(m, ws, B);
+    if (rc) return rc;
+    if (B > 0 && (!xhat_d || !xfom_d || !err_d || (precision != 0 && precision != 1))) {
+        set_error("bad arguments to rom_relative_error");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    if ((rc = decode_states(m, ws, xhat_d, B, precision, s))) return rc;
+    const dim3 grid(m->n_sub, ws->Bp / 64);
+    if (precision == DDROM_PREC_FP64)
+        hipLaunchKernelGGL(k_err_part<double>, grid, dim3(256), 0, s, (const double*)ws->state_out, m->state_dof_d,
+                           m->fom_meta_d, B, ws->Bp, m->N_x, xfom_d, ws->err_part);
+    else
+        hipLaunchKernelGGL(k_err_part<float>, grid, dim3(256), 0, s, (const float*)ws->state_out, m->state_dof_d,
+                           m->fom_meta_d, B, ws->Bp, m->N_x, xfom_d, ws->err_part);
+    hipLaunchKernelGGL(k_err_final, dim3((B + 255) / 256), dim3(256), 0, s, ws->err_part, m->n_sub, B, ws->Bp, err_d);
+    HIPCHECK(hipGetLastError());
+    return 0;
 }
 
 int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, const double* xhat_d, int B,

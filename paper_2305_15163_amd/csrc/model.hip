@@ -330,24 +330,28 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     }
     m->n_bc = (int)bc_field.size();
 
-    // ---- decoders: interior subnets and full interface decoders ----
+    // ---- decoders: interior subnets and full interface decoders (solver rounds, value and
+    //      Jacobian rows), then full interior and interface decoders (values only, for the
+    //      decoded subdomain states after a solve) ----
     std::vector<double> W1, b1, W2, xref;
     std::vector<int2> bands;
-    m->segs_h.assign(2 * n_sub, DecSeg{});
-    m->band_nnz.assign(2 * n_sub, 0);
+    m->segs_h.assign(4 * n_sub, DecSeg{});
+    m->band_nnz.assign(4 * n_sub, 0);
     long long out_rows = 0;
-    for (int part = 0; part < 2; ++part)
+    for (int part = 0; part < 4; ++part)
         for (int sd = 0; sd < n_sub; ++sd) {
-            const ddrom_decoder_desc& dd = part == 0 ? d->dec_om[sd] : d->dec_ga[sd];
+            const bool interior = part == 0 || part == 2;
+            const ddrom_decoder_desc& dd = interior ? d->dec_om[sd] : d->dec_ga[sd];
             DecSeg& sg = m->segs_h[part * n_sub + sd];
             sg.sd = sd;
-            sg.n = part == 0 ? m->n_om[sd] : m->n_ga[sd];
-            sg.xoff = m->xoff[sd] + (part == 0 ? 0 : m->n_om[sd]);
+            sg.n = interior ? m->n_om[sd] : m->n_ga[sd];
+            sg.xoff = m->xoff[sd] + (interior ? 0 : m->n_om[sd]);
             sg.bmax = dd.N > 0 ? dd.b : 1;
             if (dd.N == 0) {
                 sg.rows = 0; sg.hid = 0;
                 sg.w1 = (long long)W1.size(); sg.b1 = (long long)b1.size(); sg.band = (long long)bands.size();
-                sg.w2 = (long long)W2.size(); sg.xref = (long long)xref.size(); sg.out = out_rows;
+                sg.w2 = (long long)W2.size(); sg.xref = (long long)xref.size();
+                sg.out = part < 2 ? out_rows : m->state_off[sd] + (part == 3 ? m->N_om[sd] : 0);
                 continue;
             }
             std::vector<int> rows;
@@ -366,8 +370,12 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             sg.band = (long long)bands.size(); bands.insert(bands.end(), hd.band.begin(), hd.band.end());
             sg.w2 = (long long)W2.size(); W2.insert(W2.end(), hd.W2.begin(), hd.W2.end());
             sg.xref = (long long)xref.size(); xref.insert(xref.end(), hd.xref.begin(), hd.xref.end());
-            sg.out = out_rows;
-            out_rows += (long long)hd.rows * (1 + sg.n);
+            if (part < 2) {
+                sg.out = out_rows;
+                out_rows += (long long)hd.rows * (1 + sg.n);
+            } else {
+                sg.out = m->state_off[sd] + (part == 3 ? m->N_om[sd] : 0);   // row of the state buffer
+            }
             {
                 long long nnz = 0;
                 for (const int2& q : hd.band) nnz += q.y;
@@ -379,11 +387,11 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     // Decode work items: runs of consecutive kept rows whose staged weights (W1~ rows and
     // biases of the hidden units they read, their W2~ values, x_ref, band descriptors) fit
     // in DEC_STAGE bytes of FP32.
-    m->seg_chunk0.assign(2 * n_sub, 0);
-    m->seg_chunk1.assign(2 * n_sub, 0);
-    m->seg_stage_f32.assign(2 * n_sub, 0);
-    m->seg_stage_f64.assign(2 * n_sub, 0);
-    for (int sgi = 0; sgi < 2 * n_sub; ++sgi) {
+    m->seg_chunk0.assign(4 * n_sub, 0);
+    m->seg_chunk1.assign(4 * n_sub, 0);
+    m->seg_stage_f32.assign(4 * n_sub, 0);
+    m->seg_stage_f64.assign(4 * n_sub, 0);
+    for (int sgi = 0; sgi < 4 * n_sub; ++sgi) {
         m->seg_chunk0[sgi] = (int)m->chunks_h.size();
         const DecSeg& sg = m->segs_h[sgi];
         const int2* bd = bands.data() + sg.band;
@@ -514,6 +522,20 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         return DDROM_EINVAL;
     }
 
+    // ---- global DoF of every row of the DD state [x_1^Omega; x_1^Gamma; ...] ----
+    std::vector<int> state_dof((size_t)m->n_state);
+    {
+        const int nn = nx * ny;
+        for (int sd = 0; sd < n_sub; ++sd) {
+            const int nint = (int)intn[sd].size(), nif = (int)ifn[sd].size();
+            long long o = m->state_off[sd];
+            for (int f = 0; f < 2; ++f)
+                for (int p = 0; p < nint; ++p) state_dof[o++] = intn[sd][p] + f * nn;
+            for (int f = 0; f < 2; ++f)
+                for (int p = 0; p < nif; ++p) state_dof[o++] = ifn[sd][p] + f * nn;
+        }
+    }
+
     // ---- upload ----
     std::vector<float> W1f(W1.begin(), W1.end()), b1f(b1.begin(), b1.end()), W2f(W2.begin(), W2.end()),
         xreff(xref.begin(), xref.end());
@@ -526,7 +548,8 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         (rc = upload(&m->rchunks_d, m->rchunks_h)) || (rc = upload(&m->bc_xy_d, bc_xy)) ||
         (rc = upload(&m->bc_field_d, bc_field)) || (rc = upload(&m->CA_d, CAflat)) ||
         (rc = upload(&m->cchunks_d, cch)) || (rc = upload(&m->fom_src_d, fsrc)) ||
-        (rc = upload(&m->fom_meta_d, fmeta)) || (rc = upload(&m->fom_sd_of_row_d, sd_of_row)))
+        (rc = upload(&m->fom_meta_d, fmeta)) || (rc = upload(&m->fom_sd_of_row_d, sd_of_row)) ||
+        (rc = upload(&m->state_dof_d, state_dof)))
         return rc;
     return 0;
 }
@@ -534,7 +557,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
 void free_model(ddrom_model* m) {
     void* ptrs[] = {m->W1f, m->b1f, m->W2f, m->xreff, m->W1d, m->b1d, m->W2d, m->xrefd, m->bands, m->segs_d,
                     m->chunks_d, m->gather_d, m->rsegs_d, m->rchunks_d, m->bc_xy_d, m->bc_field_d, m->CA_d,
-                    m->cchunks_d, m->fom_src_d, m->fom_meta_d, m->fom_sd_of_row_d};
+                    m->cchunks_d, m->fom_src_d, m->fom_meta_d, m->fom_sd_of_row_d, m->state_dof_d};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }

@@ -80,6 +80,8 @@ def lib():
         L.ddrom_mlp_trainer_params.argtypes = [vp, vp, vp]
         L.mlp_train_step.argtypes = [vp, vp, vp, vp, ip, C.c_float, ip, vp, vp, vp]
         L.rom_solve_warm.argtypes = [vp, vp, vp, vp, ip, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rom_decode_states.argtypes = [vp, vp, vp, ip, ip, vp, vp]
+        L.rom_relative_error.argtypes = [vp, vp, vp, ip, ip, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -387,3 +389,25 @@ def rom_solve_warm(model: Model, ws: Workspace, p: Proposal, mu, o: Opts, out=No
                                 _ptr(out["iters"]), _ptr(out["status"]), _ptr(out["fnorm"]), _ptr(out["fnorm0"]),
                                 _ptr(out["fallback"]), _stream()), "rom_solve_warm")
     return out
+
+
+# ---- after a solve -------------------------------------------------------------------
+
+def decode_states(model: Model, ws: Workspace, xhat, precision=PREC_FP64):
+    """Decoded DD states [B][n_state] (FP64) of latents xhat [B][n_D]."""
+    xhat = _dev(xhat)
+    B = xhat.shape[0]
+    x = torch.empty((B, model.n_state), dtype=torch.float64, device="cuda")
+    _check(lib().rom_decode_states(model.h, ws.h, _ptr(xhat), B, int(precision), _ptr(x), _stream()),
+           "rom_decode_states")
+    return x
+
+
+def relative_error(model: Model, ws: Workspace, xhat, xfom, precision=PREC_FP64):
+    """eq. relative_error of the decoded states of xhat [B][n_D] against FOM states xfom [B][N_x]."""
+    xhat, xfom = _dev(xhat), _dev(xfom)
+    B = xhat.shape[0]
+    err = torch.empty((B,), dtype=torch.float64, device="cuda")
+    _check(lib().rom_relative_error(model.h, ws.h, _ptr(xhat), B, int(precision), _ptr(xfom), _ptr(err), _stream()),
+           "rom_relative_error")
+    return err
