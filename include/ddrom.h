@@ -231,6 +231,37 @@ int rom_solve_warm(const ddrom_model* m, ddrom_workspace* ws, const ddrom_mlp* p
                    const ddrom_opts* o, double* xhat_d, double* lam_d, int* iters_d, int* status_d, double* fnorm_d,
                    double* fnorm0_d, int* fallback_d, hipStream_t s);
 
+/* ---- Autoencoder training -------------------------------------------------------------
+ * One shallow band-masked autoencoder (eq. autoencoder_architecture, Sections 3.4 and 7.3):
+ * N state components, latent n, hidden width w = N s, three-band mask of b entries per band
+ * shifted by s per row (band k in {-1,0,1} of row r covers columns r s + k b s + t, t < b).
+ * BF16 matrix-core products with FP32 accumulation; FP32 master weights; Adam (0.9, 0.999,
+ * 1e-8).  Parameters, packed FP32:
+ *   W1e [N][3][b]  encoder input layer by band slot (its entry for column c = r s + k b s + t
+ *                  connects input r to hidden unit c; slots with c outside [0, w) are zero)
+ *   b1e [w], W2e [n][w], W1d [w][n], b1d [w]
+ *   W2d [N][3][b]  decoder output layer by band slot (row r, column r s + k b s + t)
+ * The loss of a minibatch is (1/B) sum_b ||scale o (y_b - x~_b)||^2 on normalised snapshots
+ * x~ (eq. autoencoder_AbsMSE_loss with the de-normalisation scale). */
+typedef struct ddrom_ae_trainer ddrom_ae_trainer;
+
+/* params_h: host, packed as above (ddrom_ae_trainer_size(t, 0) floats).  precision 0: BF16
+ * operands; 1: each FP32 operand split into a BF16 head and tail, three matrix-core products
+ * per tile (about 16 significant bits, FP32-class gradients at three times the matrix work). */
+int ddrom_ae_trainer_create(int N, int n, int b, int s, int activation, int max_batch, int precision,
+                            const float* params_h, ddrom_ae_trainer** out);
+void ddrom_ae_trainer_destroy(ddrom_ae_trainer* t);
+/* query 0: parameter count, 1: hidden width w, 2: band slots 3 N b. */
+long long ddrom_ae_trainer_size(const ddrom_ae_trainer* t, int query);
+/* Copy the FP32 master weights (packed) to device memory params_d. */
+int ddrom_ae_trainer_params(const ddrom_ae_trainer* t, float* params_d, hipStream_t s);
+/* One minibatch: rows_d [B] index the normalised snapshots X_d [n_snap][N] (FP32, device);
+ * scale_d [N] the de-normalisation scale.  loss_d (nullable, device [1]) receives the loss
+ * before the update, grad_d (nullable, device, packed) the gradient; update != 0 applies one
+ * Adam step with learning rate lr.  1 <= B <= max_batch. */
+int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int B, const float* scale_d, float lr,
+                  int update, float* loss_d, float* grad_d, hipStream_t s);
+
 /* ---- After a solve ------------------------------------------------------------------
  * Decoded subdomain states g_i(xhat_i) of B solves from their latents xhat_d [B][n_D] with the
  * full interior and interface decoders (every row, values only): xsd_d [B][n_state] FP64 in the

@@ -1,0 +1,496 @@
+// Training of the shallow band-masked autoencoders (Sections 3.4 and 7.3) on the GPU:
+// BF16 matrix-core (MFMA) products with FP32 accumulation, FP32 master weights, Adam.
+//
+// Network (eq. autoencoder_architecture), on normalised snapshots x~ (columns of a
+// minibatch, feature-major layouts [features][B]):
+//   encoder  ze = E1 x~ + b1e,  ae = sigma(ze),  xh = W2e ae          (E1: w x N, masked)
+//   decoder  zd = W1d xh + b1d, ad = sigma(zd),  y  = D2 ad           (D2: N x w, masked)
+//   loss     (1/B) sum_b sum_r (scale_r (y - x~)_rb)^2                 (raw-space MSE)
+// D2 carries the three-band mask (row r: columns r s + k b s + t, k in {-1,0,1}, t < b) and E1
+// its transpose.  Both masked weights are stored by band slot, W[r][k][t] (the slot of mask
+// entry (r, c = r s + k b s + t)); slots whose column falls outside [0, w) hold zeros.
+//
+// Masked products run on dense 16 x 16 tiles: a 16-row tile of a band touches a window of
+// 15 s + b columns per band, so the tile is expanded (zeros outside the band) into BF16 MFMA
+// operands; the weight gradients are sampled dense products over the minibatch, kept only at
+// band slots.  The dense latent layers (w <-> n) are skinny GEMMs (split over K where K = w).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ddrom;
+
+#define AECHECK(x)                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) {                                                             \
+            set_error(std::string(#x) + ": " + hipGetErrorString(e_));                      \
+            return DDROM_EHIP;                                                              \
+        }                                                                                   \
+    } while (0)
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ short to_bf16(float f) {
+    const unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (short)((u >> 16) | 0x40u);
+    return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+// 16 x 16 x 16 BF16 product, FP32 accumulate.  Lane l supplies A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16] (i < 4) and holds D[4 (l / 16) + i][l % 16].  With x3 != 0 each
+// operand is split into a BF16 head and a BF16 tail (a = a_h + a_l) and the product is
+// a_h b_h + a_h b_l + a_l b_h: three matrix-core products, about 16 significant bits.
+__device__ __forceinline__ f32x4 mma16(const float a[4], const float b[4], f32x4 c, int x3) {
+    bf16x4 ah, bh;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        ah[i] = to_bf16(a[i]);
+        bh[i] = to_bf16(b[i]);
+    }
+    if (x3) {
+        bf16x4 al, bl;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            al[i] = to_bf16(a[i] - bf16_to_f(ah[i]));
+            bl[i] = to_bf16(b[i] - bf16_to_f(bh[i]));
+        }
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void act_fwd(float z, int act, float& a, float& d) {
+    if (act == DDROM_ACT_IDENTITY) {
+        a = z;
+        d = 1.f;
+        return;
+    }
+    const float sg = 1.f / (1.f + __expf(-z));
+    if (act == DDROM_ACT_SIGMOID) {
+        a = sg;
+        d = sg * (1.f - sg);
+    } else {
+        a = z * sg;
+        d = sg + z * sg * (1.f - sg);
+    }
+}
+
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// ---- dense products:  C[m][n] = sum_k A(m, k) B(k, n),  A(m, k) = A[m sam + k sak] ----
+// One wave per 16 x 16 output tile, four waves per workgroup (2 x 2 tiles).  With split > 1
+// the K range is cut in `split` parts written to C + z M ldc (summed by k_split_sum).
+// EPI 0: store; 1: + bias[m], Z = pre-activation, C = sigma; 2: times sigma'(aux[m][n]).
+template <int EPI>
+__global__ __launch_bounds__(256) void k_dense(int M, int N, int K, const float* __restrict__ A, long long sam,
+                                               long long sak, const float* __restrict__ Bm, long long sbk,
+                                               long long sbn, float* __restrict__ C, int ldc, int split,
+                                               const float* __restrict__ bias, float* __restrict__ Z,
+                                               const float* __restrict__ aux, int act, int x3) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = (blockIdx.y * 2 + (wave >> 1)) * 16, n0 = (blockIdx.x * 2 + (wave & 1)) * 16;
+    const int z = blockIdx.z;
+    const int kc = (K + split - 1) / split;
+    const int kb = z * kc, ke = min(K, kb + kc);
+    const int am = m0 + (lane & 15), bn = n0 + (lane & 15), kq = 4 * (lane >> 4);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (m0 < M && n0 < N) {
+        for (int k0 = kb; k0 < ke; k0 += 16) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + kq + i;
+                a[i] = (am < M && k < ke) ? A[(long long)am * sam + (long long)k * sak] : 0.f;
+                b[i] = (bn < N && k < ke) ? Bm[(long long)k * sbk + (long long)bn * sbn] : 0.f;
+            }
+            acc = mma16(a, b, acc, x3);
+        }
+    }
+    if (m0 >= M || n0 >= N) return;
+    float* Cz = C + (size_t)z * M * ldc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + kq + i, n = n0 + (lane & 15);
+        if (m >= M || n >= N) continue;
+        float v = acc[i];
+        const size_t ci = (size_t)m * ldc + n;
+        if (EPI == 1) {
+            v += bias[m];
+            Z[ci] = v;
+            float a, d;
+            act_fwd(v, act, a, d);
+            v = a;
+        } else if (EPI == 2) {
+            float a, d;
+            act_fwd(aux[ci], act, a, d);
+            v *= d;
+        }
+        Cz[ci] = v;
+    }
+}
+
+// C[e] = sum_z P[z][e] (fixed order)
+__global__ void k_split_sum(const float* __restrict__ P, int split, long long n, float* __restrict__ C) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < split; ++z) s += P[(size_t)z * n + e];
+    C[e] = s;
+}
+
+// ---- transposed band product:  Z[c][b] = sum_{r,k,t : c = r s + k b s + t} W[r][k][t] A[r][b] ----
+// One wave per 16 (c) x 16 (b) tile, four waves per workgroup along b.  For band k the rows
+// touching columns [c0, c0 + 16) form a run of at most (15 + b) / s + 1 rows, taken 16 at a
+// time.  EPI 1: + bias[c], Z = pre-activation, out = sigma; 2: out = sum times sigma'(aux).
+template <int EPI>
+__global__ __launch_bounds__(256) void k_band_t(int N, int w, int bw, int sw, int B, const float* __restrict__ W,
+                                                const float* __restrict__ Ain, float* __restrict__ out,
+                                                const float* __restrict__ bias, float* __restrict__ Z,
+                                                const float* __restrict__ aux, int act, int x3) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c0 = blockIdx.x * 16, n0 = (blockIdx.y * 4 + wave) * 16;
+    if (n0 >= B) return;
+    const int cm = c0 + (lane & 15), kq = 4 * (lane >> 4), bn = n0 + (lane & 15);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kb = -1; kb <= 1; ++kb) {
+        const int off = kb * bw * sw;
+        const int r_lo = max(0, floor_div(c0 - (bw - 1) - off + sw - 1, sw));
+        const int r_hi = min(N - 1, floor_div(c0 + 15 - off, sw));
+        for (int rr = r_lo; rr <= r_hi; rr += 16) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = rr + kq + i;
+                const int t = cm - r * sw - off;
+                const bool in = r <= r_hi && t >= 0 && t < bw && cm < w;
+                a[i] = in ? W[((size_t)r * 3 + (kb + 1)) * bw + t] : 0.f;
+                b[i] = (r <= r_hi && bn < B) ? Ain[(size_t)r * B + bn] : 0.f;
+            }
+            acc = mma16(a, b, acc, x3);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = c0 + kq + i, n = n0 + (lane & 15);
+        if (c >= w || n >= B) continue;
+        const size_t ci = (size_t)c * B + n;
+        float v = acc[i];
+        if (EPI == 1) {
+            v += bias[c];
+            Z[ci] = v;
+            float a, d;
+            act_fwd(v, act, a, d);
+            v = a;
+        } else {
+            float a, d;
+            act_fwd(aux[ci], act, a, d);
+            v *= d;
+        }
+        out[ci] = v;
+    }
+}
+
+// ---- band product with the loss:  y[r][b] = sum_{k,t} W[r][k][t] A[r s + k b s + t][b] ----
+// diff = scale_r (y - x~), dY = (2 / B) scale_r diff, per-workgroup partial sums of diff^2.
+__global__ __launch_bounds__(256) void k_band_loss(int N, int w, int bw, int sw, int B, const float* __restrict__ W,
+                                                   const float* __restrict__ Ain, const float* __restrict__ Xb,
+                                                   const float* __restrict__ scale, float* __restrict__ dY,
+                                                   double* __restrict__ part, int x3) {
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 16, n0 = (blockIdx.y * 4 + wave) * 16;
+    const int rm = r0 + (lane & 15), kq = 4 * (lane >> 4), bn = n0 + (lane & 15);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (n0 < B) {
+        for (int kb = -1; kb <= 1; ++kb) {
+            const int off = kb * bw * sw;
+            const int cb = max(0, r0 * sw + off), ce = min(w, (r0 + 15) * sw + off + bw);
+            for (int cc = cb; cc < ce; cc += 16) {
+                float a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int c = cc + kq + i;
+                    const int t = c - rm * sw - off;
+                    const bool in = rm < N && c < ce && t >= 0 && t < bw;
+                    a[i] = in ? W[((size_t)rm * 3 + (kb + 1)) * bw + t] : 0.f;
+                    b[i] = (c < ce && bn < B) ? Ain[(size_t)c * B + bn] : 0.f;
+                }
+                acc = mma16(a, b, acc, x3);
+            }
+        }
+    }
+    double sq = 0.0;
+    if (n0 < B) {
+        const float sc2 = 2.f / (float)B;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + kq + i, n = n0 + (lane & 15);
+            if (r >= N || n >= B) continue;
+            const size_t ci = (size_t)r * B + n;
+            const float d = scale[r] * (acc[i] - Xb[ci]);
+            dY[ci] = sc2 * scale[r] * d;
+            sq += (double)d * d;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if (lane == 0) red[wave] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// ---- band-slot gradient:  G[r][k][t] = sum_b P[r][b] Q[r s + k b s + t][b] ----
+// Per 16-row tile, each band's column window is cut in 16-column tiles; a wave forms the dense
+// 16 x 16 product over the minibatch and keeps the band slots.
+__global__ __launch_bounds__(256) void k_band_grad(int N, int w, int bw, int sw, int B, const float* __restrict__ P,
+                                                   const float* __restrict__ Q, float* __restrict__ G, int x3) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 16;
+    const int ntile = (15 * sw + bw + 15) / 16;      // column tiles per band window
+    const int rm = r0 + (lane & 15), kq = 4 * (lane >> 4);
+    for (int tt = wave; tt < 3 * ntile; tt += 4) {
+        const int kb = tt / ntile - 1, ci = tt % ntile;
+        const int off = kb * bw * sw;
+        const int cc = r0 * sw + off + 16 * ci;
+        const int cn = cc + (lane & 15);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int s0 = 0; s0 < B; s0 += 16) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int smp = s0 + kq + i;
+                a[i] = (rm < N && smp < B) ? P[(size_t)rm * B + smp] : 0.f;
+                b[i] = (cn >= 0 && cn < w && smp < B) ? Q[(size_t)cn * B + smp] : 0.f;
+            }
+            acc = mma16(a, b, acc, x3);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + kq + i;
+            const int t = cn - r * sw - off;
+            if (r < N && cn >= 0 && cn < w && t >= 0 && t < bw) G[((size_t)r * 3 + (kb + 1)) * bw + t] = acc[i];
+        }
+    }
+}
+
+// minibatch of normalised snapshots, feature-major: Xb[r][b] = X[rows[b]][r]
+__global__ void k_ae_gather(const float* __restrict__ X, int N, const int* __restrict__ rows, int B,
+                            float* __restrict__ Xb) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)N * B) return;
+    const int r = (int)(e / B), b = (int)(e % B);
+    Xb[e] = X[(size_t)rows[b] * N + r];
+}
+
+__global__ void k_rowsum(const float* __restrict__ D, int M, int B, float* __restrict__ out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s += D[(size_t)m * B + b];
+    out[m] = s;
+}
+
+__global__ void k_fill(float* p, long long n, float v) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+__global__ void k_loss_final(const double* __restrict__ part, int n, int B, float* __restrict__ loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    loss[0] = (float)(s / B);
+}
+
+__global__ void k_ae_tick(int* t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) t[0] += 1;
+}
+
+__global__ void k_ae_adam(long long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                          float* __restrict__ v, const int* __restrict__ t, float lr) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const int step = t[0];
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+inline unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+struct ddrom_ae_trainer {
+    int N = 0, n = 0, bw = 0, sw = 0, w = 0, act = 0, max_B = 0;
+    long long n_band = 0, n_params = 0;
+    long long o_w1e = 0, o_b1e = 0, o_w2e = 0, o_w1d = 0, o_b1d = 0, o_w2d = 0;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    float *Xb = nullptr, *ze = nullptr, *ae = nullptr, *zd = nullptr, *ad = nullptr, *dY = nullptr, *dzd = nullptr;
+    float *dze = nullptr, *xh = nullptr, *dxh = nullptr, *kpart = nullptr;
+    double* lpart = nullptr;
+    int* t = nullptr;
+    int split = 1;
+    int x3 = 0;                // 1: split-BF16 (three products) for FP32-class operands
+};
+
+extern "C" {
+
+int ddrom_ae_trainer_create(int N, int n, int b, int s, int activation, int max_batch, int precision,
+                            const float* params_h, ddrom_ae_trainer** out) {
+    if (!out || !params_h || N <= 0 || n <= 0 || n > 64 || b <= 0 || s <= 0 || max_batch <= 0 || activation < 0 ||
+        activation > 2 || (precision != 0 && precision != 1)) {
+        set_error("bad arguments to ddrom_ae_trainer_create");
+        return DDROM_EINVAL;
+    }
+    *out = nullptr;
+    std::unique_ptr<ddrom_ae_trainer> t(new ddrom_ae_trainer());
+    t->N = N; t->n = n; t->bw = b; t->sw = s; t->w = N * s; t->act = activation; t->max_B = max_batch;
+    t->x3 = precision;
+    const long long w = t->w;
+    t->n_band = 3LL * N * b;
+    t->o_w1e = 0;
+    t->o_b1e = t->o_w1e + t->n_band;
+    t->o_w2e = t->o_b1e + w;
+    t->o_w1d = t->o_w2e + (long long)n * w;
+    t->o_b1d = t->o_w1d + w * n;
+    t->o_w2d = t->o_b1d + w;
+    t->n_params = t->o_w2d + t->n_band;
+    t->split = (int)std::max<long long>(1, std::min<long long>(64, w / 1024));
+    const size_t pb = (size_t)t->n_params * sizeof(float);
+    const size_t Bm = (size_t)max_batch;
+    struct A { void** p; size_t bytes; } allocs[] = {
+        {(void**)&t->p, pb}, {(void**)&t->g, pb}, {(void**)&t->m, pb}, {(void**)&t->v, pb},
+        {(void**)&t->Xb, N * Bm * 4}, {(void**)&t->ze, w * Bm * 4}, {(void**)&t->ae, w * Bm * 4},
+        {(void**)&t->zd, w * Bm * 4}, {(void**)&t->ad, w * Bm * 4}, {(void**)&t->dY, N * Bm * 4},
+        {(void**)&t->dzd, w * Bm * 4}, {(void**)&t->dze, w * Bm * 4}, {(void**)&t->xh, n * Bm * 4},
+        {(void**)&t->dxh, n * Bm * 4}, {(void**)&t->kpart, (size_t)t->split * n * Bm * 4},
+        {(void**)&t->lpart, (size_t)cdiv(N, 16) * cdiv(max_batch, 64) * 8}, {(void**)&t->t, sizeof(int)},
+    };
+    for (auto& a : allocs)
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            set_error("trainer allocation failed");
+            ddrom_ae_trainer_destroy(t.release());
+            return DDROM_ENOMEM;
+        }
+    if (hipMemcpy(t->p, params_h, pb, hipMemcpyHostToDevice) != hipSuccess || hipMemset(t->m, 0, pb) != hipSuccess ||
+        hipMemset(t->v, 0, pb) != hipSuccess || hipMemset(t->t, 0, sizeof(int)) != hipSuccess) {
+        set_error("trainer initialisation failed");
+        ddrom_ae_trainer_destroy(t.release());
+        return DDROM_EHIP;
+    }
+    *out = t.release();
+    return 0;
+}
+
+void ddrom_ae_trainer_destroy(ddrom_ae_trainer* t) {
+    if (!t) return;
+    void* ptrs[] = {t->p, t->g, t->m, t->v, t->Xb, t->ze, t->ae, t->zd, t->ad, t->dY, t->dzd, t->dze, t->xh, t->dxh,
+                    t->kpart, t->lpart, t->t};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete t;
+}
+
+long long ddrom_ae_trainer_size(const ddrom_ae_trainer* t, int q) {
+    if (!t) return -1;
+    switch (q) {
+        case 0: return t->n_params;
+        case 1: return t->w;
+        case 2: return t->n_band;
+        default: return -1;
+    }
+}
+
+int ddrom_ae_trainer_params(const ddrom_ae_trainer* t, float* params_d, hipStream_t s) {
+    if (!t || !params_d) {
+        set_error("bad arguments to ddrom_ae_trainer_params");
+        return DDROM_EINVAL;
+    }
+    AECHECK(hipMemcpyAsync(params_d, t->p, (size_t)t->n_params * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return 0;
+}
+
+int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int B, const float* scale_d, float lr,
+                  int update, float* loss_d, float* grad_d, hipStream_t s) {
+    if (!t || !X_d || !rows_d || !scale_d || B <= 0 || B > t->max_B) {
+        set_error("bad arguments to ae_train_step (batch must be 1..max_batch)");
+        return DDROM_EINVAL;
+    }
+    const int N = t->N, n = t->n, w = t->w, bw = t->bw, sw = t->sw, act = t->act;
+    float* P = t->p;
+    float* G = t->g;
+    const dim3 blk(256);
+    hipLaunchKernelGGL(k_ae_gather, dim3(cdiv((long long)N * B, 256)), blk, 0, s, X_d, N, rows_d, B, t->Xb);
+    // encoder: ze = E1 x~ + b1e, ae = sigma(ze)
+    hipLaunchKernelGGL(k_band_t<1>, dim3(cdiv(w, 16), cdiv(B, 64)), blk, 0, s, N, w, bw, sw, B, P + t->o_w1e, t->Xb,
+                       t->ae, P + t->o_b1e, t->ze, (const float*)nullptr, act, t->x3);
+    // xh = W2e ae (K = w, split)
+    hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(B, 32), cdiv(n, 32), t->split), blk, 0, s, n, B, w, P + t->o_w2e,
+                       (long long)w, 1LL, t->ae, (long long)B, 1LL, t->kpart, B, t->split, (const float*)nullptr,
+                       (float*)nullptr, (const float*)nullptr, act, t->x3);
+    hipLaunchKernelGGL(k_split_sum, dim3(cdiv((long long)n * B, 256)), blk, 0, s, t->kpart, t->split, (long long)n * B,
+                       t->xh);
+    // decoder: zd = W1d xh + b1d, ad = sigma(zd)
+    hipLaunchKernelGGL(k_dense<1>, dim3(cdiv(B, 32), cdiv(w, 32), 1), blk, 0, s, w, B, n, P + t->o_w1d, (long long)n,
+                       1LL, t->xh, (long long)B, 1LL, t->ad, B, 1, P + t->o_b1d, t->zd, (const float*)nullptr, act, t->x3);
+    // y = D2 ad, loss and dY
+    const dim3 lgrid(cdiv(N, 16), cdiv(B, 64));
+    hipLaunchKernelGGL(k_band_loss, lgrid, blk, 0, s, N, w, bw, sw, B, P + t->o_w2d, t->ad, t->Xb, scale_d, t->dY,
+                       t->lpart, t->x3);
+    if (loss_d) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, s, t->lpart, (int)(lgrid.x * lgrid.y), B, loss_d);
+    // gradients
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(t->n_band, 256)), blk, 0, s, G + t->o_w2d, t->n_band, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(t->n_band, 256)), blk, 0, s, G + t->o_w1e, t->n_band, 0.f);
+    hipLaunchKernelGGL(k_band_grad, dim3(cdiv(N, 16)), blk, 0, s, N, w, bw, sw, B, t->dY, t->ad, G + t->o_w2d, t->x3);
+    // dzd = (D2^T dY) o sigma'(zd)
+    hipLaunchKernelGGL(k_band_t<2>, dim3(cdiv(w, 16), cdiv(B, 64)), blk, 0, s, N, w, bw, sw, B, P + t->o_w2d, t->dY,
+                       t->dzd, (const float*)nullptr, (float*)nullptr, t->zd, act, t->x3);
+    // gW1d = dzd xh^T, gb1d = sum_b dzd
+    hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(n, 32), cdiv(w, 32), 1), blk, 0, s, w, n, B, t->dzd, (long long)B, 1LL,
+                       t->xh, 1LL, (long long)B, G + t->o_w1d, n, 1, (const float*)nullptr, (float*)nullptr,
+                       (const float*)nullptr, act, t->x3);
+    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 256)), blk, 0, s, t->dzd, w, B, G + t->o_b1d);
+    // dxh = W1d^T dzd (K = w, split)
+    hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(B, 32), cdiv(n, 32), t->split), blk, 0, s, n, B, w, P + t->o_w1d, 1LL,
+                       (long long)n, t->dzd, (long long)B, 1LL, t->kpart, B, t->split, (const float*)nullptr,
+                       (float*)nullptr, (const float*)nullptr, act, t->x3);
+    hipLaunchKernelGGL(k_split_sum, dim3(cdiv((long long)n * B, 256)), blk, 0, s, t->kpart, t->split, (long long)n * B,
+                       t->dxh);
+    // gW2e = dxh ae^T
+    hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(w, 32), cdiv(n, 32), 1), blk, 0, s, n, w, B, t->dxh, (long long)B, 1LL,
+                       t->ae, 1LL, (long long)B, G + t->o_w2e, w, 1, (const float*)nullptr, (float*)nullptr,
+                       (const float*)nullptr, act, t->x3);
+    // dze = (W2e^T dxh) o sigma'(ze)
+    hipLaunchKernelGGL(k_dense<2>, dim3(cdiv(B, 32), cdiv(w, 32), 1), blk, 0, s, w, B, n, P + t->o_w2e, 1LL,
+                       (long long)w, t->dxh, (long long)B, 1LL, t->dze, B, 1, (const float*)nullptr, (float*)nullptr,
+                       t->ze, act, t->x3);
+    // gW1e[r][k][t] = sum_b x~[r][b] dze[c][b], gb1e = sum_b dze
+    hipLaunchKernelGGL(k_band_grad, dim3(cdiv(N, 16)), blk, 0, s, N, w, bw, sw, B, t->Xb, t->dze, G + t->o_w1e, t->x3);
+    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 256)), blk, 0, s, t->dze, w, B, G + t->o_b1e);
+    if (grad_d) AECHECK(hipMemcpyAsync(grad_d, G, (size_t)t->n_params * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (update) {
+        hipLaunchKernelGGL(k_ae_tick, dim3(1), dim3(1), 0, s, t->t);
+        hipLaunchKernelGGL(k_ae_adam, dim3(cdiv(t->n_params, 256)), blk, 0, s, t->n_params, P, G, t->m, t->v, t->t, lr);
+    }
+    AECHECK(hipGetLastError());
+    return 0;
+}
+
+}  // extern "C"

@@ -81,6 +81,12 @@ def lib():
         L.mlp_train_step.argtypes = [vp, vp, vp, vp, ip, C.c_float, ip, vp, vp, vp]
         L.rom_solve_warm.argtypes = [vp, vp, vp, vp, ip, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp]
         L.rom_decode_states.argtypes = [vp, vp, vp, ip, ip, vp, vp]
+        L.ddrom_ae_trainer_create.argtypes = [ip, ip, ip, ip, ip, ip, ip, C.POINTER(C.c_float), C.POINTER(vp)]
+        L.ddrom_ae_trainer_destroy.argtypes = [vp]
+        L.ddrom_ae_trainer_size.argtypes = [vp, ip]
+        L.ddrom_ae_trainer_size.restype = C.c_longlong
+        L.ddrom_ae_trainer_params.argtypes = [vp, vp, vp]
+        L.ae_train_step.argtypes = [vp, vp, vp, ip, vp, C.c_float, ip, vp, vp, vp]
         L.rom_relative_error.argtypes = [vp, vp, vp, ip, ip, vp, vp, vp]
         _lib = L
     return _lib
@@ -97,6 +103,14 @@ def _ptr(t):
 
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, name):
+    """Device tensors handed to the library by pointer must be contiguous CUDA tensors of the
+    stated dtype (a strided view would be read with the wrong layout)."""
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA tensor of dtype {dtype}")
+    return t
 
 
 def _dev(x, dtype=torch.float64):
@@ -344,7 +358,10 @@ class ProposalTrainer:
 
     def step(self, mu, target, rows, lr: float = 1e-3, update: bool = True, loss: bool = False, grad: bool = False):
         """One minibatch; mu [N][2] FP64, target [N][out] FP32 (standardised), rows [B] int32,
-        all device tensors.  Returns (loss tensor or None, gradient tensor or None)."""
+        all contiguous device tensors.  Returns (loss tensor or None, gradient tensor or None)."""
+        _need(mu, torch.float64, "mu")
+        _need(target, torch.float32, "target")
+        _need(rows, torch.int32, "rows")
         B = int(rows.shape[0])
         lt = torch.empty((1,), dtype=torch.float32, device="cuda") if loss else None
         gt = torch.empty((self.n_params,), dtype=torch.float32, device="cuda") if grad else None
@@ -411,3 +428,83 @@ def relative_error(model: Model, ws: Workspace, xhat, xfom, precision=PREC_FP64)
     _check(lib().rom_relative_error(model.h, ws.h, _ptr(xhat), B, int(precision), _ptr(xfom), _ptr(err), _stream()),
            "rom_relative_error")
     return err
+
+
+# ---- autoencoder training ------------------------------------------------------------
+
+def band_slots(N: int, b: int, s: int):
+    """Column of every band slot [N][3][b] and its validity (inside [0, N s))."""
+    r = np.arange(N)[:, None, None]
+    k = np.arange(-1, 2)[None, :, None]
+    t = np.arange(b)[None, None, :]
+    cols = r * s + k * b * s + t
+    return cols, (cols >= 0) & (cols < N * s)
+
+
+def ae_pack(N: int, n: int, b: int, s: int, W1e_csr, b1e, W2e, W1d, b1d, W2d_csr) -> np.ndarray:
+    """Packed trainer parameters from weights whose masked layers list their entries in row
+    order of the mask (decoder: rows r, columns ascending) and of its transpose (encoder:
+    hidden units c, inputs ascending)."""
+    cols, valid = band_slots(N, b, s)
+    flat_valid = np.flatnonzero(valid.ravel())
+    w2d = np.zeros(3 * N * b)
+    w2d[flat_valid] = np.asarray(W2d_csr)                       # row-major order == slot order
+    rows = np.broadcast_to(np.arange(N)[:, None, None], cols.shape).ravel()[flat_valid]
+    order = np.lexsort((rows, cols.ravel()[flat_valid]))        # encoder entries sorted by (c, r)
+    w1e = np.zeros(3 * N * b)
+    w1e[flat_valid[order]] = np.asarray(W1e_csr)
+    return np.concatenate([w1e, b1e, np.asarray(W2e).ravel(), np.asarray(W1d).ravel(), b1d, w2d]).astype(np.float32)
+
+
+def ae_unpack(flat, N: int, n: int, b: int, s: int):
+    """Inverse of ae_pack: (W1e_csr, b1e, W2e, W1d, b1d, W2d_csr)."""
+    flat = np.asarray(flat, dtype=np.float64)
+    w = N * s
+    nb = 3 * N * b
+    o = [0, nb, nb + w, nb + w + n * w, nb + w + 2 * n * w, nb + 2 * w + 2 * n * w, 2 * nb + 2 * w + 2 * n * w]
+    cols, valid = band_slots(N, b, s)
+    flat_valid = np.flatnonzero(valid.ravel())
+    rows = np.broadcast_to(np.arange(N)[:, None, None], cols.shape).ravel()[flat_valid]
+    order = np.lexsort((rows, cols.ravel()[flat_valid]))
+    w1e = flat[o[0]:o[1]][flat_valid[order]]
+    w2d = flat[o[5]:o[6]][flat_valid]
+    return (w1e, flat[o[1]:o[2]], flat[o[2]:o[3]].reshape(n, w), flat[o[3]:o[4]].reshape(w, n),
+            flat[o[4]:o[5]], w2d)
+
+
+class AETrainer:
+    """GPU trainer of one band-masked autoencoder (BF16 matrix cores, FP32 masters, Adam)."""
+
+    def __init__(self, N: int, n: int, b: int, s: int, activation: int, max_batch: int, packed, precision: int = 0):
+        pr = np.ascontiguousarray(np.asarray(packed, dtype=np.float32))
+        h = C.c_void_p()
+        _check(lib().ddrom_ae_trainer_create(int(N), int(n), int(b), int(s), int(activation), int(max_batch),
+                                             int(precision), pr.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)),
+               "ddrom_ae_trainer_create")
+        self.h = h
+        self.N, self.n, self.b, self.s = int(N), int(n), int(b), int(s)
+        self.n_params = int(lib().ddrom_ae_trainer_size(h, 0))
+
+    def step(self, X, rows, scale, lr: float = 1e-3, update: bool = True, loss: bool = False, grad: bool = False):
+        """X [n_snap][N], rows [B] (int32), scale [N]: contiguous FP32 device tensors."""
+        _need(X, torch.float32, "X")
+        _need(rows, torch.int32, "rows")
+        _need(scale, torch.float32, "scale")
+        if X.shape[-1] != self.N or scale.shape[0] != self.N:
+            raise ValueError("snapshot width or scale length differs from the trainer's N")
+        B = int(rows.shape[0])
+        lt = torch.empty((1,), dtype=torch.float32, device="cuda") if loss else None
+        gt = torch.empty((self.n_params,), dtype=torch.float32, device="cuda") if grad else None
+        _check(lib().ae_train_step(self.h, _ptr(X), _ptr(rows), B, _ptr(scale), float(lr), int(bool(update)),
+                                   _ptr(lt), _ptr(gt), _stream()), "ae_train_step")
+        return lt, gt
+
+    def params(self):
+        out = torch.empty((self.n_params,), dtype=torch.float32, device="cuda")
+        _check(lib().ddrom_ae_trainer_params(self.h, _ptr(out), _stream()), "ddrom_ae_trainer_params")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ddrom_ae_trainer_destroy(self.h)
+            self.h = None

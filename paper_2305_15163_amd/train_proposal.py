@@ -70,8 +70,8 @@ def train(model_pack: dict, n_train: int = 4096, seed: int = 4, epochs: int = 20
     tr = dr.ProposalTrainer(sizes, dr.pack_mlp_params(init), max_batch=batch)
     N = len(mus_k)
     train_idx, test_idx = si.train_split(N, 0.1, seed)
-    mu_d = torch.as_tensor(mus_k, dtype=torch.float64, device="cuda")
-    T_d = torch.as_tensor(Tn, device="cuda")
+    mu_d = torch.as_tensor(np.ascontiguousarray(mus_k), dtype=torch.float64, device="cuda")
+    T_d = torch.as_tensor(np.ascontiguousarray(Tn), device="cuda")
     hist = []
     best = (np.inf, 0, None)
 
