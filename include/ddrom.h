@@ -83,6 +83,11 @@ typedef struct {
     const ddrom_decoder_desc* dec_ga;       /* [n_sub] interface decoders g_i^Gamma */
     const int* hr_count;                    /* [n_sub] */
     const int* const* hr_nodes;             /* [n_sub] -> [hr_count[i]] */
+    /* Work-item shapes (0: library default): [0] decoder rows per decode work item (1..64),
+     * [1] sampled nodes per residual work item (>= 4), [2] interface rows per constraint
+     * work item (>= 4).  They change the schedule only; results are identical up to the
+     * order of partial sums. */
+    int tile[3];
 } ddrom_model_desc;
 
 typedef struct ddrom_model ddrom_model;
@@ -109,8 +114,8 @@ int ddrom_model_create(const ddrom_model_desc* desc, ddrom_model** out);
 void ddrom_model_destroy(ddrom_model* m);
 
 /* Sizes: query = 0 n_sub, 1 n_D, 2 n_C, 3 N_A, 4 N_x (= 2 nx ny), 5 sum_i (N_i^Omega + N_i^Gamma),
- * 6 total HR nodes.  Per subdomain (sd >= 0): 10 n_i^Omega, 11 n_i^Gamma, 12 N_i^Omega,
- * 13 N_i^Gamma, 14 |I_o| of the interior subnet, 15 |I_h| of the interior subnet,
+ * 6 total HR nodes, 7..9 the work-item shapes in use (decoder rows, residual nodes,
+ * constraint rows).  Per subdomain (sd >= 0): 10 n_i^Omega, 11 n_i^Gamma, 12 N_i^Omega, 13 N_i^Gamma, 14 |I_o| of the interior subnet, 15 |I_h| of the interior subnet,
  * 16 HR nodes, 17 offset of xhat_i^Omega in xhat, 18 own nodes, 19 mask entries of the kept
  * interior rows, 20 mask entries of the interface decoder, 21 hidden units of the interface
  * decoder. */
@@ -221,6 +226,17 @@ int ddrom_mlp_trainer_params(const ddrom_mlp_trainer* t, float* params_d, hipStr
 int mlp_train_step(ddrom_mlp_trainer* t, const double* mu_d, const float* target_d, const int* rows_d, int B,
                    float lr, int update, float* loss_d, float* grad_d, hipStream_t s);
 
+/* Uneven batch: n_models models, each with its own workspace (distinct), parameters mu_d[k]
+ * [Bs[k]][2] and outputs (host arrays of device pointers; lam_d, iters_d, status_d, fnorm_d
+ * and their entries may be NULL).  Zero start, options as in rom_solve_batch.  One captured
+ * graph holds the solver rounds of all models as concurrent branches (each model on its own
+ * streams), replayed until no solve of any model is running; results equal separate
+ * rom_solve_batch calls.  The graph is kept in wss[0]. */
+int rom_solve_multi(int n_models, const ddrom_model* const* models, ddrom_workspace* const* wss,
+                    const double* const* mu_d, const int* Bs, const ddrom_opts* o, double* const* xhat_d,
+                    double* const* lam_d, int* const* iters_d, int* const* status_d, double* const* fnorm_d,
+                    hipStream_t s);
+
 /* rom_solve_batch warm-started from the network's proposal, with the zero start (zero
  * latents, least-squares multiplier) as fallback: each solve evaluates the zero start's first
  * KKT residual norm f_zero, then the proposal's; the proposal is kept only if its norm is
@@ -276,6 +292,17 @@ int rom_decode_states(const ddrom_model* m, ddrom_workspace* ws, const double* x
  * and interface DoFs.  Decodes in `precision`; sums in FP64. */
 int rom_relative_error(const ddrom_model* m, ddrom_workspace* ws, const double* xhat_d, int B, int precision,
                        const double* xfom_d, double* err_d, hipStream_t s);
+
+/* Work-item shape search for one model description and batch (host-driven, synchronous):
+ * the batched solve (zero start, options o) of the B parameters mu_d [B][2] is timed with
+ * HIP events, median of `reps` runs after one untimed run, for candidate shapes (decoder rows
+ * 16..64, residual nodes 8..48, constraint rows 32..256) by coordinate descent from the
+ * library defaults: each dimension in turn keeps its fastest value.  Writes the chosen
+ * shape to tile_out[3] (for desc->tile) and, if table_h is non-NULL, up to max_table rows
+ * [decoder rows, residual nodes, constraint rows, ms] of the shapes tried, their count in
+ * *n_tried.  desc->tile is ignored.  Builds and frees a model and workspace per shape. */
+int ddrom_autotune(const ddrom_model_desc* desc, const double* mu_d, int B, const ddrom_opts* o, int reps,
+                   int* tile_out, float* table_h, int max_table, int* n_tried);
 
 /* Measurement helper: average device time (ms) per launch of the four evaluation kernels
  * of one solver round, ms_h[0] interior decoder subnets, [1] interface decoders,

@@ -48,6 +48,10 @@ CONFIGS = {
     "cfg2c": dict(nx=480, ny=480, nsx=8, nsy=8, n_om="draw", n_ga="half", b=9, s=2, act=ACT_SIGMOID,
                   epochs=300, batch=16, train_grid=(8, 8), hr_frac=(0.05, 0.25), seed=23),
     # small configurations for tests
+    "tinymix": dict(nx=16, ny=12, nsx=2, nsy=2, n_om="draw", n_ga="half", b=3, s=2, act=ACT_SIGMOID,
+                    epochs=300, batch=4, train_grid=(4, 4), hr_frac=(0.3, 0.6), seed=31),
+    "tinybig": dict(nx=48, ny=48, nsx=8, nsy=8, n_om=6, n_ga=3, b=3, s=2, act=ACT_SIGMOID,
+                    epochs=60, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=32),
     "tiny": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID,
                  epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
 }

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/model.hip", "csrc/kernels.hip", "csrc/mlp.hip", "csrc/aetrain.hip"]
+SOURCES = ["csrc/model.hip", "csrc/kernels.hip", "csrc/mlp.hip", "csrc/aetrain.hip", "csrc/autotune.hip"]
 OUT = os.path.join(HERE, "libddrom.so")
 
 

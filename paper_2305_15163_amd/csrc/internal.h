@@ -141,6 +141,8 @@ struct ddrom_model {
     int total_own = 0;
     int* fom_sd_of_row_d = nullptr;              // owner subdomain of each flattened own-node slot
     int* state_dof_d = nullptr;                  // [n_state] global DoF of each row of the DD state
+    int tile_dec_rows = 0, tile_res_nodes = 0, tile_con_orows = 0;   // work-item shapes in use
+    std::vector<int> cchunk0;                    // [n_sub + 1] first constraint work item of each subdomain
 };
 
 struct SolveState {
@@ -177,6 +179,8 @@ struct ddrom_workspace {
     void* state_out = nullptr;      // decoded DD states [n_state][Bp], allocated on first use
     int state_prec = -1;            // precision state_out was allocated for
     double* err_part = nullptr;     // [n_sub][2][Bp] error numerators / denominators
+    double* kkt_scr = nullptr;      // [Bp][kkt_stride] KKT blocks of models too large for LDS
+    long long kkt_stride = 0;
     double* mu = nullptr;           // [Bp][2]
     double* RB = nullptr;           // per-solve reduced blocks [Bp][RS]
     int rs = 0, RS = 0;             // per-subdomain block size, per-solve stride

@@ -438,13 +438,14 @@ __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rch
 // (C A_i)^T is stored row-major with stride ca_ld so the 8 multipliers of an interface row
 // are one contiguous scalar load.  Partial sums over interface-row runs go to separate slots.
 template <typename T, int NG>
-__global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, const ResSeg* __restrict__ rsegs,
+__global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, int chunk_base,
+                                            const ResSeg* __restrict__ rsegs,
                                             const DecSeg* __restrict__ segs, const double* __restrict__ CA, int n_C,
                                             int ca_ld, const T* __restrict__ dec, const int* __restrict__ n_live,
                                             int B, int Bp, double* __restrict__ c_part, double* __restrict__ E_part,
                                             int mmax) {
     constexpr int JB = 8;
-    const ConChunk cc = cch[blockIdx.x];
+    const ConChunk cc = cch[chunk_base + blockIdx.x];
     const ResSeg rs = rsegs[cc.sd];
     if ((int)blockIdx.y * 64 >= live_count(n_live, B)) return;
     const int b = blockIdx.y * 64 + threadIdx.x;   // slot
@@ -595,6 +596,8 @@ struct UpdArgs {
     SolveState* st;
     const int* live;       // slot -> solve
     const int* n_live;
+    double* gscr;          // per-slot scratch of the big KKT arrays when they exceed LDS
+    long long gstride;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -621,24 +624,31 @@ __device__ __forceinline__ int packed_idx(int i, int j, int n) {   // i <= j, up
 }
 
 // LDS layout of the update kernel (offsets in doubles).
+// Memory of the update kernel (offsets in doubles): a small part always in LDS, and the
+// per-subdomain blocks and the Schur system, in LDS when they fit beside it, else in a
+// per-slot area of global scratch.
 struct UpdLds {
-    int lam, c, sl, red, E, P, q, rho, X, S, total;
+    int lam, c, sl, red, small;      // small part: lam [nC], c [nC], s_lambda [nC], reduction [16]
+    int E, P, q, rho, X, S, big;     // big part, relative to its base
 };
 __host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int MG) {
     UpdLds L;
+    const int nc = nC > 0 ? nC : 1;
     L.lam = 0;
-    L.c = L.lam + 64;
-    L.sl = L.c + 64;
-    L.red = L.sl + 64;
-    L.E = L.red + 16;                        // [n_sub][nC][mg]  Ehat_i
+    L.c = L.lam + nc;
+    L.sl = L.c + nc;
+    L.red = L.sl + nc;
+    L.small = L.red + 16;
+    L.E = 0;                                 // [n_sub][nC][mg]  Ehat_i
     L.P = L.E + n_sub * nC * mg;             // [n_sub][nC][mg]  Ehat_i (W_i)_Gamma
     L.q = L.P + n_sub * nC * mg;             // [n_sub][nC]      Ehat_i (t_i)_Gamma
     L.rho = L.q + n_sub * nC;                // [n_sub][NN]      rho_i
     L.X = L.rho + n_sub * NN;                // [n_sub][NN][MG+1]  [W_i | t_i]
     L.S = L.X + n_sub * NN * (MG + 1);       // [nC][nC+1]       [S | right-hand side]
-    L.total = L.S + nC * (nC + 1);
+    L.big = L.S + nC * (nC + 1);
     return L;
 }
+constexpr int UPD_LDS_DOUBLES = 8192;        // 64 KiB
 
 // Dense n x n system [M | r] (in LDS, row stride n + 1) solved by one wave with row i in
 // lane i, held in registers: Gaussian elimination with partial pivoting in which the pivot
@@ -694,6 +704,83 @@ __device__ __noinline__ bool wave_lu_solve(const double* M, int n, double* x, in
     return wave_lu_reg<64>(M, n, x, lane);
 }
 
+// Systems larger than a wave (64 < n <= 256): the whole workgroup eliminates with partial
+// pivoting, rows spread over threads, then back-substitutes column by column.  M may live in
+// global memory.  redv [9] / redi [9] / piv: LDS scratch.  Every thread returns the same value.
+__device__ bool block_lu_solve(double* M, int n, double* x, double* redv, int* redi, int tid, int nth) {
+    const int ld = n + 1, lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = n;
+        for (int i = k + tid; i < n; i += nth) {
+            const double v = fabs(M[(size_t)i * ld + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (lane == 0) {
+            redv[wave] = best;
+            redi[wave] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double bb = redv[0];
+            int ii = redi[0];
+            for (int w = 1; w < nw; ++w)
+                if (redv[w] > bb || (redv[w] == bb && redi[w] < ii)) { bb = redv[w]; ii = redi[w]; }
+            redv[8] = bb;
+            redi[8] = ii;
+        }
+        __syncthreads();
+        const int p = redi[8];
+        const double bestv = redv[8];
+        if (!(bestv > 0.0) || !isfinite(bestv)) ok = false;
+        if (p != k && p < n)
+            for (int j = tid; j <= n; j += nth) {
+                const double t = M[(size_t)k * ld + j];
+                M[(size_t)k * ld + j] = M[(size_t)p * ld + j];
+                M[(size_t)p * ld + j] = t;
+            }
+        __syncthreads();
+        const double pv = M[(size_t)k * ld + k];
+        if (pv != 0.0)
+            for (int i = k + 1 + tid; i < n; i += nth) {
+                const double f = M[(size_t)i * ld + k] / pv;
+                for (int j = k + 1; j <= n; ++j) M[(size_t)i * ld + j] -= f * M[(size_t)k * ld + j];
+            }
+        __syncthreads();
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        if (tid == 0) x[i] = M[(size_t)i * ld + n] / M[(size_t)i * ld + i];
+        __syncthreads();
+        const double xi = x[i];
+        for (int j = tid; j < i; j += nth) M[(size_t)j * ld + n] -= M[(size_t)j * ld + i] * xi;
+        __syncthreads();
+    }
+    return ok;
+}
+
+// Solve [M | r] with every thread of the workgroup calling: one wave when n <= 64, else the
+// workgroup.  The result is valid for all threads after the call.
+__device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, double* redv, int* redi, int* okf, int tid,
+                                       int nth) {
+    if (n <= 64) {
+        if (tid == 0) okf[0] = 1;
+        __syncthreads();
+        if ((tid >> 6) == 0) {
+            const bool ok = wave_lu_solve(M, n, x, tid & 63);
+            if (!ok && (tid & 63) == 0) okf[0] = 0;
+        }
+        __syncthreads();
+        return okf[0] != 0;
+    }
+    return block_lu_solve(M, n, x, redv, redi, tid, nth);
+}
+
 // ------------------------------------------------------------------------------------
 // Per-solve update: merit, Armijo test, KKT step (one workgroup of NW waves per solve slot)
 // ------------------------------------------------------------------------------------
@@ -706,11 +793,12 @@ __device__ __noinline__ bool wave_lu_solve(const double* M, int n, double* x, in
 // these solves need no LDS traffic and no workgroup barrier.  S (a sum over subdomains in a
 // fixed order) and its pivoted solve then go through LDS.  NN >= n_i^Omega + n_i^Gamma and
 // MG >= n_i^Gamma bound every block (smaller blocks are padded with identity rows).
-template <int NN, int MG>
+template <int NN, int MG, int GB>
 __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     __shared__ int flag_bad;
+    __shared__ int lu_idx[9], lu_ok[1];
     const int slot = blockIdx.x;
     const int nl = live_count(a.n_live, a.B);
     if (slot >= nl) return;
@@ -724,12 +812,13 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     double* c_s = sm + L.c;
     double* sl_s = sm + L.sl;
     double* red = sm + L.red;
-    double* Es = sm + L.E;
-    double* Ps = sm + L.P;
-    double* qs = sm + L.q;
-    double* rho = sm + L.rho;
-    double* Xs = sm + L.X;
-    double* Sm = sm + L.S;
+    double* big = GB ? a.gscr + (size_t)slot * a.gstride : sm + L.small;
+    double* Es = big + L.E;
+    double* Ps = big + L.P;
+    double* qs = big + L.q;
+    double* rho = big + L.rho;
+    double* Xs = big + L.X;
+    double* Sm = big + L.S;
     const double* rb = a.RB + (size_t)slot * a.RS;
     const int ld = nC + 1;
 
@@ -763,7 +852,7 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
             Sm[e] = s;
         }
         __syncthreads();
-        if (wave == 0) wave_lu_solve(Sm, nC, lam_s, lane);
+        kkt_lu(Sm, nC, lam_s, red, lu_idx, lu_ok, tid, nth);
         __syncthreads();
     }
 
@@ -933,24 +1022,27 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         if (lane < NN)
 #pragma unroll
             for (int l = 0; l <= MG; ++l) Xs[((size_t)sd * NN + lane) * (MG + 1) + l] = Xr[l];
-        // P_i = Ehat_i (W_i)_Gamma, q_i = Ehat_i (t_i)_Gamma (constraint row jj in lane jj)
+        // P_i = Ehat_i (W_i)_Gamma, q_i = Ehat_i (t_i)_Gamma (constraint row j0 + lane in lane)
         const double* E = Es + (size_t)sd * nC * mg;
-        double P[MG + 1];
+        for (int j0 = 0; j0 < nC; j0 += 64) {
+            const int jj = j0 + lane;
+            double P[MG + 1];
 #pragma unroll
-        for (int l = 0; l <= MG; ++l) P[l] = 0.0;
+            for (int l = 0; l <= MG; ++l) P[l] = 0.0;
 #pragma unroll
-        for (int k = 0; k < MG; ++k) {
-            if (k < ng) {
-                const double e = lane < nC ? E[lane * mg + k] : 0.0;
+            for (int k = 0; k < MG; ++k) {
+                if (k < ng) {
+                    const double e = jj < nC ? E[jj * mg + k] : 0.0;
 #pragma unroll
-                for (int l = 0; l <= MG; ++l) P[l] += e * lane_bcast(Xr[l], no + k);
+                    for (int l = 0; l <= MG; ++l) P[l] += e * lane_bcast(Xr[l], no + k);
+                }
             }
-        }
-        if (lane < nC) {
+            if (jj < nC) {
 #pragma unroll
-            for (int l = 0; l < MG; ++l)
-                if (l < mg) Ps[((size_t)sd * nC + lane) * mg + l] = l < ng ? P[l] : 0.0;
-            qs[(size_t)sd * nC + lane] = P[MG];
+                for (int l = 0; l < MG; ++l)
+                    if (l < mg) Ps[((size_t)sd * nC + jj) * mg + l] = l < ng ? P[l] : 0.0;
+                qs[(size_t)sd * nC + jj] = P[MG];
+            }
         }
     }
     __syncthreads();
@@ -981,7 +1073,7 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
             Sm[e] = s;
         }
         __syncthreads();
-        if (wave == 0 && !wave_lu_solve(Sm, nC, sl_s, lane) && lane == 0) flag_bad = 1;
+        if (!kkt_lu(Sm, nC, sl_s, red, lu_idx, lu_ok, tid, nth) && tid == 0) flag_bad = 1;
         __syncthreads();
         if (flag_bad) {
             if (tid == 0) {
@@ -1369,32 +1461,35 @@ static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const dd
 static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const int* n_live, int B,
                       hipStream_t s) {
     if (m->n_cchunks == 0 || m->n_C == 0) return 0;
-    dim3 grid(m->n_cchunks, ws->Bp / 64), block(64);
-    const int ng = m->mmax;
-    for (int sd = 0; sd < m->n_sub; ++sd)
-        if (m->n_ga[sd] != ng) {
-            set_error("constraint kernel needs equal interface latent sizes");
-            return DDROM_EINVAL;
-        }
+    // one launch per run of consecutive subdomains with the same interface latent size
+    for (int s0 = 0; s0 < m->n_sub;) {
+        int s1 = s0 + 1;
+        while (s1 < m->n_sub && m->n_ga[s1] == m->n_ga[s0]) ++s1;
+        const int c0 = m->cchunk0[s0], c1 = m->cchunk0[s1], ng = m->n_ga[s0];
+        if (c1 > c0) {
+            dim3 grid(c1 - c0, ws->Bp / 64), block(64);
 #define CON_CASE(G)                                                                                               \
     case G:                                                                                                       \
         if (prec == DDROM_PREC_FP64)                                                                              \
-            hipLaunchKernelGGL((k_con<double, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d, \
-                               m->n_C, m->ca_ld, (const double*)ws->dec_out, n_live, B, ws->Bp, ws->c_part,       \
-                               ws->E_part, m->mmax);                                                              \
+            hipLaunchKernelGGL((k_con<double, G>), grid, block, 0, s, m->cchunks_d, c0, m->rsegs_d, m->segs_d,    \
+                               m->CA_d, m->n_C, m->ca_ld, (const double*)ws->dec_out, n_live, B, ws->Bp,          \
+                               ws->c_part, ws->E_part, std::max(1, m->mmax));                                     \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_con<float, G>), grid, block, 0, s, m->cchunks_d, m->rsegs_d, m->segs_d, m->CA_d,  \
-                               m->n_C, m->ca_ld, (const float*)ws->dec_out, n_live, B, ws->Bp, ws->c_part,        \
-                               ws->E_part, m->mmax);                                                              \
+            hipLaunchKernelGGL((k_con<float, G>), grid, block, 0, s, m->cchunks_d, c0, m->rsegs_d, m->segs_d,     \
+                               m->CA_d, m->n_C, m->ca_ld, (const float*)ws->dec_out, n_live, B, ws->Bp,           \
+                               ws->c_part, ws->E_part, std::max(1, m->mmax));                                     \
         break;
-    switch (ng) {
-        CON_CASE(1) CON_CASE(2) CON_CASE(3) CON_CASE(4) CON_CASE(6)
-        default:
-            set_error("unsupported interface latent size");
-            return DDROM_EINVAL;
-    }
+            switch (ng) {
+                CON_CASE(1) CON_CASE(2) CON_CASE(3) CON_CASE(4) CON_CASE(6)
+                default:
+                    set_error("unsupported interface latent size " + std::to_string(ng));
+                    return DDROM_EINVAL;
+            }
 #undef CON_CASE
-    HIPCHECK(hipGetLastError());
+            HIPCHECK(hipGetLastError());
+        }
+        s0 = s1;
+    }
     return 0;
 }
 
@@ -1415,16 +1510,22 @@ static ModelDevInts get_ints(const ddrom_model* m) {
     return g_ints[m];
 }
 
-// One evaluation of all active solves at their trial points (xt).  The interface decoders
-// and the constraint sums run on a second stream forked from `s` (they depend only on the
-// interface latents), overlapping the interior decoders and the residual kernel.
+// One evaluation of all active solves at their trial points (xt).  With `fork`, the interface
+// decoders and the constraint sums run on a second stream forked from `s` (they depend only on
+// the interface latents), overlapping the interior decoders and the residual kernel; without
+// it everything runs on `s` in the same order.  Under graph capture `s` must then be the
+// capture's origin stream: a join into a stream that is itself a forked branch makes the two
+// streams each other's children in HIP's capture bookkeeping, and ending the capture recurses
+// through that cycle.
 static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const int* live,
-                          const int* n_live, const double* xhat, hipStream_t s) {
+                          const int* n_live, const double* xhat, hipStream_t s, bool fork = true) {
     int rc;
     const int n = m->n_sub;
-    hipStream_t s2 = ws->stream2;
-    HIPCHECK(hipEventRecord(ws->ev_fork, s));
-    HIPCHECK(hipStreamWaitEvent(s2, ws->ev_fork, 0));
+    hipStream_t s2 = fork ? ws->stream2 : s;
+    if (fork) {
+        HIPCHECK(hipEventRecord(ws->ev_fork, s));
+        HIPCHECK(hipStreamWaitEvent(s2, ws->ev_fork, 0));
+    }
     for (int g0 = n; g0 < 2 * n;) {
         int g1 = g0 + 1;
         while (g1 < 2 * n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
@@ -1432,9 +1533,9 @@ static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, i
             return rc;
         g0 = g1;
     }
-    HIPCHECK(hipEventRecord(ws->ev_ga, s2));
+    if (fork) HIPCHECK(hipEventRecord(ws->ev_ga, s2));
     if ((rc = launch_con(m, prec, ws, n_live, B, s2))) return rc;
-    HIPCHECK(hipEventRecord(ws->ev_con, s2));
+    if (fork) HIPCHECK(hipEventRecord(ws->ev_con, s2));
     for (int g0 = 0; g0 < n;) {
         int g1 = g0 + 1;
         while (g1 < n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
@@ -1442,14 +1543,14 @@ static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, i
             return rc;
         g0 = g1;
     }
-    HIPCHECK(hipStreamWaitEvent(s, ws->ev_ga, 0));
+    if (fork) HIPCHECK(hipStreamWaitEvent(s, ws->ev_ga, 0));
     for (int s0 = 0; s0 < n;) {
         int s1 = s0 + 1;
         while (s1 < n && m->n_om[s1] == m->n_om[s0] && m->n_ga[s1] == m->n_ga[s0]) ++s1;
         if ((rc = launch_res(m, prec, s0, s1, ws, live, n_live, B, s))) return rc;
         s0 = s1;
     }
-    HIPCHECK(hipStreamWaitEvent(s, ws->ev_con, 0));
+    if (fork) HIPCHECK(hipStreamWaitEvent(s, ws->ev_con, 0));
     return 0;
 }
 
@@ -1469,7 +1570,9 @@ static UpdArgs upd_args(const ddrom_model* m, ddrom_workspace* ws, int B, const 
 // Block bounds (NN >= n_i^Omega + n_i^Gamma, MG >= n_i^Gamma) of the compiled update kernels.
 static const int kUpdShapes[][2] = {{3, 1}, {4, 0}, {5, 2}, {6, 0}, {6, 2}, {8, 0}, {9, 3}, {12, 4}, {18, 6}, {20, 12}};
 
-static int launch_update(const ddrom_model* m, const UpdArgs& ua, int B, hipStream_t s) {
+// Block bounds of the update kernel for a model, and whether its big arrays need global scratch
+// (doubles per slot in *gbig, 0 when they fit in LDS).
+static int update_shape(const ddrom_model* m, int* NN, int* MG, long long* gbig) {
     int pick = -1;
     for (int k = 0; k < (int)(sizeof(kUpdShapes) / sizeof(kUpdShapes[0])); ++k)
         if (kUpdShapes[k][0] >= m->NNmax && kUpdShapes[k][1] >= m->mmax) { pick = k; break; }
@@ -1477,15 +1580,33 @@ static int launch_update(const ddrom_model* m, const UpdArgs& ua, int B, hipStre
         set_error("subdomain block too large for the update kernel");
         return DDROM_EINVAL;
     }
-    const int NN = kUpdShapes[pick][0], MG = kUpdShapes[pick][1];
-    const size_t lds = (size_t)upd_lds(m->n_sub, m->n_C, std::max(1, m->mmax), NN, MG).total * sizeof(double);
-    if (lds > 65536) {
-        set_error("KKT update needs more than 64 KiB of LDS (too many subdomains or constraints)");
+    *NN = kUpdShapes[pick][0];
+    *MG = kUpdShapes[pick][1];
+    const UpdLds L = upd_lds(m->n_sub, m->n_C, std::max(1, m->mmax), *NN, *MG);
+    *gbig = L.small + L.big <= UPD_LDS_DOUBLES ? 0 : L.big;
+    return 0;
+}
+
+static int launch_update(const ddrom_model* m, const ddrom_workspace* ws, const UpdArgs& ua, int B, hipStream_t s) {
+    int NN, MG, rc;
+    long long gbig;
+    if ((rc = update_shape(m, &NN, &MG, &gbig))) return rc;
+    const UpdLds L = upd_lds(m->n_sub, m->n_C, std::max(1, m->mmax), NN, MG);
+    const int GB = gbig > 0;
+    if (GB && (!ws->kkt_scr || ws->kkt_stride < gbig)) {
+        set_error("workspace lacks KKT scratch");
         return DDROM_EINVAL;
     }
+    const size_t lds = (size_t)(GB ? L.small : L.small + L.big) * sizeof(double);
     const int nw = std::max(1, std::min(8, m->n_sub));
-#define UPD_CASE(A, G)                                                                                 \
-    if (NN == A && MG == G) hipLaunchKernelGGL((k_update<A, G>), dim3(B), dim3(64 * nw), lds, s, ua);
+    UpdArgs a = ua;
+    a.gscr = ws->kkt_scr;
+    a.gstride = ws->kkt_stride;
+#define UPD_CASE(A, G)                                                                                   \
+    if (NN == A && MG == G) {                                                                            \
+        if (GB) hipLaunchKernelGGL((k_update<A, G, 1>), dim3(B), dim3(64 * nw), lds, s, a);            \
+        else hipLaunchKernelGGL((k_update<A, G, 0>), dim3(B), dim3(64 * nw), lds, s, a);               \
+    }
     UPD_CASE(3, 1) UPD_CASE(4, 0) UPD_CASE(5, 2) UPD_CASE(6, 0) UPD_CASE(6, 2) UPD_CASE(8, 0) UPD_CASE(9, 3)
     UPD_CASE(12, 4) UPD_CASE(18, 6) UPD_CASE(20, 12)
 #undef UPD_CASE
@@ -1493,15 +1614,16 @@ static int launch_update(const ddrom_model* m, const UpdArgs& ua, int B, hipStre
     return 0;
 }
 
-static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const UpdArgs& ua, hipStream_t s) {
+static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const UpdArgs& ua, hipStream_t s,
+                        bool fork = true) {
     int rc;
-    if ((rc = evaluate_round(m, ws, prec, B, ws->live, ws->counter, ws->xt, s))) return rc;
+    if ((rc = evaluate_round(m, ws, prec, B, ws->live, ws->counter, ws->xt, s, fork))) return rc;
     ModelDevInts di = get_ints(m);
     const int n_etiles = (m->estride + m->n_C * std::max(1, m->mmax) + RED_E - 1) / RED_E;
     hipLaunchKernelGGL(k_reduce, dim3(m->n_sub + 1, n_etiles, ws->Bp / 64), dim3(256), 0, s, m->n_sub, m->n_C,
                        std::max(1, m->mmax), m->estride, ws->rs, ws->RS, ws->Bp, B, di.n_om, di.n_ga, di.slot0,
                        di.cpart0, m->n_cparts, ws->gn_part, ws->c_part, ws->E_part, ws->counter, ws->RB);
-    if ((rc = launch_update(m, ua, B, s))) return rc;
+    if ((rc = launch_update(m, ws, ua, B, s))) return rc;
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, B, ws->st, ws->live, ws->counter);
     HIPCHECK(hipGetLastError());
     return 0;
@@ -1578,6 +1700,9 @@ long long ddrom_model_size(const ddrom_model* m, int q, int sd) {
         case 4: return m->N_x;
         case 5: return m->n_state;
         case 6: { long long t = 0; for (int v : m->nb) t += v; return t; }
+        case 7: return m->tile_dec_rows;
+        case 8: return m->tile_res_nodes;
+        case 9: return m->tile_con_orows;
         case 10: return sd < 0 ? -1 : m->n_om[sd];
         case 11: return sd < 0 ? -1 : m->n_ga[sd];
         case 12: return sd < 0 ? -1 : m->N_om[sd];
@@ -1644,6 +1769,22 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
             return DDROM_ENOMEM;
         }
     }
+    {
+        int NN, MG, rc;
+        long long gbig;
+        if ((rc = update_shape(m, &NN, &MG, &gbig))) {
+            ddrom_workspace_destroy(w.release());
+            return rc;
+        }
+        if (gbig > 0) {
+            w->kkt_stride = gbig;
+            if (hipMalloc((void**)&w->kkt_scr, (size_t)gbig * Bp * sizeof(double)) != hipSuccess) {
+                set_error("workspace allocation failed (KKT scratch)");
+                ddrom_workspace_destroy(w.release());
+                return DDROM_ENOMEM;
+            }
+        }
+    }
     // all-zero block after the decoder outputs (read by boundary stencil slots)
     w->zero_row = m->dec_rows;
     if (hipMemset(w->dec_out, 0, (size_t)(m->dec_rows + 1 + m->nmax) * Bp * sizeof(double)) != hipSuccess) {
@@ -1680,6 +1821,7 @@ void ddrom_workspace_destroy(ddrom_workspace* w) {
         if (p) (void)hipFree(p);
     if (w->counter_h) (void)hipHostFree(w->counter_h);
     if (w->state_out) (void)hipFree(w->state_out);
+    if (w->kkt_scr) (void)hipFree(w->kkt_scr);
     if (w->err_part) (void)hipFree(w->err_part);
     if (w->graph) (void)hipGraphExecDestroy(w->graph);
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
@@ -1909,6 +2051,120 @@ int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
     }
     FinalOut fo{xhat_d, lam_d, fnorm_d, fnorm0_d, iters_d, status_d, nullptr};
     return solve_common(m, ws, mu_d, B, xhat0_d, lam0_d, o, s, 1, fo);
+}
+
+// Several models in one launch sequence: every model keeps its own workspace and streams; a
+// graph of K rounds forks each round into one branch per model (they run concurrently) and
+// joins them; the host replays it until no solve of any model is running.
+int rom_solve_multi(int n_models, const ddrom_model* const* models, ddrom_workspace* const* wss,
+                    const double* const* mu_d, const int* Bs, const ddrom_opts* o, double* const* xhat_d,
+                    double* const* lam_d, int* const* iters_d, int* const* status_d, double* const* fnorm_d,
+                    hipStream_t caller) {
+    if (n_models <= 0 || !models || !wss || !mu_d || !Bs || !o || !xhat_d || o->max_iter < 0 ||
+        o->max_backtracks < 0 || (o->precision != 0 && o->precision != 1)) {
+        set_error("bad arguments to rom_solve_multi");
+        return DDROM_EINVAL;
+    }
+    int rc;
+    for (int k = 0; k < n_models; ++k) {
+        if ((rc = check_ws(models[k], wss[k], Bs[k]))) return rc;
+        if (Bs[k] <= 0 || !mu_d[k] || !xhat_d[k]) {
+            set_error("every model of rom_solve_multi needs a batch, parameters and an output");
+            return DDROM_EINVAL;
+        }
+        for (int q = 0; q < k; ++q)
+            if (wss[q] == wss[k]) {
+                set_error("rom_solve_multi needs one workspace per model");
+                return DDROM_EINVAL;
+            }
+    }
+    ddrom_workspace* w0 = wss[0];
+    hipStream_t s0 = w0->stream;
+    HIPCHECK(hipEventRecord(w0->ev_in, caller));
+    for (int k = 0; k < n_models; ++k) {
+        ddrom_workspace* ws = wss[k];
+        const ddrom_model* m = models[k];
+        const int B = Bs[k];
+        HIPCHECK(hipStreamWaitEvent(ws->stream, w0->ev_in, 0));
+        hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, ws->stream, B, ws->Bp, m->n_D, m->n_C, mu_d[k],
+                           (const double*)nullptr, (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt,
+                           ws->st, 0);
+        if (m->n_bc > 0)
+            hipLaunchKernelGGL(k_bc, dim3(m->n_bc, ws->Bp / 64), dim3(64), 0, ws->stream, m->bc_xy_d, m->bc_field_d,
+                               m->n_bc, ws->mu, B, ws->Bp, m->nu, ws->bc);
+        hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, ws->stream, B, ws->st, ws->live, ws->counter);
+        HIPCHECK(hipGetLastError());
+        if (k > 0) {
+            HIPCHECK(hipEventRecord(ws->ev_out, ws->stream));
+            HIPCHECK(hipStreamWaitEvent(s0, ws->ev_out, 0));
+        }
+    }
+    const int K = 8;
+    long long max_rounds = 0;
+    std::ostringstream key;
+    key << "multi:" << o->precision << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":"
+        << o->armijo_c1 << ":" << o->max_backtracks << ":" << o->stall_tol;
+    for (int k = 0; k < n_models; ++k) key << ":" << (const void*)models[k] << "/" << (const void*)wss[k] << "/" << Bs[k];
+    max_rounds = 1 + (long long)std::max(1, o->max_iter) * (o->max_backtracks + 1) + 1;
+    if (w0->graph_key != key.str() || !w0->graph) {
+        if (w0->graph) {
+            (void)hipGraphExecDestroy(w0->graph);
+            w0->graph = nullptr;
+        }
+        hipGraph_t g;
+        HIPCHECK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+        int crc = 0;
+        for (int r = 0; r < K && !crc; ++r) {
+            if (hipEventRecord(w0->ev_in, s0) != hipSuccess) { crc = DDROM_EHIP; break; }
+            for (int k = 1; k < n_models && !crc; ++k)
+                if (hipStreamWaitEvent(wss[k]->stream, w0->ev_in, 0) != hipSuccess) crc = DDROM_EHIP;
+            // model 0 runs on the origin stream and may fork; the others are branches of it
+            for (int k = 0; k < n_models && !crc; ++k) {
+                const UpdArgs ua = upd_args(models[k], wss[k], Bs[k], o, 0);
+                crc = round_launch(models[k], wss[k], o->precision, Bs[k], ua, wss[k]->stream, k == 0);
+            }
+            for (int k = 1; k < n_models && !crc; ++k) {
+                if (hipEventRecord(wss[k]->ev_out, wss[k]->stream) != hipSuccess ||
+                    hipStreamWaitEvent(s0, wss[k]->ev_out, 0) != hipSuccess)
+                    crc = DDROM_EHIP;
+            }
+        }
+        hipError_t ce = hipStreamEndCapture(s0, &g);
+        if (crc) return crc;
+        if (ce != hipSuccess) {
+            set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
+            return DDROM_EHIP;
+        }
+        hipError_t ie = hipGraphInstantiate(&w0->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            w0->graph = nullptr;
+            set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+            return DDROM_EHIP;
+        }
+        w0->graph_key = key.str();
+    }
+    for (long long done = 0; done < max_rounds; done += K) {
+        HIPCHECK(hipGraphLaunch(w0->graph, s0));
+        for (int k = 0; k < n_models; ++k)
+            HIPCHECK(hipMemcpyAsync(wss[k]->counter_h, wss[k]->counter, sizeof(int), hipMemcpyDeviceToHost, s0));
+        HIPCHECK(hipStreamSynchronize(s0));
+        int live = 0;
+        for (int k = 0; k < n_models; ++k) live += *wss[k]->counter_h;
+        if (live == 0) break;
+    }
+    for (int k = 0; k < n_models; ++k) {
+        const ddrom_model* m = models[k];
+        ddrom_workspace* ws = wss[k];
+        hipLaunchKernelGGL(k_finalize, dim3(Bs[k]), dim3(64), 0, s0, Bs[k], m->n_D, m->n_C, ws->x, ws->lam, ws->st,
+                           xhat_d[k], lam_d ? lam_d[k] : nullptr, iters_d ? iters_d[k] : nullptr,
+                           status_d ? status_d[k] : nullptr, fnorm_d ? fnorm_d[k] : nullptr, (double*)nullptr,
+                           (int*)nullptr);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipEventRecord(w0->ev_out, s0));
+    HIPCHECK(hipStreamWaitEvent(caller, w0->ev_out, 0));
+    return 0;
 }
 
 int rom_solve_warm(const ddrom_model* m, ddrom_workspace* ws, const ddrom_mlp* p, const double* mu_d, int B,

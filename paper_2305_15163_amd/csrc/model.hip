@@ -12,11 +12,11 @@
 namespace ddrom {
 
 static constexpr int RING = 48;          // hidden-unit ring of the decode kernel (window bound)
-static constexpr int DEC_ROWS = 48;      // max output rows per decode work item
+static constexpr int DEC_ROWS = 48;      // default max output rows per decode work item
 static constexpr int DEC_STAGE = 15360;  // bytes of FP32 weights staged in LDS per decode work item
-static constexpr int RES_NODES = 24;     // sampled nodes per residual work item
+static constexpr int RES_NODES = 24;     // default sampled nodes per residual work item
 static constexpr int CON_ROWS = 8;       // constraint rows per constraint work item
-static constexpr int CON_OROWS = 256;    // interface rows per constraint work item
+static constexpr int CON_OROWS = 256;    // default interface rows per constraint work item
 
 template <typename T>
 static int upload(T** dst, const std::vector<T>& src) {
@@ -122,6 +122,13 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     m->hx = 2.0 / (nx + 1); m->hy = d->ly / (ny + 1);
     m->N_x = 2 * n_nodes;
     m->n_C = d->n_C;
+    m->tile_dec_rows = d->tile[0] > 0 ? d->tile[0] : DEC_ROWS;
+    m->tile_res_nodes = d->tile[1] > 0 ? d->tile[1] : RES_NODES;
+    m->tile_con_orows = d->tile[2] > 0 ? d->tile[2] : CON_OROWS;
+    if (m->tile_dec_rows > 64 || m->tile_res_nodes < 4 || m->tile_con_orows < 4) {
+        set_error("work-item shapes: decoder rows 1..64, residual nodes >= 4, constraint rows >= 4");
+        return DDROM_EINVAL;
+    }
 
     // ---- DD maps: owned, own-interface, halo, interior and interface nodes ----
     std::vector<int> owner(n_nodes);
@@ -210,8 +217,8 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         m->mmax = std::max(m->mmax, m->n_ga[sd]);
     }
     m->NNmax = m->nmax;
-    if (m->n_C > 63) {
-        set_error("n_C above 63 is not supported by the KKT kernel");
+    if (m->n_C > 256) {
+        set_error("n_C above 256 is not supported by the KKT kernel");
         return DDROM_EINVAL;
     }
 
@@ -415,7 +422,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             // a new work item.
             int lo = row_lo(r), hi = row_hi(r), e = r + 1;
             int vlo = lo, vhi = hi;
-            while (e < sg.rows && e - r < DEC_ROWS) {
+            while (e < sg.rows && e - r < m->tile_dec_rows) {
                 const int rl = row_lo(e), rh = row_hi(e);
                 int nvlo = vlo, nvhi = vhi;
                 if (rl >= nvhi || rh <= nvlo) nvlo = nvhi = rl;
@@ -454,7 +461,8 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         rs.gather = (long long)gather.size();
         gather.insert(gather.end(), gath_sd[sd].begin(), gath_sd[sd].end());
         rs.slot0 = slot;
-        for (int p = 0; p < m->nb[sd]; p += RES_NODES) m->rchunks_h.push_back(ResChunk{sd, p, std::min(m->nb[sd], p + RES_NODES), slot++});
+        for (int p = 0; p < m->nb[sd]; p += m->tile_res_nodes)
+            m->rchunks_h.push_back(ResChunk{sd, p, std::min(m->nb[sd], p + m->tile_res_nodes), slot++});
         rs.slot1 = slot;
         int NN = rs.n_om + rs.n_ga;
         m->estride = std::max(m->estride, NN * (NN + 1) / 2 + NN + 1);
@@ -466,6 +474,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     std::vector<double> CAflat;
     m->CA_off.resize(n_sub);
     m->ca_ld = (m->n_C + 7) / 8 * 8;
+    m->cchunk0.assign(n_sub + 1, 0);
     int cpart = 0;
     for (int sd = 0; sd < n_sub; ++sd) {
         const int Ng = m->N_ga[sd];
@@ -478,12 +487,15 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             for (int o = 0; o < Ng; ++o) t[(size_t)o * m->ca_ld + j] = CA[sd][(size_t)j * Ng + o];
         CAflat.insert(CAflat.end(), t.begin(), t.end());
         m->rsegs_h[sd].cpart0 = cpart;
+        m->cchunk0[sd] = (int)cch.size();
+        const int orows = m->tile_con_orows;
         if (Ng > 0 && m->n_C > 0)
-            for (int o = 0; o < Ng; o += CON_OROWS, ++cpart)
+            for (int o = 0; o < Ng; o += orows, ++cpart)
                 for (int j = 0; j < m->n_C; j += CON_ROWS)
-                    cch.push_back(ConChunk{sd, j, std::min(m->n_C, j + CON_ROWS), o, std::min(Ng, o + CON_OROWS), cpart, {0, 0}});
+                    cch.push_back(ConChunk{sd, j, std::min(m->n_C, j + CON_ROWS), o, std::min(Ng, o + orows), cpart, {0, 0}});
         m->rsegs_h[sd].cpart1 = cpart;
     }
+    m->cchunk0[n_sub] = (int)cch.size();
     m->n_cchunks = (int)cch.size();
     m->n_cparts = cpart;
 

@@ -30,7 +30,8 @@ class ModelDesc(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nu", C.c_double), ("ly", C.c_double),
                 ("nsx", C.c_int), ("nsy", C.c_int), ("activation", C.c_int), ("n_C", C.c_int), ("N_A", C.c_int),
                 ("C", C.POINTER(C.c_double)), ("dec_om", C.POINTER(DecoderDesc)), ("dec_ga", C.POINTER(DecoderDesc)),
-                ("hr_count", C.POINTER(C.c_int)), ("hr_nodes", C.POINTER(C.POINTER(C.c_int)))]
+                ("hr_count", C.POINTER(C.c_int)), ("hr_nodes", C.POINTER(C.POINTER(C.c_int))),
+                ("tile", C.c_int * 3)]
 
 
 class MlpDesc(C.Structure):
@@ -81,6 +82,9 @@ def lib():
         L.mlp_train_step.argtypes = [vp, vp, vp, vp, ip, C.c_float, ip, vp, vp, vp]
         L.rom_solve_warm.argtypes = [vp, vp, vp, vp, ip, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp, vp]
         L.rom_decode_states.argtypes = [vp, vp, vp, ip, ip, vp, vp]
+        L.ddrom_autotune.argtypes = [C.POINTER(ModelDesc), vp, ip, C.POINTER(Opts), ip, C.POINTER(C.c_int),
+                                     C.POINTER(C.c_float), ip, C.POINTER(C.c_int)]
+        L.rom_solve_multi.argtypes = [ip, vp, vp, vp, vp, C.POINTER(Opts), vp, vp, vp, vp, vp, vp]
         L.ddrom_ae_trainer_create.argtypes = [ip, ip, ip, ip, ip, ip, ip, C.POINTER(C.c_float), C.POINTER(vp)]
         L.ddrom_ae_trainer_destroy.argtypes = [vp]
         L.ddrom_ae_trainer_size.argtypes = [vp, ip]
@@ -118,38 +122,48 @@ def _dev(x, dtype=torch.float64):
     return t.to("cuda").contiguous()
 
 
-class Model:
-    """Device model built from a model pack (dict of numpy arrays, see oracle.pack's format)."""
+def model_desc(pack: dict, tile=(0, 0, 0)):
+    """ddrom_model_desc of a model pack; the second value holds the host arrays it points to."""
+    n = int(pack["n_sub"])
+    keep = []
 
-    def __init__(self, pack: dict):
+    def dptr(a):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    decs = {}
+    for part in ("om", "ga"):
+        arr = (DecoderDesc * n)()
+        for i in range(n):
+            W1 = np.asarray(pack[f"{part}{i}_W1"])
+            b, s = (int(v) for v in pack[f"{part}{i}_bs"])
+            N = int(np.asarray(pack[f"{part}{i}_xref"]).shape[0])
+            arr[i] = DecoderDesc(N, int(W1.shape[1]) if W1.ndim == 2 else 0, int(W1.shape[0]), b, s,
+                                 dptr(W1), dptr(pack[f"{part}{i}_b1"]), dptr(pack[f"{part}{i}_W2"]),
+                                 dptr(pack[f"{part}{i}_xref"]))
+        decs[part] = arr
+    keep.append(decs)
+    hr = [np.ascontiguousarray(np.asarray(pack[f"hr{i}"], dtype=np.int32)) for i in range(n)]
+    keep.extend(hr)
+    hr_cnt = (C.c_int * n)(*[len(h) for h in hr])
+    hr_ptrs = (C.POINTER(C.c_int) * n)(*[h.ctypes.data_as(C.POINTER(C.c_int)) for h in hr])
+    keep.extend([hr_cnt, hr_ptrs])
+    Cm = np.asarray(pack["C"], dtype=np.float64)
+    desc = ModelDesc(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"]), int(pack["nsx"]),
+                     int(pack["nsy"]), int(pack["act"]), int(Cm.shape[0]), int(Cm.shape[1]), dptr(Cm),
+                     decs["om"], decs["ga"], hr_cnt, hr_ptrs, (C.c_int * 3)(*[int(v) for v in tile]))
+    return desc, keep
+
+
+class Model:
+    """Device model built from a model pack (dict of numpy arrays, see oracle.pack's format).
+    tile = (decoder rows, residual nodes, constraint rows) per work item, 0 for the default."""
+
+    def __init__(self, pack: dict, tile=(0, 0, 0)):
         L = lib()
         n = int(pack["n_sub"])
-        keep = []
-
-        def dptr(a):
-            a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
-            keep.append(a)
-            return a.ctypes.data_as(C.POINTER(C.c_double))
-
-        decs = {}
-        for part in ("om", "ga"):
-            arr = (DecoderDesc * n)()
-            for i in range(n):
-                W1 = np.asarray(pack[f"{part}{i}_W1"])
-                b, s = (int(v) for v in pack[f"{part}{i}_bs"])
-                N = int(np.asarray(pack[f"{part}{i}_xref"]).shape[0])
-                arr[i] = DecoderDesc(N, int(W1.shape[1]) if W1.ndim == 2 else 0, int(W1.shape[0]), b, s,
-                                     dptr(W1), dptr(pack[f"{part}{i}_b1"]), dptr(pack[f"{part}{i}_W2"]),
-                                     dptr(pack[f"{part}{i}_xref"]))
-            decs[part] = arr
-        hr = [np.ascontiguousarray(np.asarray(pack[f"hr{i}"], dtype=np.int32)) for i in range(n)]
-        keep.extend(hr)
-        hr_cnt = (C.c_int * n)(*[len(h) for h in hr])
-        hr_ptrs = (C.POINTER(C.c_int) * n)(*[h.ctypes.data_as(C.POINTER(C.c_int)) for h in hr])
-        Cm = np.asarray(pack["C"], dtype=np.float64)
-        desc = ModelDesc(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"]), int(pack["nsx"]),
-                         int(pack["nsy"]), int(pack["act"]), int(Cm.shape[0]), int(Cm.shape[1]), dptr(Cm),
-                         decs["om"], decs["ga"], hr_cnt, hr_ptrs)
+        desc, keep = model_desc(pack, tile)
         h = C.c_void_p()
         _check(L.ddrom_model_create(C.byref(desc), C.byref(h)), "ddrom_model_create")
         self.h = h
@@ -164,6 +178,7 @@ class Model:
         self.N_om = [self.size(12, i) for i in range(n)]
         self.N_ga = [self.size(13, i) for i in range(n)]
         self.xoff = [self.size(17, i) for i in range(n)]
+        self.tile = (self.size(7), self.size(8), self.size(9))
 
     def size(self, q, sd=-1):
         return int(lib().ddrom_model_size(self.h, q, sd))
@@ -508,3 +523,37 @@ class AETrainer:
         if getattr(self, "h", None) and _lib is not None:
             _lib.ddrom_ae_trainer_destroy(self.h)
             self.h = None
+
+
+def rom_solve_multi(models, wss, mus, o: Opts):
+    """Uneven batch over several models in one graph.  Returns one dict(xhat, lam, iters,
+    status, fnorm) of device tensors per model."""
+    k = len(models)
+    mus = [_dev(m) for m in mus]
+    f = dict(dtype=torch.float64, device="cuda")
+    i32 = dict(dtype=torch.int32, device="cuda")
+    outs = [dict(xhat=torch.empty((m_.shape[0], md.n_D), **f), lam=torch.empty((m_.shape[0], max(1, md.n_C)), **f),
+                 iters=torch.empty((m_.shape[0],), **i32), status=torch.empty((m_.shape[0],), **i32),
+                 fnorm=torch.empty((m_.shape[0],), **f)) for md, m_ in zip(models, mus)]
+    vpa = C.c_void_p * k
+    arr = lambda key: vpa(*[C.c_void_p(o_[key].data_ptr()) for o_ in outs])
+    Bs = (C.c_int * k)(*[int(m_.shape[0]) for m_ in mus])
+    _check(lib().rom_solve_multi(k, vpa(*[md.h for md in models]), vpa(*[w.h for w in wss]),
+                                 vpa(*[C.c_void_p(m_.data_ptr()) for m_ in mus]), Bs, C.byref(o), arr("xhat"),
+                                 arr("lam"), arr("iters"), arr("status"), arr("fnorm"), _stream()), "rom_solve_multi")
+    return outs
+
+
+def autotune_tiles(pack: dict, mu, o: Opts, reps: int = 5):
+    """Work-item shape search (ddrom_autotune) for a model pack and a batch of parameters.
+    Returns (tile, rows) with rows = [(dec rows, res nodes, con rows, ms), ...] as tried."""
+    mu = _dev(mu)
+    desc, keep = model_desc(pack)
+    tile = (C.c_int * 3)()
+    table = (C.c_float * (4 * 64))()
+    n = C.c_int()
+    _check(lib().ddrom_autotune(C.byref(desc), _ptr(mu), int(mu.shape[0]), C.byref(o), int(reps), tile, table, 64,
+                                C.byref(n)), "ddrom_autotune")
+    rows = [(int(table[4 * k]), int(table[4 * k + 1]), int(table[4 * k + 2]), float(table[4 * k + 3]))
+            for k in range(min(64, n.value))]
+    return tuple(int(v) for v in tile), rows

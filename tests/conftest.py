@@ -31,3 +31,20 @@ def cfg0_pack():
     from oracle.build_model import build
     pack, *_ = build("cfg0", workers=1, verbose=False)
     return pack
+
+
+@pytest.fixture(scope="session")
+def tinymix_pack():
+    """16x12 grid, 2x2 subdomains whose latent sizes (from {4, 6, 8, 12}) and hyper-reduction
+    fractions (0.3 to 0.6) differ per subdomain."""
+    from oracle.build_model import build
+    pack, *_ = build("tinymix", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
+def tinybig_pack():
+    """48x48 grid, 8x8 subdomains, 96 constraints: the KKT system exceeds one wave's rows."""
+    from oracle.build_model import build
+    pack, *_ = build("tinybig", workers=1, verbose=False)
+    return pack

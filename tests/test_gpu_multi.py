@@ -1,0 +1,186 @@
+"""Uneven batches on the GPU, through the C ABI: a KKT system larger than one wave's rows
+(96 constraints, 64 subdomains) against the FP64 oracle, work-item shapes that change the
+schedule only, and the multi-model solve against separate single-model solves."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import seeded_inputs as si
+from oracle.pack import load_pack
+from oracle.rom import SQPOptions, evaluate, sqp_solve, sqp_step
+
+
+@pytest.fixture(scope="module")
+def dr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_15163_amd as d
+    d.lib()
+    return d
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b))))
+
+
+@pytest.fixture(scope="module")
+def big(dr, tinybig_pack):
+    print("[case tinybig]", flush=True)
+    return dr.Model(tinybig_pack), load_pack(tinybig_pack)
+
+
+def test_big_kkt_gn_blocks(dr, big):
+    gm, om = big
+    assert gm.n_C > 64 and gm.n_sub == 64
+    B = 3
+    mus = si.heldout_mu(B, 41)
+    xh = si.normal((B, gm.n_D), seed=42, scale=0.5)
+    ws = dr.Workspace(gm, B)
+    H, g, EG, c, rr = (t.cpu().numpy() for t in dr.gn_blocks(gm, ws, mus, xh, precision=dr.PREC_FP64))
+    for b in range(B):
+        ev = evaluate(om, mus[b], xh[b])
+        for i, (o, (a, m)) in enumerate(zip(om.offsets(), om.sizes())):
+            assert relerr(H[b, i, :a + m, :a + m], ev.H[i]) <= 1e-11
+            assert relerr(g[b, o:o + a + m], ev.g[i]) <= 1e-10
+            assert relerr(EG[b, i, :, :m], ev.EG[i]) <= 1e-12
+        assert relerr(c[b], ev.c) <= 1e-12
+
+
+def test_big_kkt_step(dr, big):
+    """One SQP step: the Schur complement of 96 constraints is factored by a whole workgroup
+    from global scratch."""
+    gm, om = big
+    B = 4
+    mus = si.heldout_mu(B, 43)
+    xh = si.normal((B, gm.n_D), seed=44, scale=0.3)
+    lam = si.normal((B, gm.n_C), seed=45, scale=0.01)
+    ws = dr.Workspace(gm, B)
+    o = dr.opts(precision=dr.PREC_FP64, max_backtracks=20)
+    x1, l1, fn, st = (t.cpu().numpy() for t in dr.sqp_step(gm, ws, mus, xh, lam, o))
+    for b in range(B):
+        xr, lr, _, fr, sr, _, _ = sqp_step(om, mus[b], xh[b], lam[b], SQPOptions(max_backtracks=20))
+        assert int(st[b]) == (1 if sr == -1 else sr)
+        assert relerr(x1[b], xr) <= 1e-10
+        assert relerr(l1[b], lr) <= 1e-8
+        assert abs(fn[b] - fr) <= 1e-10 * max(1.0, fr)
+
+
+def test_big_kkt_short_solve(dr, big):
+    """Two iterations from the zero start (the Gauss-Newton blocks of this briefly trained
+    model stay well conditioned over them; later ones lose definiteness for some parameters),
+    batch of 5 with 64 subdomains each."""
+    gm, om = big
+    B, it = 5, 2
+    mus = si.heldout_mu(B, 17)
+    ws = dr.Workspace(gm, B)
+    out = dr.rom_solve_batch(gm, ws, mus, dr.opts(max_iter=it, tol_rel=1e-12, precision=dr.PREC_FP64))
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    for b in range(B):
+        ref = sqp_solve(om, mus[b], opts=SQPOptions(max_iter=it, tol_abs=0.0, tol_rel=1e-12))
+        print("tinybig", b, "status", out["status"][b], ref.status, "iters", out["iters"][b], ref.iters, flush=True)
+        assert int(out["status"][b]) == ref.status
+        assert int(out["iters"][b]) == ref.iters
+        assert relerr(out["xhat"][b], ref.xhat) <= 1e-9
+        assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-7
+
+
+@pytest.mark.parametrize("tile", [(8, 4, 4), (64, 7, 16), (13, 40, 300)])
+def test_tiles_change_schedule_only(dr, tile, tinymix_pack, cfg0_pack):
+    """Other work-item shapes: decoded rows are bitwise the same, residual and constraint
+    partial sums are grouped differently (FP64 solves agree to 1e-10)."""
+    for name, pack in (("tinymix", tinymix_pack), ("cfg0", cfg0_pack)):
+        print(f"[tiles {tile} {name}]", flush=True)
+        ref_m, m = dr.Model(pack), dr.Model(pack, tile=tile)
+        assert m.tile == tile
+        B = 9
+        mus = si.heldout_mu(B, 51)
+        xh = si.normal((B, m.n_D), seed=52, scale=0.5)
+        ws_r, ws = dr.Workspace(ref_m, B), dr.Workspace(m, B)
+        for i in range(m.n_sub):
+            for part in (0, 1):
+                a = dr.ae_decode_hr(ref_m, ws_r, i, part, xh, precision=dr.PREC_FP64).cpu().numpy()
+                b = dr.ae_decode_hr(m, ws, i, part, xh, precision=dr.PREC_FP64).cpu().numpy()
+                assert np.array_equal(a, b)
+        ga = [t.cpu().numpy() for t in dr.gn_blocks(ref_m, ws_r, mus, xh, precision=dr.PREC_FP64)]
+        gb = [t.cpu().numpy() for t in dr.gn_blocks(m, ws, mus, xh, precision=dr.PREC_FP64)]
+        for x, y in zip(gb, ga):
+            assert relerr(x, y) <= 1e-12
+        o = dr.opts(max_iter=60, tol_rel=1e-10, precision=dr.PREC_FP64)
+        ra = dr.rom_solve_batch(ref_m, ws_r, mus, o)
+        rb = dr.rom_solve_batch(m, ws, mus, o)
+        assert np.array_equal(ra["status"].cpu().numpy(), rb["status"].cpu().numpy())
+        assert relerr(rb["xhat"].cpu().numpy(), ra["xhat"].cpu().numpy()) <= 1e-10
+
+
+def test_tile_limits_rejected(dr, tiny_pack):
+    for bad in ((65, 0, 0), (0, 3, 0), (0, 0, 2)):
+        with pytest.raises(RuntimeError):
+            dr.Model(tiny_pack, tile=bad)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_equals_separate_solves(dr, precision, tiny_pack, tinymix_pack, tinybig_pack, cfg0_pack):
+    """Four models of different subdomain counts, latent sizes and constraint counts, uneven
+    batch sizes, one graph: every output equals the model's own rom_solve_batch bitwise
+    (same kernels, same per-solve arithmetic).  Run twice (cached graph), then with other
+    batches on the same workspaces."""
+    packs = [tiny_pack, tinymix_pack, tinybig_pack, cfg0_pack]
+    models = [dr.Model(p) for p in packs]
+    Bs = [5, 70, 3, 33]
+    wss = [dr.Workspace(m, B) for m, B in zip(models, Bs)]
+    # FP32 decoders stop at their noise floor (relative ~1e-6): a tolerance above it
+    o = dr.opts(max_iter=40, tol_rel=1e-9 if precision == 0 else 1e-5, precision=precision)
+
+    def check(Bsz, seed):
+        mus = [si.heldout_mu(B, seed + k) for k, B in enumerate(Bsz)]
+        print(f"[multi precision={precision} B={Bsz}]", flush=True)
+        outs = dr.rom_solve_multi(models, wss, mus, o)
+        for m, ws, mu, got in zip(models, wss, mus, outs):
+            ref = dr.rom_solve_batch(m, ws, mu, o)
+            for key in ("xhat", "lam", "iters", "status", "fnorm"):
+                assert torch.equal(got[key], ref[key]), key
+        return outs
+
+    a = check(Bs, 60)
+    b = check(Bs, 60)
+    for x, y in zip(a, b):
+        assert torch.equal(x["xhat"], y["xhat"])
+    check([2, 1, 3, 17], 70)
+    st = np.concatenate([x["status"].cpu().numpy() for x in a])
+    assert np.mean(st == 0) > 0.5                     # the converging models do converge
+
+
+def test_multi_rejects_shared_workspace(dr, tiny_pack):
+    m = dr.Model(tiny_pack)
+    ws = dr.Workspace(m, 4)
+    with pytest.raises(RuntimeError):
+        dr.rom_solve_multi([m, m], [ws, ws], [si.heldout_mu(2, 1), si.heldout_mu(2, 2)], dr.opts())
+
+
+def test_autotune_picks_a_candidate(dr, tinymix_pack, tmp_path):
+    """The shape search returns one of the shapes it timed, its fastest (by construction of
+    the coordinate descent, no slower than the default it started from), and the persisted
+    table serves the second request without measuring."""
+    from paper_2305_15163_amd import autotune
+    mus = si.heldout_mu(24, 81)
+    o = dr.opts(max_iter=30, tol_rel=1e-6, precision=dr.PREC_FP32_DECODER)
+    tile, rows = dr.autotune_tiles(tinymix_pack, mus, o, reps=2)
+    print(f"[autotune tinymix] {tile} from {len(rows)} shapes", flush=True)
+    assert len(rows) >= 10 and all(r[3] > 0 for r in rows)
+    assert tile in [r[:3] for r in rows]
+    default = rows[0]
+    assert min(r[3] for r in rows if r[:3] == tile) <= default[3]
+    path = str(tmp_path / "tiles.json")
+    t1 = autotune.tiles_for(tinymix_pack, mus, o, path=path, reps=2)
+    table = autotune.load(path)
+    assert len(table) == 1
+    key = autotune.bucket(tinymix_pack, len(mus), o.precision)
+    table[key]["tile"] = [8, 4, 4]                 # a stored entry is used as it is
+    autotune.save(path, table)
+    assert autotune.tiles_for(tinymix_pack, mus, o, path=path) == (8, 4, 4)
+    m = dr.Model(tinymix_pack, tile=t1)
+    assert m.tile == t1

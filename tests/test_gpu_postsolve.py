@@ -22,9 +22,9 @@ def dr():
     return d
 
 
-@pytest.fixture(scope="module", params=["tiny", "cfg0"])
-def case(request, dr, tiny_pack, cfg0_pack):
-    pack = tiny_pack if request.param == "tiny" else cfg0_pack
+@pytest.fixture(scope="module", params=["tiny", "cfg0", "tinymix"])
+def case(request, dr):
+    pack = request.getfixturevalue(request.param + "_pack")
     print(f"[case {request.param}]", flush=True)
     return dr.Model(pack), load_pack(pack)
 

@@ -20,7 +20,9 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("dd_fom_residual", "ae_decode_hr", "ae_jacobian_hr", "sqp_step", "rom_solve_batch",
-              "ddrom_model_create", "ddrom_workspace_create", "ddrom_last_error"):
+              "ddrom_model_create", "ddrom_workspace_create", "ddrom_last_error", "rom_solve_multi", "ddrom_autotune",
+              "rom_solve_warm", "mlp_proposal", "mlp_train_step", "ae_train_step", "rom_decode_states",
+              "rom_relative_error"):
         assert n in names
 
 
