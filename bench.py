@@ -66,6 +66,77 @@ def decoder_work(model, B):
     return flops * B, wbytes + B * (obytes + 8.0 * model.n_D)
 
 
+UNEVEN = dict(models=("cfg2a", "cfg2b", "cfg2c"), batch=1024, seed=2, precision=1, tol_rel=1e-6, stall_tol=1e-5,
+              max_iter=60,
+              workload="uneven batch: 1024 held-out (a,lambda) split evenly (seeded) over three Burgers models "
+                       "with 60x60-node subdomains: 120x120 2x2, 240x240 4x4, 480x480 8x8; per-subdomain latent "
+                       "sizes from {4,6,8,12} and HR fractions from [5%, 25%]; FP32 decoder + FP64 KKT; zero start")
+
+
+def uneven_leg(a, torch, dr):
+    """1024 solves over three models in one multi-model graph (rom_solve_multi), each model with
+    the work-item shape of the persisted table (measured by the shape search when missing);
+    timed like the headline, and beside it the same solves as three rom_solve_batch calls."""
+    from paper_2305_15163_amd import autotune
+    import seeded_inputs as si
+    cfg = UNEVEN
+    paths = [os.path.join(ROOT, "models", f"{c}.npz") for c in cfg["models"]]
+    missing = [p for p in paths if not os.path.exists(p)]
+    if missing:
+        print(f"[bench] uneven batch skipped: missing {missing}", file=sys.stderr, flush=True)
+        return None
+    B = cfg["batch"]
+    mu_all = si.heldout_mu(B, cfg["seed"])
+    which = si.model_assignment(B, len(paths), cfg["seed"])
+    o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"], stall_tol=cfg["stall_tol"])
+    table = os.path.join(ROOT, "paper_2305_15163_amd", "tiles.json")
+    models, wss, mus, tiles, info = [], [], [], [], []
+    for k, p in enumerate(paths):
+        pack = dict(np.load(p, allow_pickle=False))
+        mu_k = np.ascontiguousarray(mu_all[which == k])
+        tile = autotune.tiles_for(pack, mu_k, o, path=table, verbose=True)
+        m = dr.Model(pack, tile=tile)
+        models.append(m)
+        wss.append(dr.Workspace(m, len(mu_k)))
+        mus.append(torch.as_tensor(mu_k, device="cuda"))
+        tiles.append(list(m.tile))
+        info.append({"model": cfg["models"][k], "solves": int(len(mu_k)), "subdomains": m.n_sub, "n_D": m.n_D,
+                     "n_C": m.n_C, "tile": list(m.tile)})
+        del pack
+        print(f"[bench] uneven: model {cfg['models'][k]} ready ({len(mu_k)} solves, tile {m.tile})",
+              file=sys.stderr, flush=True)
+
+    def run_multi():
+        return dr.rom_solve_multi(models, wss, mus, o)
+
+    def run_separate():
+        return [dr.rom_solve_batch(m, w, mu, o) for m, w, mu in zip(models, wss, mus)]
+
+    def timed(fn, tag):
+        for w in range(a.warmup):
+            fn()
+            torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            outs = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"[bench] uneven {tag}: timed {a.steps} steps in {dt:.3f}s", file=sys.stderr, flush=True)
+        return dt, outs
+
+    dt_m, outs = timed(run_multi, "multi-model graph")
+    dt_s, _ = timed(run_separate, "three separate batches")
+    for k, r in enumerate(outs):
+        st = r["status"].cpu().numpy()
+        it = r["iters"].cpu().numpy()
+        info[k]["iters_mean"] = float(it.mean())
+        info[k]["status_counts"] = {dr.STATUS[s]: int((st == s).sum()) for s in np.unique(st)}
+    return {"workload": cfg["workload"], "solves_per_s": B * a.steps / dt_m, "ms_per_step": 1e3 * dt_m / a.steps,
+            "separate_batches_solves_per_s": B * a.steps / dt_s, "models": info,
+            "tiles_from": "work-item shape search (ddrom_autotune), table paper_2305_15163_amd/tiles.json"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +145,8 @@ def main():
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--plain", type=int, default=8, help="parameters for the plain per-solve GPU SQP leg")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the three-model uneven batch leg")
+    ap.add_argument("--uneven-only", action="store_true", help="run only the three-model uneven batch leg")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -83,6 +156,11 @@ def main():
     import torch
     import paper_2305_15163_amd as dr
     import seeded_inputs as si
+
+    if a.uneven_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"uneven_batch": uneven_leg(a, torch, dr)}), flush=True)
+        return
 
     cfg = CONFIGS[a.config]
     path = os.path.join(ROOT, "models", f"{a.config}.npz")
@@ -199,6 +277,9 @@ def main():
         "plain_sqp": plain,
         "speedup_vs_plain": (value / plain["solves_per_s"]) if plain else None,
     }
+
+    if not a.no_uneven:
+        line["uneven_batch"] = uneven_leg(a, torch, dr)
 
     if not a.no_cpu:
         from threadpoolctl import threadpool_limits

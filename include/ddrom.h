@@ -228,10 +228,11 @@ int mlp_train_step(ddrom_mlp_trainer* t, const double* mu_d, const float* target
 
 /* Uneven batch: n_models models, each with its own workspace (distinct), parameters mu_d[k]
  * [Bs[k]][2] and outputs (host arrays of device pointers; lam_d, iters_d, status_d, fnorm_d
- * and their entries may be NULL).  Zero start, options as in rom_solve_batch.  One captured
- * graph holds the solver rounds of all models as concurrent branches (each model on its own
- * streams), replayed until no solve of any model is running; results equal separate
- * rom_solve_batch calls.  The graph is kept in wss[0]. */
+ * and their entries may be NULL).  Zero start, options as in rom_solve_batch.  Each model
+ * replays its workspace's captured graph of solver rounds (the one rom_solve_batch captures
+ * for the same batch size and options) on its own streams, concurrently with the other models;
+ * only models with running solves are relaunched.  Results equal separate rom_solve_batch
+ * calls bitwise. */
 int rom_solve_multi(int n_models, const ddrom_model* const* models, ddrom_workspace* const* wss,
                     const double* const* mu_d, const int* Bs, const ddrom_opts* o, double* const* xhat_d,
                     double* const* lam_d, int* const* iters_d, int* const* status_d, double* const* fnorm_d,

@@ -110,7 +110,7 @@ struct ddrom_model {
     // decoders (values only, rows of the DD state buffer)
     std::vector<ddrom::DecSeg> segs_h;
     ddrom::DecSeg* segs_d = nullptr;
-    std::vector<ddrom::DecChunk> chunks_h;       // sorted by segment
+    std::vector<ddrom::DecChunk> chunks_h;       // grouped by family and latent size, each segment's contiguous
     ddrom::DecChunk* chunks_d = nullptr;
     std::vector<int> seg_chunk0, seg_chunk1;     // chunk range per segment
     long long dec_rows = 0;                      // Bp-rows of the decoder output buffer
@@ -142,7 +142,16 @@ struct ddrom_model {
     int* fom_sd_of_row_d = nullptr;              // owner subdomain of each flattened own-node slot
     int* state_dof_d = nullptr;                  // [n_state] global DoF of each row of the DD state
     int tile_dec_rows = 0, tile_res_nodes = 0, tile_con_orows = 0;   // work-item shapes in use
-    std::vector<int> cchunk0;                    // [n_sub + 1] first constraint work item of each subdomain
+
+    // Launch plans: the work items of each kernel family are stored grouped by latent class, so
+    // that one launch covers every subdomain of a class.  Decoder families: 0 interior subnets,
+    // 1 interface decoders, 2 full interior, 3 full interface.
+    struct DecPlan { int c0, c1, n; long long stage_f32, stage_f64; };
+    struct ResPlan { int c0, c1, n_om, n_ga; };
+    struct ConPlan { int c0, c1, n_ga; };
+    std::vector<DecPlan> dec_plan[4];
+    std::vector<ResPlan> res_plan;
+    std::vector<ConPlan> con_plan;
 };
 
 struct SolveState {

@@ -746,12 +746,17 @@ __device__ bool block_lu_solve(double* M, int n, double* x, double* redv, int* r
                 M[(size_t)p * ld + j] = t;
             }
         __syncthreads();
+        // rank-1 update of the trailing block [k+1, n) x [k+1, n], one entry per thread (column
+        // k is read, never written, in this step)
         const double pv = M[(size_t)k * ld + k];
-        if (pv != 0.0)
-            for (int i = k + 1 + tid; i < n; i += nth) {
-                const double f = M[(size_t)i * ld + k] / pv;
-                for (int j = k + 1; j <= n; ++j) M[(size_t)i * ld + j] -= f * M[(size_t)k * ld + j];
+        const int w = n - k;            // columns k+1 .. n (right-hand side included)
+        if (pv != 0.0) {
+            const double rp = 1.0 / pv;
+            for (int e = tid; e < (n - k - 1) * w; e += nth) {
+                const int i = k + 1 + e / w, j = k + 1 + e % w;
+                M[(size_t)i * ld + j] -= (M[(size_t)i * ld + k] * rp) * M[(size_t)k * ld + j];
             }
+        }
         __syncthreads();
     }
     for (int i = n - 1; i >= 0; --i) {
@@ -762,6 +767,44 @@ __device__ bool block_lu_solve(double* M, int n, double* x, double* redv, int* r
         __syncthreads();
     }
     return ok;
+}
+
+// S[i][j] = sum over subdomains sd and l < mg of A[sd][i][l] Bm[sd][j][l] for i, j < nC, written
+// to S with row stride ld; A and Bm are [ns][nC][mg] with subdomain stride `sds`.  Each thread
+// accumulates a 4 x 4 block in registers (8 loads per 16 FMAs), subdomains in ascending order,
+// so every entry is the same fixed-order sum whatever the thread count.
+__device__ void gram_sum(const double* A, const double* Bm, size_t sds, int ns, int nC, int mg, double* S, int ld,
+                         int tid, int nth) {
+    const int nT = (nC + 3) >> 2;
+    for (int t = tid; t < nT * nT; t += nth) {
+        const int i0 = (t / nT) * 4, j0 = (t % nT) * 4;
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int sd = 0; sd < ns; ++sd) {
+            const double* As = A + sd * sds;
+            const double* Bs = Bm + sd * sds;
+            for (int l = 0; l < mg; ++l) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    av[a] = i0 + a < nC ? As[(i0 + a) * mg + l] : 0.0;
+                    bv[a] = j0 + a < nC ? Bs[(j0 + a) * mg + l] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (i0 + a < nC && j0 + b < nC) S[(i0 + a) * ld + j0 + b] = acc[a][b];
+    }
 }
 
 // Solve [M | r] with every thread of the workgroup calling: one wave when n <= 64, else the
@@ -841,15 +884,16 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     //      equations (sum_i Ehat_i Ehat_i^T) lambda = -sum_i Ehat_i g_i^Gamma ----
     const bool ls_start = S.phase == PH_ZERO || (S.phase == PH_INIT && !(S.flags & SF_LAMFIX));
     if (ls_start && !a.lam_given && nC > 0) {
-        for (int e = tid; e < nC * ld; e += nth) {
-            const int i = e / ld, jj = e % ld;
+        // (entries k >= n_i^Gamma of each Ehat_i row are zero)
+        gram_sum(Es, Es, (size_t)nC * mg, ns, nC, mg, Sm, ld, tid, nth);
+        for (int i = tid; i < nC; i += nth) {
             double s = 0.0;
             for (int sd = 0; sd < ns; ++sd) {
                 const int m = a.n_ga[sd], no = a.n_om[sd];
                 const double* E = Es + (size_t)sd * nC * mg;
-                for (int k = 0; k < m; ++k) s += E[i * mg + k] * (jj < nC ? E[jj * mg + k] : -gv(sd, no + k));
+                for (int k = 0; k < m; ++k) s -= E[i * mg + k] * gv(sd, no + k);
             }
-            Sm[e] = s;
+            Sm[i * ld + nC] = s;
         }
         __syncthreads();
         kkt_lu(Sm, nC, lam_s, red, lu_idx, lu_ok, tid, nth);
@@ -1057,20 +1101,11 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     double* stp = a.step + (size_t)b * (nD + nC);
     if (nC > 0) {
         // [S | c - q] with S = sum_i P_i Ehat_i^T, summed over subdomains in a fixed order
-        for (int e = tid; e < nC * ld; e += nth) {
-            const int i = e / ld, jj = e % ld;
+        gram_sum(Ps, Es, (size_t)nC * mg, ns, nC, mg, Sm, ld, tid, nth);
+        for (int i = tid; i < nC; i += nth) {
             double s = 0.0;
-            if (jj < nC) {
-                for (int sd = 0; sd < ns; ++sd) {
-                    const double* P = Ps + ((size_t)sd * nC + i) * mg;
-                    const double* E = Es + ((size_t)sd * nC + jj) * mg;
-                    for (int l = 0; l < mg; ++l) s += P[l] * E[l];
-                }
-            } else {
-                for (int sd = 0; sd < ns; ++sd) s += qs[(size_t)sd * nC + i];
-                s = c_s[i] - s;
-            }
-            Sm[e] = s;
+            for (int sd = 0; sd < ns; ++sd) s += qs[(size_t)sd * nC + i];
+            Sm[i * ld + nC] = c_s[i] - s;
         }
         __syncthreads();
         if (!kkt_lu(Sm, nC, sl_s, red, lu_idx, lu_ok, tid, nth) && tid == 0) flag_bad = 1;
@@ -1386,14 +1421,10 @@ __global__ void k_err_final(const double* __restrict__ part, int n_sub, int B, i
 namespace {
 
 template <int TAG, int VO = 0>
-static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const double* xhat, int xstride,
-                         int xoff_override, const int* live, const int* n_live, int B, void* out, int Bp,
-                         hipStream_t s) {
-    const int c0 = m->seg_chunk0[g0], c1 = m->seg_chunk1[g1 - 1];
+static int launch_decode_items(const ddrom_model* m, int prec, int c0, int c1, int n, long long stage,
+                               const double* xhat, int xstride, int xoff_override, const int* live, const int* n_live,
+                               int B, void* out, int Bp, hipStream_t s) {
     if (c1 <= c0) return 0;
-    const int n = m->segs_h[g0].n;
-    long long stage = 0;
-    for (int g = g0; g < g1; ++g) stage = std::max(stage, prec == DDROM_PREC_FP64 ? m->seg_stage_f64[g] : m->seg_stage_f32[g]);
     const int act = m->act;
     const int rk = act == DDROM_ACT_SWISH ? 2 : 1;
     const int waves = prec == DDROM_PREC_FP64 ? 1 : (act == DDROM_ACT_SWISH ? 2 : 4);
@@ -1432,11 +1463,33 @@ static int launch_decode(const ddrom_model* m, int prec, int g0, int g1, const d
     return 0;
 }
 
-static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const ddrom_workspace* ws,
-                      const int* live, const int* n_live, int B, hipStream_t s) {
-    const ddrom::ResSeg& rs = m->rsegs_h[sd0];
-    // one chunk per slot, slots of consecutive subdomains are consecutive
-    const int c0 = rs.slot0, c1 = m->rsegs_h[sd1 - 1].slot1;
+// Work items of one segment (seg_chunk0/1), or every work item of a decoder family's plan.
+template <int TAG, int VO = 0>
+static int launch_decode_seg(const ddrom_model* m, int prec, int g, const double* xhat, int xstride,
+                             int xoff_override, const int* live, const int* n_live, int B, void* out, int Bp,
+                             hipStream_t s) {
+    return launch_decode_items<TAG, VO>(m, prec, m->seg_chunk0[g], m->seg_chunk1[g], m->segs_h[g].n,
+                                        prec == DDROM_PREC_FP64 ? m->seg_stage_f64[g] : m->seg_stage_f32[g], xhat,
+                                        xstride, xoff_override, live, n_live, B, out, Bp, s);
+}
+
+template <int TAG, int VO = 0>
+static int launch_decode_family(const ddrom_model* m, int prec, int f, const double* xhat, const int* live,
+                                const int* n_live, int B, void* out, int Bp, hipStream_t s) {
+    for (const auto& pl : m->dec_plan[f]) {
+        const int rc = launch_decode_items<TAG, VO>(m, prec, pl.c0, pl.c1, pl.n,
+                                                    prec == DDROM_PREC_FP64 ? pl.stage_f64 : pl.stage_f32, xhat,
+                                                    m->n_D, -1, live, n_live, B, out, Bp, s);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+
+// One launch per latent class of the residual plan.
+static int launch_res_item(const ddrom_model* m, int prec, const ddrom_model::ResPlan& rs, const ddrom_workspace* ws,
+                           const int* live, const int* n_live, int B, hipStream_t s) {
+    const int c0 = rs.c0, c1 = rs.c1;
     dim3 grid(c1 - c0, ws->Bp / 64), block(256);
 #define RES_CASE(A, G)                                                                                            \
     if (rs.n_om == A && rs.n_ga == G) {                                                                           \
@@ -1458,15 +1511,22 @@ static int launch_res(const ddrom_model* m, int prec, int sd0, int sd1, const dd
     return DDROM_EINVAL;
 }
 
+static int launch_res(const ddrom_model* m, int prec, const ddrom_workspace* ws, const int* live, const int* n_live,
+                      int B, hipStream_t s) {
+    for (const auto& pl : m->res_plan) {
+        const int rc = launch_res_item(m, prec, pl, ws, live, n_live, B, s);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
 static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const int* n_live, int B,
                       hipStream_t s) {
     if (m->n_cchunks == 0 || m->n_C == 0) return 0;
-    // one launch per run of consecutive subdomains with the same interface latent size
-    for (int s0 = 0; s0 < m->n_sub;) {
-        int s1 = s0 + 1;
-        while (s1 < m->n_sub && m->n_ga[s1] == m->n_ga[s0]) ++s1;
-        const int c0 = m->cchunk0[s0], c1 = m->cchunk0[s1], ng = m->n_ga[s0];
-        if (c1 > c0) {
+    // one launch per interface latent size
+    for (const auto& pl : m->con_plan) {
+        const int c0 = pl.c0, c1 = pl.c1, ng = pl.n_ga;
+        {
             dim3 grid(c1 - c0, ws->Bp / 64), block(64);
 #define CON_CASE(G)                                                                                               \
     case G:                                                                                                       \
@@ -1488,7 +1548,6 @@ static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws,
 #undef CON_CASE
             HIPCHECK(hipGetLastError());
         }
-        s0 = s1;
     }
     return 0;
 }
@@ -1510,47 +1569,23 @@ static ModelDevInts get_ints(const ddrom_model* m) {
     return g_ints[m];
 }
 
-// One evaluation of all active solves at their trial points (xt).  With `fork`, the interface
-// decoders and the constraint sums run on a second stream forked from `s` (they depend only on
-// the interface latents), overlapping the interior decoders and the residual kernel; without
-// it everything runs on `s` in the same order.  Under graph capture `s` must then be the
-// capture's origin stream: a join into a stream that is itself a forked branch makes the two
-// streams each other's children in HIP's capture bookkeeping, and ending the capture recurses
-// through that cycle.
+// One evaluation of all active solves at their trial points (xt).  The interface decoders
+// and the constraint sums run on a second stream forked from `s` (they depend only on the
+// interface latents), overlapping the interior decoders and the residual kernel.
 static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const int* live,
-                          const int* n_live, const double* xhat, hipStream_t s, bool fork = true) {
+                          const int* n_live, const double* xhat, hipStream_t s) {
     int rc;
-    const int n = m->n_sub;
-    hipStream_t s2 = fork ? ws->stream2 : s;
-    if (fork) {
-        HIPCHECK(hipEventRecord(ws->ev_fork, s));
-        HIPCHECK(hipStreamWaitEvent(s2, ws->ev_fork, 0));
-    }
-    for (int g0 = n; g0 < 2 * n;) {
-        int g1 = g0 + 1;
-        while (g1 < 2 * n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
-        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, live, n_live, B, ws->dec_out, ws->Bp, s2)))
-            return rc;
-        g0 = g1;
-    }
-    if (fork) HIPCHECK(hipEventRecord(ws->ev_ga, s2));
+    hipStream_t s2 = ws->stream2;
+    HIPCHECK(hipEventRecord(ws->ev_fork, s));
+    HIPCHECK(hipStreamWaitEvent(s2, ws->ev_fork, 0));
+    if ((rc = launch_decode_family<0>(m, prec, 1, xhat, live, n_live, B, ws->dec_out, ws->Bp, s2))) return rc;
+    HIPCHECK(hipEventRecord(ws->ev_ga, s2));
     if ((rc = launch_con(m, prec, ws, n_live, B, s2))) return rc;
-    if (fork) HIPCHECK(hipEventRecord(ws->ev_con, s2));
-    for (int g0 = 0; g0 < n;) {
-        int g1 = g0 + 1;
-        while (g1 < n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
-        if ((rc = launch_decode<0>(m, prec, g0, g1, xhat, m->n_D, -1, live, n_live, B, ws->dec_out, ws->Bp, s)))
-            return rc;
-        g0 = g1;
-    }
-    if (fork) HIPCHECK(hipStreamWaitEvent(s, ws->ev_ga, 0));
-    for (int s0 = 0; s0 < n;) {
-        int s1 = s0 + 1;
-        while (s1 < n && m->n_om[s1] == m->n_om[s0] && m->n_ga[s1] == m->n_ga[s0]) ++s1;
-        if ((rc = launch_res(m, prec, s0, s1, ws, live, n_live, B, s))) return rc;
-        s0 = s1;
-    }
-    if (fork) HIPCHECK(hipStreamWaitEvent(s, ws->ev_con, 0));
+    HIPCHECK(hipEventRecord(ws->ev_con, s2));
+    if ((rc = launch_decode_family<0>(m, prec, 0, xhat, live, n_live, B, ws->dec_out, ws->Bp, s))) return rc;
+    HIPCHECK(hipStreamWaitEvent(s, ws->ev_ga, 0));
+    if ((rc = launch_res(m, prec, ws, live, n_live, B, s))) return rc;
+    HIPCHECK(hipStreamWaitEvent(s, ws->ev_con, 0));
     return 0;
 }
 
@@ -1614,10 +1649,9 @@ static int launch_update(const ddrom_model* m, const ddrom_workspace* ws, const 
     return 0;
 }
 
-static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const UpdArgs& ua, hipStream_t s,
-                        bool fork = true) {
+static int round_launch(const ddrom_model* m, ddrom_workspace* ws, int prec, int B, const UpdArgs& ua, hipStream_t s) {
     int rc;
-    if ((rc = evaluate_round(m, ws, prec, B, ws->live, ws->counter, ws->xt, s, fork))) return rc;
+    if ((rc = evaluate_round(m, ws, prec, B, ws->live, ws->counter, ws->xt, s))) return rc;
     ModelDevInts di = get_ints(m);
     const int n_etiles = (m->estride + m->n_C * std::max(1, m->mmax) + RED_E - 1) / RED_E;
     hipLaunchKernelGGL(k_reduce, dim3(m->n_sub + 1, n_etiles, ws->Bp / 64), dim3(256), 0, s, m->n_sub, m->n_C,
@@ -1875,7 +1909,7 @@ static int decode_common(const ddrom_model* m, ddrom_workspace* ws, int sd, int 
     if (B == 0) return 0;
     const int seg = part * m->n_sub + sd;
     const ddrom::DecSeg& sg = m->segs_h[seg];
-    if ((rc = launch_decode<0>(m, prec, seg, seg + 1, xhat_d, sg.n, 0, nullptr, nullptr, B, ws->dec_out, ws->Bp, s)))
+    if ((rc = launch_decode_seg<0>(m, prec, seg, xhat_d, sg.n, 0, nullptr, nullptr, B, ws->dec_out, ws->Bp, s)))
         return rc;
     const long long tot = (long long)sg.rows * (1 + sg.n) * B;
     if (tot == 0) return 0;
@@ -1938,6 +1972,50 @@ struct FinalOut {
 };
 
 // prop != nullptr: warm start from the network's proposal, the zero start as fallback.
+// Rounds captured per graph launch; the host checks the live count between launches.
+constexpr int kGraphRounds = 8;
+
+// Upper bound on solver rounds: the first evaluation, max_iter steps of at most max_backtracks + 1
+// trial evaluations each, one more, and the two extra evaluations of a warm start.
+static long long solver_max_rounds(const ddrom_opts* o, int warm) {
+    return 1 + (long long)std::max(1, o->max_iter) * (o->max_backtracks + 1) + 1 + 2 * warm;
+}
+
+// The workspace's captured graph of kGraphRounds solver rounds for this batch size and these
+// options (captured on first use, kept until the key changes).
+static int solver_graph(const ddrom_model* m, ddrom_workspace* ws, int B, const ddrom_opts* o, const UpdArgs& ua,
+                        int lam_given, int warm) {
+    const int prec = o->precision;
+    std::ostringstream key;
+    key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
+        << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << lam_given << ":" << warm;
+    if (ws->graph && ws->graph_key == key.str()) return 0;
+    if (ws->graph) {
+        (void)hipGraphExecDestroy(ws->graph);
+        ws->graph = nullptr;
+    }
+    hipStream_t s = ws->stream;
+    hipGraph_t g;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int crc = 0;
+    for (int k = 0; k < kGraphRounds && !crc; ++k) crc = round_launch(m, ws, prec, B, ua, s);
+    hipError_t ce = hipStreamEndCapture(s, &g);
+    if (crc) return crc;
+    if (ce != hipSuccess) {
+        set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
+        return DDROM_EHIP;
+    }
+    hipError_t ie = hipGraphInstantiate(&ws->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        ws->graph = nullptr;
+        set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+        return DDROM_EHIP;
+    }
+    ws->graph_key = key.str();
+    return 0;
+}
+
 static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int B, const double* x0,
                         const double* l0, const ddrom_opts* o, hipStream_t caller, int use_graph, const FinalOut& fo,
                         const ddrom_mlp* prop = nullptr) {
@@ -1971,40 +2049,13 @@ static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double*
     const int prec = o->precision;
     // The first round evaluates the initial latents; later rounds are line-search trials
     // (a warm solve first evaluates the zero start, then the proposal, maybe the zero start again).
-    const long long max_rounds = 1 + (long long)std::max(1, o->max_iter) * (o->max_backtracks + 1) + 1 + 2 * warm;
-    const int K = 8;
-    std::ostringstream key;
-    key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
-        << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << (l0 != nullptr) << ":" << warm;
+    const long long max_rounds = solver_max_rounds(o, warm);
     long long done = 0;
     if (use_graph) {
-        if (ws->graph_key != key.str() || !ws->graph) {
-            if (ws->graph) {
-                (void)hipGraphExecDestroy(ws->graph);
-                ws->graph = nullptr;
-            }
-            hipGraph_t g;
-            HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            int crc = 0;
-            for (int k = 0; k < K && !crc; ++k) crc = round_launch(m, ws, prec, B, ua, s);
-            hipError_t ce = hipStreamEndCapture(s, &g);
-            if (crc) return crc;
-            if (ce != hipSuccess) {
-                set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
-                return DDROM_EHIP;
-            }
-            hipError_t ie = hipGraphInstantiate(&ws->graph, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (ie != hipSuccess) {
-                ws->graph = nullptr;
-                set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
-                return DDROM_EHIP;
-            }
-            ws->graph_key = key.str();
-        }
+        if ((rc = solver_graph(m, ws, B, o, ua, l0 != nullptr, warm))) return rc;
         while (done < max_rounds) {
             HIPCHECK(hipGraphLaunch(ws->graph, s));
-            done += K;
+            done += kGraphRounds;
             HIPCHECK(hipMemcpyAsync(ws->counter_h, ws->counter, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
             if (*ws->counter_h == 0) break;
@@ -2053,9 +2104,9 @@ int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
     return solve_common(m, ws, mu_d, B, xhat0_d, lam0_d, o, s, 1, fo);
 }
 
-// Several models in one launch sequence: every model keeps its own workspace and streams; a
-// graph of K rounds forks each round into one branch per model (they run concurrently) and
-// joins them; the host replays it until no solve of any model is running.
+// Multi-model solve: every model replays its own captured graph of solver rounds (the one
+// rom_solve_batch uses for the same batch size and options) on its own streams, so the models'
+// rounds run concurrently; the host relaunches only the models that still have running solves.
 int rom_solve_multi(int n_models, const ddrom_model* const* models, ddrom_workspace* const* wss,
                     const double* const* mu_d, const int* Bs, const ddrom_opts* o, double* const* xhat_d,
                     double* const* lam_d, int* const* iters_d, int* const* status_d, double* const* fnorm_d,
@@ -2078,14 +2129,13 @@ int rom_solve_multi(int n_models, const ddrom_model* const* models, ddrom_worksp
                 return DDROM_EINVAL;
             }
     }
-    ddrom_workspace* w0 = wss[0];
-    hipStream_t s0 = w0->stream;
-    HIPCHECK(hipEventRecord(w0->ev_in, caller));
+    HIPCHECK(hipEventRecord(wss[0]->ev_in, caller));
+    std::vector<char> running(n_models, 1);
     for (int k = 0; k < n_models; ++k) {
         ddrom_workspace* ws = wss[k];
         const ddrom_model* m = models[k];
         const int B = Bs[k];
-        HIPCHECK(hipStreamWaitEvent(ws->stream, w0->ev_in, 0));
+        HIPCHECK(hipStreamWaitEvent(ws->stream, wss[0]->ev_in, 0));
         hipLaunchKernelGGL(k_init, dim3(ws->Bp), dim3(64), 0, ws->stream, B, ws->Bp, m->n_D, m->n_C, mu_d[k],
                            (const double*)nullptr, (const double*)nullptr, ws->mu, ws->x, ws->xt, ws->lam, ws->lamt,
                            ws->st, 0);
@@ -2094,76 +2144,36 @@ int rom_solve_multi(int n_models, const ddrom_model* const* models, ddrom_worksp
                                m->n_bc, ws->mu, B, ws->Bp, m->nu, ws->bc);
         hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, ws->stream, B, ws->st, ws->live, ws->counter);
         HIPCHECK(hipGetLastError());
-        if (k > 0) {
-            HIPCHECK(hipEventRecord(ws->ev_out, ws->stream));
-            HIPCHECK(hipStreamWaitEvent(s0, ws->ev_out, 0));
-        }
+        if ((rc = solver_graph(m, ws, B, o, upd_args(m, ws, B, o, 0), 0, 0))) return rc;
     }
-    const int K = 8;
-    long long max_rounds = 0;
-    std::ostringstream key;
-    key << "multi:" << o->precision << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":"
-        << o->armijo_c1 << ":" << o->max_backtracks << ":" << o->stall_tol;
-    for (int k = 0; k < n_models; ++k) key << ":" << (const void*)models[k] << "/" << (const void*)wss[k] << "/" << Bs[k];
-    max_rounds = 1 + (long long)std::max(1, o->max_iter) * (o->max_backtracks + 1) + 1;
-    if (w0->graph_key != key.str() || !w0->graph) {
-        if (w0->graph) {
-            (void)hipGraphExecDestroy(w0->graph);
-            w0->graph = nullptr;
+    const long long max_rounds = solver_max_rounds(o, 0);
+    for (long long done = 0; done < max_rounds; done += kGraphRounds) {
+        int any = 0;
+        for (int k = 0; k < n_models; ++k) {
+            if (!running[k]) continue;
+            HIPCHECK(hipGraphLaunch(wss[k]->graph, wss[k]->stream));
+            HIPCHECK(hipMemcpyAsync(wss[k]->counter_h, wss[k]->counter, sizeof(int), hipMemcpyDeviceToHost,
+                                    wss[k]->stream));
         }
-        hipGraph_t g;
-        HIPCHECK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
-        int crc = 0;
-        for (int r = 0; r < K && !crc; ++r) {
-            if (hipEventRecord(w0->ev_in, s0) != hipSuccess) { crc = DDROM_EHIP; break; }
-            for (int k = 1; k < n_models && !crc; ++k)
-                if (hipStreamWaitEvent(wss[k]->stream, w0->ev_in, 0) != hipSuccess) crc = DDROM_EHIP;
-            // model 0 runs on the origin stream and may fork; the others are branches of it
-            for (int k = 0; k < n_models && !crc; ++k) {
-                const UpdArgs ua = upd_args(models[k], wss[k], Bs[k], o, 0);
-                crc = round_launch(models[k], wss[k], o->precision, Bs[k], ua, wss[k]->stream, k == 0);
-            }
-            for (int k = 1; k < n_models && !crc; ++k) {
-                if (hipEventRecord(wss[k]->ev_out, wss[k]->stream) != hipSuccess ||
-                    hipStreamWaitEvent(s0, wss[k]->ev_out, 0) != hipSuccess)
-                    crc = DDROM_EHIP;
-            }
+        for (int k = 0; k < n_models; ++k) {
+            if (!running[k]) continue;
+            HIPCHECK(hipStreamSynchronize(wss[k]->stream));
+            running[k] = *wss[k]->counter_h != 0;
+            any |= running[k];
         }
-        hipError_t ce = hipStreamEndCapture(s0, &g);
-        if (crc) return crc;
-        if (ce != hipSuccess) {
-            set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
-            return DDROM_EHIP;
-        }
-        hipError_t ie = hipGraphInstantiate(&w0->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) {
-            w0->graph = nullptr;
-            set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
-            return DDROM_EHIP;
-        }
-        w0->graph_key = key.str();
-    }
-    for (long long done = 0; done < max_rounds; done += K) {
-        HIPCHECK(hipGraphLaunch(w0->graph, s0));
-        for (int k = 0; k < n_models; ++k)
-            HIPCHECK(hipMemcpyAsync(wss[k]->counter_h, wss[k]->counter, sizeof(int), hipMemcpyDeviceToHost, s0));
-        HIPCHECK(hipStreamSynchronize(s0));
-        int live = 0;
-        for (int k = 0; k < n_models; ++k) live += *wss[k]->counter_h;
-        if (live == 0) break;
+        if (!any) break;
     }
     for (int k = 0; k < n_models; ++k) {
         const ddrom_model* m = models[k];
         ddrom_workspace* ws = wss[k];
-        hipLaunchKernelGGL(k_finalize, dim3(Bs[k]), dim3(64), 0, s0, Bs[k], m->n_D, m->n_C, ws->x, ws->lam, ws->st,
-                           xhat_d[k], lam_d ? lam_d[k] : nullptr, iters_d ? iters_d[k] : nullptr,
+        hipLaunchKernelGGL(k_finalize, dim3(Bs[k]), dim3(64), 0, ws->stream, Bs[k], m->n_D, m->n_C, ws->x, ws->lam,
+                           ws->st, xhat_d[k], lam_d ? lam_d[k] : nullptr, iters_d ? iters_d[k] : nullptr,
                            status_d ? status_d[k] : nullptr, fnorm_d ? fnorm_d[k] : nullptr, (double*)nullptr,
                            (int*)nullptr);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipEventRecord(ws->ev_out, ws->stream));
+        HIPCHECK(hipStreamWaitEvent(caller, ws->ev_out, 0));
     }
-    HIPCHECK(hipGetLastError());
-    HIPCHECK(hipEventRecord(w0->ev_out, s0));
-    HIPCHECK(hipStreamWaitEvent(caller, w0->ev_out, 0));
     return 0;
 }
 
@@ -2189,15 +2199,10 @@ static int decode_states(const ddrom_model* m, ddrom_workspace* ws, const double
             return DDROM_ENOMEM;
         }
     }
-    const int n = m->n_sub;
     int rc;
-    for (int g0 = 2 * n; g0 < 4 * n;) {
-        int g1 = g0 + 1;
-        while (g1 < 4 * n && m->segs_h[g1].n == m->segs_h[g0].n) ++g1;
-        if ((rc = launch_decode<0, 1>(m, prec, g0, g1, xhat_d, m->n_D, -1, nullptr, nullptr, B, ws->state_out, ws->Bp, s)))
+    for (int f = 2; f < 4; ++f)
+        if ((rc = launch_decode_family<0, 1>(m, prec, f, xhat_d, nullptr, nullptr, B, ws->state_out, ws->Bp, s)))
             return rc;
-        g0 = g1;
-    }
     return 0;
 }
 
@@ -2266,11 +2271,9 @@ int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* 
         HIPCHECK(hipEventRecord(ws->t0, s));
         for (int r = 0; r < reps; ++r) {
             int c = 0;
-            if (which == 0) c = launch_decode<1>(m, precision, 0, m->n_sub, ws->xt, m->n_D, -1, nullptr, nullptr, B,
-                                                 ws->dec_out, ws->Bp, s);
-            else if (which == 1) c = launch_decode<1>(m, precision, m->n_sub, 2 * m->n_sub, ws->xt, m->n_D, -1,
-                                                      nullptr, nullptr, B, ws->dec_out, ws->Bp, s);
-            else if (which == 2) c = launch_res(m, precision, 0, m->n_sub, ws, nullptr, nullptr, B, s);
+            if (which < 2)
+                c = launch_decode_family<1>(m, precision, which, ws->xt, nullptr, nullptr, B, ws->dec_out, ws->Bp, s);
+            else if (which == 2) c = launch_res(m, precision, ws, nullptr, nullptr, B, s);
             else c = launch_con(m, precision, ws, nullptr, B, s);
             if (c) return c;
         }

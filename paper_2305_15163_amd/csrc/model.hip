@@ -448,6 +448,39 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         m->seg_chunk1[sgi] = (int)m->chunks_h.size();
     }
 
+    // ---- decoder launch plans: per family, segments of equal latent size (ascending) become
+    //      one contiguous run of work items, each segment's items still contiguous ----
+    {
+        std::vector<DecChunk> sorted;
+        sorted.reserve(m->chunks_h.size());
+        std::vector<int> c0(4 * n_sub, 0), c1(4 * n_sub, 0);
+        for (int f = 0; f < 4; ++f) {
+            std::vector<int> order(n_sub);
+            for (int sd = 0; sd < n_sub; ++sd) order[sd] = f * n_sub + sd;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int b) { return m->segs_h[a].n < m->segs_h[b].n; });
+            for (size_t k = 0; k < order.size();) {
+                size_t e = k + 1;
+                while (e < order.size() && m->segs_h[order[e]].n == m->segs_h[order[k]].n) ++e;
+                ddrom_model::DecPlan pl{(int)sorted.size(), 0, m->segs_h[order[k]].n, 0, 0};
+                for (size_t q = k; q < e; ++q) {
+                    const int g = order[q];
+                    c0[g] = (int)sorted.size();
+                    for (int c = m->seg_chunk0[g]; c < m->seg_chunk1[g]; ++c) sorted.push_back(m->chunks_h[c]);
+                    c1[g] = (int)sorted.size();
+                    pl.stage_f32 = std::max(pl.stage_f32, m->seg_stage_f32[g]);
+                    pl.stage_f64 = std::max(pl.stage_f64, m->seg_stage_f64[g]);
+                }
+                pl.c1 = (int)sorted.size();
+                if (pl.c1 > pl.c0) m->dec_plan[f].push_back(pl);
+                k = e;
+            }
+        }
+        m->chunks_h.swap(sorted);
+        m->seg_chunk0.swap(c0);
+        m->seg_chunk1.swap(c1);
+    }
+
     // ---- residual work items and GN partial slots ----
     m->rsegs_h.resize(n_sub);
     int slot = 0;
@@ -468,13 +501,36 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         m->estride = std::max(m->estride, NN * (NN + 1) / 2 + NN + 1);
     }
     m->n_slots = slot;
+    // residual launch plan: work items grouped by (n_i^Omega, n_i^Gamma); each item keeps its
+    // partial slot, and the slots of a subdomain stay consecutive for the reduction
+    {
+        std::vector<int> order(n_sub);
+        for (int sd = 0; sd < n_sub; ++sd) order[sd] = sd;
+        auto cls = [&](int sd) { return std::make_pair(m->n_om[sd], m->n_ga[sd]); };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cls(a) < cls(b); });
+        std::vector<ResChunk> sorted;
+        sorted.reserve(m->rchunks_h.size());
+        for (size_t k = 0; k < order.size();) {
+            size_t e = k + 1;
+            while (e < order.size() && cls(order[e]) == cls(order[k])) ++e;
+            ddrom_model::ResPlan pl{(int)sorted.size(), 0, m->n_om[order[k]], m->n_ga[order[k]]};
+            for (size_t q = k; q < e; ++q) {
+                const ResSeg& rs = m->rsegs_h[order[q]];
+                for (int sl = rs.slot0; sl < rs.slot1; ++sl) sorted.push_back(m->rchunks_h[sl]);
+            }
+            pl.c1 = (int)sorted.size();
+            if (pl.c1 > pl.c0) m->res_plan.push_back(pl);
+            k = e;
+        }
+        m->rchunks_h.swap(sorted);
+    }
 
     // ---- constraint work items ----
     std::vector<ConChunk> cch;
     std::vector<double> CAflat;
     m->CA_off.resize(n_sub);
     m->ca_ld = (m->n_C + 7) / 8 * 8;
-    m->cchunk0.assign(n_sub + 1, 0);
+    std::vector<int> cchunk0(n_sub + 1, 0);
     int cpart = 0;
     for (int sd = 0; sd < n_sub; ++sd) {
         const int Ng = m->N_ga[sd];
@@ -487,7 +543,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             for (int o = 0; o < Ng; ++o) t[(size_t)o * m->ca_ld + j] = CA[sd][(size_t)j * Ng + o];
         CAflat.insert(CAflat.end(), t.begin(), t.end());
         m->rsegs_h[sd].cpart0 = cpart;
-        m->cchunk0[sd] = (int)cch.size();
+        cchunk0[sd] = (int)cch.size();
         const int orows = m->tile_con_orows;
         if (Ng > 0 && m->n_C > 0)
             for (int o = 0; o < Ng; o += orows, ++cpart)
@@ -495,9 +551,28 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
                     cch.push_back(ConChunk{sd, j, std::min(m->n_C, j + CON_ROWS), o, std::min(Ng, o + orows), cpart, {0, 0}});
         m->rsegs_h[sd].cpart1 = cpart;
     }
-    m->cchunk0[n_sub] = (int)cch.size();
+    cchunk0[n_sub] = (int)cch.size();
     m->n_cchunks = (int)cch.size();
     m->n_cparts = cpart;
+    // constraint launch plan: work items grouped by n_i^Gamma
+    {
+        std::vector<int> order(n_sub);
+        for (int sd = 0; sd < n_sub; ++sd) order[sd] = sd;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m->n_ga[a] < m->n_ga[b]; });
+        std::vector<ConChunk> sorted;
+        sorted.reserve(cch.size());
+        for (size_t k = 0; k < order.size();) {
+            size_t e = k + 1;
+            while (e < order.size() && m->n_ga[order[e]] == m->n_ga[order[k]]) ++e;
+            ddrom_model::ConPlan pl{(int)sorted.size(), 0, m->n_ga[order[k]]};
+            for (size_t q = k; q < e; ++q)
+                for (int c = cchunk0[order[q]]; c < cchunk0[order[q] + 1]; ++c) sorted.push_back(cch[c]);
+            pl.c1 = (int)sorted.size();
+            if (pl.c1 > pl.c0) m->con_plan.push_back(pl);
+            k = e;
+        }
+        cch.swap(sorted);
+    }
 
     // ---- DD FOM residual tables ----
     std::vector<int> fsrc;

@@ -90,3 +90,8 @@ def train_split(n: int, frac_test: float, seed: int):
 def epoch_order(n: int, seed: int, epoch: int) -> np.ndarray:
     """Minibatch visiting order of one training epoch (a seeded permutation of range(n))."""
     return np.random.Generator(np.random.PCG64([int(seed), int(epoch)])).permutation(n)
+
+
+def model_assignment(n: int, n_models: int, seed: int) -> np.ndarray:
+    """Model index of each of n solves, split evenly over n_models in a seeded random order."""
+    return rng(seed).permutation(np.arange(n) % n_models)
