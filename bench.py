@@ -137,6 +137,31 @@ def uneven_leg(a, torch, dr):
             "tiles_from": "work-item shape search (ddrom_autotune), table paper_2305_15163_amd/tiles.json"}
 
 
+def roofline_only(a, torch, dr, si):
+    """The dominant kernel's 20 all-live timing launches of the headline workload, then 5 device
+    copies of 256 MiB (torch copy kernel: 256 MiB read and 256 MiB written each), whose byte
+    counters calibrate FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    cfg = CONFIGS["cfg1"]
+    pack = dict(np.load(os.path.join(ROOT, "models", "cfg1.npz"), allow_pickle=False))
+    torch.cuda.set_device(0)
+    model = dr.Model(pack)
+    B = cfg["batch"]
+    ws = dr.Workspace(model, B)
+    mu = torch.as_tensor(si.heldout_mu(B, cfg["seed"]), device="cuda")
+    ms = dr.time_kernels(model, ws, mu, torch.zeros((B, model.n_D), dtype=torch.float64, device="cuda"),
+                         precision=cfg["precision"], reps=20)
+    n = 64 << 20
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    flops, bytes_ = decoder_work(model, B)
+    print(json.dumps({"roofline_workload": "cfg1 interior decoder, 20 timing launches (B=512, all live)",
+                      "ms_per_launch": ms, "algorithmic_bytes_per_launch": bytes_, "flops_per_launch": flops,
+                      "copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +172,9 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="parameters for the plain per-solve GPU SQP leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-model uneven batch leg")
     ap.add_argument("--uneven-only", action="store_true", help="run only the three-model uneven batch leg")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="run only the dominant kernel's timing launches and a device copy of known size "
+                         "(the workload of the hardware-counter runs)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -156,6 +184,10 @@ def main():
     import torch
     import paper_2305_15163_amd as dr
     import seeded_inputs as si
+
+    if a.roofline_only:
+        roofline_only(a, torch, dr, si)
+        return
 
     if a.uneven_only:
         torch.cuda.set_device(0)

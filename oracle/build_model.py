@@ -52,6 +52,8 @@ CONFIGS = {
                     epochs=300, batch=4, train_grid=(4, 4), hr_frac=(0.3, 0.6), seed=31),
     "tinybig": dict(nx=48, ny=48, nsx=8, nsy=8, n_om=6, n_ga=3, b=3, s=2, act=ACT_SIGMOID,
                     epochs=60, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=32),
+    "tinyhuge": dict(nx=48, ny=48, nsx=8, nsy=8, n_om=12, n_ga=6, b=3, s=2, act=ACT_SIGMOID,
+                     epochs=30, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=33),
     "tiny": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID,
                  epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
 }

@@ -625,8 +625,9 @@ __device__ __forceinline__ int packed_idx(int i, int j, int n) {   // i <= j, up
 
 // LDS layout of the update kernel (offsets in doubles).
 // Memory of the update kernel (offsets in doubles): a small part always in LDS, and the
-// per-subdomain blocks and the Schur system, in LDS when they fit beside it, else in a
-// per-slot area of global scratch.
+// per-subdomain blocks and the Schur system, in LDS when they fit beside it (GB = 0), else in
+// a per-slot area of global scratch, the Schur system kept in LDS while it fits (GB = 1) or
+// in the scratch too (GB = 2).
 struct UpdLds {
     int lam, c, sl, red, small;      // small part: lam [nC], c [nC], s_lambda [nC], reduction [16]
     int E, P, q, rho, X, S, big;     // big part, relative to its base
@@ -648,7 +649,8 @@ __host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int
     L.big = L.S + nC * (nC + 1);
     return L;
 }
-constexpr int UPD_LDS_DOUBLES = 8192;        // 64 KiB
+constexpr int UPD_LDS_DOUBLES = 8192;        // 64 KiB: everything in LDS up to this size
+constexpr int UPD_LDS_MAX_DOUBLES = 19968;   // 156 KiB of the 160 KiB a workgroup may hold
 
 // Dense n x n system [M | r] (in LDS, row stride n + 1) solved by one wave with row i in
 // lane i, held in registers: Gaussian elimination with partial pivoting in which the pivot
@@ -704,113 +706,132 @@ __device__ __noinline__ bool wave_lu_solve(const double* M, int n, double* x, in
     return wave_lu_reg<64>(M, n, x, lane);
 }
 
-// Systems larger than a wave (64 < n <= 256): the whole workgroup eliminates with partial
-// pivoting, rows spread over threads, then back-substitutes column by column.  M may live in
-// global memory.  redv [9] / redi [9] / piv: LDS scratch.  Every thread returns the same value.
-__device__ bool block_lu_solve(double* M, int n, double* x, double* redv, int* redi, int tid, int nth) {
-    const int ld = n + 1, lane = tid & 63, wave = tid >> 6, nw = nth >> 6;
-    bool ok = true;
+// Systems larger than a wave (64 < n <= 256): Gaussian elimination with partial pivoting over
+// the whole workgroup.  Rows are not moved: perm (LDS, n entries) holds the pivot order.  Per
+// step, wave 0 picks the pivot among the remaining rows (lowest position on ties) and the
+// workgroup applies the rank-1 update to the trailing block, one entry per thread: two
+// barriers per step.  Wave 0 then back-substitutes alone (rows in its lanes, no barriers).
+// M (row stride n + 1, right-hand side in column n) may be in LDS or global memory; x (LDS)
+// receives the solution.  okf: LDS flag.  Every thread returns the same value.
+__device__ bool block_lu_solve(double* M, int n, double* x, int* perm, int* okf, int tid, int nth) {
+    const int ld = n + 1, lane = tid & 63, wave = tid >> 6;
+    for (int q = tid; q < n; q += nth) perm[q] = q;
+    if (tid == 0) okf[0] = 1;
+    __syncthreads();
     for (int k = 0; k < n; ++k) {
-        double best = -1.0;
-        int bi = n;
-        for (int i = k + tid; i < n; i += nth) {
-            const double v = fabs(M[(size_t)i * ld + k]);
-            if (v > best) { best = v; bi = i; }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (lane == 0) {
-            redv[wave] = best;
-            redi[wave] = bi;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double bb = redv[0];
-            int ii = redi[0];
-            for (int w = 1; w < nw; ++w)
-                if (redv[w] > bb || (redv[w] == bb && redi[w] < ii)) { bb = redv[w]; ii = redi[w]; }
-            redv[8] = bb;
-            redi[8] = ii;
-        }
-        __syncthreads();
-        const int p = redi[8];
-        const double bestv = redv[8];
-        if (!(bestv > 0.0) || !isfinite(bestv)) ok = false;
-        if (p != k && p < n)
-            for (int j = tid; j <= n; j += nth) {
-                const double t = M[(size_t)k * ld + j];
-                M[(size_t)k * ld + j] = M[(size_t)p * ld + j];
-                M[(size_t)p * ld + j] = t;
+        if (wave == 0) {
+            double best = -1.0;
+            int bi = n;
+            for (int q = k + lane; q < n; q += 64) {
+                const double v = fabs(M[(size_t)perm[q] * ld + k]);
+                if (v > best) { best = v; bi = q; }
             }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off, 64);
+                const int oi = __shfl_xor(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (lane == 0) {
+                if (!(best > 0.0) || !isfinite(best)) okf[0] = 0;
+                if (bi < n && bi != k) {
+                    const int t = perm[k];
+                    perm[k] = perm[bi];
+                    perm[bi] = t;
+                }
+            }
+        }
         __syncthreads();
-        // rank-1 update of the trailing block [k+1, n) x [k+1, n], one entry per thread (column
-        // k is read, never written, in this step)
-        const double pv = M[(size_t)k * ld + k];
+        const int pr = perm[k];
+        const double pv = M[(size_t)pr * ld + k];
         const int w = n - k;            // columns k+1 .. n (right-hand side included)
         if (pv != 0.0) {
             const double rp = 1.0 / pv;
             for (int e = tid; e < (n - k - 1) * w; e += nth) {
-                const int i = k + 1 + e / w, j = k + 1 + e % w;
-                M[(size_t)i * ld + j] -= (M[(size_t)i * ld + k] * rp) * M[(size_t)k * ld + j];
+                const int r = perm[k + 1 + e / w], j = k + 1 + e % w;
+                M[(size_t)r * ld + j] -= (M[(size_t)r * ld + k] * rp) * M[(size_t)pr * ld + j];
             }
         }
         __syncthreads();
     }
-    for (int i = n - 1; i >= 0; --i) {
-        if (tid == 0) x[i] = M[(size_t)i * ld + n] / M[(size_t)i * ld + i];
-        __syncthreads();
-        const double xi = x[i];
-        for (int j = tid; j < i; j += nth) M[(size_t)j * ld + n] -= M[(size_t)j * ld + i] * xi;
-        __syncthreads();
+    if (wave == 0) {
+        // lane l holds the right-hand sides of positions l, l + 64, ... (at most 4)
+        double rhs[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int q = lane + 64 * t;
+            rhs[t] = q < n ? M[(size_t)perm[q] * ld + n] : 0.0;
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            const int r = perm[i];
+            const int owner = i & 63, slot = i >> 6;
+            double ri = 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (t == slot) ri = rhs[t];
+            const double xi = __shfl(ri, owner, 64) / M[(size_t)r * ld + i];
+            if (lane == 0) x[i] = xi;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int q = lane + 64 * t;
+                if (q < i) rhs[t] -= M[(size_t)perm[q] * ld + i] * xi;
+            }
+        }
     }
-    return ok;
+    __syncthreads();
+    return okf[0] != 0;
 }
 
 // S[i][j] = sum over subdomains sd and l < mg of A[sd][i][l] Bm[sd][j][l] for i, j < nC, written
-// to S with row stride ld; A and Bm are [ns][nC][mg] with subdomain stride `sds`.  Each thread
-// accumulates a 4 x 4 block in registers (8 loads per 16 FMAs), subdomains in ascending order,
-// so every entry is the same fixed-order sum whatever the thread count.
-__device__ void gram_sum(const double* A, const double* Bm, size_t sds, int ns, int nC, int mg, double* S, int ld,
-                         int tid, int nth) {
-    const int nT = (nC + 3) >> 2;
+// to S with row stride ld; A and Bm are [ns][nC][mg] with subdomain strides sdsA, sdsB.  Each thread
+// accumulates a T x T block in registers (2T loads per T^2 FMAs), subdomains in ascending
+// order, so every entry is the same fixed-order sum whatever the block size or thread count.
+template <int T>
+__device__ void gram_sum_t(const double* A, size_t sdsA, const double* Bm, size_t sdsB, int ns, int nC, int mg,
+                           double* S, int ld, int tid, int nth) {
+    const int nT = (nC + T - 1) / T;
     for (int t = tid; t < nT * nT; t += nth) {
-        const int i0 = (t / nT) * 4, j0 = (t % nT) * 4;
-        double acc[4][4];
+        const int i0 = (t / nT) * T, j0 = (t % nT) * T;
+        double acc[T][T];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < T; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            for (int b = 0; b < T; ++b) acc[a][b] = 0.0;
         for (int sd = 0; sd < ns; ++sd) {
-            const double* As = A + sd * sds;
-            const double* Bs = Bm + sd * sds;
+            const double* As = A + sd * sdsA;
+            const double* Bs = Bm + sd * sdsB;
             for (int l = 0; l < mg; ++l) {
-                double av[4], bv[4];
+                double av[T], bv[T];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) {
+                for (int a = 0; a < T; ++a) {
                     av[a] = i0 + a < nC ? As[(i0 + a) * mg + l] : 0.0;
                     bv[a] = j0 + a < nC ? Bs[(j0 + a) * mg + l] : 0.0;
                 }
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                for (int a = 0; a < T; ++a)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+                    for (int b = 0; b < T; ++b) acc[a][b] += av[a] * bv[b];
             }
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < T; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int b = 0; b < T; ++b)
                 if (i0 + a < nC && j0 + b < nC) S[(i0 + a) * ld + j0 + b] = acc[a][b];
     }
 }
 
+// Block size by the work per thread: single entries while nC^2 gives each thread few of them,
+// larger register blocks once every thread would otherwise loop over many entries.
+__device__ __forceinline__ void gram_sum(const double* A, size_t sdsA, const double* Bm, size_t sdsB, int ns, int nC,
+                                         int mg, double* S, int ld, int tid, int nth) {
+    if (nC * nC >= 16 * nth) gram_sum_t<4>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
+    else if (nC * nC >= 4 * nth) gram_sum_t<2>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
+    else gram_sum_t<1>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
+}
+
 // Solve [M | r] with every thread of the workgroup calling: one wave when n <= 64, else the
 // workgroup.  The result is valid for all threads after the call.
-__device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, double* redv, int* redi, int* okf, int tid,
-                                       int nth) {
+__device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, int* perm, int* okf, int tid, int nth) {
     if (n <= 64) {
         if (tid == 0) okf[0] = 1;
         __syncthreads();
@@ -821,7 +842,7 @@ __device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, double* redv
         __syncthreads();
         return okf[0] != 0;
     }
-    return block_lu_solve(M, n, x, redv, redi, tid, nth);
+    return block_lu_solve(M, n, x, perm, okf, tid, nth);
 }
 
 // ------------------------------------------------------------------------------------
@@ -834,14 +855,15 @@ __device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, double* redv
 // Each wave solves its subdomains' systems H_i [W_i | t_i] = [[0; I_m] | rho_i] in registers:
 // row r of the augmented block lives in lane r and pivot rows are broadcast lane to lane, so
 // these solves need no LDS traffic and no workgroup barrier.  S (a sum over subdomains in a
-// fixed order) and its pivoted solve then go through LDS.  NN >= n_i^Omega + n_i^Gamma and
-// MG >= n_i^Gamma bound every block (smaller blocks are padded with identity rows).
+// fixed order) and its pivoted solve then go through LDS (or global scratch, GB = 2).
+// NN >= n_i^Omega + n_i^Gamma and MG >= n_i^Gamma bound every block (smaller blocks are padded
+// with identity rows).
 template <int NN, int MG, int GB>
 __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     __shared__ int flag_bad;
-    __shared__ int lu_idx[9], lu_ok[1];
+    __shared__ int lu_perm[256], lu_ok[1];
     const int slot = blockIdx.x;
     const int nl = live_count(a.n_live, a.B);
     if (slot >= nl) return;
@@ -856,23 +878,27 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     double* sl_s = sm + L.sl;
     double* red = sm + L.red;
     double* big = GB ? a.gscr + (size_t)slot * a.gstride : sm + L.small;
-    double* Es = big + L.E;
+    const double* rb = a.RB + (size_t)slot * a.RS;
+    // E_hat blocks: copied into LDS with everything else (GB = 0), else read where the reduction
+    // left them (subdomain stride rs)
+    double* Es = GB ? const_cast<double*>(rb) + a.estride : big + L.E;
+    const size_t esds = GB ? (size_t)a.rs : (size_t)nC * mg;
     double* Ps = big + L.P;
     double* qs = big + L.q;
     double* rho = big + L.rho;
     double* Xs = big + L.X;
-    double* Sm = big + L.S;
-    const double* rb = a.RB + (size_t)slot * a.RS;
+    double* Sm = GB == 1 ? sm + L.small : big + L.S;     // GB = 1: the Schur system alone in LDS
     const int ld = nC + 1;
 
     for (int jj = tid; jj < nC; jj += nth) {
         c_s[jj] = rb[(size_t)ns * a.rs + jj];
         lam_s[jj] = a.lamt[(size_t)b * nC + jj];
     }
-    for (int e = tid; e < ns * nC * mg; e += nth) {
-        const int sd = e / (nC * mg), r = e % (nC * mg);
-        Es[e] = rb[(size_t)sd * a.rs + a.estride + r];
-    }
+    if (!GB)
+        for (int e = tid; e < ns * nC * mg; e += nth) {
+            const int sd = e / (nC * mg), r = e % (nC * mg);
+            Es[e] = rb[(size_t)sd * a.rs + a.estride + r];
+        }
     if (tid == 0) flag_bad = 0;
     __syncthreads();
     auto gv = [&](int sd, int e) {
@@ -885,18 +911,18 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     const bool ls_start = S.phase == PH_ZERO || (S.phase == PH_INIT && !(S.flags & SF_LAMFIX));
     if (ls_start && !a.lam_given && nC > 0) {
         // (entries k >= n_i^Gamma of each Ehat_i row are zero)
-        gram_sum(Es, Es, (size_t)nC * mg, ns, nC, mg, Sm, ld, tid, nth);
+        gram_sum(Es, esds, Es, esds, ns, nC, mg, Sm, ld, tid, nth);
         for (int i = tid; i < nC; i += nth) {
             double s = 0.0;
             for (int sd = 0; sd < ns; ++sd) {
                 const int m = a.n_ga[sd], no = a.n_om[sd];
-                const double* E = Es + (size_t)sd * nC * mg;
+                const double* E = Es + sd * esds;
                 for (int k = 0; k < m; ++k) s -= E[i * mg + k] * gv(sd, no + k);
             }
             Sm[i * ld + nC] = s;
         }
         __syncthreads();
-        kkt_lu(Sm, nC, lam_s, red, lu_idx, lu_ok, tid, nth);
+        kkt_lu(Sm, nC, lam_s, lu_perm, lu_ok, tid, nth);
         __syncthreads();
     }
 
@@ -910,7 +936,7 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
             if (r < NNi) {
                 v = gv(sd, r);
                 if (r >= no) {
-                    const double* E = Es + (size_t)sd * nC * mg + (r - no);
+                    const double* E = Es + sd * esds + (r - no);
                     for (int jj = 0; jj < nC; ++jj) v += E[jj * mg] * lam_s[jj];
                 }
             }
@@ -1067,7 +1093,7 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
 #pragma unroll
             for (int l = 0; l <= MG; ++l) Xs[((size_t)sd * NN + lane) * (MG + 1) + l] = Xr[l];
         // P_i = Ehat_i (W_i)_Gamma, q_i = Ehat_i (t_i)_Gamma (constraint row j0 + lane in lane)
-        const double* E = Es + (size_t)sd * nC * mg;
+        const double* E = Es + sd * esds;
         for (int j0 = 0; j0 < nC; j0 += 64) {
             const int jj = j0 + lane;
             double P[MG + 1];
@@ -1101,14 +1127,14 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     double* stp = a.step + (size_t)b * (nD + nC);
     if (nC > 0) {
         // [S | c - q] with S = sum_i P_i Ehat_i^T, summed over subdomains in a fixed order
-        gram_sum(Ps, Es, (size_t)nC * mg, ns, nC, mg, Sm, ld, tid, nth);
+        gram_sum(Ps, (size_t)nC * mg, Es, esds, ns, nC, mg, Sm, ld, tid, nth);
         for (int i = tid; i < nC; i += nth) {
             double s = 0.0;
             for (int sd = 0; sd < ns; ++sd) s += qs[(size_t)sd * nC + i];
             Sm[i * ld + nC] = c_s[i] - s;
         }
         __syncthreads();
-        if (!kkt_lu(Sm, nC, sl_s, red, lu_idx, lu_ok, tid, nth) && tid == 0) flag_bad = 1;
+        if (!kkt_lu(Sm, nC, sl_s, lu_perm, lu_ok, tid, nth) && tid == 0) flag_bad = 1;
         __syncthreads();
         if (flag_bad) {
             if (tid == 0) {
@@ -1125,7 +1151,7 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         const int ng = a.n_ga[sd], NNi = a.n_om[sd] + ng;
         if (r >= NNi) continue;
         const double* X = Xs + ((size_t)sd * NN + r) * (MG + 1);
-        const double* E = Es + (size_t)sd * nC * mg;
+        const double* E = Es + sd * esds;
         double s = X[MG];
         for (int l = 0; l < ng; ++l) {
             double u = 0.0;
@@ -1622,24 +1648,42 @@ static int update_shape(const ddrom_model* m, int* NN, int* MG, long long* gbig)
     return 0;
 }
 
+// 0: all update arrays in LDS; 1: the Schur system in LDS, the per-subdomain arrays in global
+// scratch; 2: all of them in global scratch.  LDS doubles needed in *lds_doubles.
+static int update_mode(const ddrom_model* m, int NN, int MG, long long gbig, long long* lds_doubles) {
+    const UpdLds L = upd_lds(m->n_sub, m->n_C, std::max(1, m->mmax), NN, MG);
+    if (gbig == 0) {
+        *lds_doubles = L.small + L.big;
+        return 0;
+    }
+    const long long s = (long long)m->n_C * (m->n_C + 1);
+    if (L.small + s <= UPD_LDS_MAX_DOUBLES) {
+        *lds_doubles = L.small + s;
+        return 1;
+    }
+    *lds_doubles = L.small;
+    return 2;
+}
+
 static int launch_update(const ddrom_model* m, const ddrom_workspace* ws, const UpdArgs& ua, int B, hipStream_t s) {
     int NN, MG, rc;
     long long gbig;
     if ((rc = update_shape(m, &NN, &MG, &gbig))) return rc;
-    const UpdLds L = upd_lds(m->n_sub, m->n_C, std::max(1, m->mmax), NN, MG);
-    const int GB = gbig > 0;
+    long long lds_doubles = 0;
+    const int GB = update_mode(m, NN, MG, gbig, &lds_doubles);
     if (GB && (!ws->kkt_scr || ws->kkt_stride < gbig)) {
         set_error("workspace lacks KKT scratch");
         return DDROM_EINVAL;
     }
-    const size_t lds = (size_t)(GB ? L.small : L.small + L.big) * sizeof(double);
+    const size_t lds = (size_t)lds_doubles * sizeof(double);
     const int nw = std::max(1, std::min(8, m->n_sub));
     UpdArgs a = ua;
     a.gscr = ws->kkt_scr;
     a.gstride = ws->kkt_stride;
 #define UPD_CASE(A, G)                                                                                   \
     if (NN == A && MG == G) {                                                                            \
-        if (GB) hipLaunchKernelGGL((k_update<A, G, 1>), dim3(B), dim3(64 * nw), lds, s, a);            \
+        if (GB == 2) hipLaunchKernelGGL((k_update<A, G, 2>), dim3(B), dim3(64 * nw), lds, s, a);       \
+        else if (GB == 1) hipLaunchKernelGGL((k_update<A, G, 1>), dim3(B), dim3(64 * nw), lds, s, a);  \
         else hipLaunchKernelGGL((k_update<A, G, 0>), dim3(B), dim3(64 * nw), lds, s, a);               \
     }
     UPD_CASE(3, 1) UPD_CASE(4, 0) UPD_CASE(5, 2) UPD_CASE(6, 0) UPD_CASE(6, 2) UPD_CASE(8, 0) UPD_CASE(9, 3)

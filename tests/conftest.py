@@ -48,3 +48,12 @@ def tinybig_pack():
     from oracle.build_model import build
     pack, *_ = build("tinybig", workers=1, verbose=False)
     return pack
+
+
+@pytest.fixture(scope="session")
+def tinyhuge_pack():
+    """48x48 grid, 8x8 subdomains, latents (12, 6), 192 constraints: the Schur system exceeds
+    the LDS a workgroup holds."""
+    from oracle.build_model import build
+    pack, *_ = build("tinyhuge", workers=1, verbose=False)
+    return pack

@@ -88,6 +88,27 @@ def test_big_kkt_short_solve(dr, big):
         assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-7
 
 
+def test_huge_kkt_step(dr, tinyhuge_pack):
+    """One SQP step with 192 constraints: the Schur system is factored in global scratch."""
+    print("[case tinyhuge]", flush=True)
+    gm, om = dr.Model(tinyhuge_pack), load_pack(tinyhuge_pack)
+    assert gm.n_C == 192
+    B = 3
+    mus = si.heldout_mu(B, 43)
+    xh = si.normal((B, gm.n_D), seed=44, scale=0.3)
+    lam = si.normal((B, gm.n_C), seed=45, scale=0.01)
+    ws = dr.Workspace(gm, B)
+    o = dr.opts(precision=dr.PREC_FP64, max_backtracks=20)
+    x1, l1, fn, st = (t.cpu().numpy() for t in dr.sqp_step(gm, ws, mus, xh, lam, o))
+    for b in range(B):
+        xr, lr, _, fr, sr, _, _ = sqp_step(om, mus[b], xh[b], lam[b], SQPOptions(max_backtracks=20))
+        assert int(st[b]) == (1 if sr == -1 else sr)
+        # Gauss-Newton blocks of this briefly trained model have condition numbers near 1e5
+        assert relerr(x1[b], xr) <= 1e-9
+        assert relerr(l1[b], lr) <= 1e-7
+        assert abs(fn[b] - fr) <= 1e-10 * max(1.0, fr)
+
+
 @pytest.mark.parametrize("tile", [(8, 4, 4), (64, 7, 16), (13, 40, 300)])
 def test_tiles_change_schedule_only(dr, tile, tinymix_pack, cfg0_pack):
     """Other work-item shapes: decoded rows are bitwise the same, residual and constraint
