@@ -598,6 +598,8 @@ struct UpdArgs {
     const int* n_live;
     double* gscr;          // per-slot scratch of the big KKT arrays when they exceed LDS
     long long gstride;
+    int sdc;               // subdomains per LDS-staged chunk of the Schur assembly (0: not staged)
+    int stage_off;         // LDS offset (doubles) of the staging area
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -629,7 +631,8 @@ __device__ __forceinline__ int packed_idx(int i, int j, int n) {   // i <= j, up
 // a per-slot area of global scratch, the Schur system kept in LDS while it fits (GB = 1) or
 // in the scratch too (GB = 2).
 struct UpdLds {
-    int lam, c, sl, red, small;      // small part: lam [nC], c [nC], s_lambda [nC], reduction [16]
+    int lam, c, sl, red, u, small;   // small part: lam [nC], c [nC], s_lambda [nC], reduction [16],
+                                     // Ehat_i^T v per subdomain [n_sub][mg]
     int E, P, q, rho, X, S, big;     // big part, relative to its base
 };
 __host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int MG) {
@@ -639,7 +642,8 @@ __host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int
     L.c = L.lam + nc;
     L.sl = L.c + nc;
     L.red = L.sl + nc;
-    L.small = L.red + 16;
+    L.u = L.red + 16;
+    L.small = L.u + n_sub * mg;
     L.E = 0;                                 // [n_sub][nC][mg]  Ehat_i
     L.P = L.E + n_sub * nC * mg;             // [n_sub][nC][mg]  Ehat_i (W_i)_Gamma
     L.q = L.P + n_sub * nC * mg;             // [n_sub][nC]      Ehat_i (t_i)_Gamma
@@ -652,12 +656,13 @@ __host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int
 constexpr int UPD_LDS_DOUBLES = 8192;        // 64 KiB: everything in LDS up to this size
 constexpr int UPD_LDS_MAX_DOUBLES = 19968;   // 156 KiB of the 160 KiB a workgroup may hold
 
-// Dense n x n system [M | r] (in LDS, row stride n + 1) solved by one wave with row i in
-// lane i, held in registers: Gaussian elimination with partial pivoting in which the pivot
-// row is broadcast lane to lane and never moved (the pivot order is recorded), then back
-// substitution in reverse pivot order.  The solution goes to x (LDS, written by lane 0).
-// Sizes n <= NCP are padded with identity rows and columns.  Returns false if a pivot is
-// zero or not finite.
+// Symmetric positive definite n x n system [M | r] (row stride n + 1; the Schur complement of
+// the KKT matrix, or the normal equations of the initial multiplier) solved by one wave with
+// row i in lane i, held in registers: Gaussian elimination without pivoting (stable for such
+// matrices), the pivot row broadcast lane to lane, then back substitution.  The solution goes
+// to x (LDS, written by lane 0).  Columns are indexed statically (NCP >= n), steps at run time,
+// so that the register footprint stays one row per lane.  Returns false if a pivot is not
+// positive (the matrix is not positive definite) or not finite.
 template <int NCP>
 __device__ bool wave_lu_reg(const double* M, int n, double* x, int lane) {
     const int ld = n + 1;
@@ -665,127 +670,103 @@ __device__ bool wave_lu_reg(const double* M, int n, double* x, int lane) {
 #pragma unroll
     for (int c = 0; c < NCP; ++c) row[c] = (lane < n && c < n) ? M[lane * ld + c] : (lane == c ? 1.0 : 0.0);
     row[NCP] = lane < n ? M[lane * ld + n] : 0.0;
-    bool used = lane >= NCP;
     bool ok = true;
-    int pk[NCP];
+    for (int k = 0; k < n; ++k) {
+        double rk = 0.0;
 #pragma unroll
-    for (int k = 0; k < NCP; ++k) {
-        double best = used ? -1.0 : fabs(row[k]);
-        int bi = lane;
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        const int p = __builtin_amdgcn_readfirstlane(bi);
-        pk[k] = p;
-        if (!(best > 0.0) || !isfinite(best)) ok = false;
-        const double pv = lane_bcast(row[k], p);
-        const double f = (!used && lane != p) ? row[k] / pv : 0.0;
-        used = used || lane == p;
+        for (int c = 0; c < NCP; ++c)
+            if (c == k) rk = row[c];
+        const double pv = lane_bcast(rk, k);
+        if (!(pv > 0.0) || !isfinite(pv)) ok = false;
+        const double f = lane > k ? rk / pv : 0.0;
 #pragma unroll
-        for (int c = k + 1; c <= NCP; ++c) row[c] -= f * lane_bcast(row[c], p);
+        for (int c = 0; c <= NCP; ++c)
+            if (c > k) row[c] -= f * lane_bcast(row[c], k);
     }
-    // Lanes pivoted after step k hold stale column-k entries, but their right-hand sides are
-    // no longer read once step k is reached.
     double r = row[NCP];
+    for (int k = n - 1; k >= 0; --k) {
+        double rk = 0.0;
 #pragma unroll
-    for (int k = NCP - 1; k >= 0; --k) {
-        const int p = pk[k];
-        const double xk = lane_bcast(r, p) / lane_bcast(row[k], p);
-        if (k < n && lane == 0) x[k] = xk;
-        r -= row[k] * xk;
+        for (int c = 0; c < NCP; ++c)
+            if (c == k) rk = row[c];
+        const double xk = lane_bcast(r, k) / lane_bcast(rk, k);
+        if (lane == 0) x[k] = xk;
+        if (lane < k) r -= rk * xk;
     }
     return ok;
 }
 
-__device__ __noinline__ bool wave_lu_solve(const double* M, int n, double* x, int lane) {
+__device__ bool wave_lu_solve(const double* M, int n, double* x, int lane) {
     if (n <= 8) return wave_lu_reg<8>(M, n, x, lane);
     if (n <= 16) return wave_lu_reg<16>(M, n, x, lane);
     if (n <= 32) return wave_lu_reg<32>(M, n, x, lane);
     return wave_lu_reg<64>(M, n, x, lane);
 }
 
-// Systems larger than a wave (64 < n <= 256): Gaussian elimination with partial pivoting over
-// the whole workgroup.  Rows are not moved: perm (LDS, n entries) holds the pivot order.  Per
-// step, wave 0 picks the pivot among the remaining rows (lowest position on ties) and the
-// workgroup applies the rank-1 update to the trailing block, one entry per thread: two
-// barriers per step.  Wave 0 then back-substitutes alone (rows in its lanes, no barriers).
-// M (row stride n + 1, right-hand side in column n) may be in LDS or global memory; x (LDS)
-// receives the solution.  okf: LDS flag.  Every thread returns the same value.
-__device__ bool block_lu_solve(double* M, int n, double* x, int* perm, int* okf, int tid, int nth) {
-    const int ld = n + 1, lane = tid & 63, wave = tid >> 6;
-    for (int q = tid; q < n; q += nth) perm[q] = q;
+// Symmetric positive definite systems larger than a wave (64 < n <= 256), M in LDS or global
+// memory: elimination without pivoting over the whole workgroup, rows over waves and columns
+// over lanes with the pivot row in registers, one barrier per step; wave 0 then back-substitutes
+// alone (positions in its lanes, no barriers).  x (LDS) receives the solution; okf: LDS flag.
+// Every thread returns the same value.
+__device__ bool block_lu_solve(double* M, int n, double* x, int* okf, int tid, int nth) {
+    const int ld = n + 1, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nth >> 6;
     if (tid == 0) okf[0] = 1;
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        if (wave == 0) {
-            double best = -1.0;
-            int bi = n;
-            for (int q = k + lane; q < n; q += 64) {
-                const double v = fabs(M[(size_t)perm[q] * ld + k]);
-                if (v > best) { best = v; bi = q; }
+        const double pv = M[(size_t)k * ld + k];
+        if (!(pv > 0.0) || !isfinite(pv)) {
+            if (tid == 0) okf[0] = 0;
+        } else {
+            const double rp = 1.0 / pv;
+            double prow[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int j = k + 1 + lane + 64 * c;
+                prow[c] = j <= n ? M[(size_t)k * ld + j] : 0.0;
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            if (lane == 0) {
-                if (!(best > 0.0) || !isfinite(best)) okf[0] = 0;
-                if (bi < n && bi != k) {
-                    const int t = perm[k];
-                    perm[k] = perm[bi];
-                    perm[bi] = t;
+            for (int i = k + 1 + wave; i < n; i += nw) {
+                const double f = M[(size_t)i * ld + k] * rp;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = k + 1 + lane + 64 * c;
+                    if (j <= n) M[(size_t)i * ld + j] -= f * prow[c];
                 }
             }
         }
         __syncthreads();
-        const int pr = perm[k];
-        const double pv = M[(size_t)pr * ld + k];
-        const int w = n - k;            // columns k+1 .. n (right-hand side included)
-        if (pv != 0.0) {
-            const double rp = 1.0 / pv;
-            for (int e = tid; e < (n - k - 1) * w; e += nth) {
-                const int r = perm[k + 1 + e / w], j = k + 1 + e % w;
-                M[(size_t)r * ld + j] -= (M[(size_t)r * ld + k] * rp) * M[(size_t)pr * ld + j];
-            }
-        }
-        __syncthreads();
     }
-    if (wave == 0) {
-        // lane l holds the right-hand sides of positions l, l + 64, ... (at most 4)
+    const bool ok = okf[0] != 0;
+    if (wave == 0 && ok) {
         double rhs[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int q = lane + 64 * t;
-            rhs[t] = q < n ? M[(size_t)perm[q] * ld + n] : 0.0;
+            rhs[t] = q < n ? M[(size_t)q * ld + n] : 0.0;
         }
         for (int i = n - 1; i >= 0; --i) {
-            const int r = perm[i];
-            const int owner = i & 63, slot = i >> 6;
+            const int slot = i >> 6;
             double ri = 0.0;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 if (t == slot) ri = rhs[t];
-            const double xi = __shfl(ri, owner, 64) / M[(size_t)r * ld + i];
+            const double xi = lane_bcast(ri, i & 63) / M[(size_t)i * ld + i];
             if (lane == 0) x[i] = xi;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int q = lane + 64 * t;
-                if (q < i) rhs[t] -= M[(size_t)perm[q] * ld + i] * xi;
+                if (q < i) rhs[t] -= M[(size_t)q * ld + i] * xi;
             }
         }
     }
     __syncthreads();
-    return okf[0] != 0;
+    return ok;
 }
 
 // S[i][j] = sum over subdomains sd and l < mg of A[sd][i][l] Bm[sd][j][l] for i, j < nC, written
 // to S with row stride ld; A and Bm are [ns][nC][mg] with subdomain strides sdsA, sdsB.  Each thread
 // accumulates a T x T block in registers (2T loads per T^2 FMAs), subdomains in ascending
 // order, so every entry is the same fixed-order sum whatever the block size or thread count.
-template <int T>
+template <int T, int MG>
 __device__ void gram_sum_t(const double* A, size_t sdsA, const double* Bm, size_t sdsB, int ns, int nC, int mg,
                            double* S, int ld, int tid, int nth) {
     const int nT = (nC + T - 1) / T;
@@ -799,18 +780,21 @@ __device__ void gram_sum_t(const double* A, size_t sdsA, const double* Bm, size_
         for (int sd = 0; sd < ns; ++sd) {
             const double* As = A + sd * sdsA;
             const double* Bs = Bm + sd * sdsB;
-            for (int l = 0; l < mg; ++l) {
-                double av[T], bv[T];
+            // all columns of this subdomain's rows are loaded before any product (mg <= MG)
+            double av[T][MG], bv[T][MG];
 #pragma unroll
-                for (int a = 0; a < T; ++a) {
-                    av[a] = i0 + a < nC ? As[(i0 + a) * mg + l] : 0.0;
-                    bv[a] = j0 + a < nC ? Bs[(j0 + a) * mg + l] : 0.0;
+            for (int a = 0; a < T; ++a)
+#pragma unroll
+                for (int l = 0; l < MG; ++l) {
+                    av[a][l] = (i0 + a < nC && l < mg) ? As[(i0 + a) * mg + l] : 0.0;
+                    bv[a][l] = (j0 + a < nC && l < mg) ? Bs[(j0 + a) * mg + l] : 0.0;
                 }
+#pragma unroll
+            for (int l = 0; l < MG; ++l)
 #pragma unroll
                 for (int a = 0; a < T; ++a)
 #pragma unroll
-                    for (int b = 0; b < T; ++b) acc[a][b] += av[a] * bv[b];
-            }
+                    for (int b = 0; b < T; ++b) acc[a][b] += av[a][l] * bv[b][l];
         }
 #pragma unroll
         for (int a = 0; a < T; ++a)
@@ -822,16 +806,206 @@ __device__ void gram_sum_t(const double* A, size_t sdsA, const double* Bm, size_
 
 // Block size by the work per thread: single entries while nC^2 gives each thread few of them,
 // larger register blocks once every thread would otherwise loop over many entries.
+template <int MG>
 __device__ __forceinline__ void gram_sum(const double* A, size_t sdsA, const double* Bm, size_t sdsB, int ns, int nC,
                                          int mg, double* S, int ld, int tid, int nth) {
-    if (nC * nC >= 16 * nth) gram_sum_t<4>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
-    else if (nC * nC >= 4 * nth) gram_sum_t<2>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
-    else gram_sum_t<1>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
+    if (nC * nC >= 16 * nth) gram_sum_t<4, MG>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
+    else if (nC * nC >= 4 * nth) gram_sum_t<2, MG>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
+    else gram_sum_t<1, MG>(A, sdsA, Bm, sdsB, ns, nC, mg, S, ld, tid, nth);
+}
+
+// The same sums for arrays in global memory, staged through LDS: chunks of sdc subdomains of A
+// and Bm are copied to stage as [sdc * mg][nC] (one (subdomain, row) per thread, its mg <= MG
+// contiguous entries; the next chunk's entries are loaded into registers while the current
+// chunk's products run), then each thread adds the chunk's products into its own tiles of the
+// upper triangle (tile row <= tile column), at most two 4 x 4 tiles per thread held in
+// registers across the chunks; the lower triangle is mirrored at the end, so S is exactly
+// symmetric (A Bm^T is symmetric when A_sd = Bm_sd W_sd with symmetric W_sd).  Needs
+// (nC / 4 rounded up)^2 / 2 tiles <= 2 nth and sdc nC <= nth.  Every thread must call it (it
+// holds barriers).
+template <int MG>
+__device__ void gram_sum_staged(const double* A, size_t sdsA, const double* Bm, size_t sdsB, int ns, int nC, int mg,
+                                double* S, int ld, double* stage, int sdc, int tid, int nth) {
+    const int nT = (nC + 3) >> 2;
+    const int ntile = nT * (nT + 1) / 2;
+    int ti[2], tj[2];
+    bool own[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        int t = tid + q * nth;
+        own[q] = t < ntile;
+        // t -> (row r, column c >= r) of the upper triangle, row by row
+        int r = 0;
+        while (own[q] && t >= nT - r) {
+            t -= nT - r;
+            ++r;
+        }
+        ti[q] = r * 4;
+        tj[q] = (r + t) * 4;
+    }
+    double acc[2][4][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[q][a][b] = 0.0;
+    double* sA = stage;
+    double* sB = stage + (size_t)sdc * mg * nC;
+    // this thread's (subdomain in chunk, row) of the copy
+    const int cd = tid / nC, cj = tid - cd * nC;
+    double pa[MG], pb[MG];
+    auto fetch = [&](int s0) {
+        const bool on = cd < sdc && s0 + cd < ns;
+#pragma unroll
+        for (int l = 0; l < MG; ++l) {
+            pa[l] = (on && l < mg) ? A[(s0 + cd) * sdsA + cj * mg + l] : 0.0;
+            pb[l] = (on && l < mg) ? Bm[(s0 + cd) * sdsB + cj * mg + l] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int s0 = 0; s0 < ns; s0 += sdc) {
+        const int nsd = min(sdc, ns - s0), kc = nsd * mg;
+        __syncthreads();   // the previous chunk's products are done
+        if (cd < nsd)
+#pragma unroll
+            for (int l = 0; l < MG; ++l)
+                if (l < mg) {
+                    sA[(cd * mg + l) * nC + cj] = pa[l];
+                    sB[(cd * mg + l) * nC + cj] = pb[l];
+                }
+        __syncthreads();
+        if (s0 + sdc < ns) fetch(s0 + sdc);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (!own[q]) continue;
+            for (int k = 0; k < kc; ++k) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    av[a] = ti[q] + a < nC ? sA[k * nC + ti[q] + a] : 0.0;
+                    bv[a] = tj[q] + a < nC ? sB[k * nC + tj[q] + a] : 0.0;
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[q][a][b] += av[a] * bv[b];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (!own[q]) continue;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = ti[q] + a, j = tj[q] + b;
+                if (i < nC && j < nC && i <= j) {
+                    S[i * ld + j] = acc[q][a][b];
+                    S[j * ld + i] = acc[q][a][b];
+                }
+            }
+    }
+}
+
+// u[sd][l] = sum_j Ehat_sd[j][l] v[j] for l < n_sd^Gamma (0 for l up to mg), one (sd, l) per
+// thread, j ascending.
+__device__ void et_vec(const double* Es, size_t esds, int ns, int nC, int mg, const int* n_ga, const double* v,
+                       double* u, int tid, int nth) {
+    for (int t = tid; t < ns * mg; t += nth) {
+        const int sd = t / mg, l = t % mg;
+        double acc = 0.0;
+        if (l < n_ga[sd]) {
+            const double* E = Es + sd * esds + l;
+#pragma unroll 8
+            for (int jj = 0; jj < nC; ++jj) acc += E[jj * mg] * v[jj];
+        }
+        u[t] = acc;
+    }
+}
+
+// The same for 64 < n <= 128 and n + 1 <= CWM * waves with the augmented matrix in registers:
+// wave w holds columns [w CW, (w + 1) CW) of every row (rows lane and lane + 64).  At step k the
+// wave owning column k forms the multipliers M[r][k] / M[k][k] of the rows below and publishes
+// them through a double-buffered LDS array; every wave then updates its columns with the
+// pivot row taken from its own registers.  One barrier per step.  The factors are written back
+// to M (LDS or global) and wave 0 back-substitutes.  fbuf: 256 doubles of LDS; sh: 1 int.
+template <int CWM>
+__device__ bool block_lu_reg(double* M, int n, double* x, double* fbuf, int* sh, int tid, int nth) {
+    const int ld = n + 1, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nth >> 6;
+    const int CW = (n + 1 + nw - 1) / nw;
+    const int jb = wave * CW;
+    double rw0[CWM], rw1[CWM];
+#pragma unroll
+    for (int c = 0; c < CWM; ++c) {
+        const int j = jb + c;
+        const bool cj = c < CW && j <= n;
+        rw0[c] = (cj && lane < n) ? M[(size_t)lane * ld + j] : 0.0;
+        rw1[c] = (cj && lane + 64 < n) ? M[(size_t)(lane + 64) * ld + j] : 0.0;
+    }
+    if (tid == 0) sh[0] = 1;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const int wk = k / CW, ck = k - wk * CW;
+        double* fb = fbuf + (k & 1) * 128;
+        const int pl = k & 63;
+        const bool hi = k >= 64;
+        if (wave == wk) {
+            double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < CWM; ++c)
+                if (c == ck) { v0 = rw0[c]; v1 = rw1[c]; }
+            const double pv = lane_bcast(hi ? v1 : v0, pl);
+            const bool pok = pv > 0.0 && isfinite(pv);
+            const double rp = pok ? 1.0 / pv : 0.0;
+            fb[lane] = lane > k ? v0 * rp : 0.0;
+            fb[lane + 64] = lane + 64 > k ? v1 * rp : 0.0;
+            if (lane == 0 && !pok) sh[0] = 0;
+        }
+        __syncthreads();
+        const double f0 = fb[lane], f1 = fb[lane + 64];
+#pragma unroll
+        for (int c = 0; c < CWM; ++c) {
+            const int j = jb + c;
+            if (c < CW && j > k && j <= n) {
+                const double pr = lane_bcast(hi ? rw1[c] : rw0[c], pl);
+                rw0[c] -= f0 * pr;
+                rw1[c] -= f1 * pr;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CWM; ++c) {
+        const int j = jb + c;
+        if (c < CW && j <= n) {
+            if (lane < n) M[(size_t)lane * ld + j] = rw0[c];
+            if (lane + 64 < n) M[(size_t)(lane + 64) * ld + j] = rw1[c];
+        }
+    }
+    __syncthreads();
+    const bool ok = sh[0] != 0;
+    if (wave == 0 && ok) {
+        double rhs0 = lane < n ? M[(size_t)lane * ld + n] : 0.0;
+        double rhs1 = lane + 64 < n ? M[(size_t)(lane + 64) * ld + n] : 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+            const double ri = lane_bcast(i >= 64 ? rhs1 : rhs0, i & 63);
+            const double xi = ri / M[(size_t)i * ld + i];
+            if (lane == 0) x[i] = xi;
+            if (lane < i) rhs0 -= M[(size_t)lane * ld + i] * xi;
+            if (lane + 64 < i) rhs1 -= M[(size_t)(lane + 64) * ld + i] * xi;
+        }
+    }
+    __syncthreads();
+    return ok;
 }
 
 // Solve [M | r] with every thread of the workgroup calling: one wave when n <= 64, else the
 // workgroup.  The result is valid for all threads after the call.
-__device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, int* perm, int* okf, int tid, int nth) {
+__device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, int* okf, double* fbuf, int tid, int nth) {
+    constexpr int CWM = 17;
+    if (n > 64 && n <= 128 && n + 1 <= CWM * (nth >> 6)) return block_lu_reg<CWM>(M, n, x, fbuf, okf, tid, nth);
     if (n <= 64) {
         if (tid == 0) okf[0] = 1;
         __syncthreads();
@@ -842,7 +1016,7 @@ __device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, int* perm, i
         __syncthreads();
         return okf[0] != 0;
     }
-    return block_lu_solve(M, n, x, perm, okf, tid, nth);
+    return block_lu_solve(M, n, x, okf, tid, nth);
 }
 
 // ------------------------------------------------------------------------------------
@@ -863,7 +1037,8 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* sm = reinterpret_cast<double*>(smem_raw);
     __shared__ int flag_bad;
-    __shared__ int lu_perm[256], lu_ok[1];
+    __shared__ int lu_ok[1];
+    __shared__ double lu_f[256];
     const int slot = blockIdx.x;
     const int nl = live_count(a.n_live, a.B);
     if (slot >= nl) return;
@@ -877,6 +1052,8 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     double* c_s = sm + L.c;
     double* sl_s = sm + L.sl;
     double* red = sm + L.red;
+    double* us = sm + L.u;
+    constexpr int MGS = MG > 0 ? MG : 1;      // mg = max(1, max_i n_i^Gamma) <= MGS
     double* big = GB ? a.gscr + (size_t)slot * a.gstride : sm + L.small;
     const double* rb = a.RB + (size_t)slot * a.RS;
     // E_hat blocks: copied into LDS with everything else (GB = 0), else read where the reduction
@@ -911,22 +1088,38 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     const bool ls_start = S.phase == PH_ZERO || (S.phase == PH_INIT && !(S.flags & SF_LAMFIX));
     if (ls_start && !a.lam_given && nC > 0) {
         // (entries k >= n_i^Gamma of each Ehat_i row are zero)
-        gram_sum(Es, esds, Es, esds, ns, nC, mg, Sm, ld, tid, nth);
+        if (GB && a.sdc > 0)
+            gram_sum_staged<MGS>(Es, esds, Es, esds, ns, nC, mg, Sm, ld, sm + a.stage_off, a.sdc, tid, nth);
+        else
+            gram_sum<MGS>(Es, esds, Es, esds, ns, nC, mg, Sm, ld, tid, nth);
         for (int i = tid; i < nC; i += nth) {
             double s = 0.0;
             for (int sd = 0; sd < ns; ++sd) {
                 const int m = a.n_ga[sd], no = a.n_om[sd];
                 const double* E = Es + sd * esds;
-                for (int k = 0; k < m; ++k) s -= E[i * mg + k] * gv(sd, no + k);
+                double ev[MGS], gk[MGS];
+#pragma unroll
+                for (int k = 0; k < MGS; ++k) {
+                    ev[k] = k < m ? E[i * mg + k] : 0.0;
+                    gk[k] = k < m ? gv(sd, no + k) : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < MGS; ++k)
+                    if (k < m) s -= ev[k] * gk[k];
             }
             Sm[i * ld + nC] = s;
         }
         __syncthreads();
-        kkt_lu(Sm, nC, lam_s, lu_perm, lu_ok, tid, nth);
+        kkt_lu(Sm, nC, lam_s, lu_ok, lu_f, tid, nth);
         __syncthreads();
     }
 
-    // ---- merit at the trial point: phi = 0.5 (sum_i ||rho_i||^2 + ||c||^2), rho_i kept ----
+    // ---- merit at the trial point: phi = 0.5 (sum_i ||rho_i||^2 + ||c||^2), rho_i kept;
+    //      rho_i^Gamma = g_i^Gamma + Ehat_i^T lambda ----
+    if (nC > 0) {
+        et_vec(Es, esds, ns, nC, mg, a.n_ga, lam_s, us, tid, nth);
+        __syncthreads();
+    }
     {
         double acc = 0.0;
         for (int e = tid; e < ns * NN; e += nth) {
@@ -935,10 +1128,7 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
             double v = 0.0;
             if (r < NNi) {
                 v = gv(sd, r);
-                if (r >= no) {
-                    const double* E = Es + sd * esds + (r - no);
-                    for (int jj = 0; jj < nC; ++jj) v += E[jj * mg] * lam_s[jj];
-                }
+                if (r >= no && nC > 0) v += us[sd * mg + (r - no)];
             }
             rho[e] = v;
             acc += v * v;
@@ -1064,28 +1254,36 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         for (int l = 0; l < MG; ++l) A[NN + l] = (l < ng && lane == no + l) ? 1.0 : 0.0;
         A[NN + MG] = (real_row && lane < NN) ? rho[sd * NN + lane] : 0.0;
         // forward elimination without pivoting (H_i is symmetric positive definite; a
-        // non-positive pivot marks the block as not positive definite)
+        // non-positive pivot marks the block as not positive definite).  Steps run to NNi: the
+        // identity padding beyond it changes nothing.
         bool bad = false;
+        for (int k = 0; k < NNi; ++k) {
+            double Ak = 0.0;
 #pragma unroll
-        for (int k = 0; k < NN; ++k) {
-            const double piv = lane_bcast(A[k], k);
-            if (k < NNi && (!(piv > 0.0) || !isfinite(piv))) bad = true;
-            const double f = (lane > k) ? A[k] / piv : 0.0;
+            for (int c = 0; c < NN; ++c)
+                if (c == k) Ak = A[c];
+            const double piv = lane_bcast(Ak, k);
+            if (!(piv > 0.0) || !isfinite(piv)) bad = true;
+            const double f = (lane > k) ? Ak / piv : 0.0;
 #pragma unroll
-            for (int c = k + 1; c < NA; ++c) A[c] -= f * lane_bcast(A[c], k);
+            for (int c = 0; c < NA; ++c)
+                if (c > k) A[c] -= f * lane_bcast(A[c], k);
         }
         // back substitution, column-oriented: x_k = A[k][rhs] / A[k][k], then rows above
         double Xr[MG + 1];
 #pragma unroll
         for (int l = 0; l <= MG; ++l) Xr[l] = 0.0;
+        for (int k = NNi - 1; k >= 0; --k) {
+            double Ak = 0.0;
 #pragma unroll
-        for (int k = NN - 1; k >= 0; --k) {
-            const double rdk = 1.0 / lane_bcast(A[k], k);
+            for (int c = 0; c < NN; ++c)
+                if (c == k) Ak = A[c];
+            const double rdk = 1.0 / lane_bcast(Ak, k);
 #pragma unroll
             for (int l = 0; l <= MG; ++l) {
                 const double xk = lane_bcast(A[NN + l], k) * rdk;
                 if (lane == k) Xr[l] = xk;
-                if (lane < k) A[NN + l] -= A[k] * xk;
+                if (lane < k) A[NN + l] -= Ak * xk;
             }
         }
         if (bad && lane == 0) flag_bad = 1;
@@ -1096,15 +1294,16 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         const double* E = Es + sd * esds;
         for (int j0 = 0; j0 < nC; j0 += 64) {
             const int jj = j0 + lane;
-            double P[MG + 1];
+            double P[MG + 1], ev[MG > 0 ? MG : 1];
 #pragma unroll
             for (int l = 0; l <= MG; ++l) P[l] = 0.0;
 #pragma unroll
+            for (int k = 0; k < MG; ++k) ev[k] = (k < ng && jj < nC) ? E[jj * mg + k] : 0.0;   // loads first
+#pragma unroll
             for (int k = 0; k < MG; ++k) {
                 if (k < ng) {
-                    const double e = jj < nC ? E[jj * mg + k] : 0.0;
 #pragma unroll
-                    for (int l = 0; l <= MG; ++l) P[l] += e * lane_bcast(Xr[l], no + k);
+                    for (int l = 0; l <= MG; ++l) P[l] += ev[k] * lane_bcast(Xr[l], no + k);
                 }
             }
             if (jj < nC) {
@@ -1127,14 +1326,18 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     double* stp = a.step + (size_t)b * (nD + nC);
     if (nC > 0) {
         // [S | c - q] with S = sum_i P_i Ehat_i^T, summed over subdomains in a fixed order
-        gram_sum(Ps, (size_t)nC * mg, Es, esds, ns, nC, mg, Sm, ld, tid, nth);
+        if (GB && a.sdc > 0)
+            gram_sum_staged<MGS>(Ps, (size_t)nC * mg, Es, esds, ns, nC, mg, Sm, ld, sm + a.stage_off, a.sdc, tid,
+                                 nth);
+        else
+            gram_sum<MGS>(Ps, (size_t)nC * mg, Es, esds, ns, nC, mg, Sm, ld, tid, nth);
         for (int i = tid; i < nC; i += nth) {
             double s = 0.0;
             for (int sd = 0; sd < ns; ++sd) s += qs[(size_t)sd * nC + i];
             Sm[i * ld + nC] = c_s[i] - s;
         }
         __syncthreads();
-        if (!kkt_lu(Sm, nC, sl_s, lu_perm, lu_ok, tid, nth) && tid == 0) flag_bad = 1;
+        if (!kkt_lu(Sm, nC, sl_s, lu_ok, lu_f, tid, nth) && tid == 0) flag_bad = 1;
         __syncthreads();
         if (flag_bad) {
             if (tid == 0) {
@@ -1146,18 +1349,17 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         }
     }
     // s_i = -(t_i + W_i u_i),  u_i = Ehat_i^T s_lambda
+    if (nC > 0) {
+        et_vec(Es, esds, ns, nC, mg, a.n_ga, sl_s, us, tid, nth);
+        __syncthreads();
+    }
     for (int e = tid; e < ns * NN; e += nth) {
         const int sd = e / NN, r = e % NN;
         const int ng = a.n_ga[sd], NNi = a.n_om[sd] + ng;
         if (r >= NNi) continue;
         const double* X = Xs + ((size_t)sd * NN + r) * (MG + 1);
-        const double* E = Es + sd * esds;
         double s = X[MG];
-        for (int l = 0; l < ng; ++l) {
-            double u = 0.0;
-            for (int jj = 0; jj < nC; ++jj) u += E[jj * mg + l] * sl_s[jj];
-            s += X[l] * u;
-        }
+        for (int l = 0; l < ng; ++l) s += X[l] * us[sd * mg + l];
         stp[a.xoff[sd] + r] = -s;
     }
     for (int jj = tid; jj < nC; jj += nth) stp[nD + jj] = sl_s[jj];
@@ -1675,11 +1877,23 @@ static int launch_update(const ddrom_model* m, const ddrom_workspace* ws, const 
         set_error("workspace lacks KKT scratch");
         return DDROM_EINVAL;
     }
-    const size_t lds = (size_t)lds_doubles * sizeof(double);
     const int nw = std::max(1, std::min(8, m->n_sub));
     UpdArgs a = ua;
     a.gscr = ws->kkt_scr;
     a.gstride = ws->kkt_stride;
+    // Schur assembly staged through the LDS left over (at most two upper-triangle tiles per thread)
+    a.sdc = 0;
+    a.stage_off = (int)lds_doubles;
+    if (GB && m->n_C > 0) {
+        const int nT = (m->n_C + 3) / 4, mg = std::max(1, m->mmax);
+        const long long per_sd = 2LL * mg * m->n_C;
+        const long long room = UPD_LDS_MAX_DOUBLES - lds_doubles;
+        if (nT * (nT + 1) / 2 <= 2 * 64 * nw && room >= per_sd && m->n_C <= 64 * nw) {
+            a.sdc = (int)std::min<long long>({(long long)m->n_sub, room / per_sd, (long long)(64 * nw / m->n_C)});
+            lds_doubles += (long long)a.sdc * per_sd;
+        }
+    }
+    const size_t lds = (size_t)lds_doubles * sizeof(double);
 #define UPD_CASE(A, G)                                                                                   \
     if (NN == A && MG == G) {                                                                            \
         if (GB == 2) hipLaunchKernelGGL((k_update<A, G, 2>), dim3(B), dim3(64 * nw), lds, s, a);       \
