@@ -36,6 +36,25 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6  # one FP32 FMA per lane per clock: 256 CU x 4 
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the interior-decoder timing launch (k_decode<float, 8, 0, 4, 1, 0>, B = 512), from two
+# counter runs of `bench.py --roofline-only` (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per
+# dispatch, mean of 20), each scaled by what the same counter reads for a 256 MiB device copy in the
+# same run (FETCH_SIZE 131083.5 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  Valid only for the
+# decoder source it was measured on (hash below); otherwise traffic is reported as null.
+DECODE_COUNTERS = dict(fetch_kib=9531.3, write_kib=288288.0, fetch_scale=262144.0 / 131083.5, write_scale=1.0,
+                       source_sha1="7920ca569ad7ff87",
+                       profile="profiles/k_decode_f32_burgers240_4x4_b512.md")
+
+
+def decoder_source_sha1():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2305_15163_amd", "csrc", "kernels.hip")) as f:
+        s = f.read()
+    i = s.index("template <typename T, int NL, int ACT, int WAVES, int TAG, int VO = 0>\n__global__")
+    j = s.index("\n}\n", i) + 3
+    return hashlib.sha1(s[i:j].encode()).hexdigest()[:16]
+
+
 CONFIGS = {
     "cfg1": dict(batch=512, seed=1, precision=1, tol_rel=1e-6, stall_tol=1e-5, max_iter=60,
                  workload="Burgers 240x240, 4x4 subdomains, latent (8,4), width 2x, band 9, HR 10%, "
@@ -137,6 +156,51 @@ def uneven_leg(a, torch, dr):
             "tiles_from": "work-item shape search (ddrom_autotune), table paper_2305_15163_amd/tiles.json"}
 
 
+AE_SHAPES = (("interior", 28322, 8), ("interface", 1912, 4))   # N, latent: the largest 120x120-subdomain AEs
+
+
+def ae_training_leg(a, torch, dr, si):
+    """GPU autoencoder training steps at the 480x480, 4x4 workload's largest subdomain shapes
+    (interior N = 28322, latent 8; interface N = 1912, latent 4), width 2N, band 9, minibatch 64,
+    BF16 matrix-core products with FP32 accumulation, FP32 masters and Adam.  Synthetic
+    snapshots in [-1, 1].  Per step: FLOPs = 2 B (4 nnz + 6 n w) (forward and backward of the two
+    band layers and the two dense layers); algorithmic bytes = the minibatch read twice
+    (input and target, FP32) + 36 bytes per parameter (BF16 weights read in the forward and
+    backward passes: 4; FP32 gradient written and read: 8; Adam's FP32 master, m and v read and
+    written: 24)."""
+    from paper_2305_15163_amd.train_ae import glorot_init
+    B, out = 64, []
+    for name, N, n in AE_SHAPES:
+        b_, s_ = 9, 2
+        tr = dr.AETrainer(N, n, b_, s_, 0, B, glorot_init(N, n, b_, s_, 3))
+        X = torch.as_tensor(si.uniform((256, N), -1, 1, 5).astype(np.float32), device="cuda")
+        sc = torch.ones(N, device="cuda")
+        rows = [torch.as_tensor(si.rng(k).permutation(256)[:B].astype(np.int32), device="cuda") for k in range(8)]
+        for k in range(5):
+            tr.step(X, rows[k % 8], sc)
+        torch.cuda.synchronize()
+        K = 50
+        t0 = time.perf_counter()
+        for k in range(K):
+            tr.step(X, rows[k % 8], sc)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / K
+        cols, valid = dr.ddrom.band_slots(N, b_, s_)
+        nnz, w = int(valid.sum()), N * s_
+        n_par = int(tr.n_params)
+        flops = 2.0 * B * (4 * nnz + 6 * n * w)
+        bytes_ = 2.0 * B * N * 4 + 36.0 * n_par
+        out.append({"autoencoder": name, "N": N, "latent": n, "width": w, "parameters": n_par, "batch": B,
+                    "ms_per_step": 1e3 * dt, "samples_per_s": B / dt, "tflops": flops / dt / 1e12,
+                    "algorithmic_bytes_per_step": bytes_, "hbm_GBs_if_algorithmic": bytes_ / dt / 1e9,
+                    "frac_of_hbm_peak": bytes_ / dt / 1e9 / PEAK_HBM_GBS})
+        print(f"[bench] ae training {name}: {1e3 * dt:.3f} ms/step", file=sys.stderr, flush=True)
+        del tr, X
+    return {"workload": "480x480, 4x4: one interior and one interface autoencoder of the largest subdomain, "
+                        "width 2N, band 9, minibatch 64, BF16 MFMA + FP32 masters/Adam, synthetic snapshots",
+            "steps_timed": 50, "autoencoders": out}
+
+
 def roofline_only(a, torch, dr, si):
     """The dominant kernel's 20 all-live timing launches of the headline workload, then 5 device
     copies of 256 MiB (torch copy kernel: 256 MiB read and 256 MiB written each), whose byte
@@ -172,6 +236,7 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="parameters for the plain per-solve GPU SQP leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-model uneven batch leg")
     ap.add_argument("--uneven-only", action="store_true", help="run only the three-model uneven batch leg")
+    ap.add_argument("--no-ae", action="store_true", help="skip the autoencoder training leg")
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the dominant kernel's timing launches and a device copy of known size "
                          "(the workload of the hardware-counter runs)")
@@ -268,7 +333,12 @@ def main():
         roof = {"bound": "alu", "kernel": "k_decode<double,...> (interior subnets, all solves live)",
                 "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_VECTOR_TFLOPS}
-    roof["traffic"] = None
+    dc = DECODE_COUNTERS
+    if cfg["precision"] == 1 and a.config == "cfg1" and decoder_source_sha1() == dc["source_sha1"]:
+        roof["traffic"] = 1024.0 * (dc["fetch_kib"] * dc["fetch_scale"] + dc["write_kib"] * dc["write_scale"])
+        roof["traffic_source"] = dc["profile"]
+    else:
+        roof["traffic"] = None
     roof["algorithmic_bytes_per_launch"] = bytes_
     roof["hbm_GBs_if_algorithmic"] = bytes_ / (ms[0] * 1e-3) / 1e9
     roof["ms_per_launch"] = {"decode_interior": ms[0], "decode_interface": ms[1], "residual_gn": ms[2], "constraint": ms[3]}
@@ -312,6 +382,8 @@ def main():
 
     if not a.no_uneven:
         line["uneven_batch"] = uneven_leg(a, torch, dr)
+    if not a.no_ae:
+        line["ae_training"] = ae_training_leg(a, torch, dr, si)
 
     if not a.no_cpu:
         from threadpoolctl import threadpool_limits
