@@ -42,7 +42,7 @@ PEAK_HBM_GBS = 8000.0
 # same run (FETCH_SIZE 131083.5 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  Valid only for the
 # decoder source it was measured on (hash below); otherwise traffic is reported as null.
 DECODE_COUNTERS = dict(fetch_kib=9531.3, write_kib=288288.0, fetch_scale=262144.0 / 131083.5, write_scale=1.0,
-                       source_sha1="7920ca569ad7ff87",
+                       source_sha1="7920ca569ad7ff87", tile=(48, 24, 256),
                        profile="profiles/k_decode_f32_burgers240_4x4_b512.md")
 
 
@@ -205,13 +205,18 @@ def roofline_only(a, torch, dr, si):
     """The dominant kernel's 20 all-live timing launches of the headline workload, then 5 device
     copies of 256 MiB (torch copy kernel: 256 MiB read and 256 MiB written each), whose byte
     counters calibrate FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    from paper_2305_15163_amd import autotune
     cfg = CONFIGS["cfg1"]
     pack = dict(np.load(os.path.join(ROOT, "models", "cfg1.npz"), allow_pickle=False))
     torch.cuda.set_device(0)
-    model = dr.Model(pack)
     B = cfg["batch"]
+    mu_h = si.heldout_mu(B, cfg["seed"])
+    o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"],
+                stall_tol=cfg["stall_tol"])
+    tile = autotune.tiles_for(pack, mu_h, o, path=os.path.join(ROOT, "paper_2305_15163_amd", "tiles.json"))
+    model = dr.Model(pack, tile=tile)
     ws = dr.Workspace(model, B)
-    mu = torch.as_tensor(si.heldout_mu(B, cfg["seed"]), device="cuda")
+    mu = torch.as_tensor(mu_h, device="cuda")
     ms = dr.time_kernels(model, ws, mu, torch.zeros((B, model.n_D), dtype=torch.float64, device="cuda"),
                          precision=cfg["precision"], reps=20)
     n = 64 << 20
@@ -222,6 +227,7 @@ def roofline_only(a, torch, dr, si):
     torch.cuda.synchronize()
     flops, bytes_ = decoder_work(model, B)
     print(json.dumps({"roofline_workload": "cfg1 interior decoder, 20 timing launches (B=512, all live)",
+                      "work_item_shape": list(model.tile),
                       "ms_per_launch": ms, "algorithmic_bytes_per_launch": bytes_, "flops_per_launch": flops,
                       "copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}), flush=True)
 
@@ -267,13 +273,17 @@ def main():
     pack = dict(np.load(path, allow_pickle=False))
     torch.cuda.set_device(0)
     print(f"[bench] loading model {path}", file=sys.stderr, flush=True)
-    model = dr.Model(pack)
     B = cfg["batch"]
-    ws = dr.Workspace(model, B)
     mu_h = si.heldout_mu(B, cfg["seed"])
     mu = torch.as_tensor(mu_h, device="cuda")
     o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"],
                 stall_tol=cfg["stall_tol"])
+    # work-item shapes from the persisted table of measured shapes (measured now when missing)
+    from paper_2305_15163_amd import autotune
+    tile = autotune.tiles_for(pack, mu_h, o, path=os.path.join(ROOT, "paper_2305_15163_amd", "tiles.json"),
+                              verbose=True)
+    model = dr.Model(pack, tile=tile)
+    ws = dr.Workspace(model, B)
     f = dict(dtype=torch.float64, device="cuda")
     out = dict(xhat=torch.empty((B, model.n_D), **f), lam=torch.empty((B, max(1, model.n_C)), **f),
                iters=torch.empty((B,), dtype=torch.int32, device="cuda"),
@@ -334,7 +344,8 @@ def main():
                 "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_VECTOR_TFLOPS}
     dc = DECODE_COUNTERS
-    if cfg["precision"] == 1 and a.config == "cfg1" and decoder_source_sha1() == dc["source_sha1"]:
+    if (cfg["precision"] == 1 and a.config == "cfg1" and decoder_source_sha1() == dc["source_sha1"]
+            and tuple(model.tile) == dc["tile"]):
         roof["traffic"] = 1024.0 * (dc["fetch_kib"] * dc["fetch_scale"] + dc["write_kib"] * dc["write_scale"])
         roof["traffic_source"] = dc["profile"]
     else:
@@ -368,6 +379,7 @@ def main():
         "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if cfg["precision"] == 1 else "f64", "data": "synthetic",
         "config": {"workload": cfg["workload"], "batch": B, "subdomains": model.n_sub, "n_D": model.n_D,
+                   "work_item_shape": list(model.tile),
                    "n_C": model.n_C, "stop": f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
                                              f"or line-search stagnation below {cfg['stall_tol']:g} ||F0||",
                    "start": ("learned proposal, zero-start fallback" if prop is not None else "zero start")},

@@ -656,51 +656,56 @@ __host__ __device__ inline UpdLds upd_lds(int n_sub, int nC, int mg, int NN, int
 constexpr int UPD_LDS_DOUBLES = 8192;        // 64 KiB: everything in LDS up to this size
 constexpr int UPD_LDS_MAX_DOUBLES = 19968;   // 156 KiB of the 160 KiB a workgroup may hold
 
-// Symmetric positive definite n x n system [M | r] (row stride n + 1; the Schur complement of
-// the KKT matrix, or the normal equations of the initial multiplier) solved by one wave with
-// row i in lane i, held in registers: Gaussian elimination without pivoting (stable for such
-// matrices), the pivot row broadcast lane to lane, then back substitution.  The solution goes
-// to x (LDS, written by lane 0).  Columns are indexed statically (NCP >= n), steps at run time,
-// so that the register footprint stays one row per lane.  Returns false if a pivot is not
-// positive (the matrix is not positive definite) or not finite.
-template <int NCP>
-__device__ bool wave_lu_reg(const double* M, int n, double* x, int lane) {
-    const int ld = n + 1;
-    double row[NCP + 1];
-#pragma unroll
-    for (int c = 0; c < NCP; ++c) row[c] = (lane < n && c < n) ? M[lane * ld + c] : (lane == c ? 1.0 : 0.0);
-    row[NCP] = lane < n ? M[lane * ld + n] : 0.0;
-    bool ok = true;
+// One wave's Gauss-Jordan elimination without pivoting of a symmetric positive definite n x n
+// system held row-per-lane in registers (n <= 64; lanes >= n are ignored).  At step k every
+// other row subtracts its multiple of row k, both below and above the diagonal, so no back
+// substitution is needed: the solution is r / pivot.  Each row is shifted left by one register
+// per step, so the current column is always row[0] and every register index is static; the
+// right-hand sides (NR of them) stay in place.  ok is cleared when a pivot is not positive or
+// not finite.  On return r[l] holds the solution for this lane's row.
+template <int NC, int NR>
+__device__ __forceinline__ void wave_gj(double (&row)[NC], double (&r)[NR], int n, int lane, bool& ok) {
+    double diag = 1.0;
     for (int k = 0; k < n; ++k) {
-        double rk = 0.0;
-#pragma unroll
-        for (int c = 0; c < NCP; ++c)
-            if (c == k) rk = row[c];
+        const double rk = row[0];
         const double pv = lane_bcast(rk, k);
         if (!(pv > 0.0) || !isfinite(pv)) ok = false;
-        const double f = lane > k ? rk / pv : 0.0;
+        const double rp = 1.0 / pv;
+        const double f = (lane != k && lane < n) ? rk * rp : 0.0;
+        if (lane == k) diag = rk;
 #pragma unroll
-        for (int c = 0; c <= NCP; ++c)
-            if (c > k) row[c] -= f * lane_bcast(row[c], k);
-    }
-    double r = row[NCP];
-    for (int k = n - 1; k >= 0; --k) {
-        double rk = 0.0;
+        for (int c = 1; c < NC; ++c) row[c - 1] = row[c] - f * lane_bcast(row[c], k);
+        row[NC - 1] = 0.0;
 #pragma unroll
-        for (int c = 0; c < NCP; ++c)
-            if (c == k) rk = row[c];
-        const double xk = lane_bcast(r, k) / lane_bcast(rk, k);
-        if (lane == 0) x[k] = xk;
-        if (lane < k) r -= rk * xk;
+        for (int l = 0; l < NR; ++l) r[l] -= f * lane_bcast(r[l], k);
     }
+    const double rd = 1.0 / diag;
+#pragma unroll
+    for (int l = 0; l < NR; ++l) r[l] = lane < n ? r[l] * rd : 0.0;
+}
+
+// Symmetric positive definite n x n system [M | r] (LDS, row stride n + 1: the Schur complement of
+// the KKT matrix, or the normal equations of the initial multiplier) solved by one wave with
+// wave_gj; the solution goes to x (LDS).  Returns false if a pivot is not positive (the matrix is
+// not positive definite) or not finite.
+template <int NCP>
+__device__ bool wave_spd_reg(const double* M, int n, double* x, int lane) {
+    const int ld = n + 1;
+    double row[NCP], r[1];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) row[c] = (lane < n && c < n) ? M[lane * ld + c] : 0.0;
+    r[0] = lane < n ? M[lane * ld + n] : 0.0;
+    bool ok = true;
+    wave_gj<NCP, 1>(row, r, n, lane, ok);
+    if (lane < n) x[lane] = r[0];
     return ok;
 }
 
-__device__ bool wave_lu_solve(const double* M, int n, double* x, int lane) {
-    if (n <= 8) return wave_lu_reg<8>(M, n, x, lane);
-    if (n <= 16) return wave_lu_reg<16>(M, n, x, lane);
-    if (n <= 32) return wave_lu_reg<32>(M, n, x, lane);
-    return wave_lu_reg<64>(M, n, x, lane);
+__device__ bool wave_spd_solve(const double* M, int n, double* x, int lane) {
+    if (n <= 8) return wave_spd_reg<8>(M, n, x, lane);
+    if (n <= 16) return wave_spd_reg<16>(M, n, x, lane);
+    if (n <= 32) return wave_spd_reg<32>(M, n, x, lane);
+    return wave_spd_reg<64>(M, n, x, lane);
 }
 
 // Symmetric positive definite systems larger than a wave (64 < n <= 256), M in LDS or global
@@ -1010,7 +1015,7 @@ __device__ __forceinline__ bool kkt_lu(double* M, int n, double* x, int* okf, do
         if (tid == 0) okf[0] = 1;
         __syncthreads();
         if ((tid >> 6) == 0) {
-            const bool ok = wave_lu_solve(M, n, x, tid & 63);
+            const bool ok = wave_spd_solve(M, n, x, tid & 63);
             if (!ok && (tid & 63) == 0) okf[0] = 0;
         }
         __syncthreads();
@@ -1253,39 +1258,16 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
 #pragma unroll
         for (int l = 0; l < MG; ++l) A[NN + l] = (l < ng && lane == no + l) ? 1.0 : 0.0;
         A[NN + MG] = (real_row && lane < NN) ? rho[sd * NN + lane] : 0.0;
-        // forward elimination without pivoting (H_i is symmetric positive definite; a
-        // non-positive pivot marks the block as not positive definite).  Steps run to NNi: the
-        // identity padding beyond it changes nothing.
-        bool bad = false;
-        for (int k = 0; k < NNi; ++k) {
-            double Ak = 0.0;
+        // Gauss-Jordan elimination without pivoting (H_i is symmetric positive definite; a
+        // non-positive pivot marks the block as not positive definite) over the NNi real rows
+        double Hr[NN], Xr[MG + 1];
 #pragma unroll
-            for (int c = 0; c < NN; ++c)
-                if (c == k) Ak = A[c];
-            const double piv = lane_bcast(Ak, k);
-            if (!(piv > 0.0) || !isfinite(piv)) bad = true;
-            const double f = (lane > k) ? Ak / piv : 0.0;
+        for (int c = 0; c < NN; ++c) Hr[c] = A[c];
 #pragma unroll
-            for (int c = 0; c < NA; ++c)
-                if (c > k) A[c] -= f * lane_bcast(A[c], k);
-        }
-        // back substitution, column-oriented: x_k = A[k][rhs] / A[k][k], then rows above
-        double Xr[MG + 1];
-#pragma unroll
-        for (int l = 0; l <= MG; ++l) Xr[l] = 0.0;
-        for (int k = NNi - 1; k >= 0; --k) {
-            double Ak = 0.0;
-#pragma unroll
-            for (int c = 0; c < NN; ++c)
-                if (c == k) Ak = A[c];
-            const double rdk = 1.0 / lane_bcast(Ak, k);
-#pragma unroll
-            for (int l = 0; l <= MG; ++l) {
-                const double xk = lane_bcast(A[NN + l], k) * rdk;
-                if (lane == k) Xr[l] = xk;
-                if (lane < k) A[NN + l] -= Ak * xk;
-            }
-        }
+        for (int l = 0; l <= MG; ++l) Xr[l] = A[NN + l];
+        bool okb = true;
+        wave_gj<NN, MG + 1>(Hr, Xr, NNi, lane, okb);
+        const bool bad = !okb;
         if (bad && lane == 0) flag_bad = 1;
         if (lane < NN)
 #pragma unroll
