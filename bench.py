@@ -39,10 +39,10 @@ PEAK_HBM_GBS = 8000.0
 # HBM traffic of the interior-decoder timing launch (k_decode<float, 8, 0, 4, 1, 0>, B = 512), from two
 # counter runs of `bench.py --roofline-only` (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; KiB per
 # dispatch, mean of 20), each scaled by what the same counter reads for a 256 MiB device copy in the
-# same run (FETCH_SIZE 131083.5 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  Valid only for the
-# decoder source it was measured on (hash below); otherwise traffic is reported as null.
-DECODE_COUNTERS = dict(fetch_kib=9531.3, write_kib=288288.0, fetch_scale=262144.0 / 131083.5, write_scale=1.0,
-                       source_sha1="7920ca569ad7ff87", tile=(48, 24, 256),
+# same run (FETCH_SIZE 131084.8 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  Valid only for the
+# decoder source and work-item shape it was measured on; otherwise traffic is reported as null.
+DECODE_COUNTERS = dict(fetch_kib=10881.8, write_kib=288288.0, fetch_scale=262144.0 / 131084.8, write_scale=1.0,
+                       source_sha1="7920ca569ad7ff87", tile=(16, 24, 256),
                        profile="profiles/k_decode_f32_burgers240_4x4_b512.md")
 
 
