@@ -92,17 +92,21 @@ __device__ __forceinline__ void act_fwd(float z, int act, float& a, float& d) {
 __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // ---- dense products:  C[m][n] = sum_k A(m, k) B(k, n),  A(m, k) = A[m sam + k sak] ----
-// One wave per 16 x 16 output tile, four waves per workgroup (2 x 2 tiles).  With split > 1
-// the K range is cut in `split` parts written to C + z M ldc (summed by k_split_sum).
+// One wave per 16 x 16 output tile, four waves per workgroup (2 x 2 tiles, or 1 x 4 with wn).
+// With split > 1 the K range is cut in `split` parts written to C + z M ldc (summed by
+// k_split_sum).
 // EPI 0: store; 1: + bias[m], Z = pre-activation, C = sigma; 2: times sigma'(aux[m][n]).
 template <int EPI>
 __global__ __launch_bounds__(256) void k_dense(int M, int N, int K, const float* __restrict__ A, long long sam,
                                                long long sak, const float* __restrict__ Bm, long long sbk,
                                                long long sbn, float* __restrict__ C, int ldc, int split,
                                                const float* __restrict__ bias, float* __restrict__ Z,
-                                               const float* __restrict__ aux, int act, int x3) {
+                                               const float* __restrict__ aux, int act, int x3, int wn) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m0 = (blockIdx.y * 2 + (wave >> 1)) * 16, n0 = (blockIdx.x * 2 + (wave & 1)) * 16;
+    // wn = 0: the four waves take 2 x 2 tiles (32 x 32 per workgroup); wn = 1: four tiles along N
+    // (16 x 64 per workgroup), for products with at most 16 rows
+    const int m0 = wn ? blockIdx.y * 16 : (blockIdx.y * 2 + (wave >> 1)) * 16;
+    const int n0 = wn ? (blockIdx.x * 4 + wave) * 16 : (blockIdx.x * 2 + (wave & 1)) * 16;
     const int z = blockIdx.z;
     const int kc = (K + split - 1) / split;
     const int kb = z * kc, ke = min(K, kb + kc);
@@ -143,13 +147,21 @@ __global__ __launch_bounds__(256) void k_dense(int M, int N, int K, const float*
     }
 }
 
-// C[e] = sum_z P[z][e] (fixed order)
-__global__ void k_split_sum(const float* __restrict__ P, int split, long long n, float* __restrict__ C) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+// C[e] = sum_z P[z][e]: one workgroup per output, thread t sums z = t, t + 256, ..., then a
+// fixed-order tree in LDS (the same order whatever the data).
+__global__ __launch_bounds__(256) void k_split_sum(const float* __restrict__ P, int split, long long n,
+                                                   float* __restrict__ C) {
+    __shared__ float red[256];
+    const long long e = blockIdx.x;
     float s = 0.f;
-    for (int z = 0; z < split; ++z) s += P[(size_t)z * n + e];
-    C[e] = s;
+    for (int z = threadIdx.x; z < split; z += 256) s += P[(size_t)z * n + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) C[e] = red[0];
 }
 
 // ---- transposed band product:  Z[c][b] = sum_{r,k,t : c = r s + k b s + t} W[r][k][t] A[r][b] ----
@@ -261,13 +273,35 @@ __global__ __launch_bounds__(256) void k_band_grad(int N, int w, int bw, int sw,
     const int r0 = blockIdx.x * 16;
     const int ntile = (15 * sw + bw + 15) / 16;      // column tiles per band window
     const int rm = r0 + (lane & 15), kq = 4 * (lane >> 4);
+    // the rows' operand fragments are the same for every column tile: the first KC minibatch
+    // chunks of 16 stay in registers
+    constexpr int KC = 4;
+    float pa[KC][4];
+#pragma unroll
+    for (int it = 0; it < KC; ++it)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int smp = it * 16 + kq + i;
+            pa[it][i] = (rm < N && smp < B) ? P[(size_t)rm * B + smp] : 0.f;
+        }
     for (int tt = wave; tt < 3 * ntile; tt += 4) {
         const int kb = tt / ntile - 1, ci = tt % ntile;
         const int off = kb * bw * sw;
         const int cc = r0 * sw + off + 16 * ci;
         const int cn = cc + (lane & 15);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        for (int s0 = 0; s0 < B; s0 += 16) {
+#pragma unroll
+        for (int it = 0; it < KC; ++it) {
+            if (it * 16 >= B) break;
+            float b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int smp = it * 16 + kq + i;
+                b[i] = (cn >= 0 && cn < w && smp < B) ? Q[(size_t)cn * B + smp] : 0.f;
+            }
+            acc = mma16(pa[it], b, acc, x3);
+        }
+        for (int s0 = KC * 16; s0 < B; s0 += 16) {
             float a[4], b[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -372,7 +406,9 @@ int ddrom_ae_trainer_create(int N, int n, int b, int s, int activation, int max_
     t->o_b1d = t->o_w1d + w * n;
     t->o_w2d = t->o_b1d + w;
     t->n_params = t->o_w2d + t->n_band;
-    t->split = (int)std::max<long long>(1, std::min<long long>(64, w / 1024));
+    // about 64 K entries per split part of the skinny products with K = w (enough workgroups to
+    // fill the device), at most 256 parts
+    t->split = (int)std::max<long long>(1, std::min<long long>(256, w / 64));
     const size_t pb = (size_t)t->n_params * sizeof(float);
     const size_t Bm = (size_t)max_batch;
     struct A { void** p; size_t bytes; } allocs[] = {
@@ -442,14 +478,17 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
     hipLaunchKernelGGL(k_band_t<1>, dim3(cdiv(w, 16), cdiv(B, 64)), blk, 0, s, N, w, bw, sw, B, P + t->o_w1e, t->Xb,
                        t->ae, P + t->o_b1e, t->ze, (const float*)nullptr, act, t->x3);
     // xh = W2e ae (K = w, split)
-    hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(B, 32), cdiv(n, 32), t->split), blk, 0, s, n, B, w, P + t->o_w2e,
-                       (long long)w, 1LL, t->ae, (long long)B, 1LL, t->kpart, B, t->split, (const float*)nullptr,
-                       (float*)nullptr, (const float*)nullptr, act, t->x3);
-    hipLaunchKernelGGL(k_split_sum, dim3(cdiv((long long)n * B, 256)), blk, 0, s, t->kpart, t->split, (long long)n * B,
-                       t->xh);
+    const int wn = n <= 16;
+    const dim3 sgrid = wn ? dim3(cdiv(B, 64), cdiv(n, 16), t->split) : dim3(cdiv(B, 32), cdiv(n, 32), t->split);
+    hipLaunchKernelGGL(k_dense<0>, sgrid, blk, 0, s, n, B, w, P + t->o_w2e, (long long)w, 1LL, t->ae, (long long)B,
+                       1LL, t->kpart, B, t->split, (const float*)nullptr, (float*)nullptr, (const float*)nullptr, act,
+                       t->x3, wn);
+    hipLaunchKernelGGL(k_split_sum, dim3((unsigned)((long long)n * B)), blk, 0, s, t->kpart, t->split,
+                       (long long)n * B, t->xh);
     // decoder: zd = W1d xh + b1d, ad = sigma(zd)
     hipLaunchKernelGGL(k_dense<1>, dim3(cdiv(B, 32), cdiv(w, 32), 1), blk, 0, s, w, B, n, P + t->o_w1d, (long long)n,
-                       1LL, t->xh, (long long)B, 1LL, t->ad, B, 1, P + t->o_b1d, t->zd, (const float*)nullptr, act, t->x3);
+                       1LL, t->xh, (long long)B, 1LL, t->ad, B, 1, P + t->o_b1d, t->zd, (const float*)nullptr, act,
+                       t->x3, 0);
     // y = D2 ad, loss and dY
     const dim3 lgrid(cdiv(N, 16), cdiv(B, 64));
     hipLaunchKernelGGL(k_band_loss, lgrid, blk, 0, s, N, w, bw, sw, B, P + t->o_w2d, t->ad, t->Xb, scale_d, t->dY,
@@ -465,22 +504,22 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
     // gW1d = dzd xh^T, gb1d = sum_b dzd
     hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(n, 32), cdiv(w, 32), 1), blk, 0, s, w, n, B, t->dzd, (long long)B, 1LL,
                        t->xh, 1LL, (long long)B, G + t->o_w1d, n, 1, (const float*)nullptr, (float*)nullptr,
-                       (const float*)nullptr, act, t->x3);
+                       (const float*)nullptr, act, t->x3, 0);
     hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 256)), blk, 0, s, t->dzd, w, B, G + t->o_b1d);
     // dxh = W1d^T dzd (K = w, split)
-    hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(B, 32), cdiv(n, 32), t->split), blk, 0, s, n, B, w, P + t->o_w1d, 1LL,
-                       (long long)n, t->dzd, (long long)B, 1LL, t->kpart, B, t->split, (const float*)nullptr,
-                       (float*)nullptr, (const float*)nullptr, act, t->x3);
-    hipLaunchKernelGGL(k_split_sum, dim3(cdiv((long long)n * B, 256)), blk, 0, s, t->kpart, t->split, (long long)n * B,
-                       t->dxh);
+    hipLaunchKernelGGL(k_dense<0>, sgrid, blk, 0, s, n, B, w, P + t->o_w1d, 1LL, (long long)n, t->dzd, (long long)B,
+                       1LL, t->kpart, B, t->split, (const float*)nullptr, (float*)nullptr, (const float*)nullptr, act,
+                       t->x3, wn);
+    hipLaunchKernelGGL(k_split_sum, dim3((unsigned)((long long)n * B)), blk, 0, s, t->kpart, t->split,
+                       (long long)n * B, t->dxh);
     // gW2e = dxh ae^T
     hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(w, 32), cdiv(n, 32), 1), blk, 0, s, n, w, B, t->dxh, (long long)B, 1LL,
                        t->ae, 1LL, (long long)B, G + t->o_w2e, w, 1, (const float*)nullptr, (float*)nullptr,
-                       (const float*)nullptr, act, t->x3);
+                       (const float*)nullptr, act, t->x3, 0);
     // dze = (W2e^T dxh) o sigma'(ze)
     hipLaunchKernelGGL(k_dense<2>, dim3(cdiv(B, 32), cdiv(w, 32), 1), blk, 0, s, w, B, n, P + t->o_w2e, 1LL,
                        (long long)w, t->dxh, (long long)B, 1LL, t->dze, B, 1, (const float*)nullptr, (float*)nullptr,
-                       t->ze, act, t->x3);
+                       t->ze, act, t->x3, 0);
     // gW1e[r][k][t] = sum_b x~[r][b] dze[c][b], gb1e = sum_b dze
     hipLaunchKernelGGL(k_band_grad, dim3(cdiv(N, 16)), blk, 0, s, N, w, bw, sw, B, t->Xb, t->dze, G + t->o_w1e, t->x3);
     hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 256)), blk, 0, s, t->dze, w, B, G + t->o_b1e);
