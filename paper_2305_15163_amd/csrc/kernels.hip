@@ -313,9 +313,12 @@ struct NodeLoads {
 template <typename T, int NO, int NG>
 __device__ __forceinline__ void load_node(const int* __restrict__ code, const T* dom, const T* dga, const T* dz,
                                           const double* bcb, int Bp, NodeLoads<T, NO>& L) {
+    int cds[N_SLOTS];   // all codes first: one batch of scalar loads per node
+#pragma unroll
+    for (int t = 0; t < N_SLOTS; ++t) cds[t] = code[t];
 #pragma unroll
     for (int t = 0; t < N_SLOTS; ++t) {
-        const int cd = code[t];
+        const int cd = cds[t];
         L.kind[t] = src_kind(cd);
         const int idx = src_index(cd);
         const T* base = L.kind[t] == SRC_OMEGA ? dom + (size_t)idx * (1 + NO) * Bp
@@ -337,36 +340,41 @@ __device__ __forceinline__ void accumulate_node(const NodeLoads<T, NO>& L, doubl
     double zu[NN], zv[NN];
 #pragma unroll
     for (int e = 0; e < NN; ++e) { zu[e] = 0.0; zv[e] = 0.0; }
+    // a u slot feeds d r_u only, a v slot d r_v only, except the two centre slots, which also
+    // feed the other field's equation (the advection cross terms); zero products are skipped
 #pragma unroll
     for (int t = 0; t < N_SLOTS; ++t) {
-        double a_u, a_v;
-        if (t < 5) { a_u = cu[t]; a_v = (t == S_UC) ? cv[5] : 0.0; }
-        else { a_v = cv[t - 5]; a_u = (t == S_VC) ? cu[5] : 0.0; }
+        const bool us = t < 5;
+        const double a = us ? cu[t] : cv[t - 5];
+        const bool cross = t == S_UC || t == S_VC;
+        const double ac = t == S_UC ? cv[5] : cu[5];
         // the kind is wave-uniform: scalar branches, all loads already issued
         if (L.kind[t] == SRC_OMEGA) {
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
                 const double jk = (double)L.jv[t][k];
-                zu[k] += a_u * jk;
-                zv[k] += a_v * jk;
+                if (us) zu[k] = fma(a, jk, zu[k]); else zv[k] = fma(a, jk, zv[k]);
+                if (cross) { if (us) zv[k] = fma(ac, jk, zv[k]); else zu[k] = fma(ac, jk, zu[k]); }
             }
         } else if (L.kind[t] == SRC_GAMMA) {
 #pragma unroll
             for (int k = 0; k < NG; ++k) {
                 const double jk = (double)L.jv[t][k];
-                zu[NO + k] += a_u * jk;
-                zv[NO + k] += a_v * jk;
+                if (us) zu[NO + k] = fma(a, jk, zu[NO + k]); else zv[NO + k] = fma(a, jk, zv[NO + k]);
+                if (cross) {
+                    if (us) zv[NO + k] = fma(ac, jk, zv[NO + k]); else zu[NO + k] = fma(ac, jk, zu[NO + k]);
+                }
             }
         }
     }
     int e = 0;
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
-        g[i] += zu[i] * ru + zv[i] * rv;
+        g[i] = fma(zv[i], rv, fma(zu[i], ru, g[i]));
 #pragma unroll
-        for (int j = i; j < NN; ++j) H[e++] += zu[i] * zu[j] + zv[i] * zv[j];
+        for (int j = i; j < NN; ++j, ++e) H[e] = fma(zv[i], zv[j], fma(zu[i], zu[j], H[e]));
     }
-    rr += ru * ru + rv * rv;
+    rr = fma(rv, rv, fma(ru, ru, rr));
 }
 
 // One workgroup = a run of sampled nodes of one subdomain x 64 solve slots.  Its four waves
@@ -396,7 +404,9 @@ __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rch
     const ResChunk rc = rchunks[rbase + blockIdx.x];
     const ResSeg rs = rsegs[rc.sd];
     const long long oo = segs[rs.seg_om].out, og = segs[rs.seg_ga].out;
-    const int tid = threadIdx.x, lane = tid & 63, prt = tid >> 6;
+    // the quarter index is wave-uniform: the node codes then come in by scalar loads and the
+    // source-kind branches are scalar, so a node's gathers are issued without waiting
+    const int tid = threadIdx.x, lane = tid & 63, prt = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = j0 + lane;
     const int np = rc.p1 - rc.p0;
     const int pb = rc.p0 + np * prt / 4, pe = rc.p0 + np * (prt + 1) / 4;
