@@ -444,24 +444,33 @@ __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rch
 // ------------------------------------------------------------------------------------
 // Weak compatibility constraint: c_i = C A_i g_i^Gamma, E_i^Gamma = C A_i dg_i^Gamma/dxhat
 // ------------------------------------------------------------------------------------
-// One wave = (subdomain, 8 constraint rows, a run of interface rows) x 64 solve slots;
-// (C A_i)^T is stored row-major with stride ca_ld so the 8 multipliers of an interface row
-// are one contiguous scalar load.  Partial sums over interface-row runs go to separate slots.
+// One workgroup = (subdomain, 8 constraint rows, a run of interface rows) x 64 solve slots.
+// Its four waves take consecutive quarters of the row run (short dependent chains, also when
+// few solves run) and their sums are combined in LDS in a fixed order, so every solve's sums
+// are formed the same way whatever the batch.  (C A_i)^T is stored row-major with stride ca_ld
+// so the 8 multipliers of an interface row are one contiguous scalar load.  Partial sums over
+// interface-row runs go to separate slots.
 template <typename T, int NG>
-__global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, int chunk_base,
-                                            const ResSeg* __restrict__ rsegs,
-                                            const DecSeg* __restrict__ segs, const double* __restrict__ CA, int n_C,
-                                            int ca_ld, const T* __restrict__ dec, const int* __restrict__ n_live,
-                                            int B, int Bp, double* __restrict__ c_part, double* __restrict__ E_part,
-                                            int mmax) {
+__global__ __launch_bounds__(256) void k_con(const ConChunk* __restrict__ cch, int chunk_base,
+                                             const ResSeg* __restrict__ rsegs,
+                                             const DecSeg* __restrict__ segs, const double* __restrict__ CA, int n_C,
+                                             int ca_ld, const T* __restrict__ dec, const int* __restrict__ n_live,
+                                             int B, int Bp, double* __restrict__ c_part, double* __restrict__ E_part,
+                                             int mmax) {
     constexpr int JB = 8;
+    constexpr int NE = JB * (1 + NG);
+    constexpr int CH = 16;
+    __shared__ double red[3][CH][64];
     const ConChunk cc = cch[chunk_base + blockIdx.x];
     const ResSeg rs = rsegs[cc.sd];
     if ((int)blockIdx.y * 64 >= live_count(n_live, B)) return;
-    const int b = blockIdx.y * 64 + threadIdx.x;   // slot
+    const int tid = threadIdx.x, lane = tid & 63, prt = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int b = blockIdx.y * 64 + lane;   // slot
     const T* dga = dec + (size_t)segs[rs.seg_ga].out * Bp + b;
     const double* ca = CA + rs.ca + cc.j0;
     const int nj = cc.j1 - cc.j0;
+    const int no = cc.o1 - cc.o0;
+    const int ob = cc.o0 + no * prt / 4, oe = cc.o0 + no * (prt + 1) / 4;
     double c[JB], E[JB][NG];
 #pragma unroll
     for (int j = 0; j < JB; ++j) {
@@ -470,7 +479,7 @@ __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, in
         for (int k = 0; k < NG; ++k) E[j][k] = 0.0;
     }
 #pragma unroll 2
-    for (int o = cc.o0; o < cc.o1; ++o) {
+    for (int o = ob; o < oe; ++o) {
         const T* row = dga + (size_t)o * (1 + NG) * Bp;
         const double x = (double)row[0];
         double J[NG];
@@ -485,14 +494,26 @@ __global__ __launch_bounds__(64) void k_con(const ConChunk* __restrict__ cch, in
             for (int k = 0; k < NG; ++k) E[j][k] += aj * J[k];
         }
     }
+    // entry e < JB is c[e]; entry JB + j * NG + k is E[j][k]
+    auto val = [&](int e) { return e < JB ? c[e] : E[(e - JB) / NG][(e - JB) % NG]; };
 #pragma unroll
-    for (int j = 0; j < JB; ++j) {
-        if (j < nj) {
-            const int jj = cc.j0 + j;
-            c_part[((size_t)cc.part * n_C + jj) * Bp + b] = c[j];
+    for (int c0 = 0; c0 < NE; c0 += CH) {
+        if (prt > 0)
 #pragma unroll
-            for (int k = 0; k < NG; ++k) E_part[(((size_t)cc.part * n_C + jj) * mmax + k) * Bp + b] = E[j][k];
-        }
+            for (int e = c0; e < c0 + CH && e < NE; ++e) red[prt - 1][e - c0][lane] = val(e);
+        __syncthreads();
+        if (prt == 0)
+#pragma unroll
+            for (int e = c0; e < c0 + CH && e < NE; ++e) {
+                const int j = e < JB ? e : (e - JB) / NG;
+                if (j < nj) {
+                    const double v = ((val(e) + red[0][e - c0][lane]) + red[1][e - c0][lane]) + red[2][e - c0][lane];
+                    const int jj = cc.j0 + j;
+                    if (e < JB) c_part[((size_t)cc.part * n_C + jj) * Bp + b] = v;
+                    else E_part[(((size_t)cc.part * n_C + jj) * mmax + (e - JB) % NG) * Bp + b] = v;
+                }
+            }
+        __syncthreads();
     }
 }
 
@@ -514,7 +535,7 @@ __global__ __launch_bounds__(256) void k_reduce(int n_sub, int n_C, int mmax, in
     __shared__ double wpart[3][RED_E][64];
     __shared__ double tile[RED_E][65];
     const int sd = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b0 = blockIdx.z * 64, b = b0 + lane;   // slots
     if (b0 >= live_count(n_live, B)) return;
     int n_e, ne_gn = 0, ng = 0;
@@ -1747,7 +1768,7 @@ static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws,
     for (const auto& pl : m->con_plan) {
         const int c0 = pl.c0, c1 = pl.c1, ng = pl.n_ga;
         {
-            dim3 grid(c1 - c0, ws->Bp / 64), block(64);
+            dim3 grid(c1 - c0, ws->Bp / 64), block(256);
 #define CON_CASE(G)                                                                                               \
     case G:                                                                                                       \
         if (prec == DDROM_PREC_FP64)                                                                              \
