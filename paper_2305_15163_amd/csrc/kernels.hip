@@ -298,11 +298,20 @@ __global__ void k_bc(const double* __restrict__ xy, const int* __restrict__ fiel
 // ------------------------------------------------------------------------------------
 // HR residual, chain rule and Gauss-Newton partial sums
 // ------------------------------------------------------------------------------------
-// One wave = a run of sampled nodes of one subdomain x 64 solves.  For each node the ten
-// stencil DoFs are gathered without branches: every slot reads a value and NO Jacobian
-// entries from the decoder output (boundary slots read an all-zero block and take their
-// value from the per-solve Dirichlet buffer), so all loads of a node are in flight together;
-// the uniform source kind then selects which Jacobian columns each slot feeds.
+// Workgroup -> work item within its 64-solve group (blockIdx.y).  Workgroups go to the 8 XCDs
+// round-robin by linear id, so within one group the workgroups with equal blockIdx.x % 8 share
+// an XCD; they take one contiguous run of work items, so that neighbouring items, which read many
+// of the same decoder rows, share one L2.  Solve groups keep their dispatch order (idle groups
+// exit at once, after the live ones).  A bijection on each group's items: the last
+// gridDim.x % 8 items keep the plain order.
+__device__ __forceinline__ int xcd_item() {
+    const int l = blockIdx.x, cpx = (int)gridDim.x >> 3;
+    return l < 8 * cpx ? (l & 7) * cpx + (l >> 3) : l;
+}
+
+// The ten stencil DoFs of one sampled node for 64 solves (lanes): values and Jacobian rows
+// gathered from the decoder output or, for boundary slots, the per-solve Dirichlet buffer.
+// All loads of a node are issued before any is used.
 template <typename T, int NO>
 struct NodeLoads {
     int kind[N_SLOTS];
@@ -321,23 +330,44 @@ __device__ __forceinline__ void load_node(const int* __restrict__ code, const T*
         const int cd = cds[t];
         L.kind[t] = src_kind(cd);
         const int idx = src_index(cd);
-        const T* base = L.kind[t] == SRC_OMEGA ? dom + (size_t)idx * (1 + NO) * Bp
-                      : (L.kind[t] == SRC_GAMMA ? dga + (size_t)idx * (1 + NG) * Bp : dz);
-        const double bv = bcb[(size_t)(L.kind[t] == SRC_BOUND ? idx : 0) * Bp];
-        const T dv = base[0];
-        L.v[t] = L.kind[t] == SRC_BOUND ? bv : (double)dv;
+        // FP64, or up to 12 latents (every lane keeps all its sums in registers): a branch-free
+        // gather, every slot reads a value and NO Jacobian entries (a boundary slot an all-zero
+        // block, its value from the Dirichlet buffer); measured faster there than the scalar
+        // branches below, which add registers
+        if constexpr (sizeof(T) == 8 || NO + NG <= 12) {
+            const T* base = L.kind[t] == SRC_OMEGA ? dom + (size_t)idx * (1 + NO) * Bp
+                          : (L.kind[t] == SRC_GAMMA ? dga + (size_t)idx * (1 + NG) * Bp : dz);
+            const double bv = bcb[(size_t)(L.kind[t] == SRC_BOUND ? idx : 0) * Bp];
+            const T dv = base[0];
+            L.v[t] = L.kind[t] == SRC_BOUND ? bv : (double)dv;
 #pragma unroll
-        for (int k = 0; k < NO; ++k) L.jv[t][k] = base[(size_t)(1 + k) * Bp];
+            for (int k = 0; k < NO; ++k) L.jv[t][k] = base[(size_t)(1 + k) * Bp];
+            continue;
+        }
+        // the kind is wave-uniform, so these are scalar branches: a boundary slot reads only its
+        // Dirichlet value, an interface slot only its NG Jacobian entries
+        if (L.kind[t] == SRC_BOUND) {
+            L.v[t] = bcb[(size_t)idx * Bp];
+        } else if (L.kind[t] == SRC_OMEGA) {
+            const T* base = dom + (size_t)idx * (1 + NO) * Bp;
+            L.v[t] = (double)base[0];
+#pragma unroll
+            for (int k = 0; k < NO; ++k) L.jv[t][k] = base[(size_t)(1 + k) * Bp];
+        } else {
+            const T* base = dga + (size_t)idx * (1 + NG) * Bp;
+            L.v[t] = (double)base[0];
+#pragma unroll
+            for (int k = 0; k < NG; ++k) L.jv[t][k] = base[(size_t)(1 + k) * Bp];
+        }
     }
 }
 
 template <typename T, int NO, int NG>
-__device__ __forceinline__ void accumulate_node(const NodeLoads<T, NO>& L, double nu, double hx, double hy,
-                                                double* H, double* g, double& rr) {
+__device__ __forceinline__ void node_z(const NodeLoads<T, NO>& L, double nu, double hx, double hy, double* zu,
+                                       double* zv, double& ru, double& rv) {
     constexpr int NN = NO + NG;
-    double ru, rv, cu[6], cv[6];
+    double cu[6], cv[6];
     burgers_point(L.v, nu, hx, hy, ru, rv, cu, cv);
-    double zu[NN], zv[NN];
 #pragma unroll
     for (int e = 0; e < NN; ++e) { zu[e] = 0.0; zv[e] = 0.0; }
     // a u slot feeds d r_u only, a v slot d r_v only, except the two centre slots, which also
@@ -367,24 +397,56 @@ __device__ __forceinline__ void accumulate_node(const NodeLoads<T, NO>& L, doubl
             }
         }
     }
-    int e = 0;
-#pragma unroll
-    for (int i = 0; i < NN; ++i) {
-        g[i] = fma(zv[i], rv, fma(zu[i], ru, g[i]));
-#pragma unroll
-        for (int j = i; j < NN; ++j, ++e) H[e] = fma(zv[i], zv[j], fma(zu[i], zu[j], H[e]));
-    }
-    rr = fma(rv, rv, fma(ru, ru, rr));
 }
 
-// One workgroup = a run of sampled nodes of one subdomain x 64 solve slots.  Its four waves
-// take consecutive quarters of the node run (short dependent chains, also when few solves
-// run) and their partial sums are combined in LDS in a fixed order, so every solve's sums
-// are formed the same way whatever the batch.  For each node the ten stencil DoFs are
-// gathered without branches: every slot reads a value and NO Jacobian entries from the
-// decoder output (boundary slots read an all-zero block and take their value from the
-// per-solve Dirichlet buffer), so all loads of a node are in flight together.  The uniform
-// source kind then selects which Jacobian columns each slot feeds.
+// Gauss-Newton entries of one node, in packed order: H (upper triangle, row by row), g, rr.
+// Entry e of part P (of 4) lives in acc[e - lo(P)]; the part's range is fixed at compile time,
+// so each wave of the residual kernel keeps only its quarter of the sums in registers.  z is
+// read from LDS ([2 NN + 2][64] doubles: z_u, z_v, r_u, r_v); reads the part does not use are
+// dropped by the compiler.
+template <int NN>
+struct GnEntries {
+    static constexpr int NH = NN * (NN + 1) / 2;
+    static constexpr int NE = NH + NN + 1;
+    static constexpr int lo(int P) { return NE * P / 4; }
+    static constexpr int hi(int P) { return NE * (P + 1) / 4; }
+    static constexpr int MAXP = (NE + 3) / 4;
+};
+
+template <int NN, int P>
+__device__ __forceinline__ void gram_part(const double* zl, int lane, double* acc) {
+    using G = GnEntries<NN>;
+    constexpr int lo = G::lo(P), hi = G::hi(P);
+    double zu[NN], zv[NN];
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+        zu[i] = zl[i * 64 + lane];
+        zv[i] = zl[(NN + i) * 64 + lane];
+    }
+    const double ru = zl[2 * NN * 64 + lane], rv = zl[(2 * NN + 1) * 64 + lane];
+    int e = 0;
+#pragma unroll
+    for (int i = 0; i < NN; ++i)
+#pragma unroll
+        for (int j = i; j < NN; ++j, ++e)
+            if (e >= lo && e < hi) acc[e - lo] = fma(zv[i], zv[j], fma(zu[i], zu[j], acc[e - lo]));
+#pragma unroll
+    for (int i = 0; i < NN; ++i, ++e)
+        if (e >= lo && e < hi) acc[e - lo] = fma(zv[i], rv, fma(zu[i], ru, acc[e - lo]));
+    if (e >= lo && e < hi) acc[e - lo] = fma(rv, rv, fma(ru, ru, acc[e - lo]));
+}
+
+
+// One workgroup = a run of sampled nodes of one subdomain x 64 solve slots (lanes).  For each node
+// the ten stencil DoFs are gathered, the pointwise residual and the chain-rule vectors z_u, z_v
+// (Z R_i at that node) formed, and the Gauss-Newton entries (H_i upper triangle, g_i, r^T r) summed
+// over the run.  Every solve's sums are formed in the same order whatever the batch.  Two layouts:
+//
+//  * up to 12 latents per subdomain, every lane keeps all entries in registers; the four waves
+//    take consecutive quarters of the run and are combined in LDS in a fixed order;
+//  * above 12 (whose entries do not fit beside the gather), the run is taken four nodes at a
+//    time: each wave gathers one node and puts z_u, z_v, r_u, r_v in LDS, then each wave adds the
+//    four nodes, in node order, into its fixed quarter of the entries, which it writes out itself.
 template <typename T, int NO, int NG>
 __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rchunks, int rbase,
                                                 const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
@@ -394,50 +456,101 @@ __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rch
                                                 double hy, double* __restrict__ part, int estride,
                                                 long long zero_row) {
     constexpr int NN = NO + NG;
-    constexpr int NH = NN * (NN + 1) / 2;
-    constexpr int NE = NH + NN + 1;
-    constexpr int CH = 16;
-    __shared__ double red[3][CH][64];
+    using G = GnEntries<NN>;
     const int nl = live_count(n_live, B);
     const int j0 = blockIdx.y * 64;
     if (j0 >= nl) return;
     const ResChunk rc = rchunks[rbase + blockIdx.x];
     const ResSeg rs = rsegs[rc.sd];
     const long long oo = segs[rs.seg_om].out, og = segs[rs.seg_ga].out;
-    // the quarter index is wave-uniform: the node codes then come in by scalar loads and the
-    // source-kind branches are scalar, so a node's gathers are issued without waiting
-    const int tid = threadIdx.x, lane = tid & 63, prt = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // the wave index is uniform: node codes come in by scalar loads and the source-kind
+    // branches are scalar, so a node's gathers are issued without waiting
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = j0 + lane;
-    const int np = rc.p1 - rc.p0;
-    const int pb = rc.p0 + np * prt / 4, pe = rc.p0 + np * (prt + 1) / 4;
     const T* dom = dec + (size_t)oo * Bp + j;
     const T* dga = dec + (size_t)og * Bp + j;
     const T* dz = dec + (size_t)zero_row * Bp + j;
     const double* bcb = bc + slot_solve(live, j, nl);   // Dirichlet data are per solve
-    double H[NH], g[NN], rr = 0.0;
-#pragma unroll
-    for (int e = 0; e < NH; ++e) H[e] = 0.0;
-#pragma unroll
-    for (int e = 0; e < NN; ++e) g[e] = 0.0;
     const int* gp = gather + rs.gather;
-    for (int p = pb; p < pe; ++p) {
-        NodeLoads<T, NO> A;
-        load_node<T, NO, NG>(gp + (size_t)p * N_SLOTS, dom, dga, dz, bcb, Bp, A);
-        accumulate_node<T, NO, NG>(A, nu, hx, hy, H, g, rr);
-    }
     double* pp = part + (size_t)rc.slot * estride * Bp + j;
-    auto val = [&](int e) { return e < NH ? H[e] : (e < NH + NN ? g[e - NH] : rr); };
+    if constexpr (NN <= 12) {
+        constexpr int CH = 16;
+        __shared__ double red[3][CH][64];
+        const int np = rc.p1 - rc.p0;
+        const int pb = rc.p0 + np * w / 4, pe = rc.p0 + np * (w + 1) / 4;
+        double H[G::NH], g[NN], rr = 0.0;
 #pragma unroll
-    for (int c0 = 0; c0 < NE; c0 += CH) {
-        if (prt > 0)
+        for (int e = 0; e < G::NH; ++e) H[e] = 0.0;
 #pragma unroll
-            for (int e = c0; e < c0 + CH && e < NE; ++e) red[prt - 1][e - c0][lane] = val(e);
-        __syncthreads();
-        if (prt == 0)
+        for (int e = 0; e < NN; ++e) g[e] = 0.0;
+        for (int p = pb; p < pe; ++p) {
+            NodeLoads<T, NO> A;
+            load_node<T, NO, NG>(gp + (size_t)p * N_SLOTS, dom, dga, dz, bcb, Bp, A);
+            double zu[NN], zv[NN], ru, rv;
+            node_z<T, NO, NG>(A, nu, hx, hy, zu, zv, ru, rv);
+            int e = 0;
 #pragma unroll
-            for (int e = c0; e < c0 + CH && e < NE; ++e)
-                pp[(size_t)e * Bp] = ((val(e) + red[0][e - c0][lane]) + red[1][e - c0][lane]) + red[2][e - c0][lane];
-        __syncthreads();
+            for (int i = 0; i < NN; ++i) {
+                g[i] = fma(zv[i], rv, fma(zu[i], ru, g[i]));
+#pragma unroll
+                for (int k = i; k < NN; ++k, ++e) H[e] = fma(zv[i], zv[k], fma(zu[i], zu[k], H[e]));
+            }
+            rr = fma(rv, rv, fma(ru, ru, rr));
+        }
+        auto val = [&](int e) { return e < G::NH ? H[e] : (e < G::NH + NN ? g[e - G::NH] : rr); };
+#pragma unroll
+        for (int c0 = 0; c0 < G::NE; c0 += CH) {
+            if (w > 0)
+#pragma unroll
+                for (int e = c0; e < c0 + CH && e < G::NE; ++e) red[w - 1][e - c0][lane] = val(e);
+            __syncthreads();
+            if (w == 0)
+#pragma unroll
+                for (int e = c0; e < c0 + CH && e < G::NE; ++e)
+                    pp[(size_t)e * Bp] = ((val(e) + red[0][e - c0][lane]) + red[1][e - c0][lane]) + red[2][e - c0][lane];
+            __syncthreads();
+        }
+    } else {
+        constexpr int NZ = 2 * NN + 2;
+        __shared__ double zs[4][NZ][64];
+        double acc[G::MAXP];
+#pragma unroll
+        for (int e = 0; e < G::MAXP; ++e) acc[e] = 0.0;
+        for (int p0 = rc.p0; p0 < rc.p1; p0 += 4) {
+            const int p = p0 + w;
+            double zu[NN], zv[NN], ru = 0.0, rv = 0.0;
+            if (p < rc.p1) {
+                NodeLoads<T, NO> A;
+                load_node<T, NO, NG>(gp + (size_t)p * N_SLOTS, dom, dga, dz, bcb, Bp, A);
+                node_z<T, NO, NG>(A, nu, hx, hy, zu, zv, ru, rv);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NN; ++i) { zu[i] = 0.0; zv[i] = 0.0; }
+            }
+#pragma unroll
+            for (int i = 0; i < NN; ++i) {
+                zs[w][i][lane] = zu[i];
+                zs[w][NN + i][lane] = zv[i];
+            }
+            zs[w][2 * NN][lane] = ru;
+            zs[w][2 * NN + 1][lane] = rv;
+            __syncthreads();
+            const int nq = min(4, rc.p1 - p0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q >= nq) break;
+                if (w == 0) gram_part<NN, 0>(&zs[q][0][0], lane, acc);
+                else if (w == 1) gram_part<NN, 1>(&zs[q][0][0], lane, acc);
+                else if (w == 2) gram_part<NN, 2>(&zs[q][0][0], lane, acc);
+                else gram_part<NN, 3>(&zs[q][0][0], lane, acc);
+            }
+            __syncthreads();
+        }
+        const int lo = w == 0 ? G::lo(0) : (w == 1 ? G::lo(1) : (w == 2 ? G::lo(2) : G::lo(3)));
+        const int hi = w == 0 ? G::hi(0) : (w == 1 ? G::hi(1) : (w == 2 ? G::hi(2) : G::hi(3)));
+#pragma unroll
+        for (int e = 0; e < G::MAXP; ++e)
+            if (lo + e < hi) pp[(size_t)(lo + e) * Bp] = acc[e];
     }
 }
 
@@ -461,11 +574,12 @@ __global__ __launch_bounds__(256) void k_con(const ConChunk* __restrict__ cch, i
     constexpr int NE = JB * (1 + NG);
     constexpr int CH = 16;
     __shared__ double red[3][CH][64];
-    const ConChunk cc = cch[chunk_base + blockIdx.x];
+    const int item = xcd_item(), grp = blockIdx.y;
+    const ConChunk cc = cch[chunk_base + item];
     const ResSeg rs = rsegs[cc.sd];
-    if ((int)blockIdx.y * 64 >= live_count(n_live, B)) return;
+    if (grp * 64 >= live_count(n_live, B)) return;
     const int tid = threadIdx.x, lane = tid & 63, prt = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int b = blockIdx.y * 64 + lane;   // slot
+    const int b = grp * 64 + lane;   // slot
     const T* dga = dec + (size_t)segs[rs.seg_ga].out * Bp + b;
     const double* ca = CA + rs.ca + cc.j0;
     const int nj = cc.j1 - cc.j0;
