@@ -232,6 +232,63 @@ def roofline_only(a, torch, dr, si):
                       "copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}), flush=True)
 
 
+# Child program for the all-core oracle rate: one worker process per core, BLAS limited to one
+# thread each, every worker solving its own share of the held-out parameters for about `secs`
+# seconds after loading the model.  It never touches the GPU.
+_CPU_ALL = r"""
+import json, os, sys, time
+for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[v] = "1"
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from multiprocessing import Pool
+
+def work(args):
+    w, n, path, max_iter, secs, B, seed = args
+    import seeded_inputs as si
+    from oracle.pack import load_pack
+    from oracle.rom import SQPOptions, sqp_solve
+    om = load_pack(dict(np.load(path, allow_pickle=False)))
+    mu = si.heldout_mu(B, seed)
+    t0 = time.perf_counter(); k = 0
+    while True:
+        sqp_solve(om, mu[(w + k * n) % len(mu)], opts=SQPOptions(max_iter=max_iter, tol_abs=0.0, tol_rel=1e-8))
+        k += 1
+        if time.perf_counter() - t0 > secs:
+            break
+    return k, time.perf_counter() - t0
+
+n, path, max_iter, secs = int(sys.argv[2]), sys.argv[3], int(sys.argv[4]), float(sys.argv[5])
+B, seed = int(sys.argv[6]), int(sys.argv[7])
+with Pool(n) as pool:
+    res = pool.map(work, [(w, n, path, max_iter, secs, B, seed) for w in range(n)])
+print(json.dumps({"solves": sum(k for k, _ in res), "rate": sum(k / t for k, t in res)}))
+"""
+
+
+def cpu_all_cores(path, max_iter, B, seed, secs=10.0):
+    import subprocess
+    n = min(os.cpu_count() or 1, 16)
+    r = subprocess.run([sys.executable, "-c", _CPU_ALL, ROOT, str(n), path, str(max_iter), str(secs), str(B),
+                        str(seed)],
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError("all-core oracle run failed: " + r.stderr[-2000:])
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": d["rate"], "unit": "solves/s", "cores": n, "solves": d["solves"], "cpu_model": model,
+            "sample": f"{n} processes, one per core, BLAS limited to 1 thread each, about {secs:.0f} s each, "
+                      f"held-out parameters of the 240x240 workload"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,14 +473,23 @@ def main():
                                     "sample": f"{n_cpu} of the {B} parameters, FP64 oracle SQP (dense KKT), "
                                               f"relative KKT tolerance 1e-8, BLAS limited to 1 thread"}
             # error against the FOM on a few parameters: batched (this run) and plain SQP
-            errs, perrs = [], []
+            errs, perrs, tf = [], [], []
             for b in range(min(3, B)):
+                t3 = time.perf_counter()
                 xf = solve_fom(om.fom, mu_h[b]).x
+                tf.append(time.perf_counter() - t3)
                 errs.append(relative_error(om, xb[b], xf))
                 if plain is not None and b < len(px):
                     perrs.append(relative_error(om, px[b], xf))
             line["rel_err_vs_fom"] = {"batched": errs, "plain_sqp": perrs, "n": len(errs)}
+            # the FOM's Newton solve per parameter on one host core (the paper's speedup denominator)
+            line["fom_newton_s_per_mu"] = {"value": float(np.mean(tf)), "n": len(tf), "cores": 1,
+                                           "solves_per_s_vs_fom": line["value"] * float(np.mean(tf))}
         print(f"[bench] cpu leg {n_cpu} solves in {ct:.1f}s", file=sys.stderr, flush=True)
+        line["cpu_baseline"]["all_cores"] = cpu_all_cores(os.path.join(ROOT, "models", "cfg1.npz"), cfg["max_iter"], B,
+                                                      cfg["seed"])
+        print(f"[bench] all-core oracle leg: {line['cpu_baseline']['all_cores']['value']:.2f} solves/s on "
+              f"{line['cpu_baseline']['all_cores']['cores']} cores", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

@@ -1410,6 +1410,12 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         for (int c = 0; c < NN; ++c) Hr[c] = A[c];
 #pragma unroll
         for (int l = 0; l <= MG; ++l) Xr[l] = A[NN + l];
+        // Ehat_i rows of the first 64 constraints: loaded before the elimination, which hides
+        // their latency
+        const double* E = Es + sd * esds;
+        double ev0[MG > 0 ? MG : 1];
+#pragma unroll
+        for (int k = 0; k < MG; ++k) ev0[k] = (k < ng && lane < nC) ? E[lane * mg + k] : 0.0;
         bool okb = true;
         wave_gj<NN, MG + 1>(Hr, Xr, NNi, lane, okb);
         const bool bad = !okb;
@@ -1418,14 +1424,14 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
 #pragma unroll
             for (int l = 0; l <= MG; ++l) Xs[((size_t)sd * NN + lane) * (MG + 1) + l] = Xr[l];
         // P_i = Ehat_i (W_i)_Gamma, q_i = Ehat_i (t_i)_Gamma (constraint row j0 + lane in lane)
-        const double* E = Es + sd * esds;
         for (int j0 = 0; j0 < nC; j0 += 64) {
             const int jj = j0 + lane;
             double P[MG + 1], ev[MG > 0 ? MG : 1];
 #pragma unroll
             for (int l = 0; l <= MG; ++l) P[l] = 0.0;
 #pragma unroll
-            for (int k = 0; k < MG; ++k) ev[k] = (k < ng && jj < nC) ? E[jj * mg + k] : 0.0;   // loads first
+            for (int k = 0; k < MG; ++k)
+                ev[k] = j0 == 0 ? ev0[k] : ((k < ng && jj < nC) ? E[jj * mg + k] : 0.0);   // loads first
 #pragma unroll
             for (int k = 0; k < MG; ++k) {
                 if (k < ng) {
