@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     constexpr int RK = RingSlots<T, ACT>::K;
     const DecChunk ch = chunks[chunk_base + blockIdx.x];
     const DecSeg sg = segs[ch.seg];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nl = live_count(n_live, B);
     const int j0 = (int)blockIdx.y * WAVES * 64;
     if (j0 >= nl) return;     // every slot of this workgroup is idle
@@ -203,8 +203,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
         }
     };
     const int r_begin = nrows * part / R, r_end = nrows * (part + 1) / R;
+    // band descriptors are the same for every lane: kept in scalar registers, so the row's window
+    // and ring-slot bookkeeping run on the scalar unit
+    auto ubd = [&](int i) {
+        const int2 q = sBd[i];
+        return make_int2(__builtin_amdgcn_readfirstlane(q.x), __builtin_amdgcn_readfirstlane(q.y));
+    };
     for (int r = r_begin; r < r_end; ++r) {
-        const int2 q0 = sBd[r * 3 + 0], q1 = sBd[r * 3 + 1], q2 = sBd[r * 3 + 2];
+        const int2 q0 = ubd(r * 3 + 0), q1 = ubd(r * 3 + 1), q2 = ubd(r * 3 + 2);
         int lo = 0x7fffffff, hi = -1;
         if (q0.y > 0) { lo = min(lo, q0.x); hi = max(hi, q0.x + q0.y); }
         if (q1.y > 0) { lo = min(lo, q1.x); hi = max(hi, q1.x + q1.y); }
