@@ -41,8 +41,8 @@ PEAK_HBM_GBS = 8000.0
 # dispatch, mean of 20), each scaled by what the same counter reads for a 256 MiB device copy in the
 # same run (FETCH_SIZE 131084.8 KiB, WRITE_SIZE 262144 KiB for 262144 KiB moved).  Valid only for the
 # decoder source and work-item shape it was measured on; otherwise traffic is reported as null.
-DECODE_COUNTERS = dict(fetch_kib=10881.8, write_kib=288288.0, fetch_scale=262144.0 / 131084.8, write_scale=1.0,
-                       source_sha1="7920ca569ad7ff87", tile=(16, 24, 256),
+DECODE_COUNTERS = dict(fetch_kib=10852.9, write_kib=288288.0, fetch_scale=262144.0 / 131084.6, write_scale=1.0,
+                       source_sha1="0d6ad11c787f54f7", tile=(16, 24, 256),
                        profile="profiles/k_decode_f32_burgers240_4x4_b512.md")
 
 
