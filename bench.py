@@ -305,7 +305,7 @@ def main():
                          "(the workload of the hardware-counter runs)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(parameter solves would shard across GPUs with no communication).", file=sys.stderr)
         sys.exit(2)
 

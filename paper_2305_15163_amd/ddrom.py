@@ -51,7 +51,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2305_15163_amd.build)")
         L = C.CDLL(LIB_PATH)
         vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
         L.ddrom_last_error.restype = C.c_char_p
