@@ -109,6 +109,27 @@ def test_huge_kkt_step(dr, tinyhuge_pack):
         assert abs(fn[b] - fr) <= 1e-10 * max(1.0, fr)
 
 
+def test_huge_gn_blocks_fp32_decoder(dr, tinyhuge_pack):
+    """Latent (12, 6): the residual kernel's path for more than 12 latents per subdomain (chain-rule
+    vectors shared through LDS, each wave one quarter of the Gauss-Newton entries), with the FP32
+    decoder output's gather by source kind.  Against the FP64 oracle within FP32 rounding of the
+    decoder values and Jacobians (about 1e-6 relative); a wrong index, term or sign is O(1)."""
+    print("[case tinyhuge fp32 gn]", flush=True)
+    gm, om = dr.Model(tinyhuge_pack), load_pack(tinyhuge_pack)
+    B = 70   # two 64-solve groups, the second ragged
+    mus = si.heldout_mu(B, 51)
+    xh = si.normal((B, gm.n_D), seed=52, scale=0.3)
+    ws = dr.Workspace(gm, B)
+    H, g, EG, c, rr = (t.cpu().numpy() for t in dr.gn_blocks(gm, ws, mus, xh, precision=dr.PREC_FP32_DECODER))
+    for b in (0, 1, 63, 64, 69):
+        ev = evaluate(om, mus[b], xh[b])
+        for i, (o, (a, m)) in enumerate(zip(om.offsets(), om.sizes())):
+            assert relerr(H[b, i, :a + m, :a + m], ev.H[i]) <= 1e-4
+            assert relerr(g[b, o:o + a + m], ev.g[i]) <= 1e-4
+            assert relerr(EG[b, i, :, :m], ev.EG[i]) <= 1e-4
+        assert relerr(c[b], ev.c) <= 1e-4
+
+
 @pytest.mark.parametrize("tile", [(8, 4, 4), (64, 7, 16), (13, 40, 300)])
 def test_tiles_change_schedule_only(dr, tile, tinymix_pack, cfg0_pack):
     """Other work-item shapes: decoded rows are bitwise the same, residual and constraint
