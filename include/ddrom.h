@@ -183,7 +183,7 @@ int rom_solve_batch(const ddrom_model* m, ddrom_workspace* ws, const double* mu_
 /* ---- Learned initial iterate --------------------------------------------------------
  * A dense network maps the Burgers parameters mu = (a, lambda) to a proposal for every
  * subdomain's latents and the multipliers; it stands where the paper interpolates training
- * solutions to start its online solves (Section 6).  Inputs (log10 a, lambda), each mapped
+ * solutions to start its online solves (Section 7.2).  Inputs (log10 a, lambda), each mapped
  * affinely onto [-1, 1] over a in [1, 1e4], lambda in [5, 20]; layers W_k [out][in], b_k [out]
  * with SiLU after every layer but the last; the outputs are standardised, so the proposal is
  * y * out_std + out_mean: components [0, n_D) are xhat, the rest lambda.  FP32 arithmetic. */
@@ -287,7 +287,7 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
 int rom_decode_states(const ddrom_model* m, ddrom_workspace* ws, const double* xhat_d, int B, int precision,
                       double* xsd_d, hipStream_t s);
 
-/* Relative error of the decoded states against FOM states (eq. relative_error, Section 6):
+/* Relative error of the decoded states against FOM states (eq. relative_error, Section 7):
  * err_d[b] = sqrt( (1/n_sub) sum_i ||x_FOM|_i - g_i(xhat_i)||^2 / ||x_FOM|_i||^2 ) where x_FOM|_i
  * restricts xfom_d [B][N_x] (FP64, global order [u; v], x-fastest) to subdomain i's interior
  * and interface DoFs.  Decodes in `precision`; sums in FP64. */

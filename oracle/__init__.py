@@ -17,8 +17,11 @@ and no blocking or fusion beyond what the paper states:
                      sampling, subnet extraction.
   rom.py             Section 4: WFPC DD-LSPG objective with collocation HR, Lagrange-
                      Gauss-Newton SQP with a full dense KKT solve and Armijo backtracking;
-                     DD-FOM SQP; LS-ROM; relative error (eq. relative_error).
-  mlp.py             learned initial-iterate proposal (forward/backward, FP64).
+                     DD-FOM SQP; relative error (eq. relative_error).
+  lsrom.py           Section 3.3: LS-ROM (affine or POD maps) with collocation or gappy-POD
+                     HR, solved along routes independent of rom.py (null-space QP steps).
+  proposal.py        learned initial-iterate proposal (forward/backward, Adam, FP64)
+                     and the zero-start fallback rule.
   build_model.py     offline pipeline (snapshots -> autoencoders -> HR -> model pack).
 
 Parity unpinned: the greedy sampler (hyperreduction.greedy_sample) follows the cited

@@ -1,7 +1,7 @@
 """Oracle: learned initial iterate for the online SQP (test infrastructure only).
 
 The paper starts its online solves from an interpolation of training solutions over the
-parameter box (Section 6, experimental set-up).  Here that role is played by a small dense
+parameter box (Section 7.2, radial-basis interpolation of snapshot latents).  Here that role is played by a small dense
 network mapping the Burgers parameters (a, lambda) to every subdomain's latents and the
 multipliers, trained on converged solves of the method itself.  This module is the plain
 FP64 statement of that network, its gradient and its optimiser, plus the rule that keeps

@@ -105,16 +105,13 @@ class Evaluation:
     ZR: list
 
 
-def evaluate(model: ROMModel, mu, xhat: np.ndarray, decoders=None) -> Evaluation:
+def evaluate(model: ROMModel, mu, xhat: np.ndarray) -> Evaluation:
     """Per-subdomain SQP quantities at xhat (no multiplier terms)."""
     H, g, EG, Zr_l, ZR_l = [], [], [], [], []
     c = np.zeros(model.n_C)
     for i, (xo, xg) in enumerate(model.split(xhat)):
-        if decoders is None:
-            go, Jo = decode_jacobian(model.dec_om[i], xo)
-            gg, Jg = decode_jacobian(model.dec_ga[i], xg)
-        else:
-            go, Jo, gg, Jg = decoders(i, xo, xg)
+        go, Jo = decode_jacobian(model.dec_om[i], xo)
+        gg, Jg = decode_jacobian(model.dec_ga[i], xg)
         r, dro, drg = subdomain_residual_jac(model.fom, model.dd, i, go, gg, mu)
         z = model._zrows[i]
         Zr = r[z]
@@ -293,53 +290,6 @@ def relative_error_states(dd: DDMaps, states: list, x_fom: np.ndarray) -> float:
         to, tg = x_fom[sd.omega], x_fom[sd.gamma]
         tot += (np.sum((to - go) ** 2) + np.sum((tg - gg) ** 2)) / (np.sum(to ** 2) + np.sum(tg ** 2))
     return float(np.sqrt(tot / len(dd.subdomains)))
-
-
-# ----------------------------------------------------------------------------------
-# LS-ROM (Section 3.3): affine maps g(xhat) = x0 + Phi xhat, constant Jacobians
-# ----------------------------------------------------------------------------------
-
-@dataclass
-class AffineMap:
-    x0: np.ndarray
-    Phi: np.ndarray
-
-
-def lsrom_decoders(maps_om: list, maps_ga: list):
-    def dec(i, xo, xg):
-        mo, mg = maps_om[i], maps_ga[i]
-        return mo.x0 + mo.Phi @ xo, mo.Phi, mg.x0 + mg.Phi @ xg, mg.Phi
-    return dec
-
-
-def sqp_solve_with(model: ROMModel, mu, decoders, xhat0, opts: SQPOptions) -> SQPResult:
-    """The same SQP iteration with user-supplied subdomain maps (used for the LS-ROM)."""
-    x = np.array(xhat0, dtype=np.float64)
-    ev = evaluate(model, mu, x, decoders)
-    lam = initial_multiplier(model, ev)
-    F = kkt_rhs(model, ev, lam)
-    f0 = fn = float(np.linalg.norm(F))
-    tol = max(opts.tol_abs, opts.tol_rel * f0)
-    n_eval = 1
-    for k in range(opts.max_iter):
-        if fn <= tol:
-            return SQPResult(x, lam, CONVERGED, k, fn, f0, n_eval)
-        F = kkt_rhs(model, ev, lam)
-        phi0 = 0.5 * float(F @ F)
-        sx, sl = kkt_step(model, ev, lam)
-        alpha = 1.0
-        for nb in range(opts.max_backtracks + 1):
-            xt, lt = x + alpha * sx, lam + alpha * sl
-            evt = evaluate(model, mu, xt, decoders)
-            Ft = kkt_rhs(model, evt, lt)
-            n_eval += 1
-            if 0.5 * float(Ft @ Ft) <= (1.0 - 2.0 * opts.c1 * alpha) * phi0:
-                break
-            alpha *= 0.5
-        else:
-            return SQPResult(x, lam, LINESEARCH_FAIL, k, fn, f0, n_eval)
-        x, lam, ev, fn = xt, lt, evt, float(np.linalg.norm(Ft))
-    return SQPResult(x, lam, CONVERGED if fn <= tol else MAX_ITER, opts.max_iter, fn, f0, n_eval)
 
 
 # ----------------------------------------------------------------------------------

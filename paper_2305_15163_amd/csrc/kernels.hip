@@ -2383,7 +2383,10 @@ static long long solver_max_rounds(const ddrom_opts* o, int warm) {
 static int solver_graph(const ddrom_model* m, ddrom_workspace* ws, int B, const ddrom_opts* o, const UpdArgs& ua,
                         int lam_given, int warm) {
     const int prec = o->precision;
+    // Doubles enter the key as exact hexadecimal floating-point text, so options that differ
+    // in any bit capture a new graph.
     std::ostringstream key;
+    key << std::hexfloat;
     key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
         << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << lam_given << ":" << warm;
     if (ws->graph && ws->graph_key == key.str()) return 0;

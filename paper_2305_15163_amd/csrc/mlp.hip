@@ -6,7 +6,7 @@
 // a in [1, 1e4], lambda in [5, 20]; dense layers W_k [out][in], b_k [out]; SiLU after every
 // layer but the last; outputs standardised per component (the solver receives
 // y * std + mean in FP64).  The paper starts its solves from an interpolation of training
-// solutions (Section 6); this network takes that role and is trained on the method's own
+// solutions (Section 7.2); this network takes that role and is trained on the method's own
 // converged solves.
 #include <hip/hip_runtime.h>
 

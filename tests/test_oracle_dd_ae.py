@@ -10,7 +10,7 @@ from oracle.ddmaps import build_dd, restrict, subdomain_residual
 from oracle.hyperreduction import greedy_sample, pod_basis, subnet, subnet_decode
 
 
-# --- Section 7.4 / Tables: exact integers -------------------------------------------
+# --- Sections 7.5 / 7.6 and their tables: exact integers -------------------------------------------
 
 @pytest.mark.parametrize("nx,ny,sx,sy,expect,total,nA", [
     (480, 24, 2, 2, {(5258, 1006)}, 25056, 2016),
@@ -22,7 +22,7 @@ from oracle.hyperreduction import greedy_sample, pod_basis, subnet, subnet_decod
 ])
 def test_dd_sizes(nx, ny, sx, sy, expect, total, nA):
     """N_i^Omega = 5258 (printed 5238; forced by 25056 = 4 (5258 + 1006)), N_i^Gamma = 1006,
-    25056 aggregated DoF for the 480x24 2x2 split (Section 7.4); the other splits
+    25056 aggregated DoF for the 480x24 2x2 split (Section 7.6); the other splits
     reproduce the parameter counts of the subdomain-configuration table."""
     dd = build_dd(Grid(nx, ny), sx, sy)
     assert {(len(s.omega), len(s.gamma)) for s in dd.subdomains} == expect
@@ -68,7 +68,7 @@ def test_dd_residual_identity():
 # --- Sections 5.1 / 7.3: mask and parameter counts -----------------------------------
 
 def test_mask_nnz_and_widths():
-    """Widths 26290 / 5030 and mask nonzeros 78820 / 15040 for (b, s) = (5, 5) (Section 7.4)."""
+    """Widths 26290 / 5030 and mask nonzeros 78820 / 15040 for (b, s) = (5, 5) (Section 7.6)."""
     assert band_mask(5258, 5, 5).shape == (5258, 26290)
     assert band_mask(5258, 5, 5).nnz == 78820
     assert band_mask(1006, 5, 5).shape == (1006, 5030)
@@ -76,7 +76,7 @@ def test_mask_nnz_and_widths():
 
 
 def test_parameter_counts():
-    """Table of subdomain configurations (Section 7.4), (n^Omega, n^Gamma) = (6, 3),
+    """Table of subdomain configurations (Section 7.5), (n^Omega, n^Gamma) = (6, 3),
     (b, s) = (5, 5), 1x1 with n = 9: the largest interior autoencoder per split and the
     total over all interior and interface autoencoders."""
     P = lambda N, n: parameter_count(N, n, 5, 5)

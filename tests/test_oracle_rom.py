@@ -1,17 +1,19 @@
 """Pins of the SQP oracle: Theorem 1, Lemma 2, KKT conditions at convergence, the
-single-domain Gauss-Newton special case, the identity-activation LS-ROM special case and
-the relative-error metric."""
+single-domain Gauss-Newton special case, the identity-activation LS-ROM special case
+(against an independently written LS-ROM solver, itself pinned by Theorem 1), central
+differences of the per-subdomain Jacobians, the initial multiplier, the stagnation stop
+and the relative-error metric."""
 import numpy as np
 import pytest
-import scipy.optimize as so
 
 import seeded_inputs as si
-from oracle.autoencoder import ACT_IDENTITY, ACT_SIGMOID, Decoder, decode
+from oracle.autoencoder import ACT_IDENTITY, ACT_SIGMOID, ACT_SWISH, Decoder
 from oracle.burgers import BurgersFOM, Grid, newton_fom
 from oracle.ddmaps import build_dd, restrict
 from oracle.pack import load_pack
-from oracle.rom import (CONVERGED, AffineMap, ROMModel, SQPOptions, dd_fom_sqp, evaluate, kkt_rhs, kkt_step,
-                        lsrom_decoders, relative_error, relative_error_states, sqp_solve, sqp_solve_with)
+from oracle import lsrom
+from oracle.rom import (CONVERGED, LINESEARCH_FAIL, MAX_ITER, STALLED, ROMModel, SQPOptions, dd_fom_sqp, evaluate,
+                        initial_multiplier, kkt_rhs, kkt_step, relative_error_states, sqp_solve)
 
 
 def test_theorem1_dd_fom_equals_monolithic():
@@ -99,35 +101,173 @@ def test_kkt_conditions_at_convergence(tiny_pack):
 
 def test_single_domain_is_gauss_newton():
     """With one subdomain there is no constraint and the SQP iteration is Gauss-Newton on
-    min ||Z r(g(xhat))||: its limit equals scipy's least-squares minimiser."""
+    min ||Z r(g(xhat))|| (the single-domain case of Section 7.5): its limit equals that of a
+    plain Gauss-Newton loop on fourth-order central-difference Jacobians of the residual
+    (nothing of evaluate()'s chain rule enters)."""
     m = _random_model(nsx=1, nsy=1, seed=3)
     mu = (900.0, 9.5)
-    res = sqp_solve(m, mu, opts=SQPOptions(max_iter=80, tol_abs=0.0, tol_rel=1e-11))
+    res = sqp_solve(m, mu, opts=SQPOptions(max_iter=200, tol_abs=0.0, tol_rel=1e-13))
     assert res.status == CONVERGED, res.status
 
     def fun(x):
         return evaluate(m, mu, x).Zr[0]
 
-    def jac(x):
-        return evaluate(m, mu, x).ZR[0]
+    def jac(x, h=1e-3):
+        cols = []
+        for k in range(m.n_D):
+            e = np.zeros(m.n_D)
+            e[k] = h
+            cols.append((-fun(x + 2 * e) + 8 * fun(x + e) - 8 * fun(x - e) + fun(x - 2 * e)) / (12 * h))
+        return np.stack(cols, axis=1)
 
-    ls = so.least_squares(fun, np.zeros(m.n_D), jac=jac, method="lm", xtol=1e-15, ftol=1e-15, gtol=1e-15)
-    assert np.linalg.norm(res.xhat - ls.x) <= 1e-7 * max(1.0, np.linalg.norm(ls.x))
+    x = np.zeros(m.n_D)
+    for _ in range(80):
+        x = x - np.linalg.lstsq(jac(x), fun(x), rcond=None)[0]
+    assert np.linalg.norm(res.xhat - x) <= 1e-9 * max(1.0, np.linalg.norm(x))
+
+
+def _affine_maps(m):
+    """sigma = id: g(xhat) = (x_ref + W2 b1) + (W2 W1) xhat for every decoder of m."""
+    om = [(d.x_ref + d.W2() @ d.b1, np.asarray(d.W2() @ d.W1)) for d in m.dec_om]
+    ga = [(d.x_ref + d.W2() @ d.b1, np.asarray(d.W2() @ d.W1)) for d in m.dec_ga]
+    return om, ga
+
+
+def test_lsrom_full_basis_is_dd_fom():
+    """The independent LS-ROM solver with identity bases (Phi_i = I), B_i = I and C = I is the
+    DD FOM (eq. fom_dd_nlp): by Theorem 1 its solution is the monolithic Newton solution
+    restricted to the subdomains.  This pins the LS-ROM solver (prolongation, QP step,
+    multipliers, line search) against a different algorithm."""
+    g = Grid(12, 8)
+    f = BurgersFOM(g)
+    dd = build_dd(g, 2, 2)
+    mu = (1800.0, 12.0)
+    xm = newton_fom(f, mu).x
+    eye = lambda N: np.eye(N)
+    rom = lsrom.LSROM(f, dd, np.eye(dd.n_A), [np.zeros(len(sd.omega)) for sd in dd.subdomains],
+                      [eye(len(sd.omega)) for sd in dd.subdomains], [np.zeros(len(sd.gamma)) for sd in dd.subdomains],
+                      [eye(len(sd.gamma)) for sd in dd.subdomains], hr=None)
+    res = lsrom.solve(rom, mu, max_iter=60, tol_abs=0.0, tol_rel=1e-12)
+    assert res.status == lsrom.CONVERGED, res.status
+    o = 0
+    for sd in dd.subdomains:
+        a, b = len(sd.omega), len(sd.gamma)
+        assert np.linalg.norm(res.xhat[o:o + a] - xm[sd.omega]) <= 1e-10 * np.linalg.norm(xm[sd.omega])
+        assert np.linalg.norm(res.xhat[o + a:o + a + b] - xm[sd.gamma]) <= 1e-10 * np.linalg.norm(xm[sd.gamma])
+        o += a + b
 
 
 def test_identity_activation_equals_lsrom():
-    """sigma = id makes g affine: g(xhat) = (x_ref + W2 b1) + (W2 W1) xhat.  The NM-ROM SQP
-    equals the SQP run with the explicit affine (LS-ROM) maps."""
+    """sigma = id makes g affine: g(xhat) = (x_ref + W2 b1) + (W2 W1) xhat (Sections 3.3, 3.4).
+    The NM-ROM SQP of rom.py then equals the independent LS-ROM solver (its own residual
+    Jacobian route, null-space QP steps, Cholesky initial multiplier) iterate for iterate."""
     m = _random_model(activation=ACT_IDENTITY, seed=5)
     mu = (1000.0, 9.2)
-    opts = SQPOptions(max_iter=40, tol_abs=0.0, tol_rel=1e-12)
-    res = sqp_solve(m, mu, opts=opts)
-    maps_om = [AffineMap(d.x_ref + d.W2() @ d.b1, d.W2() @ d.W1) for d in m.dec_om]
-    maps_ga = [AffineMap(d.x_ref + d.W2() @ d.b1, d.W2() @ d.W1) for d in m.dec_ga]
-    res2 = sqp_solve_with(m, mu, lsrom_decoders(maps_om, maps_ga), np.zeros(m.n_D), opts)
-    assert res.status == CONVERGED and res2.status == CONVERGED
-    assert np.linalg.norm(res.xhat - res2.xhat) <= 1e-10 * max(1.0, np.linalg.norm(res2.xhat))
-    assert res.iters == res2.iters
+    for max_iter in (1, 2, 40):
+        opts = SQPOptions(max_iter=max_iter, tol_abs=0.0, tol_rel=1e-12)
+        res = sqp_solve(m, mu, opts=opts)
+        om, ga = _affine_maps(m)
+        rom = lsrom.LSROM(m.fom, m.dd, m.C, [a for a, _ in om], [b for _, b in om], [a for a, _ in ga],
+                          [b for _, b in ga], hr=[lsrom.collocation_operator(m.grid, q) for q in m.hr_nodes])
+        res2 = lsrom.solve(rom, mu, max_iter=max_iter, tol_abs=0.0, tol_rel=1e-12)
+        assert res.status == res2.status and res.iters == res2.iters, (max_iter, res.status, res2.status)
+        assert np.linalg.norm(res.xhat - res2.xhat) <= 1e-10 * max(1.0, np.linalg.norm(res2.xhat))
+        assert np.linalg.norm(res.lam - res2.lam) <= 1e-8 * max(1.0, np.linalg.norm(res2.lam))
+        assert abs(res.fnorm0 - res2.fnorm0) <= 1e-10 * res2.fnorm0
+    assert res.status == CONVERGED
+
+
+@pytest.mark.parametrize("activation", [ACT_SIGMOID, ACT_SWISH, ACT_IDENTITY])
+def test_evaluate_derivatives_central_differences(activation):
+    """Z R_i = d(Z r_i)/dxhat and E_i = dc/dxhat_i^Gamma (eq. gauss_newton_hessian,
+    eq. optimality_residuals), checked by central differences over the whole latent vector:
+    each block sits at its own subdomain's columns (interior, then interface) and the other
+    columns vanish.  The KKT right-hand side is minus the gradient of the Lagrangian."""
+    m = _random_model(activation=activation, seed=11)
+    mu = (1500.0, 11.0)
+    rng = np.random.default_rng(3)
+    x = 0.4 * rng.standard_normal(m.n_D)
+    lam = rng.standard_normal(m.n_C)
+    ev = evaluate(m, mu, x)
+    h = 1e-6
+    dZr = [np.zeros((z.shape[0], m.n_D)) for z in ev.Zr]
+    dc = np.zeros((m.n_C, m.n_D))
+    dL = np.zeros(m.n_D)
+
+    def lagrangian(e):
+        return 0.5 * sum(float(z @ z) for z in e.Zr) + float(lam @ e.c)
+
+    for k in range(m.n_D):
+        e = np.zeros(m.n_D)
+        e[k] = h
+        ep, em = evaluate(m, mu, x + e), evaluate(m, mu, x - e)
+        for i in range(m.n_sub):
+            dZr[i][:, k] = (ep.Zr[i] - em.Zr[i]) / (2 * h)
+        dc[:, k] = (ep.c - em.c) / (2 * h)
+        dL[k] = (lagrangian(ep) - lagrangian(em)) / (2 * h)
+    Efull = np.zeros((m.n_C, m.n_D))
+    for i, (o, (a, b)) in enumerate(zip(m.offsets(), m.sizes())):
+        ref = np.zeros_like(dZr[i])
+        ref[:, o:o + a + b] = ev.ZR[i]
+        assert np.max(np.abs(dZr[i] - ref)) <= 1e-6 * max(1.0, np.max(np.abs(ref)))
+        Efull[:, o + a:o + a + b] = ev.EG[i]
+    assert np.max(np.abs(dc - Efull)) <= 1e-7 * max(1.0, np.max(np.abs(Efull)))
+    F = kkt_rhs(m, ev, lam)
+    assert np.max(np.abs(-F[:m.n_D] - dL)) <= 1e-6 * max(1.0, np.max(np.abs(dL)))
+    assert np.array_equal(-F[m.n_D:], ev.c)
+
+
+def test_initial_multiplier_least_squares():
+    """lambda^0 = argmin ||grad_xhat f + (dc/dxhat)^T lambda|| (the first-order conditions in
+    the latents, with f the HR objective): its residual is orthogonal to the range of the
+    constraint Jacobian's transpose, and perturbing it only grows the residual.  The
+    gradient and the constraint Jacobian are taken by central differences, not from
+    evaluate()."""
+    m = _random_model(seed=13)
+    mu = (700.0, 8.0)
+    x = 0.3 * np.random.default_rng(4).standard_normal(m.n_D)
+    ev = evaluate(m, mu, x)
+    lam0 = initial_multiplier(m, ev)
+    h = 1e-6
+    grad = np.zeros(m.n_D)
+    E = np.zeros((m.n_C, m.n_D))
+    for k in range(m.n_D):
+        e = np.zeros(m.n_D)
+        e[k] = h
+        ep, em = evaluate(m, mu, x + e), evaluate(m, mu, x - e)
+        grad[k] = (0.5 * sum(float(z @ z) for z in ep.Zr) - 0.5 * sum(float(z @ z) for z in em.Zr)) / (2 * h)
+        E[:, k] = (ep.c - em.c) / (2 * h)
+    res = grad + E.T @ lam0
+    assert np.linalg.norm(E @ res) <= 1e-6 * np.linalg.norm(E) * np.linalg.norm(grad)
+    rng = np.random.default_rng(5)
+    base = np.linalg.norm(res)
+    for _ in range(5):
+        d = 1e-3 * rng.standard_normal(m.n_C) * max(1.0, np.linalg.norm(lam0))
+        assert np.linalg.norm(grad + E.T @ (lam0 + d)) > base
+
+
+def test_stall_rule(tiny_pack):
+    """Stagnation stop (reading of the stopping rule for reduced-precision decoders): with an
+    unreachable tolerance, FP64 SQP runs until rounding stops the Armijo test from passing.
+    With stall_tol set, the solve then ends STALLED at a point whose ||F|| is below
+    stall_tol ||F_0||, where the full step indeed fails the Armijo test; with stall_tol = 0
+    the same solve ends LINESEARCH_FAIL or MAX_ITER instead, and a stall_tol below the
+    reached ||F|| / ||F_0|| never reports STALLED."""
+    m = load_pack(tiny_pack)
+    mu = si.heldout_mu(1, 11)[0]
+    res = sqp_solve(m, mu, opts=SQPOptions(max_iter=200, tol_abs=0.0, tol_rel=0.0, stall_tol=1e-6))
+    assert res.status == STALLED, res.status
+    assert res.fnorm <= 1e-6 * res.fnorm0
+    ev = evaluate(m, mu, res.xhat)
+    sx, sl = kkt_step(m, ev, res.lam)
+    F0 = kkt_rhs(m, ev, res.lam)
+    F1 = kkt_rhs(m, evaluate(m, mu, res.xhat + sx), res.lam + sl)
+    assert 0.5 * float(F1 @ F1) > (1.0 - 2.0 * 1e-4) * 0.5 * float(F0 @ F0)
+    res0 = sqp_solve(m, mu, opts=SQPOptions(max_iter=res.iters + 3, tol_abs=0.0, tol_rel=0.0, stall_tol=0.0))
+    assert res0.status in (LINESEARCH_FAIL, MAX_ITER)
+    tight = 0.5 * res.fnorm / res.fnorm0
+    r2 = sqp_solve(m, mu, opts=SQPOptions(max_iter=res.iters, tol_abs=0.0, tol_rel=0.0, stall_tol=tight * 1e-3))
+    assert r2.status != STALLED
 
 
 def test_relative_error_zero_for_exact_states():
