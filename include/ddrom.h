@@ -38,7 +38,10 @@ extern "C" {
 #define DDROM_STATUS_CONVERGED 0
 #define DDROM_STATUS_MAX_ITER 1
 #define DDROM_STATUS_LINESEARCH_FAIL 2
-#define DDROM_STATUS_KKT_NOT_PD 3     /* Lemma 1 hypotheses fail: an H_i or the Schur complement is not positive definite */
+#define DDROM_STATUS_KKT_NOT_PD 3     /* Lemma 1 hypotheses fail: an H_i or the Schur complement is not positive
+                                         definite, or (at the start) the normal equations of the least-squares
+                                         multiplier are not: the constraint Jacobian lacks full row rank; the
+                                         solve then stops at its start point with lambda = 0 */
 #define DDROM_STATUS_NONFINITE 4
 #define DDROM_STATUS_STALLED 5        /* Armijo failed with ||F|| <= stall_tol ||F_0||: the arithmetic's noise floor */
 

@@ -20,7 +20,12 @@ c1 = 1e-4, alpha halving, at most `max_backtracks` halvings; otherwise the solve
 with status LINESEARCH_FAIL at the last accepted point.  The solve stops when
 ||F||_2 <= max(tol_abs, tol_rel ||F_0||_2) or after max_iter steps.  The initial
 multiplier is the least-squares solution of the interface rows of the first-order
-conditions (eq. optimality_residuals b) at the initial latents.
+conditions (eq. optimality_residuals b) at the initial latents.  A step is taken only
+where Lemma 1's hypotheses hold (every H_i positive definite, the constraint Jacobian of
+full row rank); otherwise the solve stops with KKT_NOT_PD.  Where the constraint Jacobian
+at the start lacks full row rank the least-squares multiplier is not unique: the solve
+stops at once with KKT_NOT_PD and lambda = 0.  A start whose KKT residual is not finite
+stops with NONFINITE.
 """
 from __future__ import annotations
 
@@ -163,12 +168,31 @@ def initial_multiplier(model: ROMModel, ev: Evaluation) -> np.ndarray:
 
 
 def blocks_positive_definite(ev: Evaluation) -> bool:
+    """First hypothesis of Lemma 1: every H_i is positive definite (LAPACK Cholesky succeeds)."""
     try:
         for Hi in ev.H:
             np.linalg.cholesky(Hi)
         return True
     except np.linalg.LinAlgError:
         return False
+
+
+def constraint_full_row_rank(model: ROMModel, ev: Evaluation) -> bool:
+    """Second hypothesis of Lemma 1: the constraint Jacobian [E_1, ..., E_n] (only interface
+    columns are nonzero) has full row rank n_C; numerical rank by SVD with numpy's default
+    threshold."""
+    if model.n_C == 0:
+        return True
+    return int(np.linalg.matrix_rank(np.hstack(ev.EG))) == model.n_C
+
+
+def start_multiplier(model: ROMModel, ev: Evaluation):
+    """The initial multiplier and whether it is defined: the least-squares multiplier when the
+    constraint Jacobian has full row rank; otherwise the least-squares problem has no unique
+    solution (and Lemma 1 fails), lambda = 0 is returned with False."""
+    if not constraint_full_row_rank(model, ev):
+        return np.zeros(model.n_C), False
+    return initial_multiplier(model, ev), True
 
 
 @dataclass
@@ -199,7 +223,7 @@ def sqp_step(model: ROMModel, mu, xhat, lam, opts: SQPOptions, ev: Evaluation | 
     status is -1 for an accepted step."""
     if ev is None:
         ev = evaluate(model, mu, xhat)
-    if not blocks_positive_definite(ev):
+    if not (blocks_positive_definite(ev) and constraint_full_row_rank(model, ev)):
         return xhat, lam, ev, np.linalg.norm(kkt_rhs(model, ev, lam)), KKT_NOT_PD, 0, 0.0
     F = kkt_rhs(model, ev, lam)
     phi0 = 0.5 * float(F @ F)
@@ -227,7 +251,11 @@ def sqp_solve(model: ROMModel, mu, xhat0: np.ndarray | None = None, lam0: np.nda
     the first KKT residual norm of this start."""
     x = np.zeros(model.n_D) if xhat0 is None else np.array(xhat0, dtype=np.float64)
     ev = evaluate(model, mu, x)
-    lam = initial_multiplier(model, ev) if lam0 is None else np.array(lam0, dtype=np.float64)
+    lam_ok = True
+    if lam0 is None:
+        lam, lam_ok = start_multiplier(model, ev)
+    else:
+        lam = np.array(lam0, dtype=np.float64)
     F = kkt_rhs(model, ev, lam)
     fn = float(np.linalg.norm(F))
     f0 = fn if f_ref is None else float(f_ref)
@@ -235,6 +263,8 @@ def sqp_solve(model: ROMModel, mu, xhat0: np.ndarray | None = None, lam0: np.nda
     hist = [fn]
     if not np.isfinite(fn):
         return SQPResult(x, lam, NONFINITE, 0, fn, f0, n_eval, hist)
+    if not lam_ok:
+        return SQPResult(x, lam, KKT_NOT_PD, 0, fn, f0, n_eval, hist)
     tol = max(opts.tol_abs, opts.tol_rel * f0)
     for k in range(opts.max_iter):
         if fn <= tol:
@@ -257,7 +287,7 @@ def sqp_solve_warm(model: ROMModel, mu, xhat0: np.ndarray, lam0: np.ndarray, opt
     from .proposal import use_zero_start
     x_z = np.zeros(model.n_D)
     ev_z = evaluate(model, mu, x_z)
-    lam_z = initial_multiplier(model, ev_z)
+    lam_z, _ = start_multiplier(model, ev_z)
     f_zero = float(np.linalg.norm(kkt_rhs(model, ev_z, lam_z)))
     ev_p = evaluate(model, mu, np.asarray(xhat0, dtype=np.float64))
     f_prop = float(np.linalg.norm(kkt_rhs(model, ev_p, np.asarray(lam0, dtype=np.float64))))

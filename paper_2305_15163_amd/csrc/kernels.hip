@@ -130,7 +130,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
                                                        const T* __restrict__ W2, const T* __restrict__ XR,
                                                        const double* __restrict__ xhat, int xstride, int xoff_override,
                                                        const int* __restrict__ live, const int* __restrict__ n_live,
-                                                       int B, T* __restrict__ out, int Bp) {
+                                                       int B, T* __restrict__ out, int Bp, long long oshift) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int RK = RingSlots<T, ACT>::K;
     const DecChunk ch = chunks[chunk_base + blockIdx.x];
@@ -180,7 +180,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     for (int k = 0; k < NL; ++k) xl[k] = act ? (T)xhat[(size_t)b * xstride + xo + k] : (T)0;
     __syncthreads();
 
-    T* o = out + ((size_t)sg.out + (size_t)ch.r0 * (VO ? 1 : 1 + NL)) * Bp + j;
+    // output rows are numbered from the segment's first row in the model's decoder-output
+    // layout, less oshift (nonzero when the output buffer holds this segment alone)
+    T* o = out + ((size_t)(sg.out - oshift) + (size_t)ch.r0 * (VO ? 1 : 1 + NL)) * Bp + j;
     // Units [vlo, vhi) (relative to h_lo) are valid in the ring; vhi - vlo <= DEC_RING.  Rows
     // ascend, so windows mostly slide right, but near the first rows of a decoder a clipped
     // band can start below the previous row's window: missing units are then computed on
@@ -1242,6 +1244,9 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
     // ---- initial multiplier: argmin || [g_i^Gamma + (E_i^Gamma)^T lambda]_i ||, by its normal
     //      equations (sum_i Ehat_i Ehat_i^T) lambda = -sum_i Ehat_i g_i^Gamma ----
     const bool ls_start = S.phase == PH_ZERO || (S.phase == PH_INIT && !(S.flags & SF_LAMFIX));
+    // normal equations not positive definite: the constraint Jacobian lacks full row rank, the
+    // least-squares multiplier is not unique (Lemma 1 fails); lambda = 0 is kept instead
+    bool lam_bad = false;
     if (ls_start && !a.lam_given && nC > 0) {
         // (entries k >= n_i^Gamma of each Ehat_i row are zero)
         if (GB && a.sdc > 0)
@@ -1266,8 +1271,12 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
             Sm[i * ld + nC] = s;
         }
         __syncthreads();
-        kkt_lu(Sm, nC, lam_s, lu_ok, lu_f, tid, nth);
+        lam_bad = !kkt_lu(Sm, nC, lam_s, lu_ok, lu_f, tid, nth);
         __syncthreads();
+        if (lam_bad) {
+            for (int jj = tid; jj < nC; jj += nth) lam_s[jj] = 0.0;
+            __syncthreads();
+        }
     }
 
     // ---- merit at the trial point: phi = 0.5 (sum_i ||rho_i||^2 + ||c||^2), rho_i kept;
@@ -1341,6 +1350,9 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
         S.fn = fn_t;
         if (!isfinite(fn_t)) {
             S.status = DDROM_STATUS_NONFINITE;
+            action = 2;
+        } else if (lam_bad) {
+            S.status = DDROM_STATUS_KKT_NOT_PD;
             action = 2;
         }
         for (int jj = tid; jj < nC; jj += nth) {
@@ -1790,7 +1802,7 @@ namespace {
 template <int TAG, int VO = 0>
 static int launch_decode_items(const ddrom_model* m, int prec, int c0, int c1, int n, long long stage,
                                const double* xhat, int xstride, int xoff_override, const int* live, const int* n_live,
-                               int B, void* out, int Bp, hipStream_t s) {
+                               int B, void* out, int Bp, hipStream_t s, long long oshift = 0) {
     if (c1 <= c0) return 0;
     const int act = m->act;
     const int rk = act == DDROM_ACT_SWISH ? 2 : 1;
@@ -1806,7 +1818,7 @@ static int launch_decode_items(const ddrom_model* m, int prec, int c0, int c1, i
     const unsigned lds = (unsigned)L.total;
 #define DEC_LAUNCH(T, NLV, ACTV, WV, W1p, B1p, W2p, XRp)                                                          \
     hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG, VO>), grid, block, lds, s, m->chunks_d, c0, m->segs_d, W1p, \
-                       B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, live, n_live, B, (T*)out, Bp)
+                       B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, live, n_live, B, (T*)out, Bp, oshift)
 #define DEC_ACT(NLV, ACTV)                                                                                        \
     if (prec == DDROM_PREC_FP64) DEC_LAUNCH(double, NLV, ACTV, 1, m->W1d, m->b1d, m->W2d, m->xrefd);            \
     else if (ACTV == DDROM_ACT_SWISH) DEC_LAUNCH(float, NLV, ACTV, 2, m->W1f, m->b1f, m->W2f, m->xreff);         \
@@ -1834,10 +1846,10 @@ static int launch_decode_items(const ddrom_model* m, int prec, int c0, int c1, i
 template <int TAG, int VO = 0>
 static int launch_decode_seg(const ddrom_model* m, int prec, int g, const double* xhat, int xstride,
                              int xoff_override, const int* live, const int* n_live, int B, void* out, int Bp,
-                             hipStream_t s) {
+                             hipStream_t s, long long oshift = 0) {
     return launch_decode_items<TAG, VO>(m, prec, m->seg_chunk0[g], m->seg_chunk1[g], m->segs_h[g].n,
                                         prec == DDROM_PREC_FP64 ? m->seg_stage_f64[g] : m->seg_stage_f32[g], xhat,
-                                        xstride, xoff_override, live, n_live, B, out, Bp, s);
+                                        xstride, xoff_override, live, n_live, B, out, Bp, s, oshift);
 }
 
 template <int TAG, int VO = 0>
@@ -2295,31 +2307,43 @@ static int check_ws(const ddrom_model* m, const ddrom_workspace* ws, int B) {
     return 0;
 }
 
-static int decode_common(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
-                         int prec, void* x_d, void* J_d, hipStream_t s) {
-    int rc = check_ws(m, ws, B);
-    if (rc) return rc;
-    if (sd < 0 || sd >= m->n_sub || (part != 0 && part != 1) || !xhat_d || (prec != 0 && prec != 1)) {
+static int decode_args_ok(const ddrom_model* m, int sd, int part, const double* xhat_d, int prec) {
+    if (!m || sd < 0 || sd >= m->n_sub || (part != 0 && part != 1) || !xhat_d || (prec != 0 && prec != 1)) {
         set_error("bad arguments to ae_decode_hr / ae_jacobian_hr");
         return DDROM_EINVAL;
     }
-    if (B == 0) return 0;
+    return 0;
+}
+
+// Decode one segment into a staging buffer laid out [row][1 + n][Bp] (stage holds the segment's
+// rows from the model's row `first_row` on), then write the caller's [B][rows] / [B][rows][n].
+static int decode_staged(const ddrom_model* m, int sd, int part, const double* xhat_d, int B, int prec, void* x_d,
+                         void* J_d, void* stage, int Bp, long long first_row, hipStream_t s) {
     const int seg = part * m->n_sub + sd;
     const ddrom::DecSeg& sg = m->segs_h[seg];
-    if ((rc = launch_decode_seg<0>(m, prec, seg, xhat_d, sg.n, 0, nullptr, nullptr, B, ws->dec_out, ws->Bp, s)))
-        return rc;
+    int rc = launch_decode_seg<0>(m, prec, seg, xhat_d, sg.n, 0, nullptr, nullptr, B, stage, Bp, s, first_row);
+    if (rc) return rc;
     const long long tot = (long long)sg.rows * (1 + sg.n) * B;
     if (tot == 0) return 0;
     const int bs = 256;
     dim3 grid((unsigned)((tot + bs - 1) / bs));
     if (prec == DDROM_PREC_FP64)
-        hipLaunchKernelGGL(k_dec_transpose<double>, grid, dim3(bs), 0, s, (const double*)ws->dec_out, sg.out, sg.rows,
-                           sg.n, B, ws->Bp, (double*)x_d, (double*)J_d);
+        hipLaunchKernelGGL(k_dec_transpose<double>, grid, dim3(bs), 0, s, (const double*)stage, sg.out - first_row,
+                           sg.rows, sg.n, B, Bp, (double*)x_d, (double*)J_d);
     else
-        hipLaunchKernelGGL(k_dec_transpose<float>, grid, dim3(bs), 0, s, (const float*)ws->dec_out, sg.out, sg.rows,
-                           sg.n, B, ws->Bp, (float*)x_d, (float*)J_d);
+        hipLaunchKernelGGL(k_dec_transpose<float>, grid, dim3(bs), 0, s, (const float*)stage, sg.out - first_row,
+                           sg.rows, sg.n, B, Bp, (float*)x_d, (float*)J_d);
     HIPCHECK(hipGetLastError());
     return 0;
+}
+
+static int decode_common(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
+                         int prec, void* x_d, void* J_d, hipStream_t s) {
+    int rc = check_ws(m, ws, B);
+    if (rc) return rc;
+    if ((rc = decode_args_ok(m, sd, part, xhat_d, prec))) return rc;
+    if (B == 0) return 0;
+    return decode_staged(m, sd, part, xhat_d, B, prec, x_d, J_d, ws->dec_out, ws->Bp, 0, s);
 }
 
 int ae_decode_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,

@@ -12,8 +12,8 @@ from oracle.autoencoder import decode_jacobian
 from oracle.burgers import solve_fom
 from oracle.ddmaps import subdomain_residual_jac
 from oracle.pack import load_pack
-from oracle.rom import (CONVERGED, SQPOptions, evaluate, hr_interior_rows, kkt_rhs, relative_error, sqp_solve,
-                        sqp_step)
+from oracle.rom import (CONVERGED, SQPOptions, evaluate, hr_interior_rows, kkt_matrix, kkt_rhs, relative_error,
+                        sqp_solve, sqp_step)
 
 
 @pytest.fixture(scope="module")
@@ -146,6 +146,9 @@ def test_sqp_step_parity(dr, case):
     x1, l1, fn, st = (t.cpu().numpy() for t in dr.sqp_step(gm, ws, mus, xh, lam, o))
     for b in range(B):
         xr, lr, _, fr, sr, _, _ = sqp_step(om, mus[b], xh[b], lam[b], SQPOptions(max_backtracks=20))
+        kap = np.linalg.cond(kkt_matrix(om, evaluate(om, mus[b], xh[b])))
+        print(name, b, "step x err %.2e lam err %.2e cond(K) %.2e" % (relerr(x1[b], xr), relerr(l1[b], lr), kap),
+              flush=True)
         assert int(st[b]) == (1 if sr == -1 else sr)
         assert relerr(x1[b], xr) <= 1e-10
         assert relerr(l1[b], lr) <= 1e-8
@@ -162,7 +165,12 @@ def test_rom_solve_parity(dr, case, B):
     out = {k: v.cpu().numpy() for k, v in out.items()}
     for b in range(B):
         ref = sqp_solve(om, mus[b], opts=SQPOptions(max_iter=100, tol_abs=0.0, tol_rel=1e-12))
-        print(name, b, "status", out["status"][b], ref.status, "iters", out["iters"][b], ref.iters, flush=True)
+        ev = evaluate(om, mus[b], ref.xhat)
+        kap = np.linalg.cond(kkt_matrix(om, ev))
+        print(name, b, "status", out["status"][b], ref.status, "iters", out["iters"][b], ref.iters,
+              "x err %.2e lam err %.2e cond(K) %.2e |F|/|F0| %.2e" % (
+                  relerr(out["xhat"][b], ref.xhat), relerr(out["lam"][b][:gm.n_C], ref.lam), kap,
+                  ref.fnorm / ref.fnorm0), flush=True)
         assert int(out["status"][b]) == ref.status
         assert relerr(out["xhat"][b], ref.xhat) <= 1e-10
         assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-7

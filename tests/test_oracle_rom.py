@@ -13,7 +13,7 @@ from oracle.ddmaps import build_dd, restrict
 from oracle.pack import load_pack
 from oracle import lsrom
 from oracle.rom import (CONVERGED, LINESEARCH_FAIL, MAX_ITER, STALLED, ROMModel, SQPOptions, dd_fom_sqp, evaluate,
-                        initial_multiplier, kkt_rhs, kkt_step, relative_error_states, sqp_solve)
+                        initial_multiplier, kkt_rhs, kkt_step, relative_error_states, sqp_solve, sqp_step)
 
 
 def test_theorem1_dd_fom_equals_monolithic():
@@ -287,3 +287,86 @@ def test_cfg0_solve_converges(cfg0_pack):
     res = sqp_solve(m, mu, opts=SQPOptions(max_iter=50, tol_abs=0.0, tol_rel=1e-8))
     assert res.status == CONVERGED
     assert res.fnorm <= 1e-8 * res.fnorm0
+
+
+# ---- stop statuses (Lemma 1 hypotheses, non-finite data, line search, iteration cap) ----
+
+def test_rank_deficient_constraint_stops_kkt_not_pd(tiny_pack):
+    """A zero row of C gives the constraint Jacobian a zero row: the KKT matrix of
+    eq. sqp_system has an exactly zero row (it is singular, Lemma 1's full-row-rank
+    hypothesis fails) and the least-squares multiplier is not unique.  The solve stops at
+    once with KKT_NOT_PD, lambda = 0, at the start point."""
+    from oracle.rom import KKT_NOT_PD, constraint_full_row_rank, kkt_matrix
+    from status_cases import rank_deficient_constraint
+    m = load_pack(rank_deficient_constraint(tiny_pack))
+    mu = si.heldout_mu(1, 11)[0]
+    ev = evaluate(m, mu, np.zeros(m.n_D))
+    K = kkt_matrix(m, ev)
+    assert np.all(K[m.n_D] == 0.0)
+    assert not constraint_full_row_rank(m, ev)
+    res = sqp_solve(m, mu, opts=SQPOptions(max_iter=20, tol_abs=0.0, tol_rel=1e-10))
+    assert res.status == KKT_NOT_PD and res.iters == 0
+    assert np.all(res.xhat == 0.0) and np.all(res.lam == 0.0)
+    assert res.fnorm == np.linalg.norm(kkt_rhs(m, ev, np.zeros(m.n_C)))
+
+
+def test_singular_block_stops_kkt_not_pd(tiny_pack):
+    """A zero column of an interior decoder's W1 makes Z R_0 lose a column exactly, so H_0
+    (and the KKT matrix) has a zero row: Lemma 1's positive-definiteness hypothesis fails at
+    the first step.  The solve stops with KKT_NOT_PD at the start point with the
+    least-squares multiplier."""
+    from oracle.rom import KKT_NOT_PD, kkt_matrix
+    from status_cases import singular_block
+    m = load_pack(singular_block(tiny_pack, sd=0, col=1))
+    mu = si.heldout_mu(1, 11)[0]
+    ev = evaluate(m, mu, np.zeros(m.n_D))
+    assert np.all(ev.H[0][1] == 0.0) and np.all(kkt_matrix(m, ev)[1] == 0.0)
+    res = sqp_solve(m, mu, opts=SQPOptions(max_iter=20, tol_abs=0.0, tol_rel=1e-10))
+    assert res.status == KKT_NOT_PD and res.iters == 0
+    assert np.all(res.xhat == 0.0)
+    assert np.allclose(res.lam, initial_multiplier(m, ev), rtol=0, atol=0)
+
+
+def test_nonfinite_parameter_stops_nonfinite(tiny_pack):
+    """A NaN parameter makes the Dirichlet data, hence the first KKT residual, NaN."""
+    from oracle.rom import NONFINITE
+    m = load_pack(tiny_pack)
+    for mu in ((np.nan, 10.0), (500.0, np.nan)):
+        res = sqp_solve(m, mu, opts=SQPOptions(max_iter=10))
+        assert res.status == NONFINITE and res.iters == 0 and not np.isfinite(res.fnorm)
+
+
+def test_linesearch_fail_without_backtracking(tiny_pack):
+    """max_backtracks = 0: the solve stops with LINESEARCH_FAIL exactly where the full KKT step
+    fails the Armijo test phi(1) <= (1 - 2 c1) phi(0), recomputed here from the returned point."""
+    m = load_pack(tiny_pack)
+    mus = si.heldout_mu(8, 17)
+    seen = 0
+    for mu in mus:
+        res = sqp_solve(m, mu, opts=SQPOptions(max_iter=10, tol_abs=0.0, tol_rel=1e-12, max_backtracks=0))
+        if res.status != LINESEARCH_FAIL:
+            continue
+        seen += 1
+        ev = evaluate(m, mu, res.xhat)
+        sx, sl = kkt_step(m, ev, res.lam)
+        F0 = kkt_rhs(m, ev, res.lam)
+        F1 = kkt_rhs(m, evaluate(m, mu, res.xhat + sx), res.lam + sl)
+        assert 0.5 * float(F1 @ F1) > (1.0 - 2.0 * 1e-4) * 0.5 * float(F0 @ F0)
+        assert res.fnorm == np.linalg.norm(F0)
+    assert seen >= 2
+
+
+def test_max_iter_one_is_one_step(tiny_pack):
+    """max_iter = 1 stops after one accepted step (MAX_ITER unless it already converged) at the
+    point sqp_step returns from the start."""
+    from oracle.rom import start_multiplier
+    m = load_pack(tiny_pack)
+    for mu in si.heldout_mu(3, 19):
+        res = sqp_solve(m, mu, opts=SQPOptions(max_iter=1, tol_abs=0.0, tol_rel=1e-12))
+        x0 = np.zeros(m.n_D)
+        ev = evaluate(m, mu, x0)
+        lam0, ok = start_multiplier(m, ev)
+        assert ok
+        x1, l1, _, f1, st, _, _ = sqp_step(m, mu, x0, lam0, SQPOptions(), ev)
+        assert st == -1 and res.status == MAX_ITER and res.iters == 1
+        assert np.array_equal(res.xhat, x1) and np.array_equal(res.lam, l1) and res.fnorm == f1
