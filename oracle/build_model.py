@@ -47,6 +47,11 @@ CONFIGS = {
                   epochs=300, batch=16, train_grid=(8, 8), hr_frac=(0.05, 0.25), seed=22),
     "cfg2c": dict(nx=480, ny=480, nsx=8, nsy=8, n_om="draw", n_ga="half", b=9, s=2, act=ACT_SIGMOID,
                   epochs=300, batch=16, train_grid=(8, 8), hr_frac=(0.05, 0.25), seed=23),
+    # the 240x240, 4x4, latent (8,4) shape (16 subdomains, 360 HR nodes each, 32 constraints) at
+    # a small training budget (2 x 2 parameter grid, 20 epochs): parity cases at the benchmark's
+    # sizes when its trained pack is not at hand
+    "cfg1shape": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID,
+                      epochs=20, batch=4, train_grid=(2, 2), hr_frac=0.10, seed=1),
     # small configurations for tests
     "tinymix": dict(nx=16, ny=12, nsx=2, nsy=2, n_om="draw", n_ga="half", b=3, s=2, act=ACT_SIGMOID,
                     epochs=300, batch=4, train_grid=(4, 4), hr_frac=(0.3, 0.6), seed=31),

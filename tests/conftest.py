@@ -57,3 +57,17 @@ def tinyhuge_pack():
     from oracle.build_model import build
     pack, *_ = build("tinyhuge", workers=1, verbose=False)
     return pack
+
+
+@pytest.fixture(scope="session")
+def headline_pack():
+    """The 240x240, 4x4, latent (8,4) workload's model pack: the trained pack the benchmark
+    solves (models/cfg1.npz, written by the oracle pipeline) when present, else a pack of the
+    same shape built by the oracle pipeline at a small training budget (about a minute)."""
+    import numpy as np
+    path = os.path.join(ROOT, "models", "cfg1.npz")
+    if os.path.exists(path):
+        return "cfg1", dict(np.load(path, allow_pickle=False))
+    from oracle.build_model import build
+    pack, *_ = build("cfg1shape", workers=min(4, os.cpu_count() or 1), verbose=False)
+    return "cfg1shape", pack
