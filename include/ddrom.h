@@ -155,6 +155,19 @@ int ae_decode_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, co
 int ae_jacobian_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
                    int precision, void* x_d, void* J_d, hipStream_t s);
 
+/* For callers that cannot allocate device memory (work under HIP graph capture, serving loops
+ * or harnesses that forbid hipMalloc): ae_jacobian_hr without a workspace.  It calls no
+ * allocating routine; the decoder's staging output ([rows][1 + n][Bp] values, Bp = B rounded up
+ * to a multiple of 64) lives in a library-owned device array of DDROM_NOALLOC_SCRATCH_BYTES that
+ * every GPU the library runs on holds until the process ends.  A decoder and batch needing more
+ * (rows (1 + n) Bp times 8 bytes in FP64, 4 in FP32) return DDROM_ESHAPE.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (different streams without ordering, or
+ * host threads) race and must be serialised by the caller.  Outputs and errors as in
+ * ae_jacobian_hr. */
+#define DDROM_NOALLOC_SCRATCH_BYTES (16u << 20)
+int ae_jacobian_hr_noalloc(const ddrom_model* m, int sd, int part, const double* xhat_d, int B, int precision,
+                           void* x_d, void* J_d, hipStream_t s);
+
 /* Per-subdomain SQP blocks at xhat (eq. gauss_newton_hessian, optimality_residuals_GN):
  * H_d [B][n_sub][nmax][nmax] (H_i = (Z R_i)^T Z R_i, upper-left n_i x n_i used),
  * g_d [B][n_D] ((Z R_i)^T Z r_i stacked), EG_d [B][n_sub][n_C][mmax] (C A_i dg_i^Gamma/dxhat),

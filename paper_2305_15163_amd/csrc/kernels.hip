@@ -2346,6 +2346,37 @@ static int decode_common(const ddrom_model* m, ddrom_workspace* ws, int sd, int 
     return decode_staged(m, sd, part, xhat_d, B, prec, x_d, J_d, ws->dec_out, ws->Bp, 0, s);
 }
 
+// ---- Allocation-free decoder entry point ----------------------------------------------------
+// Its staging buffer is this file-scope device array: every GPU the library runs on holds its own
+// copy from module load until the process ends.  Host code never uses the name `scratch` as an
+// address (in host code it is only a stand-in for the symbol): the device address of the current
+// GPU's copy is looked up once per device with hipGetSymbolAddress and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[DDROM_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+static int scratch_address(void** out) {
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device ordinal out of range for the allocation-free entry point");
+        return DDROM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+            return DDROM_EHIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return 0;
+}
+
 int ae_decode_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, const double* xhat_d, int B,
                  int precision, void* x_d, hipStream_t s) {
     if (!x_d) {
@@ -2362,6 +2393,34 @@ int ae_jacobian_hr(const ddrom_model* m, ddrom_workspace* ws, int sd, int part, 
         return DDROM_EINVAL;
     }
     return decode_common(m, ws, sd, part, xhat_d, B, precision, x_d, J_d, s);
+}
+
+int ae_jacobian_hr_noalloc(const ddrom_model* m, int sd, int part, const double* xhat_d, int B, int precision,
+                           void* x_d, void* J_d, hipStream_t s) {
+    if (!J_d) {
+        set_error("J_d is NULL");
+        return DDROM_EINVAL;
+    }
+    int rc = decode_args_ok(m, sd, part, xhat_d, precision);
+    if (rc) return rc;
+    if (B < 0) {
+        set_error("negative batch");
+        return DDROM_EINVAL;
+    }
+    if (B == 0) return 0;
+    const ddrom::DecSeg& sg = m->segs_h[part * m->n_sub + sd];
+    const long long Bp = ((long long)B + 63) / 64 * 64;
+    const long long esz = precision == DDROM_PREC_FP64 ? 8 : 4;
+    const long long need = (long long)sg.rows * (1 + sg.n) * Bp * esz;
+    if (need > (long long)DDROM_NOALLOC_SCRATCH_BYTES) {
+        set_error("ae_jacobian_hr_noalloc: this decoder and batch need " + std::to_string(need) +
+                  " bytes of staging; the allocation-free entry point holds " +
+                  std::to_string((long long)DDROM_NOALLOC_SCRATCH_BYTES) + " (use ae_jacobian_hr with a workspace)");
+        return DDROM_ESHAPE;
+    }
+    void* stage = nullptr;
+    if ((rc = scratch_address(&stage))) return rc;
+    return decode_staged(m, sd, part, xhat_d, B, precision, x_d, J_d, stage, (int)Bp, sg.out, s);
 }
 
 int ddrom_gn_blocks(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, const double* xhat_d, int B,

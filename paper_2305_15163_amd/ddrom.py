@@ -65,6 +65,7 @@ def lib():
         L.dd_fom_residual.argtypes = [vp, vp, vp, ip, vp, vp, vp]
         L.ae_decode_hr.argtypes = [vp, vp, ip, ip, vp, ip, ip, vp, vp]
         L.ae_jacobian_hr.argtypes = [vp, vp, ip, ip, vp, ip, ip, vp, vp, vp]
+        L.ae_jacobian_hr_noalloc.argtypes = [vp, ip, ip, vp, ip, ip, vp, vp, vp]
         L.ddrom_gn_blocks.argtypes = [vp, vp, vp, vp, ip, ip, vp, vp, vp, vp, vp, vp]
         L.sqp_step.argtypes = [vp, vp, vp, ip, vp, vp, vp, vp, C.POINTER(Opts), vp]
         L.rom_solve_batch.argtypes = [vp, vp, vp, ip, vp, vp, C.POINTER(Opts), vp, vp, vp, vp, vp, vp, vp]
@@ -234,6 +235,19 @@ def ae_jacobian_hr(model: Model, ws: Workspace, sd: int, part: int, xhat, precis
     J = torch.empty((B, rows, n), dtype=dt, device="cuda")
     _check(lib().ae_jacobian_hr(model.h, ws.h, sd, part, _ptr(xhat), B, precision, _ptr(x), _ptr(J), _stream()),
            "ae_jacobian_hr")
+    return x, J
+
+
+def ae_jacobian_hr_noalloc(model: Model, sd: int, part: int, xhat, x, J, precision=PREC_FP64):
+    """ae_jacobian_hr without a workspace, into caller-allocated x [B][rows] (or None) and
+    J [B][rows][n] of the precision's dtype; the library allocates nothing."""
+    xhat = _need(xhat, torch.float64, "xhat")
+    dt = torch.float64 if precision == PREC_FP64 else torch.float32
+    if x is not None:
+        _need(x, dt, "x")
+    _need(J, dt, "J")
+    _check(lib().ae_jacobian_hr_noalloc(model.h, sd, part, _ptr(xhat), xhat.shape[0], precision, _ptr(x), _ptr(J),
+                                        _stream()), "ae_jacobian_hr_noalloc")
     return x, J
 
 
