@@ -56,10 +56,10 @@ def decoder_source_sha1():
 
 
 CONFIGS = {
-    "cfg1": dict(batch=512, seed=1, precision=1, tol_rel=1e-6, stall_tol=1e-5, max_iter=60,
+    "cfg1": dict(batch=512, seed=1, proposal_seed=5, precision=1, tol_rel=1e-6, stall_tol=1e-5, max_iter=60,
                  workload="Burgers 240x240, 4x4 subdomains, latent (8,4), width 2x, band 9, HR 10%, "
                           "512 held-out (a,lambda), FP32 decoder + FP64 KKT"),
-    "cfg0": dict(batch=1, seed=0, precision=0, tol_rel=1e-8, stall_tol=0.0, max_iter=60,
+    "cfg0": dict(batch=1, seed=0, proposal_seed=5, precision=0, tol_rel=1e-8, stall_tol=0.0, max_iter=60,
                  workload="Burgers 36x36, 2x2 subdomains, latent (6,3), width 3x, band 5, HR 20%, "
                           "1 held-out (a,lambda), FP64"),
 }
@@ -289,6 +289,65 @@ def cpu_all_cores(path, max_iter, B, seed, secs=10.0):
                       f"held-out parameters of the 240x240 workload"}
 
 
+# Child program for the FOM reference states: one worker process per core (BLAS limited to one
+# thread each) solves the monolithic FOM by Newton for every parameter of the list it is given
+# and writes the states.  It never touches the GPU.
+_FOM_POOL = r"""
+import os, sys, time
+for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[v] = "1"
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+from multiprocessing import Pool
+
+def work(args):
+    nx, ny, mu = args
+    from oracle.burgers import BurgersFOM, Grid, solve_fom
+    t0 = time.perf_counter()
+    r = solve_fom(BurgersFOM(Grid(nx, ny)), mu)
+    return r.x, bool(r.converged), time.perf_counter() - t0
+
+n, nx, ny, src, dst = int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]), sys.argv[5], sys.argv[6]
+mus = np.load(src)
+with Pool(n) as pool:
+    res = pool.map(work, [(nx, ny, tuple(m)) for m in mus], chunksize=1)
+np.save(dst, np.stack([r[0] for r in res]))
+np.save(dst + ".meta.npy", np.array([[float(r[1]), r[2]] for r in res]))
+"""
+
+
+def fom_states(mus, nx, ny):
+    """FOM Newton states for each parameter (host CPU, one process per core, at most 16).
+    Returns (states [n][N_x], seconds per solve on one core, cores used)."""
+    import subprocess
+    import tempfile
+    n = min(os.cpu_count() or 1, 16)
+    with tempfile.TemporaryDirectory() as d:
+        src, dst = os.path.join(d, "mu.npy"), os.path.join(d, "x.npy")
+        np.save(src, np.ascontiguousarray(mus, dtype=np.float64))
+        r = subprocess.run([sys.executable, "-c", _FOM_POOL, ROOT, str(n), str(nx), str(ny), src, dst],
+                           capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError("FOM reference run failed: " + r.stderr[-2000:])
+        X = np.load(dst)
+        meta = np.load(dst + ".meta.npy")
+    if not np.all(meta[:, 0] > 0):
+        raise RuntimeError("FOM Newton did not converge for some reference parameter")
+    return X, float(meta[:, 1].mean()), n
+
+
+def error_summary(err, status, dr):
+    """eq. relative_error against the FOM over a subset of solves, overall and split by status."""
+    err = np.asarray(err, dtype=np.float64)
+    status = np.asarray(status)
+    out = {"n": int(len(err)), "mean": float(err.mean()), "median": float(np.median(err)),
+           "max": float(err.max()), "by_status": {}}
+    for k in np.unique(status):
+        e = err[status == k]
+        out["by_status"][dr.STATUS[int(k)]] = {"n": int(len(e)), "mean": float(e.mean()), "max": float(e.max())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,7 +355,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--plain", type=int, default=8, help="parameters for the plain per-solve GPU SQP leg")
+    ap.add_argument("--plain", type=int, default=64, help="parameters for the plain per-solve GPU SQP legs")
+    ap.add_argument("--n-err", type=int, default=64, help="parameters per leg for the error against the FOM")
+    ap.add_argument("--proposal-batch", type=int, default=2048, help="held-out parameters of the proposal leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-model uneven batch leg")
     ap.add_argument("--uneven-only", action="store_true", help="run only the three-model uneven batch leg")
     ap.add_argument("--no-ae", action="store_true", help="skip the autoencoder training leg")
@@ -412,33 +473,71 @@ def main():
     roof["ms_per_launch"] = {"decode_interior": ms[0], "decode_interface": ms[1], "residual_gn": ms[2], "constraint": ms[3]}
     print(f"[bench] kernel ms {ms}", file=sys.stderr, flush=True)
 
-    # plain per-solve GPU SQP: B = 1, FP64, zero start, sequential host calls
-    plain = None
+    # plain per-solve GPU SQP: B = 1, zero start, sequential host calls; once in FP64 at the
+    # relative tolerance 1e-8, once at the batch's own precision and stopping rule
+    plain, px, pst, px32, pst32 = None, None, None, None, None
     a.plain = min(a.plain, B)
     if a.plain > 0:
         ws1 = dr.Workspace(model, 1)
-        o1 = dr.opts(max_iter=cfg["max_iter"], tol_rel=1e-8, precision=0)
-        dr.rom_solve_batch(model, ws1, mu[:1], o1)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        px = []
-        for b in range(a.plain):
-            r = dr.rom_solve_batch(model, ws1, mu[b:b + 1], o1)
-            px.append(r["xhat"])
-        torch.cuda.synchronize()
-        pt = time.perf_counter() - t1
-        plain = {"solves_per_s": a.plain / pt, "n": a.plain, "precision": "f64", "batch": 1}
-        px = torch.cat(px).cpu().numpy()
-        print(f"[bench] plain per-solve SQP {plain['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
+        legs = {}
+        for tag, o1 in (("f64", dr.opts(max_iter=cfg["max_iter"], tol_rel=1e-8, precision=0)), ("batch_precision", o)):
+            dr.rom_solve_batch(model, ws1, mu[:1], o1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            outs = [dr.rom_solve_batch(model, ws1, mu[b:b + 1], o1) for b in range(a.plain)]
+            torch.cuda.synchronize()
+            pt = time.perf_counter() - t1
+            xs = torch.cat([r["xhat"] for r in outs]).cpu().numpy()
+            ss = torch.cat([r["status"] for r in outs]).cpu().numpy()
+            its = torch.cat([r["iters"] for r in outs]).cpu().numpy()
+            legs[tag] = {"solves_per_s": a.plain / pt, "n": a.plain, "batch": 1, "iters_mean": float(its.mean()),
+                         "status_counts": {dr.STATUS[k]: int((ss == k).sum()) for k in np.unique(ss)}}
+            if tag == "f64":
+                px, pst = xs, ss
+                legs[tag].update(precision="f64", stop="||F|| <= 1e-8 ||F0||")
+            else:
+                px32, pst32 = xs, ss
+                legs[tag].update(precision="f32+f64", stop=line_stop(cfg))
+            print(f"[bench] plain per-solve SQP ({tag}) {legs[tag]['solves_per_s']:.1f} solves/s", file=sys.stderr,
+                  flush=True)
+        plain = legs["f64"]
+        plain["same_precision_leg"] = legs["batch_precision"]
+
+    # learned-proposal leg at its own workload size: 2048 held-out parameters, warm start vs zero start
+    prop_leg = None
+    if prop is not None and a.proposal_batch > 0:
+        Bq = a.proposal_batch
+        mu_q_h = si.heldout_mu(Bq, cfg["proposal_seed"])
+        mu_q = torch.as_tensor(mu_q_h, device="cuda")
+        wsq = dr.Workspace(model, Bq)
+        res_q = {}
+        for tag, fn in (("warm", lambda: dr.rom_solve_warm(model, wsq, prop, mu_q, o)),
+                        ("zero_start", lambda: dr.rom_solve_batch(model, wsq, mu_q, o))):
+            fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(a.steps):
+                r = fn()
+            torch.cuda.synchronize()
+            dtq = time.perf_counter() - t1
+            rq = {k: v.cpu().numpy().copy() for k, v in r.items()}
+            res_q[tag] = rq
+            res_q[tag + "_rate"] = {"solves_per_s": Bq * a.steps / dtq, "iters_mean": float(rq["iters"].mean()),
+                                    "iters_max": int(rq["iters"].max()),
+                                    "status_counts": {dr.STATUS[k]: int((rq["status"] == k).sum())
+                                                      for k in np.unique(rq["status"])}}
+        prop_leg = {"workload": f"{Bq} held-out (a,lambda) (seed {cfg['proposal_seed']}), same model and options",
+                    "warm": res_q["warm_rate"], "zero_start": res_q["zero_start_rate"],
+                    "fallback_count": int(res_q["warm"]["fallback"].sum())}
+        print(f"[bench] proposal leg: warm {prop_leg['warm']['solves_per_s']:.0f} solves/s, zero start "
+              f"{prop_leg['zero_start']['solves_per_s']:.0f}", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if cfg["precision"] == 1 else "f64", "data": "synthetic",
         "config": {"workload": cfg["workload"], "batch": B, "subdomains": model.n_sub, "n_D": model.n_D,
-                   "work_item_shape": list(model.tile),
-                   "n_C": model.n_C, "stop": f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
-                                             f"or line-search stagnation below {cfg['stall_tol']:g} ||F0||",
+                   "work_item_shape": list(model.tile), "n_C": model.n_C, "stop": line_stop(cfg),
                    "start": ("learned proposal, zero-start fallback" if prop is not None else "zero start")},
         "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
         "status_counts": {dr.STATUS[k]: int((status == k).sum()) for k in np.unique(status)},
@@ -447,6 +546,8 @@ def main():
         "roofline": roof,
         "plain_sqp": plain,
         "speedup_vs_plain": (value / plain["solves_per_s"]) if plain else None,
+        "speedup_vs_plain_same_precision": (value / plain["same_precision_leg"]["solves_per_s"]) if plain else None,
+        "proposal": prop_leg,
     }
 
     if not a.no_uneven:
@@ -454,43 +555,90 @@ def main():
     if not a.no_ae:
         line["ae_training"] = ae_training_leg(a, torch, dr, si)
 
+    # error against the FOM (eq. relative_error) on the first n_err parameters of each leg
+    if a.n_err > 0:
+        n_err = min(a.n_err, B)
+        sets = [mu_h[:n_err]]
+        if prop_leg is not None:
+            sets.append(mu_q_h[:min(a.n_err, Bq)])
+        t2 = time.perf_counter()
+        Xf, fom_s, fom_cores = fom_states(np.concatenate(sets), model_grid(pack)[0], model_grid(pack)[1])
+        print(f"[bench] {len(Xf)} FOM reference states in {time.perf_counter() - t2:.1f}s on {fom_cores} cores",
+              file=sys.stderr, flush=True)
+        wse = dr.Workspace(model, n_err)
+        Xf_d = torch.as_tensor(Xf[:n_err], device="cuda")
+
+        def errs(xh):
+            return dr.relative_error(model, wse, torch.as_tensor(xh[:n_err], device="cuda"), Xf_d).cpu().numpy()
+
+        e_b, e_z = errs(xb), errs(res_c["xhat"])
+        rel = {"n": n_err, "subset": f"the first {n_err} of the {B} held-out parameters",
+               "batched": error_summary(e_b, status[:n_err], dr),
+               "zero_start_batch": error_summary(e_z, res_c["status"][:n_err], dr)}
+        if px is not None:
+            m = min(n_err, len(px))
+            e_p, e_p32 = errs(px)[:m], errs(px32)[:m]
+            rel["plain_f64"] = error_summary(e_p, pst[:m], dr)
+            rel["plain_same_precision"] = error_summary(e_p32, pst32[:m], dr)
+            ratio = e_b[:m] / e_p
+            rel["batched_over_plain_f64"] = {"max": float(ratio.max()), "median": float(np.median(ratio)),
+                                             "within_1.1": int((ratio <= 1.1).sum()), "n": m}
+        if prop_leg is not None:
+            nq = min(a.n_err, Bq)
+            Xq_d = torch.as_tensor(Xf[n_err:n_err + nq], device="cuda")
+            wsq2 = dr.Workspace(model, nq)
+            e_w = dr.relative_error(model, wsq2, torch.as_tensor(res_q["warm"]["xhat"][:nq], device="cuda"),
+                                    Xq_d).cpu().numpy()
+            e_q0 = dr.relative_error(model, wsq2, torch.as_tensor(res_q["zero_start"]["xhat"][:nq], device="cuda"),
+                                     Xq_d).cpu().numpy()
+            prop_leg["rel_err_vs_fom"] = {"n": nq, "warm": error_summary(e_w, res_q["warm"]["status"][:nq], dr),
+                                          "zero_start": error_summary(e_q0, res_q["zero_start"]["status"][:nq], dr)}
+        line["rel_err_vs_fom"] = rel
+        # the FOM's Newton solve per parameter on one host core (the paper's speedup denominator)
+        line["fom_newton_s_per_mu"] = {"value": fom_s, "n": len(Xf), "cores": 1,
+                                       "solves_per_s_vs_fom": line["value"] * fom_s}
+
     if not a.no_cpu:
         from threadpoolctl import threadpool_limits
-        from oracle.burgers import solve_fom
         from oracle.pack import load_pack
-        from oracle.rom import SQPOptions, relative_error, sqp_solve
+        from oracle.rom import SQPOptions, sqp_solve
         om = load_pack(pack)
         with threadpool_limits(limits=1):
             t2 = time.perf_counter()
-            n_cpu = 0
+            n_cpu, ref = 0, []
             while True:
-                sqp_solve(om, mu_h[n_cpu], opts=SQPOptions(max_iter=cfg["max_iter"], tol_abs=0.0, tol_rel=1e-8))
+                ref.append(sqp_solve(om, mu_h[n_cpu], opts=SQPOptions(max_iter=cfg["max_iter"], tol_abs=0.0,
+                                                                      tol_rel=1e-8)))
                 n_cpu += 1
                 if time.perf_counter() - t2 > 10.0 or n_cpu >= B:
                     break
             ct = time.perf_counter() - t2
-            line["cpu_baseline"] = {"value": n_cpu / ct, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                                    "sample": f"{n_cpu} of the {B} parameters, FP64 oracle SQP (dense KKT), "
-                                              f"relative KKT tolerance 1e-8, BLAS limited to 1 thread"}
-            # error against the FOM on a few parameters: batched (this run) and plain SQP
-            errs, perrs, tf = [], [], []
-            for b in range(min(3, B)):
-                t3 = time.perf_counter()
-                xf = solve_fom(om.fom, mu_h[b]).x
-                tf.append(time.perf_counter() - t3)
-                errs.append(relative_error(om, xb[b], xf))
-                if plain is not None and b < len(px):
-                    perrs.append(relative_error(om, px[b], xf))
-            line["rel_err_vs_fom"] = {"batched": errs, "plain_sqp": perrs, "n": len(errs)}
-            # the FOM's Newton solve per parameter on one host core (the paper's speedup denominator)
-            line["fom_newton_s_per_mu"] = {"value": float(np.mean(tf)), "n": len(tf), "cores": 1,
-                                           "solves_per_s_vs_fom": line["value"] * float(np.mean(tf))}
+        line["cpu_baseline"] = {"value": n_cpu / ct, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{n_cpu} of the {B} parameters, FP64 oracle SQP (dense KKT), "
+                                          f"relative KKT tolerance 1e-8, BLAS limited to 1 thread"}
+        if px is not None:
+            # the oracle's solves of the same parameters against the plain FP64 GPU solves
+            m = min(n_cpu, len(px))
+            d = [float(np.max(np.abs(px[b] - ref[b].xhat)) / max(1e-300, np.max(np.abs(ref[b].xhat))))
+                 for b in range(m)]
+            line["oracle_vs_plain_f64"] = {"n": m, "max_rel_diff_xhat": max(d),
+                                           "status_equal": int(sum(int(pst[b]) == ref[b].status for b in range(m)))}
+            print(f"[bench] oracle vs plain FP64 GPU solves: max rel diff {max(d):.2e} over {m}", file=sys.stderr,
+                  flush=True)
         print(f"[bench] cpu leg {n_cpu} solves in {ct:.1f}s", file=sys.stderr, flush=True)
-        line["cpu_baseline"]["all_cores"] = cpu_all_cores(os.path.join(ROOT, "models", "cfg1.npz"), cfg["max_iter"], B,
-                                                      cfg["seed"])
+        line["cpu_baseline"]["all_cores"] = cpu_all_cores(path, cfg["max_iter"], B, cfg["seed"])
         print(f"[bench] all-core oracle leg: {line['cpu_baseline']['all_cores']['value']:.2f} solves/s on "
               f"{line['cpu_baseline']['all_cores']['cores']} cores", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
+
+
+def line_stop(cfg):
+    return (f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
+            f"or line-search stagnation below {cfg['stall_tol']:g} ||F0||")
+
+
+def model_grid(pack):
+    return int(pack["nx"]), int(pack["ny"])
 
 
 if __name__ == "__main__":
