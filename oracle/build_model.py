@@ -30,6 +30,7 @@ from .autoencoder import ACT_SIGMOID, MaskedAE, export_decoder, train
 from .burgers import BurgersFOM, Grid, solve_fom
 from .ddmaps import build_dd
 from .hyperreduction import greedy_sample, pod_basis
+from .srpc import cover_ports, port_latent_size
 
 CONFIGS = {
     # 36x36 grid, 2x2, latent 6 -> (6,3), width 3x, band 5, 200 epochs, 5x5 training grid, HR 20%
@@ -52,6 +53,26 @@ CONFIGS = {
     # sizes when its trained pack is not at hand
     "cfg1shape": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID,
                       epochs=20, batch=4, train_grid=(2, 2), hr_frac=0.10, seed=1),
+    # strong ROM-port constraint (SRPC): port autoencoders with sigmoid activation and three-band
+    # masks of 3 entries per band shifted by 3 (Section 7.6), port latent sizes from n~ = 2 by
+    # n_j^p = max(min(N_j^p - 1, n~), 1); interior decoders as for the weak-constraint models
+    "cfg0srpc": dict(nx=36, ny=36, nsx=2, nsy=2, n_om=6, b=5, s=3, act=ACT_SIGMOID,
+                     ports=dict(n_tilde=2, b=3, s=3, act=ACT_SIGMOID),
+                     epochs=200, batch=4, train_grid=(5, 5), hr_frac=0.20, seed=0),
+    # the 240x240, 4x4 model with ports: interior decoders and HR nodes reused from the trained
+    # weak-constraint pack (--base models/cfg1.npz), ports trained on an 8 x 8 parameter grid
+    "cfg1srpc": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, b=9, s=2, act=ACT_SIGMOID,
+                     ports=dict(n_tilde=2, b=3, s=3, act=ACT_SIGMOID),
+                     epochs=1000, batch=16, train_grid=(8, 8), hr_frac=0.10, seed=1),
+    "tinysrpc2x1": dict(nx=16, ny=8, nsx=2, nsy=1, n_om=4, b=3, s=2, act=ACT_SIGMOID,
+                        ports=dict(n_tilde=3, b=3, s=3, act=ACT_SIGMOID),
+                        epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=10),
+    "tinysrpc": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, b=3, s=2, act=ACT_SIGMOID,
+                     ports=dict(n_tilde=2, b=3, s=3, act=ACT_SIGMOID),
+                     epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=8),
+    "tinysrpc3": dict(nx=18, ny=12, nsx=3, nsy=2, n_om=4, b=3, s=2, act=ACT_SIGMOID,
+                      ports=dict(n_tilde=3, b=3, s=3, act=ACT_SIGMOID),
+                      epochs=200, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=9),
     # small configurations for tests
     "tinymix": dict(nx=16, ny=12, nsx=2, nsy=2, n_om="draw", n_ga="half", b=3, s=2, act=ACT_SIGMOID,
                     epochs=300, batch=4, train_grid=(4, 4), hr_frac=(0.3, 0.6), seed=31),
@@ -111,7 +132,9 @@ def per_subdomain_choices(cfg: dict, n_sub: int):
     return n_om, n_ga, hr
 
 
-def build(name: str, workers: int = 8, verbose=True):
+def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
+    """Model pack of a configuration.  `base` (a weak-constraint pack of the same grid and
+    split) supplies the interior decoders and HR nodes of a ports configuration."""
     cfg = CONFIGS[name]
     g = Grid(cfg["nx"], cfg["ny"])
     dd = build_dd(g, cfg["nsx"], cfg["nsy"])
@@ -122,13 +145,25 @@ def build(name: str, workers: int = 8, verbose=True):
         print(f"[{name}] {len(mus)} FOM snapshots, {len(Rsnap)} residual snapshots in {time.time() - t0:.1f}s", flush=True)
 
     seeds = si.spawn_seeds(cfg["seed"], 2 * dd.n_sub + 1)
+    pc = cfg.get("ports")
+    if pc is not None:
+        cfg = dict(cfg, n_ga=0)
     n_om, n_ga, hr_frac = per_subdomain_choices(cfg, dd.n_sub)
     jobs = []
     for i, sd in enumerate(dd.subdomains):
-        jobs.append((X[:, sd.omega], len(sd.omega), n_om[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i],
-                     cfg["epochs"], cfg["batch"], ("om", i)))
-        jobs.append((X[:, sd.gamma], len(sd.gamma), n_ga[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i + 1],
-                     cfg["epochs"], cfg["batch"], ("ga", i)))
+        if base is None:
+            jobs.append((X[:, sd.omega], len(sd.omega), n_om[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i],
+                         cfg["epochs"], cfg["batch"], ("om", i)))
+        if pc is None:
+            jobs.append((X[:, sd.gamma], len(sd.gamma), n_ga[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i + 1],
+                         cfg["epochs"], cfg["batch"], ("ga", i)))
+    n_port = []
+    if pc is not None:
+        pseeds = si.spawn_seeds(cfg["seed"] + 5000, len(dd.ports))
+        for j, (car, dofs) in enumerate(dd.ports):
+            n_port.append(port_latent_size(len(dofs), pc["n_tilde"]))
+            jobs.append((X[:, dofs], len(dofs), n_port[j], pc["b"], pc["s"], pc["act"], pseeds[j], cfg["epochs"],
+                         cfg["batch"], ("pt", j)))
     jobs.sort(key=lambda j: -j[1])        # largest first
     t0 = time.time()
     if workers > 1:
@@ -146,25 +181,47 @@ def build(name: str, workers: int = 8, verbose=True):
 
     hr_nodes = []
     for i, sd in enumerate(dd.subdomains):
+        if base is not None:
+            hr_nodes.append(np.asarray(base[f"hr{i}"], dtype=np.int64))
+            continue
         Ri = Rsnap[:, sd.res_rows].T                      # N_i^r x n_snap
         Phi = pod_basis(Ri, 1e-10)
         n_own = len(sd.own_nodes)
         k = int(round(hr_frac[i] * n_own))
         loc = greedy_sample(Phi, n_own, k)
         hr_nodes.append(sd.own_nodes[loc])
-    n_C = sum(n_ga) // 2
-    C = si.gaussian_matrix(n_C, dd.n_A, seeds[-1])
+    if pc is not None:
+        hr_nodes = cover_ports(dd, hr_nodes)
+    if pc is None:
+        n_C = sum(n_ga) // 2
+        C = si.gaussian_matrix(n_C, dd.n_A, seeds[-1])
+    else:
+        C = np.zeros((0, dd.n_A))       # the strong ROM-port constraint needs no test matrix
     pack = dict(nx=g.nx, ny=g.ny, nu=g.nu, ly=g.ly, nsx=cfg["nsx"], nsy=cfg["nsy"], act=cfg["act"],
                 n_sub=dd.n_sub, C=C)
+
+    def put(prefix, d):
+        pack[f"{prefix}_W1"] = d.W1
+        pack[f"{prefix}_b1"] = d.b1
+        pack[f"{prefix}_W2"] = d.W2vals
+        pack[f"{prefix}_xref"] = d.x_ref
+        pack[f"{prefix}_bs"] = np.array([d.b, d.s])
+
     for i in range(dd.n_sub):
-        for part in ("om", "ga"):
-            d = decs[(part, i)]
-            pack[f"{part}{i}_W1"] = d.W1
-            pack[f"{part}{i}_b1"] = d.b1
-            pack[f"{part}{i}_W2"] = d.W2vals
-            pack[f"{part}{i}_xref"] = d.x_ref
-            pack[f"{part}{i}_bs"] = np.array([d.b, d.s])
+        if base is not None:
+            for key in ("W1", "b1", "W2", "xref", "bs"):
+                pack[f"om{i}_{key}"] = np.asarray(base[f"om{i}_{key}"])
+        else:
+            put(f"om{i}", decs[("om", i)])
+        if pc is None:
+            put(f"ga{i}", decs[("ga", i)])
         pack[f"hr{i}"] = hr_nodes[i]
+    if pc is not None:
+        pack["srpc"] = np.int64(1)
+        pack["port_act"] = np.int64(pc["act"])
+        pack["n_ports"] = np.int64(len(dd.ports))
+        for j in range(len(dd.ports)):
+            put(f"pt{j}", decs[("pt", j)])
     return pack, X, mus, reports
 
 
@@ -173,8 +230,11 @@ def main(argv=None):
     ap.add_argument("config")
     ap.add_argument("--out", default=None)
     ap.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--base", default=None, help="weak-constraint pack whose interior decoders and HR nodes "
+                                                 "a ports configuration reuses")
     a = ap.parse_args(argv)
-    pack, X, mus, _ = build(a.config, a.workers)
+    base = dict(np.load(a.base, allow_pickle=False)) if a.base else None
+    pack, X, mus, _ = build(a.config, a.workers, base=base)
     out = a.out or os.path.join("models", f"{a.config}.npz")
     os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
     np.savez(out, **pack)

@@ -48,17 +48,18 @@ class ROMModel:
     dec_om: list            # Decoder per subdomain (interior)
     dec_ga: list            # Decoder per subdomain (interface)
     hr_nodes: list | None   # sampled global node ids per subdomain (None: B_i = I)
-    C: np.ndarray           # n_C x N_A
+    C: np.ndarray           # n_C x N_A (weak FOM-port constraint); unused when A_hat is given
     dd: DDMaps = None
     fom: BurgersFOM = None
     CA: list = None
+    A_hat: list | None = None   # strong ROM-port constraint: sum_i A_hat[i] xhat_i^Gamma = 0
 
     def __post_init__(self):
         if self.dd is None:
             self.dd = build_dd(self.grid, self.nsx, self.nsy)
         if self.fom is None:
             self.fom = BurgersFOM(self.grid)
-        self.CA = [self.C @ A.toarray() for A in self.dd.A]
+        self.CA = None if self.A_hat is not None else [self.C @ A.toarray() for A in self.dd.A]
         self._zrows = []
         for i, sd in enumerate(self.dd.subdomains):
             n_own = len(sd.own_nodes)
@@ -76,7 +77,7 @@ class ROMModel:
 
     @property
     def n_C(self):
-        return self.C.shape[0]
+        return self.A_hat[0].shape[0] if self.A_hat is not None else self.C.shape[0]
 
     def sizes(self):
         return [(d.n, e.n) for d, e in zip(self.dec_om, self.dec_ga)]
@@ -110,21 +111,37 @@ class Evaluation:
     ZR: list
 
 
+def _decode_jac(dec, x):
+    """Value and Jacobian of a decoder: a banded one (autoencoder.Decoder) or an interface
+    decoder assembled from port decoders (srpc.PortInterfaceDecoder)."""
+    return dec.decode_jacobian(x) if hasattr(dec, "decode_jacobian") else decode_jacobian(dec, x)
+
+
+def _decode(dec, x):
+    return dec.decode(x) if hasattr(dec, "decode") else decode(dec, x)
+
+
 def evaluate(model: ROMModel, mu, xhat: np.ndarray) -> Evaluation:
-    """Per-subdomain SQP quantities at xhat (no multiplier terms)."""
+    """Per-subdomain SQP quantities at xhat (no multiplier terms).  Weak FOM-port constraint:
+    c = sum_i C A_i g_i^Gamma, E_i^Gamma = C A_i dg_i^Gamma/dxhat; strong ROM-port constraint:
+    c = sum_i Ahat_i xhat_i^Gamma, E_i^Gamma = Ahat_i."""
     H, g, EG, Zr_l, ZR_l = [], [], [], [], []
     c = np.zeros(model.n_C)
     for i, (xo, xg) in enumerate(model.split(xhat)):
-        go, Jo = decode_jacobian(model.dec_om[i], xo)
-        gg, Jg = decode_jacobian(model.dec_ga[i], xg)
+        go, Jo = _decode_jac(model.dec_om[i], xo)
+        gg, Jg = _decode_jac(model.dec_ga[i], xg)
         r, dro, drg = subdomain_residual_jac(model.fom, model.dd, i, go, gg, mu)
         z = model._zrows[i]
         Zr = r[z]
         ZR = np.hstack([dro[z] @ Jo, drg[z] @ Jg])
         H.append(ZR.T @ ZR)
         g.append(ZR.T @ Zr)
-        EG.append(model.CA[i] @ Jg)
-        c += model.CA[i] @ gg
+        if model.A_hat is not None:
+            EG.append(model.A_hat[i].copy())
+            c += model.A_hat[i] @ xg
+        else:
+            EG.append(model.CA[i] @ Jg)
+            c += model.CA[i] @ gg
         Zr_l.append(Zr)
         ZR_l.append(ZR)
     return Evaluation(H, g, EG, c, Zr_l, ZR_l)
@@ -308,7 +325,7 @@ def relative_error(model: ROMModel, xhat: np.ndarray, x_fom: np.ndarray) -> floa
     for i, (xo, xg) in enumerate(model.split(xhat)):
         sd = model.dd.subdomains[i]
         to, tg = x_fom[sd.omega], x_fom[sd.gamma]
-        num = np.sum((to - decode(model.dec_om[i], xo)) ** 2) + np.sum((tg - decode(model.dec_ga[i], xg)) ** 2)
+        num = np.sum((to - _decode(model.dec_om[i], xo)) ** 2) + np.sum((tg - _decode(model.dec_ga[i], xg)) ** 2)
         tot += num / (np.sum(to ** 2) + np.sum(tg ** 2))
     return float(np.sqrt(tot / model.n_sub))
 
