@@ -43,7 +43,8 @@ extern "C" {
                                          multiplier are not: the constraint Jacobian lacks full row rank; the
                                          solve then stops at its start point with lambda = 0 */
 #define DDROM_STATUS_NONFINITE 4
-#define DDROM_STATUS_STALLED 5        /* Armijo failed with ||F|| <= stall_tol ||F_0||: the arithmetic's noise floor */
+#define DDROM_STATUS_STALLED 5        /* near the arithmetic's noise floor (||F|| <= stall_tol ||F_0||): Armijo failed,
+                                         or an accepted step made too little progress (stall_ratio) */
 
 #define DDROM_ACT_SIGMOID 0
 #define DDROM_ACT_SWISH 1
@@ -91,6 +92,19 @@ typedef struct {
      * work item (>= 4).  They change the schedule only; results are identical up to the
      * order of partial sums. */
     int tile[3];
+    /* Strong ROM-port constraint formulation (Section 3.2, eq. dd_lspg_NLP_rom_port) when
+     * n_ports > 0: dec_port[j] is the decoder g_j^p of port j (activation port_activation),
+     * ports being the groups of interface nodes shared by the same set of subdomains, ordered
+     * by their lowest node id; a port's states are its nodes' u values then v values, nodes
+     * ascending.  dec_ga, n_C and C are then ignored: subdomain i's interface decoder is
+     * eq. gamma_map_port over the ports it carries (ascending port order, one latent copy
+     * each, so n_i^Gamma = sum of their n_j^p) and the constraint is sum_i Ahat_i xhat_i^Gamma
+     * = 0, one row per port latent component and consecutive carrier pair i_t < i_{t+1}
+     * (+1 on i_t, -1 on i_{t+1}), rows ordered port, pair, component; n_C = sum_j
+     * (|P(j)| - 1) n_j^p.  n_ports = 0: the weak FOM-port constraint with dec_ga and C. */
+    int n_ports;
+    const ddrom_decoder_desc* dec_port;     /* [n_ports] */
+    int port_activation;                    /* DDROM_ACT_* */
 } ddrom_model_desc;
 
 typedef struct ddrom_model ddrom_model;
@@ -105,6 +119,10 @@ typedef struct {
     int precision;          /* DDROM_PREC_* */
     double stall_tol;       /* 0 disables; else an Armijo failure with ||F|| <= stall_tol ||F_0|| stops the
                                solve with DDROM_STATUS_STALLED (meant for the FP32-decoder mode) */
+    double stall_ratio;     /* 0 disables; else (with stall_tol > 0) an accepted step that ends above the
+                               tolerance, at ||F|| <= stall_tol ||F_0||, but reduces ||F|| by less than the
+                               factor stall_ratio (||F_new|| > stall_ratio ||F_old||) stops the solve at the
+                               new point with DDROM_STATUS_STALLED: progress has slowed to the noise floor */
 } ddrom_opts;
 
 const char* ddrom_last_error(void);

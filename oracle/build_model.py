@@ -65,8 +65,11 @@ CONFIGS = {
                      ports=dict(n_tilde=2, b=3, s=3, act=ACT_SIGMOID),
                      epochs=1000, batch=16, train_grid=(8, 8), hr_frac=0.10, seed=1),
     "tinysrpc2x1": dict(nx=16, ny=8, nsx=2, nsy=1, n_om=4, b=3, s=2, act=ACT_SIGMOID,
-                        ports=dict(n_tilde=3, b=3, s=3, act=ACT_SIGMOID),
+                        ports=dict(n_tilde=2, b=3, s=3, act=ACT_SIGMOID),
                         epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=10),
+    "tinysrpc3x1": dict(nx=24, ny=8, nsx=3, nsy=1, n_om=4, b=3, s=2, act=ACT_SIGMOID,
+                        ports=dict(n_tilde=2, b=3, s=3, act=ACT_SIGMOID),
+                        epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=11),
     "tinysrpc": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, b=3, s=2, act=ACT_SIGMOID,
                      ports=dict(n_tilde=2, b=3, s=3, act=ACT_SIGMOID),
                      epochs=300, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=8),

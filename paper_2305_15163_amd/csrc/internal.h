@@ -93,6 +93,10 @@ struct ConChunk {
 
 struct ddrom_model {
     int nx, ny, nsx, nsy, n_sub, act, n_C, N_A, n_D, N_x, n_state;
+    int act_ga = 0;                              // activation of the interface decoders (ports' for SRPC)
+    int srpc = 0;                                // 1: strong ROM-port constraint (ports, linear constraint)
+    double* Ahat_d = nullptr;                    // SRPC: per subdomain [n_C][mmax] constraint matrix Ahat_i
+    int n_ports = 0;
     double nu, ly, hx, hy;
     int nmax, mmax, NNmax, estride;     // max latent sizes, GN partial stride
     std::vector<int> n_om, n_ga, N_om, N_ga, xoff, n_own, nb, hid_om;

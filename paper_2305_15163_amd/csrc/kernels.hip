@@ -137,16 +137,29 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     const DecSeg sg = segs[ch.seg];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nl = live_count(n_live, B);
-    const int j0 = (int)blockIdx.y * WAVES * 64;
-    if (j0 >= nl) return;     // every slot of this workgroup is idle
-    // When the running solves fill only one or two of the workgroup's 64-slot groups (the
-    // last rounds of a batch), the idle waves take a share of the rows instead: G slot
-    // groups x R row parts.  Each wave keeps its own activation ring.
-    const int live_groups = min(WAVES, (nl - j0 + 63) / 64);
-    const int R = live_groups == 1 ? WAVES : ((live_groups == 2 && WAVES % 2 == 0) ? WAVES / 2 : 1);
-    const int G = WAVES / R;
-    const int group = wave % G, part = wave / G;
-    const int j = (blockIdx.y * WAVES + group) * 64 + lane;
+    // Slot groups of 64 running solves -> waves.  While there are more running groups than
+    // workgroup rows (gridDim.y), workgroup row y takes groups 4y .. 4y + 3; when only one or
+    // two of them run (the last rounds of a batch), the idle waves take a share of the rows
+    // instead: G slot groups x R row parts.  Once the running groups fit in the workgroup rows,
+    // each workgroup row takes one group and all its waves split the rows (R = WAVES).  Each
+    // wave keeps its own activation ring.
+    const int groups_live = (nl + 63) / 64;
+    int R, G, group_abs;
+    if (groups_live <= (int)gridDim.y) {
+        if ((int)blockIdx.y >= groups_live) return;
+        R = WAVES;
+        G = 1;
+        group_abs = blockIdx.y;
+    } else {
+        const int j0 = (int)blockIdx.y * WAVES * 64;
+        if (j0 >= nl) return;     // every slot of this workgroup is idle
+        const int live_groups = min(WAVES, (nl - j0 + 63) / 64);
+        R = live_groups == 1 ? WAVES : ((live_groups == 2 && WAVES % 2 == 0) ? WAVES / 2 : 1);
+        G = WAVES / R;
+        group_abs = blockIdx.y * WAVES + wave % G;
+    }
+    const int part = wave / G;
+    const int j = group_abs * 64 + lane;
     const bool act = j < nl;
     const int b = slot_solve(live, j, nl);
 
@@ -639,6 +652,38 @@ __global__ __launch_bounds__(256) void k_con(const ConChunk* __restrict__ cch, i
     }
 }
 
+// Strong ROM-port constraint (eq. rom_strong_constraint): subdomain sd's share Ahat_sd xhat_sd^Gamma
+// of the constraint at the trial latents and its constant Jacobian block Ahat_sd, written in the
+// partial-sum layout the reduction reads (one part per subdomain).  One lane per solve slot.
+__global__ __launch_bounds__(64) void k_con_linear(const double* __restrict__ Ahat, int n_C, int mmax,
+                                                   const int* __restrict__ n_om, const int* __restrict__ n_ga,
+                                                   const int* __restrict__ xoff, const double* __restrict__ xhat,
+                                                   int xstride, const int* __restrict__ live,
+                                                   const int* __restrict__ n_live, int B, int Bp,
+                                                   double* __restrict__ c_part, double* __restrict__ E_part) {
+    constexpr int MX = 12;      // n_i^Gamma bound of the update kernel
+    const int sd = blockIdx.x;
+    const int nl = live_count(n_live, B);
+    if ((int)blockIdx.y * 64 >= nl) return;
+    const int j = blockIdx.y * 64 + threadIdx.x;     // slot
+    const bool act = j < nl;
+    const int b = slot_solve(live, j, nl);
+    const int m = n_ga[sd], o = xoff[sd] + n_om[sd];
+    const double* A = Ahat + (size_t)sd * n_C * mmax;
+    double x[MX];
+#pragma unroll
+    for (int k = 0; k < MX; ++k) x[k] = (act && k < m) ? xhat[(size_t)b * xstride + o + k] : 0.0;
+    for (int r = 0; r < n_C; ++r) {
+        const double* a = A + (size_t)r * mmax;
+        double c = 0.0;
+#pragma unroll
+        for (int k = 0; k < MX; ++k)
+            if (k < m) c += a[k] * x[k];
+        c_part[((size_t)sd * n_C + r) * Bp + j] = c;
+        for (int k = 0; k < mmax; ++k) E_part[(((size_t)sd * n_C + r) * mmax + k) * Bp + j] = k < m ? a[k] : 0.0;
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // Sum of the partial slots into one contiguous block per solve
 // ------------------------------------------------------------------------------------
@@ -735,7 +780,7 @@ struct UpdArgs {
     int n_sub, n_C, n_D, mg, estride, Bp, B;   // mg = max(1, largest n_i^Gamma): stride of the E blocks
     int lam_given;
     int max_iter, max_bt;
-    double tol_abs, tol_rel, c1, stall_tol;
+    double tol_abs, tol_rel, c1, stall_tol, stall_ratio;
     const int* n_om;       // [n_sub]
     const int* n_ga;
     const int* xoff;
@@ -1310,6 +1355,7 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
 
     // ---- decision (every thread evaluates it identically) ----
     int action = 0;   // 0: compute step, 1: backtrack, 2: stop
+    bool slow = false;
     if (S.phase == PH_ZERO) {
         // zero start of a warm solve: keep its norm and multiplier, then evaluate the proposal
         // (held in x, lam); the multiplier waits in the step buffer's lambda part
@@ -1377,12 +1423,17 @@ __global__ __launch_bounds__(512) void k_update(UpdArgs a) {
             for (int e = tid; e < nD; e += nth) a.x[(size_t)b * nD + e] = a.xt[(size_t)b * nD + e];
             for (int jj = tid; jj < nC; jj += nth) a.lam[(size_t)b * nC + jj] = lam_s[jj];
             S.iters += 1;
+            // progress of the accepted step near the noise floor
+            slow = a.stall_ratio > 0.0 && fn_t <= a.stall_tol * S.f0 && fn_t > a.stall_ratio * S.fn;
             S.fn = fn_t;
         }
     }
     if (action == 0) {
         if (S.fn <= S.tol) {
             S.status = DDROM_STATUS_CONVERGED;
+            action = 2;
+        } else if (slow) {
+            S.status = DDROM_STATUS_STALLED;
             action = 2;
         } else if (S.iters >= a.max_iter) {
             S.status = DDROM_STATUS_MAX_ITER;
@@ -1800,11 +1851,10 @@ __global__ void k_err_final(const double* __restrict__ part, int n_sub, int B, i
 namespace {
 
 template <int TAG, int VO = 0>
-static int launch_decode_items(const ddrom_model* m, int prec, int c0, int c1, int n, long long stage,
+static int launch_decode_items(const ddrom_model* m, int prec, int act, int c0, int c1, int n, long long stage,
                                const double* xhat, int xstride, int xoff_override, const int* live, const int* n_live,
                                int B, void* out, int Bp, hipStream_t s, long long oshift = 0) {
     if (c1 <= c0) return 0;
-    const int act = m->act;
     const int rk = act == DDROM_ACT_SWISH ? 2 : 1;
     const int waves = prec == DDROM_PREC_FP64 ? 1 : (act == DDROM_ACT_SWISH ? 2 : 4);
     const int esz = prec == DDROM_PREC_FP64 ? 8 : 4;
@@ -1847,7 +1897,9 @@ template <int TAG, int VO = 0>
 static int launch_decode_seg(const ddrom_model* m, int prec, int g, const double* xhat, int xstride,
                              int xoff_override, const int* live, const int* n_live, int B, void* out, int Bp,
                              hipStream_t s, long long oshift = 0) {
-    return launch_decode_items<TAG, VO>(m, prec, m->seg_chunk0[g], m->seg_chunk1[g], m->segs_h[g].n,
+    // segments of families 1 and 3 are interface decoders
+    const int act = ((g / m->n_sub) & 1) ? m->act_ga : m->act;
+    return launch_decode_items<TAG, VO>(m, prec, act, m->seg_chunk0[g], m->seg_chunk1[g], m->segs_h[g].n,
                                         prec == DDROM_PREC_FP64 ? m->seg_stage_f64[g] : m->seg_stage_f32[g], xhat,
                                         xstride, xoff_override, live, n_live, B, out, Bp, s, oshift);
 }
@@ -1855,8 +1907,9 @@ static int launch_decode_seg(const ddrom_model* m, int prec, int g, const double
 template <int TAG, int VO = 0>
 static int launch_decode_family(const ddrom_model* m, int prec, int f, const double* xhat, const int* live,
                                 const int* n_live, int B, void* out, int Bp, hipStream_t s) {
+    const int act = (f & 1) ? m->act_ga : m->act;
     for (const auto& pl : m->dec_plan[f]) {
-        const int rc = launch_decode_items<TAG, VO>(m, prec, pl.c0, pl.c1, pl.n,
+        const int rc = launch_decode_items<TAG, VO>(m, prec, act, pl.c0, pl.c1, pl.n,
                                                     prec == DDROM_PREC_FP64 ? pl.stage_f64 : pl.stage_f32, xhat,
                                                     m->n_D, -1, live, n_live, B, out, Bp, s);
         if (rc) return rc;
@@ -1883,7 +1936,7 @@ static int launch_res_item(const ddrom_model* m, int prec, const ddrom_model::Re
         HIPCHECK(hipGetLastError());                                                                              \
         return 0;                                                                                                 \
     }
-    RES_CASE(2, 1) RES_CASE(3, 2) RES_CASE(4, 2) RES_CASE(6, 3) RES_CASE(8, 4) RES_CASE(12, 6) RES_CASE(4, 0)
+    RES_CASE(2, 1) RES_CASE(3, 2) RES_CASE(4, 2) RES_CASE(4, 4) RES_CASE(6, 3) RES_CASE(8, 4) RES_CASE(12, 6) RES_CASE(4, 0)
     RES_CASE(6, 0) RES_CASE(8, 0)
 #undef RES_CASE
     set_error("unsupported latent sizes (" + std::to_string(rs.n_om) + ", " + std::to_string(rs.n_ga) + ")");
@@ -1899,8 +1952,31 @@ static int launch_res(const ddrom_model* m, int prec, const ddrom_workspace* ws,
     return 0;
 }
 
-static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const int* n_live, int B,
-                      hipStream_t s) {
+struct ModelDevInts {
+    int *n_om, *n_ga, *xoff, *slot0, *cpart0;
+};
+static ModelDevInts get_ints(const ddrom_model* m);
+
+// The model struct has no slot for these, so keep them in a side table keyed by model.
+static std::mutex g_mu;
+static std::map<const ddrom_model*, ModelDevInts> g_ints;
+
+static ModelDevInts get_ints(const ddrom_model* m) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_ints[m];
+}
+
+static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws, const double* xhat, const int* live,
+                      const int* n_live, int B, hipStream_t s) {
+    if (m->srpc) {
+        if (m->n_C == 0) return 0;
+        ModelDevInts di = get_ints(m);
+        hipLaunchKernelGGL(k_con_linear, dim3(m->n_sub, ws->Bp / 64), dim3(64), 0, s, m->Ahat_d, m->n_C,
+                           std::max(1, m->mmax), di.n_om, di.n_ga, di.xoff, xhat, m->n_D, live, n_live, B, ws->Bp,
+                           ws->c_part, ws->E_part);
+        HIPCHECK(hipGetLastError());
+        return 0;
+    }
     if (m->n_cchunks == 0 || m->n_C == 0) return 0;
     // one launch per interface latent size
     for (const auto& pl : m->con_plan) {
@@ -1934,20 +2010,6 @@ static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws,
 }  // namespace
 
 // Device copies of small per-subdomain integer tables, kept next to the model.
-struct ModelDevInts {
-    int *n_om, *n_ga, *xoff, *slot0, *cpart0;
-};
-static ModelDevInts get_ints(const ddrom_model* m);
-
-// The model struct has no slot for these, so keep them in a side table keyed by model.
-static std::mutex g_mu;
-static std::map<const ddrom_model*, ModelDevInts> g_ints;
-
-static ModelDevInts get_ints(const ddrom_model* m) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    return g_ints[m];
-}
-
 // One evaluation of all active solves at their trial points (xt).  The interface decoders
 // and the constraint sums run on a second stream forked from `s` (they depend only on the
 // interface latents), overlapping the interior decoders and the residual kernel.
@@ -1959,7 +2021,7 @@ static int evaluate_round(const ddrom_model* m, ddrom_workspace* ws, int prec, i
     HIPCHECK(hipStreamWaitEvent(s2, ws->ev_fork, 0));
     if ((rc = launch_decode_family<0>(m, prec, 1, xhat, live, n_live, B, ws->dec_out, ws->Bp, s2))) return rc;
     HIPCHECK(hipEventRecord(ws->ev_ga, s2));
-    if ((rc = launch_con(m, prec, ws, n_live, B, s2))) return rc;
+    if ((rc = launch_con(m, prec, ws, xhat, live, n_live, B, s2))) return rc;
     HIPCHECK(hipEventRecord(ws->ev_con, s2));
     if ((rc = launch_decode_family<0>(m, prec, 0, xhat, live, n_live, B, ws->dec_out, ws->Bp, s))) return rc;
     HIPCHECK(hipStreamWaitEvent(s, ws->ev_ga, 0));
@@ -1974,6 +2036,7 @@ static UpdArgs upd_args(const ddrom_model* m, ddrom_workspace* ws, int B, const 
     a.n_sub = m->n_sub; a.n_C = m->n_C; a.n_D = m->n_D; a.mg = std::max(1, m->mmax); a.estride = m->estride;
     a.Bp = ws->Bp; a.B = B; a.lam_given = lam_given; a.max_iter = o->max_iter; a.max_bt = o->max_backtracks;
     a.tol_abs = o->tol_abs; a.tol_rel = o->tol_rel; a.c1 = o->armijo_c1; a.stall_tol = o->stall_tol;
+    a.stall_ratio = o->stall_ratio;
     a.n_om = di.n_om; a.n_ga = di.n_ga; a.xoff = di.xoff;
     a.RB = ws->RB; a.rs = ws->rs; a.RS = ws->RS;
     a.x = ws->x; a.xt = ws->xt; a.lam = ws->lam; a.lamt = ws->lamt; a.step = ws->step;
@@ -2471,7 +2534,8 @@ static int solver_graph(const ddrom_model* m, ddrom_workspace* ws, int B, const 
     std::ostringstream key;
     key << std::hexfloat;
     key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
-        << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << lam_given << ":" << warm;
+        << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << o->stall_ratio << ":" << lam_given << ":"
+        << warm;
     if (ws->graph && ws->graph_key == key.str()) return 0;
     if (ws->graph) {
         (void)hipGraphExecDestroy(ws->graph);
@@ -2571,6 +2635,7 @@ int sqp_step(const ddrom_model* m, ddrom_workspace* ws, const double* mu_d, int 
     one.max_iter = 1;
     one.tol_abs = 0.0;
     one.tol_rel = 0.0;
+    one.stall_ratio = 0.0;      // one iteration: an accepted step always reports DDROM_STATUS_MAX_ITER
     FinalOut fo{xhat_d, lam_d, fnorm_d, nullptr, nullptr, status_d, nullptr};
     return solve_common(m, ws, mu_d, B, xhat_d, lam_d, &one, s, 0, fo);
 }
@@ -2757,7 +2822,7 @@ int ddrom_time_kernels(const ddrom_model* m, ddrom_workspace* ws, const double* 
             if (which < 2)
                 c = launch_decode_family<1>(m, precision, which, ws->xt, nullptr, nullptr, B, ws->dec_out, ws->Bp, s);
             else if (which == 2) c = launch_res(m, precision, ws, nullptr, nullptr, B, s);
-            else c = launch_con(m, precision, ws, nullptr, B, s);
+            else c = launch_con(m, precision, ws, ws->xt, nullptr, nullptr, B, s);
             if (c) return c;
         }
         HIPCHECK(hipEventRecord(ws->t1, s));

@@ -106,6 +106,73 @@ static int make_subnet(const ddrom_decoder_desc& d, const std::vector<int>& rows
     return 0;
 }
 
+// Interface decoder of eq. gamma_map_port for one subdomain, assembled from the decoders of the
+// ports it carries (block form of eq. interface_decoder_rom_port_blocks): the hidden units are the
+// ports' hidden units, port by port in ascending port order; a hidden unit's W1~ row holds its port
+// decoder's row in the columns of that port's latent copy (offset lat_off[a] inside xhat_i^Gamma)
+// and zeros elsewhere; output row r (an interface state of the subdomain) takes the three bands
+// of its port decoder's row for the same state, shifted to the port's hidden units.
+static int make_port_interface(const ddrom_decoder_desc* pd, const std::vector<int>& Q,
+                               const std::vector<int>& lat_off, int n_ga, const std::vector<int>& ifn_sd,
+                               const std::vector<int>& port_of, const std::vector<int>& port_pos,
+                               const std::vector<std::vector<int>>& port_nodes, int bmax, HostDecoder& out) {
+    std::vector<int> hoff(Q.size()), qidx(port_nodes.size(), -1);
+    int hid = 0;
+    for (size_t a = 0; a < Q.size(); ++a) {
+        hoff[a] = hid;
+        hid += pd[Q[a]].w;
+        qidx[Q[a]] = (int)a;
+    }
+    const int nif = (int)ifn_sd.size(), N = 2 * nif;
+    out.rows = N;
+    out.hid = hid;
+    out.W1.assign((size_t)hid * n_ga, 0.0);
+    out.b1.assign(hid, 0.0);
+    for (size_t a = 0; a < Q.size(); ++a) {
+        const ddrom_decoder_desc& e = pd[Q[a]];
+        for (int c = 0; c < e.w; ++c) {
+            for (int k = 0; k < e.n; ++k) out.W1[(size_t)(hoff[a] + c) * n_ga + lat_off[a] + k] = e.W1[(size_t)c * e.n + k];
+            out.b1[hoff[a] + c] = e.b1[c];
+        }
+    }
+    out.band.assign((size_t)N * 3, int2{0, 0});
+    out.W2.assign((size_t)N * 3 * bmax, 0.0);
+    out.xref.resize(N);
+    for (int r = 0; r < N; ++r) {
+        const int f = r / nif, q = ifn_sd[r % nif];
+        const int j = port_of[q], a = qidx[j];
+        if (j < 0 || a < 0) {
+            set_error("internal: interface node outside the subdomain's ports");
+            return DDROM_EINVAL;
+        }
+        const ddrom_decoder_desc& e = pd[j];
+        const int p = port_pos[q] + f * (int)port_nodes[j].size();
+        out.xref[r] = e.x_ref[p];
+        int lo = 1 << 30, hi = -1;
+        for (int k = 0; k < 3; ++k) {
+            int t0 = -1, t1 = -1;
+            for (int t = 0; t < e.b; ++t) {
+                const long long c = (long long)p * e.s + (long long)(k - 1) * e.b * e.s + t;
+                if (c >= 0 && c < e.w) {
+                    if (t0 < 0) t0 = t;
+                    t1 = t;
+                }
+            }
+            if (t0 < 0) continue;
+            const int c0 = p * e.s + (k - 1) * e.b * e.s + t0, len = t1 - t0 + 1;
+            for (int t = 0; t < len; ++t) out.W2[((size_t)r * 3 + k) * bmax + t] = e.W2[((size_t)p * 3 + k) * e.b + t0 + t];
+            out.band[(size_t)r * 3 + k] = int2{hoff[a] + c0, len};
+            lo = std::min(lo, hoff[a] + c0);
+            hi = std::max(hi, hoff[a] + c0 + len);
+        }
+        if (hi >= 0 && hi - lo > RING) {
+            set_error("port decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 48)");
+            return DDROM_EINVAL;
+        }
+    }
+    return 0;
+}
+
 int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     if (!d || d->nx <= 0 || d->ny <= 0 || d->nsx <= 0 || d->nsy <= 0 || d->nx % d->nsx || d->ny % d->nsy) {
         set_error("grid must be positive and split evenly by nsx x nsy");
@@ -119,6 +186,12 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     const int n_nodes = nx * ny, bx = nx / nsx, by = ny / nsy;
     m->nx = nx; m->ny = ny; m->nsx = nsx; m->nsy = nsy; m->n_sub = n_sub;
     m->act = d->activation; m->nu = d->nu; m->ly = d->ly;
+    m->srpc = d->n_ports > 0 ? 1 : 0;
+    m->act_ga = m->srpc ? d->port_activation : d->activation;
+    if (m->srpc && (d->port_activation < 0 || d->port_activation > 2 || !d->dec_port)) {
+        set_error("strong ROM-port constraint: bad port activation or no port decoders");
+        return DDROM_EINVAL;
+    }
     m->hx = 2.0 / (nx + 1); m->hy = d->ly / (ny + 1);
     m->N_x = 2 * n_nodes;
     m->n_C = d->n_C;
@@ -168,6 +241,60 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         std::sort(all.begin(), all.end());
         ifn[sd] = all;
     }
+    // ---- ports: groups of interface nodes carried by the same subdomains, numbered by their
+    //      lowest node (every interface node has at least two carriers) ----
+    std::vector<std::vector<int>> carriers(n_nodes);
+    for (int sd = 0; sd < n_sub; ++sd)
+        for (int q : ifn[sd]) carriers[q].push_back(sd);   // sd ascending by construction
+    std::vector<int> port_of(n_nodes, -1), port_pos(n_nodes, -1);
+    std::vector<std::vector<int>> port_nodes, port_car;
+    std::vector<std::vector<int>> Qp(n_sub), lat_off(n_sub);
+    std::vector<int> n_ga_srpc(n_sub, 0);
+    int port_bmax = 1;
+    if (m->srpc) {
+        std::map<std::vector<int>, int> idx;
+        for (int q = 0; q < n_nodes; ++q) {
+            if (carriers[q].size() < 2) continue;
+            auto it = idx.find(carriers[q]);
+            int j;
+            if (it == idx.end()) {
+                j = (int)port_nodes.size();
+                idx[carriers[q]] = j;
+                port_nodes.push_back({});
+                port_car.push_back(carriers[q]);
+            } else {
+                j = it->second;
+            }
+            port_of[q] = j;
+            port_pos[q] = (int)port_nodes[j].size();
+            port_nodes[j].push_back(q);
+        }
+        if ((int)port_nodes.size() != d->n_ports) {
+            std::ostringstream os;
+            os << "the split has " << port_nodes.size() << " ports, the descriptor " << d->n_ports;
+            set_error(os.str());
+            return DDROM_ESHAPE;
+        }
+        for (int j = 0; j < d->n_ports; ++j) {
+            const ddrom_decoder_desc& e = d->dec_port[j];
+            if (e.N != 2 * (int)port_nodes[j].size() || e.n <= 0 || e.b <= 0 || e.s <= 0 || e.w != e.N * e.s || !e.W1 ||
+                !e.b1 || !e.W2 || !e.x_ref) {
+                std::ostringstream os;
+                os << "port " << j << ": decoder needs N = " << 2 * port_nodes[j].size()
+                   << " states, n, b, s > 0, w = N*s and all weight pointers";
+                set_error(os.str());
+                return DDROM_EINVAL;
+            }
+            port_bmax = std::max(port_bmax, e.b);
+            for (int sd : port_car[j]) {
+                Qp[sd].push_back(j);
+                lat_off[sd].push_back(n_ga_srpc[sd]);
+                n_ga_srpc[sd] += e.n;
+            }
+        }
+        m->n_ports = d->n_ports;
+    }
+
     m->n_om.resize(n_sub); m->n_ga.resize(n_sub); m->N_om.resize(n_sub); m->N_ga.resize(n_sub);
     m->xoff.resize(n_sub); m->n_own.resize(n_sub); m->nb.resize(n_sub); m->hid_om.resize(n_sub);
     m->state_off.resize(n_sub); m->res_off.resize(n_sub);
@@ -175,7 +302,9 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     long long so = 0, ro = 0;
     for (int sd = 0; sd < n_sub; ++sd) {
         const ddrom_decoder_desc& a = d->dec_om[sd];
-        const ddrom_decoder_desc& g = d->dec_ga[sd];
+        ddrom_decoder_desc gport{};             // SRPC: the interface size only (weights come from ports)
+        gport.N = 2 * (int)ifn[sd].size();
+        const ddrom_decoder_desc& g = m->srpc ? gport : d->dec_ga[sd];
         m->N_om[sd] = 2 * (int)intn[sd].size();
         m->N_ga[sd] = 2 * (int)ifn[sd].size();
         m->n_own[sd] = (int)own[sd].size();
@@ -187,6 +316,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             return DDROM_ESHAPE;
         }
         for (const ddrom_decoder_desc* e : {&a, &g}) {
+            if (e == &gport) continue;
             if (e->N > 0 && (e->n <= 0 || e->b <= 0 || e->s <= 0 || e->w != e->N * e->s || !e->W1 || !e->b1 || !e->W2 || !e->x_ref)) {
                 set_error("decoder descriptor: need n, b, s > 0, w = N*s and all weight pointers");
                 return DDROM_EINVAL;
@@ -197,7 +327,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             }
         }
         m->n_om[sd] = a.n;
-        m->n_ga[sd] = g.N > 0 ? g.n : 0;
+        m->n_ga[sd] = m->srpc ? n_ga_srpc[sd] : (g.N > 0 ? g.n : 0);
         if (m->n_om[sd] + m->n_ga[sd] > 20 || m->n_ga[sd] > 12) {
             set_error("n_i^Omega + n_i^Gamma above 20 or n_i^Gamma above 12 is not supported by the KKT kernel");
             return DDROM_EINVAL;
@@ -217,15 +347,17 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         m->mmax = std::max(m->mmax, m->n_ga[sd]);
     }
     m->NNmax = m->nmax;
+    if (m->srpc) {
+        int nA = 0;
+        for (int j = 0; j < m->n_ports; ++j) nA += ((int)port_car[j].size() - 1) * d->dec_port[j].n;
+        m->n_C = nA;
+    }
     if (m->n_C > 256) {
         set_error("n_C above 256 is not supported by the KKT kernel");
         return DDROM_EINVAL;
     }
 
-    // ---- ports / compatibility rows, C A_i ----
-    std::vector<std::vector<int>> carriers(n_nodes);
-    for (int sd = 0; sd < n_sub; ++sd)
-        for (int q : ifn[sd]) carriers[q].push_back(sd);   // sd ascending by construction
+    // ---- compatibility rows of the FOM ports, C A_i (weak constraint) or Ahat_i (strong) ----
     int n_A = 0;
     for (int q = 0; q < n_nodes; ++q)
         if (carriers[q].size() > 1) n_A += 2 * ((int)carriers[q].size() - 1);
@@ -236,7 +368,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         set_error(os.str());
         return DDROM_ESHAPE;
     }
-    if (m->n_C > 0 && !d->C) {
+    if (!m->srpc && m->n_C > 0 && !d->C) {
         set_error("C is NULL");
         return DDROM_EINVAL;
     }
@@ -244,8 +376,25 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         return (int)(std::lower_bound(v.begin(), v.end(), q) - v.begin());
     };
     std::vector<std::vector<double>> CA(n_sub);
-    for (int sd = 0; sd < n_sub; ++sd) CA[sd].assign((size_t)m->n_C * m->N_ga[sd], 0.0);
-    {
+    for (int sd = 0; sd < n_sub; ++sd) CA[sd].assign(m->srpc ? 0 : (size_t)m->n_C * m->N_ga[sd], 0.0);
+    std::vector<double> Ahat;      // SRPC: per subdomain [n_C][mmax]
+    if (m->srpc) {
+        const int mg = std::max(1, m->mmax);
+        Ahat.assign((size_t)n_sub * m->n_C * mg, 0.0);
+        int row = 0;
+        for (int j = 0; j < m->n_ports; ++j) {
+            const std::vector<int>& car = port_car[j];
+            for (size_t t = 0; t + 1 < car.size(); ++t)
+                for (int k = 0; k < d->dec_port[j].n; ++k, ++row) {
+                    for (int side = 0; side < 2; ++side) {
+                        const int sd = car[t + side];
+                        const size_t a = std::find(Qp[sd].begin(), Qp[sd].end(), j) - Qp[sd].begin();
+                        Ahat[((size_t)sd * m->n_C + row) * mg + lat_off[sd][a] + k] = side == 0 ? 1.0 : -1.0;
+                    }
+                }
+        }
+    }
+    if (!m->srpc) {
         // rows ordered by global DoF: u-DoFs (node ascending) then v-DoFs
         int row = 0;
         for (int f = 0; f < 2; ++f)
@@ -348,12 +497,15 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     for (int part = 0; part < 4; ++part)
         for (int sd = 0; sd < n_sub; ++sd) {
             const bool interior = part == 0 || part == 2;
-            const ddrom_decoder_desc& dd = interior ? d->dec_om[sd] : d->dec_ga[sd];
+            const bool ported = m->srpc && !interior;
+            ddrom_decoder_desc pdesc{};
+            pdesc.N = m->N_ga[sd];
+            const ddrom_decoder_desc& dd = interior ? d->dec_om[sd] : (ported ? pdesc : d->dec_ga[sd]);
             DecSeg& sg = m->segs_h[part * n_sub + sd];
             sg.sd = sd;
             sg.n = interior ? m->n_om[sd] : m->n_ga[sd];
             sg.xoff = m->xoff[sd] + (interior ? 0 : m->n_om[sd]);
-            sg.bmax = dd.N > 0 ? dd.b : 1;
+            sg.bmax = dd.N > 0 ? (ported ? port_bmax : dd.b) : 1;
             if (dd.N == 0) {
                 sg.rows = 0; sg.hid = 0;
                 sg.w1 = (long long)W1.size(); sg.b1 = (long long)b1.size(); sg.band = (long long)bands.size();
@@ -368,7 +520,9 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
                 std::iota(rows.begin(), rows.end(), 0);
             }
             HostDecoder hd;
-            int rc = make_subnet(dd, rows, hd);
+            int rc = ported ? make_port_interface(d->dec_port, Qp[sd], lat_off[sd], m->n_ga[sd], ifn[sd], port_of,
+                                                  port_pos, port_nodes, port_bmax, hd)
+                            : make_subnet(dd, rows, hd);
             if (rc) return rc;
             sg.rows = hd.rows;
             sg.hid = hd.hid;
@@ -538,14 +692,19 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         m->rsegs_h[sd].ca = m->CA_off[sd];
         m->rsegs_h[sd].n_rows_ga = Ng;
         // (C A_i)^T, rows of length ca_ld so that a work item's 8 multipliers are contiguous
-        std::vector<double> t((size_t)Ng * m->ca_ld, 0.0);
-        for (int j = 0; j < m->n_C; ++j)
-            for (int o = 0; o < Ng; ++o) t[(size_t)o * m->ca_ld + j] = CA[sd][(size_t)j * Ng + o];
-        CAflat.insert(CAflat.end(), t.begin(), t.end());
+        if (!m->srpc) {
+            std::vector<double> t((size_t)Ng * m->ca_ld, 0.0);
+            for (int j = 0; j < m->n_C; ++j)
+                for (int o = 0; o < Ng; ++o) t[(size_t)o * m->ca_ld + j] = CA[sd][(size_t)j * Ng + o];
+            CAflat.insert(CAflat.end(), t.begin(), t.end());
+        }
         m->rsegs_h[sd].cpart0 = cpart;
         cchunk0[sd] = (int)cch.size();
         const int orows = m->tile_con_orows;
-        if (Ng > 0 && m->n_C > 0)
+        if (m->srpc) {
+            // the linear constraint's partials are formed per subdomain by their own kernel
+            if (m->n_C > 0) ++cpart;
+        } else if (Ng > 0 && m->n_C > 0)
             for (int o = 0; o < Ng; o += orows, ++cpart)
                 for (int j = 0; j < m->n_C; j += CON_ROWS)
                     cch.push_back(ConChunk{sd, j, std::min(m->n_C, j + CON_ROWS), o, std::min(Ng, o + orows), cpart, {0, 0}});
@@ -636,7 +795,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         (rc = upload(&m->bc_field_d, bc_field)) || (rc = upload(&m->CA_d, CAflat)) ||
         (rc = upload(&m->cchunks_d, cch)) || (rc = upload(&m->fom_src_d, fsrc)) ||
         (rc = upload(&m->fom_meta_d, fmeta)) || (rc = upload(&m->fom_sd_of_row_d, sd_of_row)) ||
-        (rc = upload(&m->state_dof_d, state_dof)))
+        (rc = upload(&m->state_dof_d, state_dof)) || (rc = upload(&m->Ahat_d, Ahat)))
         return rc;
     return 0;
 }
@@ -644,7 +803,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
 void free_model(ddrom_model* m) {
     void* ptrs[] = {m->W1f, m->b1f, m->W2f, m->xreff, m->W1d, m->b1d, m->W2d, m->xrefd, m->bands, m->segs_d,
                     m->chunks_d, m->gather_d, m->rsegs_d, m->rchunks_d, m->bc_xy_d, m->bc_field_d, m->CA_d,
-                    m->cchunks_d, m->fom_src_d, m->fom_meta_d, m->fom_sd_of_row_d, m->state_dof_d};
+                    m->cchunks_d, m->fom_src_d, m->fom_meta_d, m->fom_sd_of_row_d, m->state_dof_d, m->Ahat_d};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }

@@ -31,7 +31,8 @@ class ModelDesc(C.Structure):
                 ("nsx", C.c_int), ("nsy", C.c_int), ("activation", C.c_int), ("n_C", C.c_int), ("N_A", C.c_int),
                 ("C", C.POINTER(C.c_double)), ("dec_om", C.POINTER(DecoderDesc)), ("dec_ga", C.POINTER(DecoderDesc)),
                 ("hr_count", C.POINTER(C.c_int)), ("hr_nodes", C.POINTER(C.POINTER(C.c_int))),
-                ("tile", C.c_int * 3)]
+                ("tile", C.c_int * 3), ("n_ports", C.c_int), ("dec_port", C.POINTER(DecoderDesc)),
+                ("port_activation", C.c_int)]
 
 
 class MlpDesc(C.Structure):
@@ -41,7 +42,8 @@ class MlpDesc(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("tol_abs", C.c_double), ("tol_rel", C.c_double), ("armijo_c1", C.c_double),
-                ("max_backtracks", C.c_int), ("precision", C.c_int), ("stall_tol", C.c_double)]
+                ("max_backtracks", C.c_int), ("precision", C.c_int), ("stall_tol", C.c_double),
+                ("stall_ratio", C.c_double)]
 
 
 _lib = None
@@ -133,18 +135,25 @@ def model_desc(pack: dict, tile=(0, 0, 0)):
         keep.append(a)
         return a.ctypes.data_as(C.POINTER(C.c_double))
 
+    def desc(prefix):
+        W1 = np.asarray(pack[f"{prefix}_W1"])
+        b, s = (int(v) for v in pack[f"{prefix}_bs"])
+        N = int(np.asarray(pack[f"{prefix}_xref"]).shape[0])
+        return DecoderDesc(N, int(W1.shape[1]) if W1.ndim == 2 else 0, int(W1.shape[0]), b, s, dptr(W1),
+                           dptr(pack[f"{prefix}_b1"]), dptr(pack[f"{prefix}_W2"]), dptr(pack[f"{prefix}_xref"]))
+
+    srpc = int(pack.get("srpc", 0)) == 1
+    n_ports = int(pack["n_ports"]) if srpc else 0
     decs = {}
-    for part in ("om", "ga"):
+    for part in (("om",) if srpc else ("om", "ga")):
         arr = (DecoderDesc * n)()
         for i in range(n):
-            W1 = np.asarray(pack[f"{part}{i}_W1"])
-            b, s = (int(v) for v in pack[f"{part}{i}_bs"])
-            N = int(np.asarray(pack[f"{part}{i}_xref"]).shape[0])
-            arr[i] = DecoderDesc(N, int(W1.shape[1]) if W1.ndim == 2 else 0, int(W1.shape[0]), b, s,
-                                 dptr(W1), dptr(pack[f"{part}{i}_b1"]), dptr(pack[f"{part}{i}_W2"]),
-                                 dptr(pack[f"{part}{i}_xref"]))
+            arr[i] = desc(f"{part}{i}")
         decs[part] = arr
-    keep.append(decs)
+    ports = (DecoderDesc * max(1, n_ports))()
+    for j in range(n_ports):
+        ports[j] = desc(f"pt{j}")
+    keep.extend([decs, ports])
     hr = [np.ascontiguousarray(np.asarray(pack[f"hr{i}"], dtype=np.int32)) for i in range(n)]
     keep.extend(hr)
     hr_cnt = (C.c_int * n)(*[len(h) for h in hr])
@@ -153,7 +162,9 @@ def model_desc(pack: dict, tile=(0, 0, 0)):
     Cm = np.asarray(pack["C"], dtype=np.float64)
     desc = ModelDesc(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"]), int(pack["nsx"]),
                      int(pack["nsy"]), int(pack["act"]), int(Cm.shape[0]), int(Cm.shape[1]), dptr(Cm),
-                     decs["om"], decs["ga"], hr_cnt, hr_ptrs, (C.c_int * 3)(*[int(v) for v in tile]))
+                     decs["om"], decs["ga"] if not srpc else C.POINTER(DecoderDesc)(), hr_cnt, hr_ptrs,
+                     (C.c_int * 3)(*[int(v) for v in tile]), n_ports, ports,
+                     int(pack["port_act"]) if srpc else 0)
     return desc, keep
 
 
@@ -211,9 +222,9 @@ class Workspace:
 
 
 def opts(max_iter=50, tol_abs=0.0, tol_rel=1e-8, armijo_c1=1e-4, max_backtracks=20, precision=PREC_FP64,
-         stall_tol=0.0) -> Opts:
+         stall_tol=0.0, stall_ratio=0.0) -> Opts:
     return Opts(int(max_iter), float(tol_abs), float(tol_rel), float(armijo_c1), int(max_backtracks), int(precision),
-                float(stall_tol))
+                float(stall_tol), float(stall_ratio))
 
 
 def dd_fom_residual(model: Model, mu, xsd, jac: bool = False):

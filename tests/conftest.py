@@ -71,3 +71,21 @@ def headline_pack():
     from oracle.build_model import build
     pack, *_ = build("cfg1shape", workers=min(4, os.cpu_count() or 1), verbose=False)
     return "cfg1shape", pack
+
+
+@pytest.fixture(scope="session")
+def tinysrpc2x1_pack():
+    """16x8 grid, 2x1 split, strong ROM-port constraint: one port of 3-band port decoders
+    ((b, s) = (3, 3), sigmoid), latents (4, 2)."""
+    from oracle.build_model import build
+    pack, *_ = build("tinysrpc2x1", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
+def tinysrpc3x1_pack():
+    """24x8 grid, 3x1 split, strong ROM-port constraint: the middle subdomain carries two
+    ports (latents (4, 4)), the outer ones one (latents (4, 2))."""
+    from oracle.build_model import build
+    pack, *_ = build("tinysrpc3x1", workers=1, verbose=False)
+    return pack
