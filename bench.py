@@ -56,10 +56,12 @@ def decoder_source_sha1():
 
 
 CONFIGS = {
-    "cfg1": dict(batch=512, seed=1, proposal_seed=5, precision=1, tol_rel=1e-6, stall_tol=1e-5, max_iter=60,
+    "cfg1": dict(batch=512, seed=1, proposal_seed=5, precision=1, tol_rel=1e-6, stall_tol=1e-5, stall_ratio=0.5,
+                 max_iter=60,
                  workload="Burgers 240x240, 4x4 subdomains, latent (8,4), width 2x, band 9, HR 10%, "
                           "512 held-out (a,lambda), FP32 decoder + FP64 KKT"),
-    "cfg0": dict(batch=1, seed=0, proposal_seed=5, precision=0, tol_rel=1e-8, stall_tol=0.0, max_iter=60,
+    "cfg0": dict(batch=1, seed=0, proposal_seed=5, precision=0, tol_rel=1e-8, stall_tol=0.0, stall_ratio=0.0,
+                 max_iter=60,
                  workload="Burgers 36x36, 2x2 subdomains, latent (6,3), width 3x, band 5, HR 20%, "
                           "1 held-out (a,lambda), FP64"),
 }
@@ -86,6 +88,7 @@ def decoder_work(model, B):
 
 
 UNEVEN = dict(models=("cfg2a", "cfg2b", "cfg2c"), batch=1024, seed=2, precision=1, tol_rel=1e-6, stall_tol=1e-5,
+              stall_ratio=0.5,
               max_iter=60,
               workload="uneven batch: 1024 held-out (a,lambda) split evenly (seeded) over three Burgers models "
                        "with 60x60-node subdomains: 120x120 2x2, 240x240 4x4, 480x480 8x8; per-subdomain latent "
@@ -107,7 +110,8 @@ def uneven_leg(a, torch, dr):
     B = cfg["batch"]
     mu_all = si.heldout_mu(B, cfg["seed"])
     which = si.model_assignment(B, len(paths), cfg["seed"])
-    o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"], stall_tol=cfg["stall_tol"])
+    o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"], stall_tol=cfg["stall_tol"],
+                stall_ratio=cfg["stall_ratio"])
     table = os.path.join(ROOT, "paper_2305_15163_amd", "tiles.json")
     models, wss, mus, tiles, info = [], [], [], [], []
     for k, p in enumerate(paths):
@@ -151,7 +155,11 @@ def uneven_leg(a, torch, dr):
         it = r["iters"].cpu().numpy()
         info[k]["iters_mean"] = float(it.mean())
         info[k]["status_counts"] = {dr.STATUS[s]: int((st == s).sum()) for s in np.unique(st)}
+    stopped_ok = sum(v.get("converged", 0) + v.get("stalled", 0) for v in (i["status_counts"] for i in info))
+    converged = sum(i["status_counts"].get("converged", 0) for i in info)
     return {"workload": cfg["workload"], "solves_per_s": B * a.steps / dt_m, "ms_per_step": 1e3 * dt_m / a.steps,
+            "converged_solves_per_s": converged * a.steps / dt_m,
+            "converged_or_stalled_solves_per_s": stopped_ok * a.steps / dt_m,
             "separate_batches_solves_per_s": B * a.steps / dt_s, "models": info,
             "tiles_from": "work-item shape search (ddrom_autotune), table paper_2305_15163_amd/tiles.json"}
 
@@ -212,7 +220,7 @@ def roofline_only(a, torch, dr, si):
     B = cfg["batch"]
     mu_h = si.heldout_mu(B, cfg["seed"])
     o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"],
-                stall_tol=cfg["stall_tol"])
+                stall_tol=cfg["stall_tol"], stall_ratio=cfg["stall_ratio"])
     tile = autotune.tiles_for(pack, mu_h, o, path=os.path.join(ROOT, "paper_2305_15163_amd", "tiles.json"))
     model = dr.Model(pack, tile=tile)
     ws = dr.Workspace(model, B)
@@ -395,7 +403,7 @@ def main():
     mu_h = si.heldout_mu(B, cfg["seed"])
     mu = torch.as_tensor(mu_h, device="cuda")
     o = dr.opts(max_iter=cfg["max_iter"], tol_rel=cfg["tol_rel"], precision=cfg["precision"],
-                stall_tol=cfg["stall_tol"])
+                stall_tol=cfg["stall_tol"], stall_ratio=cfg["stall_ratio"])
     # work-item shapes from the persisted table of measured shapes (measured now when missing)
     from paper_2305_15163_amd import autotune
     tile = autotune.tiles_for(pack, mu_h, o, path=os.path.join(ROOT, "paper_2305_15163_amd", "tiles.json"),
@@ -633,8 +641,11 @@ def main():
 
 
 def line_stop(cfg):
-    return (f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
-            f"or line-search stagnation below {cfg['stall_tol']:g} ||F0||")
+    out = (f"||F|| <= {cfg['tol_rel']:g} ||F0||, max_iter {cfg['max_iter']}, "
+           f"or stagnation below {cfg['stall_tol']:g} ||F0|| (Armijo failure")
+    if cfg.get("stall_ratio", 0.0) > 0.0:
+        out += f", or an accepted step reducing ||F|| by less than the factor {cfg['stall_ratio']:g}"
+    return out + ")"
 
 
 def model_grid(pack):

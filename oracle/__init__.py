@@ -15,14 +15,18 @@ and no blocking or fusion beyond what the paper states:
                      hand-written gradients, Adam training.
   hyperreduction.py  Sections 3.3, 5.3-5.4: POD energy criterion, greedy collocation
                      sampling, subnet extraction.
-  rom.py             Section 4: WFPC DD-LSPG objective with collocation HR, Lagrange-
-                     Gauss-Newton SQP with a full dense KKT solve and Armijo backtracking;
-                     DD-FOM SQP; relative error (eq. relative_error).
+  rom.py             Section 4: DD-LSPG objective with collocation HR under the weak
+                     FOM-port or the strong ROM-port constraint, Lagrange-Gauss-Newton SQP
+                     with a full dense KKT solve and Armijo backtracking; DD-FOM SQP;
+                     relative error (eq. relative_error).
+  srpc.py            Section 3.2: ports, port decoders, the implied interface decoders and
+                     the linear ROM-port constraint.
   lsrom.py           Section 3.3: LS-ROM (affine or POD maps) with collocation or gappy-POD
                      HR, solved along routes independent of rom.py (null-space QP steps).
   proposal.py        learned initial-iterate proposal (forward/backward, Adam, FP64)
                      and the zero-start fallback rule.
   build_model.py     offline pipeline (snapshots -> autoencoders -> HR -> model pack).
+  pack.py            model pack (.npz) -> ROMModel.
 
 Parity unpinned: the greedy sampler (hyperreduction.greedy_sample) follows the cited
 algorithm by reading only; it is pinned by invariants, not by values.

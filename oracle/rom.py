@@ -220,6 +220,8 @@ class SQPOptions:
     c1: float = 1e-4
     max_backtracks: int = 20
     stall_tol: float = 0.0    # > 0: an Armijo failure with ||F|| <= stall_tol ||F_0|| stops with STALLED
+    stall_ratio: float = 0.0  # > 0 (with stall_tol): an accepted step ending above the tolerance at
+    #                           ||F|| <= stall_tol ||F_0|| with ||F_new|| > stall_ratio ||F_old|| stops with STALLED
 
 
 @dataclass
@@ -286,11 +288,14 @@ def sqp_solve(model: ROMModel, mu, xhat0: np.ndarray | None = None, lam0: np.nda
     for k in range(opts.max_iter):
         if fn <= tol:
             return SQPResult(x, lam, CONVERGED, k, fn, f0, n_eval, hist)
+        fn_old = fn
         x, lam, ev, fn, st, ne, _ = sqp_step(model, mu, x, lam, opts, ev, f0)
         n_eval += ne
         hist.append(fn)
         if st >= 0:
             return SQPResult(x, lam, st, k, fn, f0, n_eval, hist)
+        if opts.stall_ratio > 0.0 and tol < fn <= opts.stall_tol * f0 and fn > opts.stall_ratio * fn_old:
+            return SQPResult(x, lam, STALLED, k + 1, fn, f0, n_eval, hist)
     status = CONVERGED if fn <= tol else MAX_ITER
     return SQPResult(x, lam, status, opts.max_iter, fn, f0, n_eval, hist)
 

@@ -89,8 +89,7 @@ def test_headline_gn_blocks(dr, head, precision):
 def test_headline_sqp_step(dr, head):
     """One SQP iteration at B = 192 in FP64 (the 12-entry-block update kernel with a 32 x 32
     Schur complement): sampled lanes against the oracle's step (dense LAPACK KKT solve).
-    x to 1e-10; the multiplier to max(1e-10, 100 cond(K) eps): lambda is the part of the KKT
-    solution the dense and the Schur-complement routes determine least accurately."""
+    x and the multiplier to 1e-10."""
     name, gm, om = head
     print("[headline sqp_step]", flush=True)
     B = 192
@@ -106,7 +105,7 @@ def test_headline_sqp_step(dr, head):
               flush=True)
         assert int(st[b]) == (1 if sr == -1 else sr)
         assert relerr(x1[b], xr) <= 1e-10
-        assert relerr(l1[b], lr) <= max(1e-10, 100 * kap * np.finfo(float).eps)
+        assert relerr(l1[b], lr) <= 1e-10
         assert abs(fn[b] - fr) <= 1e-10 * max(1.0, fr)
 
 

@@ -63,6 +63,7 @@ def test_big_kkt_step(dr, big):
     x1, l1, fn, st = (t.cpu().numpy() for t in dr.sqp_step(gm, ws, mus, xh, lam, o))
     for b in range(B):
         xr, lr, _, fr, sr, _, _ = sqp_step(om, mus[b], xh[b], lam[b], SQPOptions(max_backtracks=20))
+        print("tinybig step", b, "x err %.2e lam err %.2e" % (relerr(x1[b], xr), relerr(l1[b], lr)), flush=True)
         assert int(st[b]) == (1 if sr == -1 else sr)
         assert relerr(x1[b], xr) <= 1e-10
         assert relerr(l1[b], lr) <= 1e-8
@@ -81,7 +82,9 @@ def test_big_kkt_short_solve(dr, big):
     out = {k: v.cpu().numpy() for k, v in out.items()}
     for b in range(B):
         ref = sqp_solve(om, mus[b], opts=SQPOptions(max_iter=it, tol_abs=0.0, tol_rel=1e-12))
-        print("tinybig", b, "status", out["status"][b], ref.status, "iters", out["iters"][b], ref.iters, flush=True)
+        print("tinybig", b, "status", out["status"][b], ref.status, "iters", out["iters"][b], ref.iters,
+              "x err %.2e lam err %.2e" % (relerr(out["xhat"][b], ref.xhat), relerr(out["lam"][b][:gm.n_C], ref.lam)),
+              flush=True)
         assert int(out["status"][b]) == ref.status
         assert int(out["iters"][b]) == ref.iters
         assert relerr(out["xhat"][b], ref.xhat) <= 1e-9
@@ -102,6 +105,7 @@ def test_huge_kkt_step(dr, tinyhuge_pack):
     x1, l1, fn, st = (t.cpu().numpy() for t in dr.sqp_step(gm, ws, mus, xh, lam, o))
     for b in range(B):
         xr, lr, _, fr, sr, _, _ = sqp_step(om, mus[b], xh[b], lam[b], SQPOptions(max_backtracks=20))
+        print("tinyhuge step", b, "x err %.2e lam err %.2e" % (relerr(x1[b], xr), relerr(l1[b], lr)), flush=True)
         assert int(st[b]) == (1 if sr == -1 else sr)
         # Gauss-Newton blocks of this briefly trained model have condition numbers near 1e5
         assert relerr(x1[b], xr) <= 1e-9

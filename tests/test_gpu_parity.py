@@ -1,5 +1,6 @@
 """Parity of the HIP library (through its C ABI) with the FP64 oracle on identical
-seeded inputs.  FP64 mode: relative 1e-12 per kernel, 1e-10 for SQP steps and solves.
+seeded inputs.  FP64 mode: relative 1e-12 per kernel, 1e-10 for SQP steps and solves
+(latents and multipliers alike, equal iteration counts).
 FP32-decoder mode: tolerances derived from FP32 rounding (stated per test)."""
 import numpy as np
 import pytest
@@ -151,7 +152,7 @@ def test_sqp_step_parity(dr, case):
               flush=True)
         assert int(st[b]) == (1 if sr == -1 else sr)
         assert relerr(x1[b], xr) <= 1e-10
-        assert relerr(l1[b], lr) <= 1e-8
+        assert relerr(l1[b], lr) <= 1e-10
         assert abs(fn[b] - fr) <= 1e-10 * max(1.0, fr)
 
 
@@ -173,8 +174,8 @@ def test_rom_solve_parity(dr, case, B):
                   ref.fnorm / ref.fnorm0), flush=True)
         assert int(out["status"][b]) == ref.status
         assert relerr(out["xhat"][b], ref.xhat) <= 1e-10
-        assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-7
-        assert abs(int(out["iters"][b]) - ref.iters) <= 1
+        assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-10
+        assert int(out["iters"][b]) == ref.iters
         assert abs(out["fnorm0"][b] - ref.fnorm0) <= 1e-12 * ref.fnorm0
 
 

@@ -177,3 +177,24 @@ def test_max_iter_one(dr, request, name):
         assert int(out["status"][b]) == MAX_ITER and int(out["iters"][b]) == 1
         assert relerr(out["xhat"][b], ref.xhat) <= 1e-10
         assert abs(out["fnorm"][b] - ref.fnorm) <= 1e-10 * ref.fnorm
+
+
+def test_stall_ratio_fp64(dr, tiny_pack):
+    """The progress form of the stagnation stop (stall_ratio) in FP64, where it fires well above
+    the rounding floor: the same step, status and point as the oracle's.  The decisive ratio of
+    each case is checked to be far from the threshold, so rounding cannot flip the decision."""
+    print("[status stall_ratio fp64]", flush=True)
+    om = load_pack(tiny_pack)
+    mus = si.heldout_mu(3, 11)
+    theta, stol = 0.05, 1e-3
+    gm, out = _solve(dr, tiny_pack, mus, max_iter=60, tol_rel=1e-14, stall_tol=stol, stall_ratio=theta)
+    for b in range(len(mus)):
+        ref = sqp_solve(om, mus[b], opts=SQPOptions(max_iter=60, tol_abs=0.0, tol_rel=1e-14, stall_tol=stol,
+                                                    stall_ratio=theta))
+        h = ref.history
+        print(f"  mu {b}: status gpu {int(out['status'][b])} oracle {ref.status}, iters gpu {int(out['iters'][b])} "
+              f"oracle {ref.iters}, ratio {h[ref.iters] / h[ref.iters - 1]:.3e}", flush=True)
+        assert ref.status == STALLED
+        assert abs(h[ref.iters] / h[ref.iters - 1] - theta) > 1e-3 * theta
+        assert int(out["status"][b]) == STALLED and int(out["iters"][b]) == ref.iters
+        assert relerr(out["xhat"][b], ref.xhat) <= 1e-10

@@ -370,3 +370,22 @@ def test_max_iter_one_is_one_step(tiny_pack):
         x1, l1, _, f1, st, _, _ = sqp_step(m, mu, x0, lam0, SQPOptions(), ev)
         assert st == -1 and res.status == MAX_ITER and res.iters == 1
         assert np.array_equal(res.xhat, x1) and np.array_equal(res.lam, l1) and res.fnorm == f1
+
+
+def test_stall_ratio_rule(tiny_pack):
+    """The progress form of the stagnation stop: with stall_ratio > 0 the solve stops STALLED at
+    the first accepted step that ends below stall_tol ||F_0|| (above the tolerance) having reduced
+    ||F|| by less than the factor stall_ratio - read off the history of the same solve run
+    without the rule, whose iterate at that step it returns exactly."""
+    m = load_pack(tiny_pack)
+    for mu in si.heldout_mu(3, 11):
+        free = sqp_solve(m, mu, opts=SQPOptions(max_iter=60, tol_abs=0.0, tol_rel=1e-14))
+        h = free.hist if hasattr(free, "hist") else free.history
+        theta, st = 0.05, 1e-3
+        k_stop = next((k for k in range(1, len(h)) if h[k] <= st * free.fnorm0 and h[k] > theta * h[k - 1]), None)
+        assert k_stop is not None
+        res = sqp_solve(m, mu, opts=SQPOptions(max_iter=60, tol_abs=0.0, tol_rel=1e-14, stall_tol=st,
+                                               stall_ratio=theta))
+        assert res.status == STALLED and res.iters == k_stop
+        ref = sqp_solve(m, mu, opts=SQPOptions(max_iter=k_stop, tol_abs=0.0, tol_rel=1e-14))
+        assert np.array_equal(res.xhat, ref.xhat) and res.fnorm == h[k_stop]
