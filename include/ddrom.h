@@ -58,13 +58,17 @@ extern "C" {
  *   W1 [w][n], b1 [w], W2 [N][3][b], x_ref [N].
  * W2 holds the values of the three-band mask of Section 7.3: slot (r, k, t) is column
  * r*s + (k-1)*b*s + t of the dense N x w matrix; slots whose column falls outside [0, w)
- * are ignored.  w must equal N*s. */
+ * are ignored.  w must equal N*s.
+ * dense != 0: W2 is the full N x w matrix ([N][w], every hidden unit feeds every state; b and s
+ * are ignored; w <= 48).  With the identity activation, W1 = I_n and b1 = 0 this is the affine
+ * map x_ref + Phi xhat of the LS-ROM (Section 3.3) with Phi = W2. */
 typedef struct {
     int N, n, w, b, s;
     const double* W1;
     const double* b1;
     const double* W2;
     const double* x_ref;
+    int dense;
 } ddrom_decoder_desc;
 
 /* Everything the online solve needs (host memory; deep-copied by ddrom_model_create).

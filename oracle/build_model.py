@@ -26,10 +26,11 @@ from concurrent.futures import ProcessPoolExecutor
 import numpy as np
 
 import seeded_inputs as si
-from .autoencoder import ACT_SIGMOID, MaskedAE, export_decoder, train
+from .autoencoder import ACT_IDENTITY, ACT_SIGMOID, MaskedAE, export_decoder, train
 from .burgers import BurgersFOM, Grid, solve_fom
 from .ddmaps import build_dd
 from .hyperreduction import greedy_sample, pod_basis
+from .lsrom import pod_maps
 from .srpc import cover_ports, port_latent_size
 
 CONFIGS = {
@@ -76,6 +77,14 @@ CONFIGS = {
     "tinysrpc3": dict(nx=18, ny=12, nsx=3, nsy=2, n_om=4, b=3, s=2, act=ACT_SIGMOID,
                       ports=dict(n_tilde=3, b=3, s=3, act=ACT_SIGMOID),
                       epochs=200, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=9),
+    # LS-ROM (Section 3.3): POD bases of the same snapshots in place of the decoders (linear maps
+    # x = Phi xhat), the same collocation HR nodes, latents and C as the nonlinear-manifold model
+    "cfg0ls": dict(nx=36, ny=36, nsx=2, nsy=2, n_om=6, n_ga=3, b=5, s=3, act=ACT_SIGMOID, ls=True,
+                   epochs=0, batch=4, train_grid=(5, 5), hr_frac=0.20, seed=0),
+    "cfg1ls": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID, ls=True,
+                   epochs=0, batch=32, train_grid=(16, 16), hr_frac=0.10, seed=1),
+    "tinyls": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID, ls=True,
+                   epochs=0, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
     # small configurations for tests
     "tinymix": dict(nx=16, ny=12, nsx=2, nsy=2, n_om="draw", n_ga="half", b=3, s=2, act=ACT_SIGMOID,
                     epochs=300, batch=4, train_grid=(4, 4), hr_frac=(0.3, 0.6), seed=31),
@@ -152,8 +161,11 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
     if pc is not None:
         cfg = dict(cfg, n_ga=0)
     n_om, n_ga, hr_frac = per_subdomain_choices(cfg, dd.n_sub)
+    ls = bool(cfg.get("ls", False))
     jobs = []
     for i, sd in enumerate(dd.subdomains):
+        if ls:
+            continue
         if base is None:
             jobs.append((X[:, sd.omega], len(sd.omega), n_om[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i],
                          cfg["epochs"], cfg["batch"], ("om", i)))
@@ -211,6 +223,9 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
         pack[f"{prefix}_bs"] = np.array([d.b, d.s])
 
     for i in range(dd.n_sub):
+        pack[f"hr{i}"] = hr_nodes[i]
+        if ls:
+            continue
         if base is not None:
             for key in ("W1", "b1", "W2", "xref", "bs"):
                 pack[f"om{i}_{key}"] = np.asarray(base[f"om{i}_{key}"])
@@ -218,7 +233,17 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
             put(f"om{i}", decs[("om", i)])
         if pc is None:
             put(f"ga{i}", decs[("ga", i)])
-        pack[f"hr{i}"] = hr_nodes[i]
+    if ls:
+        # linear maps x = Phi xhat from the POD of each subdomain's snapshots (eq. energy_criterion's
+        # basis truncated at the configured latent sizes), identity "activation"
+        for key in [k for k in pack if k.startswith(("om", "ga")) and not k.startswith(("om_", "ga_"))]:
+            del pack[key]
+        pack["act"] = np.int64(ACT_IDENTITY)
+        for i, sd in enumerate(dd.subdomains):
+            for part, idx, n in (("om", sd.omega, n_om[i]), ("ga", sd.gamma, n_ga[i])):
+                x0, Phi = pod_maps(X[:, idx].T, n=n)
+                pack[f"{part}{i}_Phi"] = Phi
+                pack[f"{part}{i}_x0"] = x0
     if pc is not None:
         pack["srpc"] = np.int64(1)
         pack["port_act"] = np.int64(pc["act"])

@@ -54,3 +54,19 @@ def _srpc_model(pack, g, dec_om, hr) -> ROMModel:
     dec_ga = interface_decoders(dd, pm, pdec)
     return ROMModel(g, int(pack["nsx"]), int(pack["nsy"]), dec_om, dec_ga, hr, np.zeros((0, dd.n_A)), dd=dd,
                     A_hat=pm.A_hat)
+
+
+def load_ls_pack(pack, use_hr: bool = True):
+    """LS-ROM pack (om{i}_Phi / om{i}_x0, ga{i}_Phi / ga{i}_x0 instead of decoders) -> the LS-ROM
+    oracle with collocation HR on the pack's nodes."""
+    from .burgers import BurgersFOM
+    from .lsrom import LSROM, collocation_operator
+    if isinstance(pack, str):
+        pack = dict(np.load(pack, allow_pickle=False))
+    g = Grid(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"]))
+    n = int(pack["n_sub"])
+    dd = build_dd(g, int(pack["nsx"]), int(pack["nsy"]))
+    get = lambda key: [np.asarray(pack[f"{key[0]}{i}_{key[1]}"], np.float64) for i in range(n)]
+    hr = [collocation_operator(g, np.asarray(pack[f"hr{i}"], np.int64)) for i in range(n)] if use_hr else None
+    return LSROM(BurgersFOM(g), dd, np.asarray(pack["C"], np.float64), get(("om", "x0")), get(("om", "Phi")),
+                 get(("ga", "x0")), get(("ga", "Phi")), hr=hr)

@@ -40,6 +40,11 @@ struct DecSeg {
 // Dynamic LDS layout of one decode work item (byte offsets, 16-byte aligned regions):
 // staged W1~ rows [span][nl], biases [span], W2~ values [rows][3][bmax], x_ref [rows],
 // band descriptors [rows][3] (int2), then one hidden-activation ring per wave.
+// Hidden-unit ring of the decode kernel: every decoded row's three bands must lie in a window
+// of at most DEC_RING consecutive (compressed) hidden units (2 b s + b <= DEC_RING for the
+// three-band masks).
+constexpr int DEC_RING = 48;
+
 struct DecLds {
     size_t w1, b1, w2, xr, bd, ring, total;
 };
@@ -52,7 +57,7 @@ __host__ __device__ inline DecLds dec_lds(int span, int rows, int nl, int bmax, 
     L.xr = al16(L.w2 + (size_t)rows * 3 * bmax * esz);
     L.bd = al16(L.xr + (size_t)rows * esz);
     L.ring = al16(L.bd + (size_t)rows * 3 * 8);
-    L.total = L.ring + (size_t)waves * 48 * 64 * esz * rk;
+    L.total = L.ring + (size_t)waves * DEC_RING * 64 * esz * rk;
     return L;
 }
 

@@ -108,7 +108,6 @@ __device__ __forceinline__ int slot_solve(const int* live, int j, int nl) {
 // compressed hidden units, so every hidden activation is computed once per lane into a
 // per-lane ring in LDS and consumed by the rows that need it.  For the sigmoid the ring
 // holds s = sigma(z) and sigma' = s - s^2 is formed on use; the swish keeps (value, sigma').
-constexpr int DEC_RING = 48;
 
 template <typename T, int ACT>
 struct RingSlots { static constexpr int K = (ACT == DDROM_ACT_SWISH) ? 2 : 1; };

@@ -11,7 +11,7 @@
 
 namespace ddrom {
 
-static constexpr int RING = 48;          // hidden-unit ring of the decode kernel (window bound)
+static constexpr int RING = DEC_RING;    // hidden-unit ring of the decode kernel (window bound)
 static constexpr int DEC_ROWS = 48;      // default max output rows per decode work item
 static constexpr int DEC_STAGE = 15360;  // bytes of FP32 weights staged in LDS per decode work item
 static constexpr int RES_NODES = 24;     // default sampled nodes per residual work item
@@ -39,7 +39,36 @@ struct HostDecoder {
 };
 
 // Subnet of eq. subnet for the output rows `rows` (ascending) of one decoder.
+// Dense output layer (every hidden unit feeds every row): one band per row covering all w
+// hidden units, values in band slot 0 ([rows][3][w]).
+static int make_dense_rows(const ddrom_decoder_desc& d, const std::vector<int>& rows, HostDecoder& out) {
+    const int N = d.N, n = d.n, w = d.w;
+    if (w > RING) {
+        set_error("dense decoder wider than the kernel's hidden-unit ring (w must be <= 48)");
+        return DDROM_EINVAL;
+    }
+    out.rows = (int)rows.size();
+    out.hid = rows.empty() ? 0 : w;
+    out.W1.assign(d.W1, d.W1 + (size_t)out.hid * n);
+    out.b1.assign(d.b1, d.b1 + out.hid);
+    out.band.assign(rows.size() * 3, int2{0, 0});
+    out.W2.assign(rows.size() * 3 * (size_t)w, 0.0);
+    out.xref.resize(rows.size());
+    for (size_t q = 0; q < rows.size(); ++q) {
+        const int r = rows[q];
+        if (r < 0 || r >= N) {
+            set_error("subnet row out of range");
+            return DDROM_EINVAL;
+        }
+        out.xref[q] = d.x_ref[r];
+        for (int t = 0; t < w; ++t) out.W2[q * 3 * w + t] = d.W2[(size_t)r * w + t];
+        out.band[q * 3] = int2{0, w};
+    }
+    return 0;
+}
+
 static int make_subnet(const ddrom_decoder_desc& d, const std::vector<int>& rows, HostDecoder& out) {
+    if (d.dense) return make_dense_rows(d, rows, out);
     const int N = d.N, n = d.n, w = d.w, b = d.b, s = d.s;
     std::vector<int> cmap(w, -1);
     for (int r : rows)
@@ -277,7 +306,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         }
         for (int j = 0; j < d->n_ports; ++j) {
             const ddrom_decoder_desc& e = d->dec_port[j];
-            if (e.N != 2 * (int)port_nodes[j].size() || e.n <= 0 || e.b <= 0 || e.s <= 0 || e.w != e.N * e.s || !e.W1 ||
+            if (e.N != 2 * (int)port_nodes[j].size() || e.dense || e.n <= 0 || e.b <= 0 || e.s <= 0 || e.w != e.N * e.s || !e.W1 ||
                 !e.b1 || !e.W2 || !e.x_ref) {
                 std::ostringstream os;
                 os << "port " << j << ": decoder needs N = " << 2 * port_nodes[j].size()
@@ -317,8 +346,10 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         }
         for (const ddrom_decoder_desc* e : {&a, &g}) {
             if (e == &gport) continue;
-            if (e->N > 0 && (e->n <= 0 || e->b <= 0 || e->s <= 0 || e->w != e->N * e->s || !e->W1 || !e->b1 || !e->W2 || !e->x_ref)) {
-                set_error("decoder descriptor: need n, b, s > 0, w = N*s and all weight pointers");
+            const bool shape_ok = e->dense ? (e->w > 0 && e->w <= RING) : (e->b > 0 && e->s > 0 && e->w == e->N * e->s);
+            if (e->N > 0 && (e->n <= 0 || !shape_ok || !e->W1 || !e->b1 || !e->W2 || !e->x_ref)) {
+                set_error("decoder descriptor: need n > 0, b, s > 0 and w = N*s (or dense with 0 < w <= 48) and all "
+                          "weight pointers");
                 return DDROM_EINVAL;
             }
             if (e->n > 24) {
@@ -505,7 +536,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             sg.sd = sd;
             sg.n = interior ? m->n_om[sd] : m->n_ga[sd];
             sg.xoff = m->xoff[sd] + (interior ? 0 : m->n_om[sd]);
-            sg.bmax = dd.N > 0 ? (ported ? port_bmax : dd.b) : 1;
+            sg.bmax = dd.N > 0 ? (ported ? port_bmax : (dd.dense ? dd.w : dd.b)) : 1;
             if (dd.N == 0) {
                 sg.rows = 0; sg.hid = 0;
                 sg.w1 = (long long)W1.size(); sg.b1 = (long long)b1.size(); sg.band = (long long)bands.size();

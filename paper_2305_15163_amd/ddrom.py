@@ -23,7 +23,7 @@ STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "kkt_not_pd", 
 class DecoderDesc(C.Structure):
     _fields_ = [("N", C.c_int), ("n", C.c_int), ("w", C.c_int), ("b", C.c_int), ("s", C.c_int),
                 ("W1", C.POINTER(C.c_double)), ("b1", C.POINTER(C.c_double)),
-                ("W2", C.POINTER(C.c_double)), ("x_ref", C.POINTER(C.c_double))]
+                ("W2", C.POINTER(C.c_double)), ("x_ref", C.POINTER(C.c_double)), ("dense", C.c_int)]
 
 
 class ModelDesc(C.Structure):
@@ -136,11 +136,17 @@ def model_desc(pack: dict, tile=(0, 0, 0)):
         return a.ctypes.data_as(C.POINTER(C.c_double))
 
     def desc(prefix):
+        if f"{prefix}_Phi" in pack:
+            # LS-ROM affine map x0 + Phi xhat as a dense decoder: W1 = I, b1 = 0, identity activation
+            Phi = np.asarray(pack[f"{prefix}_Phi"], dtype=np.float64)
+            N, n = Phi.shape
+            return DecoderDesc(N, n, n, 0, 0, dptr(np.eye(n)), dptr(np.zeros(n)), dptr(Phi),
+                               dptr(pack[f"{prefix}_x0"]), 1)
         W1 = np.asarray(pack[f"{prefix}_W1"])
         b, s = (int(v) for v in pack[f"{prefix}_bs"])
         N = int(np.asarray(pack[f"{prefix}_xref"]).shape[0])
         return DecoderDesc(N, int(W1.shape[1]) if W1.ndim == 2 else 0, int(W1.shape[0]), b, s, dptr(W1),
-                           dptr(pack[f"{prefix}_b1"]), dptr(pack[f"{prefix}_W2"]), dptr(pack[f"{prefix}_xref"]))
+                           dptr(pack[f"{prefix}_b1"]), dptr(pack[f"{prefix}_W2"]), dptr(pack[f"{prefix}_xref"]), 0)
 
     srpc = int(pack.get("srpc", 0)) == 1
     n_ports = int(pack["n_ports"]) if srpc else 0

@@ -89,3 +89,24 @@ def tinysrpc3x1_pack():
     from oracle.build_model import build
     pack, *_ = build("tinysrpc3x1", workers=1, verbose=False)
     return pack
+
+
+@pytest.fixture(scope="session")
+def tinyls_pack():
+    """LS-ROM on the 12x8, 2x2 split: POD bases (latents (4, 2)) with the tiny model's HR nodes."""
+    from oracle.build_model import build
+    pack, *_ = build("tinyls", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
+def cfg0ls_pack():
+    """LS-ROM of the 36x36, 2x2 workload: POD bases (6, 3), the same HR nodes and C as its
+    nonlinear-manifold model."""
+    import numpy as np
+    path = os.path.join(ROOT, "models", "cfg0ls.npz")
+    if os.path.exists(path):
+        return dict(np.load(path, allow_pickle=False))
+    from oracle.build_model import build
+    pack, *_ = build("cfg0ls", workers=1, verbose=False)
+    return pack

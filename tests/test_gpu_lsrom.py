@@ -1,0 +1,90 @@
+"""LS-ROM (Section 3.3) on the GPU, through the C ABI: the POD maps x = Phi xhat run as dense
+decoders with the identity activation (W1 = I, b1 = 0, W2 = Phi) on the same kernels, against
+the independent LS-ROM oracle (its own residual route, null-space QP steps) with collocation HR
+on the same nodes: maps and their constant Jacobians, FP64 solves (statuses, iteration counts,
+latents and multipliers to 1e-10) and FP32-map solves against the FOM."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import seeded_inputs as si
+from oracle import lsrom
+from oracle.burgers import solve_fom
+from oracle.pack import load_ls_pack
+
+
+@pytest.fixture(scope="module")
+def dr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_15163_amd as d
+    d.lib()
+    return d
+
+
+@pytest.fixture(scope="module", params=["tinyls", "cfg0ls"])
+def case(request, dr):
+    pack = request.getfixturevalue(request.param + "_pack")
+    print(f"[lsrom case {request.param}]", flush=True)
+    return request.param, pack, dr.Model(pack), load_ls_pack(pack)
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b))))
+
+
+def test_lsrom_maps(dr, case):
+    """Kept rows of x0 + Phi xhat and their Jacobian rows Phi (interior subnet rows, every
+    interface row)."""
+    name, pack, gm, rom = case
+    B = 70
+    ws = dr.Workspace(gm, B)
+    for i in range(gm.n_sub):
+        for part, (x0, Phi) in ((0, (rom.x0_om[i], rom.Phi_om[i])), (1, (rom.x0_ga[i], rom.Phi_ga[i]))):
+            rows = gm.subnet_rows(i, part)
+            xh = si.normal((B, Phi.shape[1]), seed=900 + 3 * i + part)
+            x, J = (t.cpu().numpy() for t in dr.ae_jacobian_hr(gm, ws, i, part, xh, precision=dr.PREC_FP64))
+            for b in range(B):
+                assert relerr(x[b], (x0 + Phi @ xh[b])[rows]) <= 1e-13
+                assert relerr(J[b], Phi[rows]) <= 1e-15
+
+
+@pytest.mark.parametrize("B", [1, 6])
+def test_lsrom_solve(dr, case, B):
+    name, pack, gm, rom = case
+    mus = si.heldout_mu(B, 17)
+    ws = dr.Workspace(gm, B)
+    out = {k: v.cpu().numpy() for k, v in dr.rom_solve_batch(gm, ws, mus, dr.opts(max_iter=100, tol_rel=1e-12,
+                                                                                  precision=dr.PREC_FP64)).items()}
+    for b in range(B):
+        ref = lsrom.solve(rom, mus[b], max_iter=100, tol_abs=0.0, tol_rel=1e-12)
+        print(name, b, "status", out["status"][b], ref.status, "iters", out["iters"][b], ref.iters,
+              "x err %.2e lam err %.2e" % (relerr(out["xhat"][b], ref.xhat), relerr(out["lam"][b][:gm.n_C], ref.lam)),
+              flush=True)
+        assert int(out["status"][b]) == ref.status and int(out["iters"][b]) == ref.iters
+        assert relerr(out["xhat"][b], ref.xhat) <= 1e-10
+        assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-10
+        assert abs(out["fnorm0"][b] - ref.fnorm0) <= 1e-12 * ref.fnorm0
+
+
+def test_lsrom_fp32_maps(dr, case):
+    """FP32 maps, FP64 residual and KKT: error against the FOM within 10% (plus 1e-4) of the
+    FP64 solve's."""
+    name, pack, gm, rom = case
+    B = 3
+    mus = si.heldout_mu(B, 29)
+    ws = dr.Workspace(gm, B)
+    x64 = dr.rom_solve_batch(gm, ws, mus, dr.opts(max_iter=60, tol_rel=1e-8, precision=dr.PREC_FP64))["xhat"]
+    x32 = dr.rom_solve_batch(gm, ws, mus, dr.opts(max_iter=60, tol_rel=1e-6, precision=dr.PREC_FP32_DECODER,
+                                                  stall_tol=1e-5, stall_ratio=0.5))["xhat"]
+    f = dict(dtype=torch.float64, device="cuda")
+    xf = torch.as_tensor(np.stack([solve_fom(rom.fom, m).x for m in mus]), **f)
+    e64 = dr.relative_error(gm, ws, x64, xf).cpu().numpy()
+    e32 = dr.relative_error(gm, ws, x32, xf).cpu().numpy()
+    for b in range(B):
+        print(name, b, "rel err fp64 %.3e fp32 %.3e" % (e64[b], e32[b]), flush=True)
+        assert e32[b] <= 1.1 * e64[b] + 1e-4

@@ -66,7 +66,7 @@ def test_big_kkt_step(dr, big):
         print("tinybig step", b, "x err %.2e lam err %.2e" % (relerr(x1[b], xr), relerr(l1[b], lr)), flush=True)
         assert int(st[b]) == (1 if sr == -1 else sr)
         assert relerr(x1[b], xr) <= 1e-10
-        assert relerr(l1[b], lr) <= 1e-8
+        assert relerr(l1[b], lr) <= 1e-10
         assert abs(fn[b] - fr) <= 1e-10 * max(1.0, fr)
 
 
@@ -87,8 +87,8 @@ def test_big_kkt_short_solve(dr, big):
               flush=True)
         assert int(out["status"][b]) == ref.status
         assert int(out["iters"][b]) == ref.iters
-        assert relerr(out["xhat"][b], ref.xhat) <= 1e-9
-        assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-7
+        assert relerr(out["xhat"][b], ref.xhat) <= 1e-10
+        assert relerr(out["lam"][b][:gm.n_C], ref.lam) <= 1e-10
 
 
 def test_huge_kkt_step(dr, tinyhuge_pack):
@@ -107,9 +107,8 @@ def test_huge_kkt_step(dr, tinyhuge_pack):
         xr, lr, _, fr, sr, _, _ = sqp_step(om, mus[b], xh[b], lam[b], SQPOptions(max_backtracks=20))
         print("tinyhuge step", b, "x err %.2e lam err %.2e" % (relerr(x1[b], xr), relerr(l1[b], lr)), flush=True)
         assert int(st[b]) == (1 if sr == -1 else sr)
-        # Gauss-Newton blocks of this briefly trained model have condition numbers near 1e5
-        assert relerr(x1[b], xr) <= 1e-9
-        assert relerr(l1[b], lr) <= 1e-7
+        assert relerr(x1[b], xr) <= 1e-10
+        assert relerr(l1[b], lr) <= 1e-10
         assert abs(fn[b] - fr) <= 1e-10 * max(1.0, fr)
 
 
