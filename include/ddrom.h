@@ -60,7 +60,7 @@ extern "C" {
  * r*s + (k-1)*b*s + t of the dense N x w matrix; slots whose column falls outside [0, w)
  * are ignored.  w must equal N*s.
  * dense != 0: W2 is the full N x w matrix ([N][w], every hidden unit feeds every state; b and s
- * are ignored; w <= 48).  With the identity activation, W1 = I_n and b1 = 0 this is the affine
+ * are ignored; w <= 56).  With the identity activation, W1 = I_n and b1 = 0 this is the affine
  * map x_ref + Phi xhat of the LS-ROM (Section 3.3) with Phi = W2. */
 typedef struct {
     int N, n, w, b, s;

@@ -26,7 +26,7 @@ from concurrent.futures import ProcessPoolExecutor
 import numpy as np
 
 import seeded_inputs as si
-from .autoencoder import ACT_IDENTITY, ACT_SIGMOID, MaskedAE, export_decoder, train
+from .autoencoder import ACT_IDENTITY, ACT_SIGMOID, ACT_SWISH, MaskedAE, export_decoder, train
 from .burgers import BurgersFOM, Grid, solve_fom
 from .ddmaps import build_dd
 from .hyperreduction import greedy_sample, pod_basis
@@ -52,6 +52,11 @@ CONFIGS = {
     # the 240x240, 4x4, latent (8,4) shape (16 subdomains, 360 HR nodes each, 32 constraints) at
     # a small training budget (2 x 2 parameter grid, 20 epochs): parity cases at the benchmark's
     # sizes when its trained pack is not at hand
+    # GPU autoencoder training at 480x480, 4x4: 1024 FOM snapshots on a 32 x 32 parameter grid,
+    # hidden width 2x, band 9, minibatch 64, 2000 epochs (the snapshot matrix alone is written
+    # here, by --snapshots; the autoencoders are trained from it)
+    "cfg3": dict(nx=480, ny=480, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID,
+                 epochs=2000, batch=64, train_grid=(32, 32), hr_frac=0.10, seed=3),
     "cfg1shape": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID,
                       epochs=20, batch=4, train_grid=(2, 2), hr_frac=0.10, seed=1),
     # strong ROM-port constraint (SRPC): port autoencoders with sigmoid activation and three-band
@@ -85,7 +90,19 @@ CONFIGS = {
                    epochs=0, batch=32, train_grid=(16, 16), hr_frac=0.10, seed=1),
     "tinyls": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID, ls=True,
                    epochs=0, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
+    # the paper's own workload (Sections 7.1-7.4): 480 x 24 grid on [-1, 1] x [0, 0.05], 2 x 2
+    # split, latents (8, 4), Swish, three-band masks of 5 entries shifted by 5, 6400 snapshots on
+    # an 80 x 80 parameter grid (10% held out), 2000 epochs at minibatch 32, residual POD from
+    # the Newton histories of the 400 solves of a 20 x 20 grid, 100 HR nodes per subdomain.  Built
+    # by --skeleton: the autoencoders are trained on the GPU from the written snapshot matrix.
+    "paper": dict(nx=480, ny=24, nsx=2, nsy=2, n_om=8, n_ga=4, b=5, s=5, act=ACT_SWISH,
+                  epochs=2000, batch=32, train_grid=(80, 80), res_grid=(20, 20), hr_count=100, hr_frac=None,
+                  seed=41),
     # small configurations for tests
+    # the paper's architecture on a small elongated grid: Swish, three-band masks of 5 entries
+    # shifted by 5 (a row's bands span 55 hidden units), latents (8, 4)
+    "tinywide": dict(nx=40, ny=8, nsx=2, nsy=2, n_om=8, n_ga=4, b=5, s=5, act=ACT_SWISH,
+                     epochs=100, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=12),
     "tinymix": dict(nx=16, ny=12, nsx=2, nsy=2, n_om="draw", n_ga="half", b=3, s=2, act=ACT_SIGMOID,
                     epochs=300, batch=4, train_grid=(4, 4), hr_frac=(0.3, 0.6), seed=31),
     "tinybig": dict(nx=48, ny=48, nsx=8, nsy=8, n_om=6, n_ga=3, b=3, s=2, act=ACT_SIGMOID,
@@ -118,6 +135,53 @@ def snapshots(nx, ny, mus, workers=1):
     return X, np.stack(R)
 
 
+def _state_job(args):
+    k, nx, ny, mu = args
+    res = solve_fom(BurgersFOM(Grid(nx, ny)), mu)
+    return k, res.x, res.converged
+
+
+def snapshot_matrix(name: str, out: str, workers: int = 8, verbose=True):
+    """The configuration's FOM snapshots [n_snap][N_x] (FP64, a-fastest parameter grid) written
+    row by row into an .npy file as the solves finish; the subdomains' interior and interface
+    index lists go beside it (<out stem>_dd.npz).  A partly written file is resumed: rows whose
+    first entry is still NaN are solved."""
+    cfg = CONFIGS[name]
+    g = Grid(cfg["nx"], cfg["ny"])
+    dd = build_dd(g, cfg["nsx"], cfg["nsy"])
+    mus = si.training_grid(*cfg["train_grid"])
+    n_x = 2 * g.nx * g.ny
+    if os.path.exists(out):
+        X = np.load(out, mmap_mode="r+")
+        if X.shape != (len(mus), n_x):
+            raise RuntimeError(f"{out}: shape {X.shape}, expected {(len(mus), n_x)}")
+    else:
+        os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
+        X = np.lib.format.open_memmap(out, mode="w+", dtype=np.float64, shape=(len(mus), n_x))
+        X[:, 0] = np.nan
+        X.flush()
+    stem = os.path.splitext(out)[0]
+    idx = {"mus": mus}
+    for i, sd in enumerate(dd.subdomains):
+        idx[f"om{i}"] = np.asarray(sd.omega, dtype=np.int64)
+        idx[f"ga{i}"] = np.asarray(sd.gamma, dtype=np.int64)
+    np.savez(stem + "_dd.npz", **idx)
+    todo = [k for k in range(len(mus)) if np.isnan(X[k, 0])]
+    t0 = time.time()
+    jobs = [(k, g.nx, g.ny, tuple(mus[k])) for k in todo]
+    with ProcessPoolExecutor(workers) as ex:
+        for done, (k, x, ok) in enumerate(ex.map(_state_job, jobs, chunksize=1), 1):
+            if not ok:
+                raise RuntimeError(f"FOM Newton failed at parameter {mus[k]}")
+            X[k] = x
+            if done % 16 == 0 or done == len(jobs):
+                X.flush()
+                if verbose:
+                    print(f"[{name}] {done}/{len(jobs)} snapshots, {time.time() - t0:.0f}s", flush=True)
+    X.flush()
+    return out
+
+
 def _train_job(args):
     X, N, n, b, s, activation, seed, epochs, batch, tag = args
     t0 = time.time()
@@ -144,15 +208,34 @@ def per_subdomain_choices(cfg: dict, n_sub: int):
     return n_om, n_ga, hr
 
 
-def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
+def state_snapshots(nx, ny, mus, workers=1):
+    jobs = [(k, nx, ny, tuple(m)) for k, m in enumerate(mus)]
+    if workers > 1:
+        with ProcessPoolExecutor(workers) as ex:
+            out = list(ex.map(_state_job, jobs, chunksize=4))
+    else:
+        out = [_state_job(j) for j in jobs]
+    if not all(o[2] for o in out):
+        raise RuntimeError("FOM Newton failed for some training parameter")
+    return np.stack([o[1] for o in out])
+
+
+def build(name: str, workers: int = 8, verbose=True, base: dict | None = None, train: bool = True):
     """Model pack of a configuration.  `base` (a weak-constraint pack of the same grid and
-    split) supplies the interior decoders and HR nodes of a ports configuration."""
+    split) supplies the interior decoders and HR nodes of a ports configuration.  With
+    train=False no autoencoder is trained: the pack lacks the decoders and carries the
+    training recipe instead (a skeleton for training elsewhere)."""
     cfg = CONFIGS[name]
     g = Grid(cfg["nx"], cfg["ny"])
     dd = build_dd(g, cfg["nsx"], cfg["nsy"])
     mus = si.training_grid(*cfg["train_grid"])
     t0 = time.time()
-    X, Rsnap = snapshots(g.nx, g.ny, mus, workers)
+    if "res_grid" in cfg:
+        # residual snapshots from the Newton histories of a coarser parameter grid's solves
+        _, Rsnap = snapshots(g.nx, g.ny, si.training_grid(*cfg["res_grid"]), workers)
+        X = state_snapshots(g.nx, g.ny, mus, workers)
+    else:
+        X, Rsnap = snapshots(g.nx, g.ny, mus, workers)
     if verbose:
         print(f"[{name}] {len(mus)} FOM snapshots, {len(Rsnap)} residual snapshots in {time.time() - t0:.1f}s", flush=True)
 
@@ -164,7 +247,7 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
     ls = bool(cfg.get("ls", False))
     jobs = []
     for i, sd in enumerate(dd.subdomains):
-        if ls:
+        if ls or not train:
             continue
         if base is None:
             jobs.append((X[:, sd.omega], len(sd.omega), n_om[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i],
@@ -173,6 +256,8 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
             jobs.append((X[:, sd.gamma], len(sd.gamma), n_ga[i], cfg["b"], cfg["s"], cfg["act"], seeds[2 * i + 1],
                          cfg["epochs"], cfg["batch"], ("ga", i)))
     n_port = []
+    if pc is not None and not train:
+        raise ValueError("a skeleton of a ports configuration is not supported")
     if pc is not None:
         pseeds = si.spawn_seeds(cfg["seed"] + 5000, len(dd.ports))
         for j, (car, dofs) in enumerate(dd.ports):
@@ -202,7 +287,7 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
         Ri = Rsnap[:, sd.res_rows].T                      # N_i^r x n_snap
         Phi = pod_basis(Ri, 1e-10)
         n_own = len(sd.own_nodes)
-        k = int(round(hr_frac[i] * n_own))
+        k = int(cfg["hr_count"]) if cfg.get("hr_count") else int(round(hr_frac[i] * n_own))
         loc = greedy_sample(Phi, n_own, k)
         hr_nodes.append(sd.own_nodes[loc])
     if pc is not None:
@@ -222,9 +307,14 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None):
         pack[f"{prefix}_xref"] = d.x_ref
         pack[f"{prefix}_bs"] = np.array([d.b, d.s])
 
+    if not train:
+        # the recipe of the autoencoders still to be trained (Section 7.3), per subdomain
+        pack.update(train_n_om=np.asarray(n_om, dtype=np.int64), train_n_ga=np.asarray(n_ga, dtype=np.int64),
+                    train_bs=np.array([cfg["b"], cfg["s"]], dtype=np.int64), train_epochs=np.int64(cfg["epochs"]),
+                    train_batch=np.int64(cfg["batch"]), train_seed=np.int64(cfg["seed"]))
     for i in range(dd.n_sub):
         pack[f"hr{i}"] = hr_nodes[i]
-        if ls:
+        if ls or not train:
             continue
         if base is not None:
             for key in ("W1", "b1", "W2", "xref", "bs"):
@@ -260,7 +350,28 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--base", default=None, help="weak-constraint pack whose interior decoders and HR nodes "
                                                  "a ports configuration reuses")
+    ap.add_argument("--snapshots", default=None, help="write only the FOM snapshot matrix (.npy) and the "
+                                                      "subdomain index lists")
+    ap.add_argument("--skeleton", default=None, help="path stem: write <stem>_skel.npz (the pack without decoders, "
+                                                     "with the training recipe), <stem>_X.npy (the state snapshots, "
+                                                     "FP64) and <stem>_X_dd.npz (parameters, subdomain index lists)")
     a = ap.parse_args(argv)
+    if a.snapshots:
+        snapshot_matrix(a.config, a.snapshots, a.workers)
+        return 0
+    if a.skeleton:
+        pack, X, mus, _ = build(a.config, a.workers, train=False)
+        os.makedirs(os.path.dirname(a.skeleton) or ".", exist_ok=True)
+        np.savez(a.skeleton + "_skel.npz", **pack)
+        np.save(a.skeleton + "_X.npy", X)
+        dd = build_dd(Grid(int(pack["nx"]), int(pack["ny"])), int(pack["nsx"]), int(pack["nsy"]))
+        idx = {"mus": mus}
+        for i, sd in enumerate(dd.subdomains):
+            idx[f"om{i}"] = np.asarray(sd.omega, dtype=np.int64)
+            idx[f"ga{i}"] = np.asarray(sd.gamma, dtype=np.int64)
+        np.savez(a.skeleton + "_X_dd.npz", **idx)
+        print("wrote", a.skeleton + "_skel.npz", a.skeleton + "_X.npy")
+        return 0
     base = dict(np.load(a.base, allow_pickle=False)) if a.base else None
     pack, X, mus, _ = build(a.config, a.workers, base=base)
     out = a.out or os.path.join("models", f"{a.config}.npz")

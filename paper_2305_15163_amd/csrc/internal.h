@@ -42,14 +42,18 @@ struct DecSeg {
 // band descriptors [rows][3] (int2), then one hidden-activation ring per wave.
 // Hidden-unit ring of the decode kernel: every decoded row's three bands must lie in a window
 // of at most DEC_RING consecutive (compressed) hidden units (2 b s + b <= DEC_RING for the
-// three-band masks).
-constexpr int DEC_RING = 48;
+// three-band masks).  A model whose windows all fit in DEC_RING units uses that ring; one with
+// wider windows (up to DEC_RING_WIDE, e.g. the band-5, shift-5 masks, window 55) uses the wide
+// ring and stages fewer weights per work item.  At 46, four waves' FP32 rings take 46 KiB, so
+// with a work item's staged weights three workgroups fit in a CU.
+constexpr int DEC_RING = 46;
+constexpr int DEC_RING_WIDE = 56;
 
 struct DecLds {
     size_t w1, b1, w2, xr, bd, ring, total;
 };
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
-__host__ __device__ inline DecLds dec_lds(int span, int rows, int nl, int bmax, int esz, int waves, int rk) {
+__host__ __device__ inline DecLds dec_lds(int span, int rows, int nl, int bmax, int esz, int waves, int rk, int ring) {
     DecLds L;
     L.w1 = 0;
     L.b1 = al16(L.w1 + (size_t)span * nl * esz);
@@ -57,7 +61,7 @@ __host__ __device__ inline DecLds dec_lds(int span, int rows, int nl, int bmax, 
     L.xr = al16(L.w2 + (size_t)rows * 3 * bmax * esz);
     L.bd = al16(L.xr + (size_t)rows * esz);
     L.ring = al16(L.bd + (size_t)rows * 3 * 8);
-    L.total = L.ring + (size_t)waves * DEC_RING * 64 * esz * rk;
+    L.total = L.ring + (size_t)waves * ring * 64 * esz * rk;
     return L;
 }
 
@@ -151,6 +155,7 @@ struct ddrom_model {
     int* fom_sd_of_row_d = nullptr;              // owner subdomain of each flattened own-node slot
     int* state_dof_d = nullptr;                  // [n_state] global DoF of each row of the DD state
     int tile_dec_rows = 0, tile_res_nodes = 0, tile_con_orows = 0;   // work-item shapes in use
+    int ring = ddrom::DEC_RING;                  // decode kernel's hidden-unit ring (DEC_RING or DEC_RING_WIDE)
 
     // Launch plans: the work items of each kernel family are stored grouped by latent class, so
     // that one launch covers every subdomain of a class.  Decoder families: 0 interior subnets,

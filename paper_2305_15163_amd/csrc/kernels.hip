@@ -122,7 +122,7 @@ __device__ __forceinline__ double sig_fast<double>(double z) { return 1.0 / (1.0
 // TAG only renames the instantiation (0: solver rounds, 1: standalone timing launches) so that
 // profiler summaries separate the two; the code is identical.  VO = 1 evaluates values only
 // (decoded states after a solve): row r goes to Bp-row out + r.
-template <typename T, int NL, int ACT, int WAVES, int TAG, int VO = 0>
+template <typename T, int NL, int ACT, int WAVES, int TAG, int VO = 0, int RING = DEC_RING>
 __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restrict__ chunks, int chunk_base,
                                                        const DecSeg* __restrict__ segs, const T* __restrict__ W1,
                                                        const T* __restrict__ B1, const int2* __restrict__ bands,
@@ -163,13 +163,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     const int b = slot_solve(live, j, nl);
 
     const int nrows = ch.r1 - ch.r0, span = ch.h_hi - ch.h_lo, bmax = sg.bmax;
-    const DecLds L = dec_lds(span, nrows, NL, bmax, (int)sizeof(T), WAVES, RK);
+    const DecLds L = dec_lds(span, nrows, NL, bmax, (int)sizeof(T), WAVES, RK, RING);
     T* sW1 = reinterpret_cast<T*>(smem + L.w1);          // [span][NL]
     T* sB1 = reinterpret_cast<T*>(smem + L.b1);          // [span]
     T* sW2 = reinterpret_cast<T*>(smem + L.w2);          // [nrows][3][bmax]
     T* sXR = reinterpret_cast<T*>(smem + L.xr);          // [nrows]
     int2* sBd = reinterpret_cast<int2*>(smem + L.bd);    // [nrows][3]
-    T* ring = reinterpret_cast<T*>(smem + L.ring) + (size_t)wave * DEC_RING * 64 * RK;
+    T* ring = reinterpret_cast<T*>(smem + L.ring) + (size_t)wave * RING * 64 * RK;
     {
         const T* gW1 = W1 + sg.w1 + (size_t)ch.h_lo * NL;
         for (int i = tid; i < span * NL; i += 64 * WAVES) sW1[i] = gW1[i];
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
     // output rows are numbered from the segment's first row in the model's decoder-output
     // layout, less oshift (nonzero when the output buffer holds this segment alone)
     T* o = out + ((size_t)(sg.out - oshift) + (size_t)ch.r0 * (VO ? 1 : 1 + NL)) * Bp + j;
-    // Units [vlo, vhi) (relative to h_lo) are valid in the ring; vhi - vlo <= DEC_RING.  Rows
+    // Units [vlo, vhi) (relative to h_lo) are valid in the ring; vhi - vlo <= RING.  Rows
     // ascend, so windows mostly slide right, but near the first rows of a decoder a clipped
     // band can start below the previous row's window: missing units are then computed on
     // whichever side they lie.
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
         T z = sB1[h];
 #pragma unroll
         for (int k = 0; k < NL; ++k) z += w[k] * xl[k];
-        T* rs = ring + (size_t)(h % DEC_RING) * 64 * RK + lane;
+        T* rs = ring + (size_t)(h % RING) * 64 * RK + lane;
         if (ACT == DDROM_ACT_SIGMOID) {
             rs[0] = sig_fast<T>(z);
         } else if (ACT == DDROM_ACT_SWISH) {
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
         vlo = min(vlo, lo);
         for (int h = vhi; h < hi; ++h) hidden(h);
         vhi = max(vhi, hi);
-        vlo = max(vlo, vhi - DEC_RING);
+        vlo = max(vlo, vhi - RING);
         T acc = sXR[r];
         T J[NL];
 #pragma unroll
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
         for (int kb = 0; kb < 3; ++kb) {
             const int2 q = kb == 0 ? q0 : (kb == 1 ? q1 : q2);
             const T* w2r = sW2 + ((size_t)r * 3 + kb) * bmax;
-            int slot = q.x % DEC_RING;
+            int slot = q.x % RING;
             for (int t = 0; t < q.y; ++t) {
                 const T wv = w2r[t];
                 const T* rs = ring + (size_t)slot * 64 * RK + lane;
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_decode(const DecChunk* __restric
 #pragma unroll
                     for (int k = 0; k < NL; ++k) J[k] += c * w[k];
                 }
-                slot = slot + 1 == DEC_RING ? 0 : slot + 1;
+                slot = slot + 1 == RING ? 0 : slot + 1;
             }
         }
         if (j < Bp) {   // waves past the padded batch (small B) compute but never store
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rch
     const int nl = live_count(n_live, B);
     const int j0 = blockIdx.y * 64;
     if (j0 >= nl) return;
-    const ResChunk rc = rchunks[rbase + blockIdx.x];
+    const ResChunk rc = rchunks[rbase + xcd_item()];
     const ResSeg rs = rsegs[rc.sd];
     const long long oo = segs[rs.seg_om].out, og = segs[rs.seg_ga].out;
     // the wave index is uniform: node codes come in by scalar loads and the source-kind
@@ -1858,7 +1858,7 @@ static int launch_decode_items(const ddrom_model* m, int prec, int act, int c0, 
     const int waves = prec == DDROM_PREC_FP64 ? 1 : (act == DDROM_ACT_SWISH ? 2 : 4);
     const int esz = prec == DDROM_PREC_FP64 ? 8 : 4;
     DecLds L;
-    L.total = (size_t)stage + (size_t)waves * DEC_RING * 64 * esz * rk;
+    L.total = (size_t)stage + (size_t)waves * m->ring * 64 * esz * rk;
     if (L.total > 65536) {
         set_error("decode work item exceeds 64 KiB of LDS");
         return DDROM_EINVAL;
@@ -1866,8 +1866,16 @@ static int launch_decode_items(const ddrom_model* m, int prec, int act, int c0, 
     dim3 grid(c1 - c0, (Bp + 64 * waves - 1) / (64 * waves)), block(64 * waves);
     const unsigned lds = (unsigned)L.total;
 #define DEC_LAUNCH(T, NLV, ACTV, WV, W1p, B1p, W2p, XRp)                                                          \
-    hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG, VO>), grid, block, lds, s, m->chunks_d, c0, m->segs_d, W1p, \
-                       B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, live, n_live, B, (T*)out, Bp, oshift)
+    do {                                                                                                          \
+        if (m->ring == DEC_RING)                                                                                  \
+            hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG, VO, DEC_RING>), grid, block, lds, s, m->chunks_d,  \
+                               c0, m->segs_d, W1p, B1p, m->bands, W2p, XRp, xhat, xstride, xoff_override, live,    \
+                               n_live, B, (T*)out, Bp, oshift);                                                   \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_decode<T, NLV, ACTV, WV, TAG, VO, DEC_RING_WIDE>), grid, block, lds, s,          \
+                               m->chunks_d, c0, m->segs_d, W1p, B1p, m->bands, W2p, XRp, xhat, xstride,           \
+                               xoff_override, live, n_live, B, (T*)out, Bp, oshift);                              \
+    } while (0)
 #define DEC_ACT(NLV, ACTV)                                                                                        \
     if (prec == DDROM_PREC_FP64) DEC_LAUNCH(double, NLV, ACTV, 1, m->W1d, m->b1d, m->W2d, m->xrefd);            \
     else if (ACTV == DDROM_ACT_SWISH) DEC_LAUNCH(float, NLV, ACTV, 2, m->W1f, m->b1f, m->W2f, m->xreff);         \

@@ -11,9 +11,9 @@
 
 namespace ddrom {
 
-static constexpr int RING = DEC_RING;    // hidden-unit ring of the decode kernel (window bound)
+static constexpr int RING = DEC_RING_WIDE;    // widest hidden-unit window the decode kernel takes
 static constexpr int DEC_ROWS = 48;      // default max output rows per decode work item
-static constexpr int DEC_STAGE = 15360;  // bytes of FP32 weights staged in LDS per decode work item
+static constexpr int DEC_STAGE = 15360;  // max bytes of FP32 weights staged in LDS per decode work item
 static constexpr int RES_NODES = 24;     // default sampled nodes per residual work item
 static constexpr int CON_ROWS = 8;       // constraint rows per constraint work item
 static constexpr int CON_OROWS = 256;    // default interface rows per constraint work item
@@ -36,6 +36,7 @@ struct HostDecoder {
     std::vector<double> W1, b1, W2, xref;   // packed subnet
     std::vector<int2> band;
     int rows = 0, hid = 0;
+    int win = 0;        // widest hidden-unit window of a row
 };
 
 // Subnet of eq. subnet for the output rows `rows` (ascending) of one decoder.
@@ -43,8 +44,9 @@ struct HostDecoder {
 // hidden units, values in band slot 0 ([rows][3][w]).
 static int make_dense_rows(const ddrom_decoder_desc& d, const std::vector<int>& rows, HostDecoder& out) {
     const int N = d.N, n = d.n, w = d.w;
+    out.win = w;
     if (w > RING) {
-        set_error("dense decoder wider than the kernel's hidden-unit ring (w must be <= 48)");
+        set_error("dense decoder wider than the kernel's hidden-unit ring (w must be <= 56)");
         return DDROM_EINVAL;
     }
     out.rows = (int)rows.size();
@@ -127,8 +129,9 @@ static int make_subnet(const ddrom_decoder_desc& d, const std::vector<int>& rows
             lo = std::min(lo, cs);
             hi = std::max(hi, cs + len);
         }
+        if (hi >= 0) out.win = std::max(out.win, hi - lo);
         if (hi >= 0 && hi - lo > RING) {
-            set_error("decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 48)");
+            set_error("decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 56)");
             return DDROM_EINVAL;
         }
     }
@@ -194,8 +197,9 @@ static int make_port_interface(const ddrom_decoder_desc* pd, const std::vector<i
             lo = std::min(lo, hoff[a] + c0);
             hi = std::max(hi, hoff[a] + c0 + len);
         }
+        if (hi >= 0) out.win = std::max(out.win, hi - lo);
         if (hi >= 0 && hi - lo > RING) {
-            set_error("port decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 48)");
+            set_error("port decoder mask window wider than the kernel's hidden-unit ring (2*b*s + b must be <= 56)");
             return DDROM_EINVAL;
         }
     }
@@ -348,7 +352,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             if (e == &gport) continue;
             const bool shape_ok = e->dense ? (e->w > 0 && e->w <= RING) : (e->b > 0 && e->s > 0 && e->w == e->N * e->s);
             if (e->N > 0 && (e->n <= 0 || !shape_ok || !e->W1 || !e->b1 || !e->W2 || !e->x_ref)) {
-                set_error("decoder descriptor: need n > 0, b, s > 0 and w = N*s (or dense with 0 < w <= 48) and all "
+                set_error("decoder descriptor: need n > 0, b, s > 0 and w = N*s (or dense with 0 < w <= 56) and all "
                           "weight pointers");
                 return DDROM_EINVAL;
             }
@@ -521,6 +525,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
     //      Jacobian rows), then full interior and interface decoders (values only, for the
     //      decoded subdomain states after a solve) ----
     std::vector<double> W1, b1, W2, xref;
+    int maxwin = 0;
     std::vector<int2> bands;
     m->segs_h.assign(4 * n_sub, DecSeg{});
     m->band_nnz.assign(4 * n_sub, 0);
@@ -555,6 +560,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
                                                   port_pos, port_nodes, port_bmax, hd)
                             : make_subnet(dd, rows, hd);
             if (rc) return rc;
+            maxwin = std::max(maxwin, hd.win);
             sg.rows = hd.rows;
             sg.hid = hd.hid;
             sg.w1 = (long long)W1.size(); W1.insert(W1.end(), hd.W1.begin(), hd.W1.end());
@@ -576,9 +582,16 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             if (part == 0) m->hid_om[sd] = hd.hid;
         }
     m->dec_rows = std::max<long long>(1, out_rows);
+    m->ring = maxwin <= DEC_RING ? DEC_RING : DEC_RING_WIDE;
+    // One work-item plan serves both precisions: the FP32 item (four waves, or two with the
+    // Swish pair of rings) and the FP64 item (one wave, weights twice as wide) must both fit in
+    // 64 KiB beside their rings.
+    const int rk_max = (m->act == DDROM_ACT_SWISH || m->act_ga == DDROM_ACT_SWISH) ? 2 : 1;
+    const int stage_budget = std::min({DEC_STAGE, 65536 - 128 - m->ring * 1024,
+                                       (65536 - 128 - m->ring * 512 * rk_max) / 2});
     // Decode work items: runs of consecutive kept rows whose staged weights (W1~ rows and
     // biases of the hidden units they read, their W2~ values, x_ref, band descriptors) fit
-    // in DEC_STAGE bytes of FP32.
+    // in stage_budget bytes of FP32.
     m->seg_chunk0.assign(4 * n_sub, 0);
     m->seg_chunk1.assign(4 * n_sub, 0);
     m->seg_stage_f32.assign(4 * n_sub, 0);
@@ -603,7 +616,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         while (r < sg.rows) {
             // The span is the union of the rows' windows (near the first rows a clipped band -1
             // can start below the first row's lowest band).  The kernel's ring holds the units
-            // [vlo, vhi) with vhi - vlo <= RING; a row that would need a wider valid range starts
+            // [vlo, vhi) with vhi - vlo <= m->ring; a row that would need a wider valid range starts
             // a new work item.
             int lo = row_lo(r), hi = row_hi(r), e = r + 1;
             int vlo = lo, vhi = hi;
@@ -613,12 +626,12 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
                 if (rl >= nvhi || rh <= nvlo) nvlo = nvhi = rl;
                 nvlo = std::min(nvlo, rl);
                 nvhi = std::max(nvhi, rh);
-                if (nvhi - rl > RING) break;
-                nvlo = std::max(nvlo, nvhi - RING);
+                if (nvhi - rl > m->ring) break;
+                nvlo = std::max(nvlo, nvhi - m->ring);
                 int nlo = std::min(lo, rl), nhi = std::max(hi, rh);
                 long long bytes = 4LL * ((long long)(nhi - nlo) * (sg.n + 1) + (long long)(e + 1 - r) * (3 * sg.bmax + 1)) +
                                   24LL * (e + 1 - r);
-                if (bytes > DEC_STAGE) break;
+                if (bytes > stage_budget) break;
                 lo = nlo;
                 hi = nhi;
                 vlo = nvlo;
@@ -626,8 +639,8 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
                 ++e;
             }
             m->chunks_h.push_back(DecChunk{sgi, r, e, lo, hi, {0, 0, 0}});
-            m->seg_stage_f32[sgi] = std::max<long long>(m->seg_stage_f32[sgi], (long long)dec_lds(hi - lo, e - r, sg.n, sg.bmax, 4, 0, 1).ring);
-            m->seg_stage_f64[sgi] = std::max<long long>(m->seg_stage_f64[sgi], (long long)dec_lds(hi - lo, e - r, sg.n, sg.bmax, 8, 0, 1).ring);
+            m->seg_stage_f32[sgi] = std::max<long long>(m->seg_stage_f32[sgi], (long long)dec_lds(hi - lo, e - r, sg.n, sg.bmax, 4, 0, 1, m->ring).ring);
+            m->seg_stage_f64[sgi] = std::max<long long>(m->seg_stage_f64[sgi], (long long)dec_lds(hi - lo, e - r, sg.n, sg.bmax, 8, 0, 1, m->ring).ring);
             r = e;
         }
         m->seg_chunk1[sgi] = (int)m->chunks_h.size();

@@ -43,6 +43,15 @@ def tinymix_pack():
 
 
 @pytest.fixture(scope="session")
+def tinywide_pack():
+    """40x8 grid, 2x2 subdomains, Swish, band-5 shift-5 masks (window 55 hidden units: the
+    decoder's wide ring), latents (8, 4)."""
+    from oracle.build_model import build
+    pack, *_ = build("tinywide", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
 def tinybig_pack():
     """48x48 grid, 8x8 subdomains, 96 constraints: the KKT system exceeds one wave's rows."""
     from oracle.build_model import build
