@@ -266,7 +266,8 @@ __global__ __launch_bounds__(256) void k_band_loss(int N, int w, int bw, int sw,
 
 // ---- band-slot gradient:  G[r][k][t] = sum_b P[r][b] Q[r s + k b s + t][b] ----
 // Per 16-row tile, each band's column window is cut in 16-column tiles; a wave forms the dense
-// 16 x 16 product over the minibatch and keeps the band slots.
+// 16 x 16 product over the minibatch and keeps the band slots (all of them: no separate
+// clearing pass).
 __global__ __launch_bounds__(256) void k_band_grad(int N, int w, int bw, int sw, int B, const float* __restrict__ P,
                                                    const float* __restrict__ Q, float* __restrict__ G, int x3) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -311,11 +312,13 @@ __global__ __launch_bounds__(256) void k_band_grad(int N, int w, int bw, int sw,
             }
             acc = mma16(a, b, acc, x3);
         }
+        // the tiles of a band cover every slot of the 16 rows once; slots whose column falls
+        // outside [0, w) summed zero operands and store 0
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = r0 + kq + i;
             const int t = cn - r * sw - off;
-            if (r < N && cn >= 0 && cn < w && t >= 0 && t < bw) G[((size_t)r * 3 + (kb + 1)) * bw + t] = acc[i];
+            if (r < N && t >= 0 && t < bw) G[((size_t)r * 3 + (kb + 1)) * bw + t] = acc[i];
         }
     }
 }
@@ -329,17 +332,15 @@ __global__ void k_ae_gather(const float* __restrict__ X, int N, const int* __res
     Xb[e] = X[(size_t)rows[b] * N + r];
 }
 
-__global__ void k_rowsum(const float* __restrict__ D, int M, int B, float* __restrict__ out) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+// out[m] = sum_b D[m][b]: one wave per row, lanes along the minibatch (coalesced loads), then
+// a butterfly sum (every lane ends with the same value).
+__global__ __launch_bounds__(256) void k_rowsum(const float* __restrict__ D, int M, int B, float* __restrict__ out) {
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (m >= M) return;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += D[(size_t)m * B + b];
-    out[m] = s;
-}
-
-__global__ void k_fill(float* p, long long n, float v) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n) p[e] = v;
+    for (int b = lane; b < B; b += 64) s += D[(size_t)m * B + b];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[m] = s;
 }
 
 __global__ void k_loss_final(const double* __restrict__ part, int n, int B, float* __restrict__ loss) {
@@ -495,8 +496,6 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
                        t->lpart, t->x3);
     if (loss_d) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, s, t->lpart, (int)(lgrid.x * lgrid.y), B, loss_d);
     // gradients
-    hipLaunchKernelGGL(k_fill, dim3(cdiv(t->n_band, 256)), blk, 0, s, G + t->o_w2d, t->n_band, 0.f);
-    hipLaunchKernelGGL(k_fill, dim3(cdiv(t->n_band, 256)), blk, 0, s, G + t->o_w1e, t->n_band, 0.f);
     hipLaunchKernelGGL(k_band_grad, dim3(cdiv(N, 16)), blk, 0, s, N, w, bw, sw, B, t->dY, t->ad, G + t->o_w2d, t->x3);
     // dzd = (D2^T dY) o sigma'(zd)
     hipLaunchKernelGGL(k_band_t<2>, dim3(cdiv(w, 16), cdiv(B, 64)), blk, 0, s, N, w, bw, sw, B, P + t->o_w2d, t->dY,
@@ -505,7 +504,7 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
     hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(n, 32), cdiv(w, 32), 1), blk, 0, s, w, n, B, t->dzd, (long long)B, 1LL,
                        t->xh, 1LL, (long long)B, G + t->o_w1d, n, 1, (const float*)nullptr, (float*)nullptr,
                        (const float*)nullptr, act, t->x3, 0);
-    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 256)), blk, 0, s, t->dzd, w, B, G + t->o_b1d);
+    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 4)), blk, 0, s, t->dzd, w, B, G + t->o_b1d);
     // dxh = W1d^T dzd (K = w, split)
     hipLaunchKernelGGL(k_dense<0>, sgrid, blk, 0, s, n, B, w, P + t->o_w1d, 1LL, (long long)n, t->dzd, (long long)B,
                        1LL, t->kpart, B, t->split, (const float*)nullptr, (float*)nullptr, (const float*)nullptr, act,
@@ -522,7 +521,7 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
                        t->ze, act, t->x3, 0);
     // gW1e[r][k][t] = sum_b x~[r][b] dze[c][b], gb1e = sum_b dze
     hipLaunchKernelGGL(k_band_grad, dim3(cdiv(N, 16)), blk, 0, s, N, w, bw, sw, B, t->Xb, t->dze, G + t->o_w1e, t->x3);
-    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 256)), blk, 0, s, t->dze, w, B, G + t->o_b1e);
+    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 4)), blk, 0, s, t->dze, w, B, G + t->o_b1e);
     if (grad_d) AECHECK(hipMemcpyAsync(grad_d, G, (size_t)t->n_params * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (update) {
         hipLaunchKernelGGL(k_ae_tick, dim3(1), dim3(1), 0, s, t->t);

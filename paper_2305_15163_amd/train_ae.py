@@ -68,13 +68,20 @@ def train_ae(X: np.ndarray, n: int, b: int, s: int, activation: int, seed: int, 
     packed = init if init is not None else glorot_init(N, n, b, s, init_seed)
     tr = dr.AETrainer(N, n, b, s, activation, batch, packed, precision)
 
+    # losses stay on the device until the end of each pass: one synchronisation per epoch
+    def pass_loss(order_h, update, lr_):
+        od = torch.as_tensor(np.asarray(order_h, dtype=np.int32), device="cuda")
+        parts, sizes = [], []
+        for k in range(0, len(order_h), batch):
+            rows = od[k:k + batch]
+            lt, _ = tr.step(Xn, rows, scale, lr=lr_, update=update, loss=True)
+            parts.append(lt)
+            sizes.append(int(rows.shape[0]))
+        w = torch.as_tensor(np.asarray(sizes, dtype=np.float64), device="cuda")
+        return float((torch.cat(parts).double() * w).sum().item()) / max(1, len(order_h))
+
     def eval_loss(idx):
-        tot = 0.0
-        for k in range(0, len(idx), batch):
-            rows = torch.as_tensor(idx[k:k + batch], dtype=torch.int32, device="cuda")
-            lt, _ = tr.step(Xn, rows, scale, update=False, loss=True)
-            tot += float(lt.item()) * len(rows)
-        return tot / max(1, len(idx))
+        return pass_loss(idx, False, 0.0)
 
     best, best_p, since_best, since_plateau, plateau_best = np.inf, None, 0, 0, np.inf
     hist = []
@@ -82,12 +89,7 @@ def train_ae(X: np.ndarray, n: int, b: int, s: int, activation: int, seed: int, 
     cur_lr = lr
     for ep in range(1, epochs + 1):
         order = g.permutation(train_idx)
-        tot = 0.0
-        for k in range(0, len(order), batch):
-            rows = torch.as_tensor(order[k:k + batch], dtype=torch.int32, device="cuda")
-            lt, _ = tr.step(Xn, rows, scale, lr=cur_lr, loss=True)
-            tot += float(lt.item()) * len(rows)
-        tr_loss = tot / len(order)
+        tr_loss = pass_loss(order, True, cur_lr)
         te_loss = eval_loss(test_idx) if n_test else tr_loss
         hist.append((tr_loss, te_loss))
         if te_loss < plateau_best:
@@ -100,11 +102,11 @@ def train_ae(X: np.ndarray, n: int, b: int, s: int, activation: int, seed: int, 
                 plateau_best = te_loss
         if te_loss < best:
             best, since_best = te_loss, 0
-            best_p = tr.params().cpu().numpy()
+            best_p = tr.params()          # a device copy
         else:
             since_best += 1
             if since_best > stop_patience:
                 break
         if verbose and ep % 50 == 0:
             print(f"  epoch {ep}: train {tr_loss:.3e} test {te_loss:.3e} lr {cur_lr:.1e}", flush=True)
-    return AEResult(best_p if best_p is not None else tr.params().cpu().numpy(), mid, sc, ep, best, hist)
+    return AEResult((best_p if best_p is not None else tr.params()).cpu().numpy(), mid, sc, ep, best, hist)

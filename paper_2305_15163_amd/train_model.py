@@ -1,0 +1,171 @@
+"""Train every subdomain autoencoder of a model on the GPU and write the model pack.
+
+Input: a skeleton pack (grid, split, hyper-reduction nodes, C and the training recipe, without
+decoders) and the FOM state snapshot matrix [n_snap][N_x] with the subdomains' interior and
+interface index lists, as written by the offline pipeline's skeleton mode.  For each subdomain
+the interior and the interface autoencoder are trained by `train_ae.train_ae` (Section 7.3:
+per-component normalisation, 10% held out, Adam with plateau decay and early stopping, BF16
+matrix-core products with FP32 masters), in several processes that share the GPU.  Each
+trained decoder is exported as the online solve reads it (eq. autoencoder_architecture b/d):
+the de-normalisation folded into W2 and x_ref, and the latent origin moved to the mean encoded
+training snapshot (b1 <- b1 + W1 m, which leaves the trial manifold unchanged).
+
+Usage:  python -m paper_2305_15163_amd.train_model <stem> --out models/<name>.npz [--procs 8]
+        (<stem>_skel.npz, <stem>_X.npy, <stem>_X_dd.npz)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+ACT_SIGMOID, ACT_SWISH, ACT_IDENTITY = 0, 1, 2
+
+
+def _act(z: np.ndarray, act: int) -> np.ndarray:
+    if act == ACT_IDENTITY:
+        return z
+    sg = 1.0 / (1.0 + np.exp(-z))
+    return sg if act == ACT_SIGMOID else z * sg
+
+
+def unpack_weights(packed, N: int, n: int, b: int, s: int) -> dict:
+    """The trainer's packed FP32 parameters as dense-index weights: the encoder's masked layer
+    as (column c, row r, value) triplets, the two dense layers and biases, the decoder's band
+    slots [N][3][b] (zero where a slot's column lies outside [0, w))."""
+    from paper_2305_15163_amd import ddrom as dr
+    w1e, b1e, W2e, W1d, b1d, w2d = dr.ae_unpack(packed, N, n, b, s)
+    cols, valid = dr.band_slots(N, b, s)
+    flat_valid = np.flatnonzero(valid.ravel())
+    rows = np.broadcast_to(np.arange(N)[:, None, None], cols.shape).ravel()[flat_valid]
+    c = cols.ravel()[flat_valid]
+    order = np.lexsort((rows, c))          # the encoder's entries are listed by (c, r)
+    vals = np.zeros(cols.shape)
+    vals[valid] = w2d
+    return dict(enc_c=c[order], enc_r=rows[order], enc_v=w1e, b1e=b1e, W2e=W2e, W1d=W1d, b1d=b1d, W2d=vals)
+
+
+def encode(wts: dict, Xn: np.ndarray, w: int, act: int) -> np.ndarray:
+    """Latents of normalised snapshots Xn [m][N] (FP64 on the host)."""
+    import scipy.sparse as sp
+    E1 = sp.csr_matrix((wts["enc_v"], (wts["enc_c"], wts["enc_r"])), shape=(w, Xn.shape[1]))
+    return _act((E1 @ Xn.T).T + wts["b1e"], act) @ wts["W2e"].T
+
+
+def decode_full(wts: dict, xh: np.ndarray, N: int, b: int, s: int, act: int) -> np.ndarray:
+    """Normalised reconstructions [m][N] of latents xh [m][n]."""
+    a = _act(xh @ wts["W1d"].T + wts["b1d"], act)              # [m][w]
+    out = np.zeros((xh.shape[0], N))
+    w = a.shape[1]
+    for k in range(3):
+        for t in range(b):
+            c = np.arange(N) * s + (k - 1) * b * s + t
+            ok = (c >= 0) & (c < w)
+            out[:, ok] += a[:, c[ok]] * wts["W2d"][ok, k, t]
+    return out
+
+
+def export_decoder(wts: dict, mid: np.ndarray, sc: np.ndarray, center: np.ndarray, b: int, s: int) -> dict:
+    return dict(W1=wts["W1d"].copy(), b1=wts["b1d"] + wts["W1d"] @ center, W2=wts["W2d"] * sc[:, None, None],
+                xref=mid.copy(), bs=np.array([b, s]))
+
+
+def _job(args):
+    """One autoencoder, in its own process: train on the GPU, export, and measure the relative
+    reconstruction error on the held-out snapshots (host FP64 evaluation of the trained
+    weights)."""
+    stem, tag, i, n, b, s, act, seed, epochs, batch, precision = args
+    import torch  # noqa: F401  (initialises the device in this process)
+    from paper_2305_15163_amd.train_ae import train_ae
+    import seeded_inputs as si
+    idx = np.load(stem + "_X_dd.npz")[f"{tag}{i}"]
+    Xall = np.load(stem + "_X.npy", mmap_mode="r")
+    X = np.ascontiguousarray(Xall[:, idx])
+    t0 = time.time()
+    res = train_ae(X, n, b, s, act, seed, epochs, batch=batch, precision=precision)
+    dt = time.time() - t0
+    N = X.shape[1]
+    wts = unpack_weights(res.packed, N, n, b, s)
+    g = si.rng(seed)                      # the held-out split train_ae drew
+    perm = g.permutation(X.shape[0])
+    n_test = max(1, int(round(0.1 * X.shape[0]))) if X.shape[0] > 1 else 0
+    test_idx, train_idx = perm[:n_test], perm[n_test:]
+    Xn_tr = (X[train_idx] - res.mid) / res.scale
+    center = encode(wts, Xn_tr, N * s, act).mean(axis=0)
+    dec = export_decoder(wts, res.mid, res.scale, center, b, s)
+    Xt = X[test_idx] if n_test else X[train_idx]
+    rec = decode_full(wts, encode(wts, (Xt - res.mid) / res.scale, N * s, act), N, b, s, act) * res.scale + res.mid
+    rel = np.linalg.norm(rec - Xt, axis=1) / np.maximum(1e-300, np.linalg.norm(Xt, axis=1))
+    rep = dict(ae=f"{tag}{i}", N=N, latent=n, epochs=res.epochs, best_test_loss=res.best_test, seconds=dt,
+               steps=res.epochs * -(-len(train_idx) // batch), rel_rec_err_mean=float(rel.mean()),
+               rel_rec_err_max=float(rel.max()))
+    return tag, i, dec, rep
+
+
+def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision: int = 0, verbose: bool = True):
+    skel = dict(np.load(stem + "_skel.npz", allow_pickle=False))
+    n_sub = int(skel["n_sub"])
+    b, s = (int(v) for v in skel["train_bs"])
+    act = int(skel["act"])
+    ep = int(skel["train_epochs"]) if epochs is None else int(epochs)
+    batch = int(skel["train_batch"])
+    import seeded_inputs as si
+    seeds = si.spawn_seeds(int(skel["train_seed"]), 2 * n_sub)
+    jobs = []
+    idx = np.load(stem + "_X_dd.npz")
+    for i in range(n_sub):
+        jobs.append((stem, "om", i, int(skel["train_n_om"][i]), b, s, act, seeds[2 * i], ep, batch, precision))
+        jobs.append((stem, "ga", i, int(skel["train_n_ga"][i]), b, s, act, seeds[2 * i + 1], ep, batch, precision))
+    jobs.sort(key=lambda j: -len(idx[f"{j[1]}{j[2]}"]))     # largest first
+    t0 = time.time()
+    if procs > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(min(procs, len(jobs))) as pool:
+            out = []
+            for r in pool.imap_unordered(_job, jobs):
+                out.append(r)
+                if verbose:
+                    print("[train_model]", json.dumps(r[3]), flush=True)
+    else:
+        out = []
+        for j in jobs:
+            out.append(_job(j))
+            if verbose:
+                print("[train_model]", json.dumps(out[-1][3]), flush=True)
+    pack = {k: v for k, v in skel.items() if not k.startswith("train_")}
+    reports = []
+    for tag, i, dec, rep in out:
+        for key, v in dec.items():
+            pack[f"{tag}{i}_{key}"] = v
+        reports.append(rep)
+    reports.sort(key=lambda r: r["ae"])
+    return pack, reports, time.time() - t0
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("stem")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--procs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=None, help="override the recipe's epoch count")
+    ap.add_argument("--precision", type=int, default=0, help="0: BF16 operands, 1: split-BF16")
+    a = ap.parse_args(argv)
+    pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision)
+    os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
+    np.savez(a.out, **pack)
+    with open(os.path.splitext(a.out)[0] + "_train.json", "w") as f:
+        json.dump(dict(seconds=dt, autoencoders=reports), f, indent=1)
+    print(f"[train_model] wrote {a.out} ({dt:.0f}s)", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

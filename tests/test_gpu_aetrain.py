@@ -70,6 +70,40 @@ def test_ae_loss_and_gradient_parity(dr, N, n, b, s, act, B):
         assert e < 3e-2, nm
 
 
+@pytest.mark.parametrize("N,n,b,s,act,B", [(150, 4, 3, 2, ACT_SIGMOID, 24), (97, 8, 9, 2, ACT_SWISH, 33),
+                                           (1912, 4, 9, 2, ACT_SIGMOID, 64), (28322, 8, 9, 2, ACT_SIGMOID, 64)])
+def test_ae_gradient_elementwise_split_bf16(dr, N, n, b, s, act, B):
+    """Split-BF16 mode (each operand as a BF16 head and tail, three matrix-core products:
+    about 16 significant bits, FP32 accumulation), every gradient entry against the FP64
+    oracle from identical FP32 weights.  The 28322-row case is the largest 120 x 120 subdomain
+    of the 480 x 480, 4 x 4 split (the skinny products over w = 56644 then run in 256 split-K
+    parts).  Bound per entry: 5e-5 of the tensor's largest entry, about three units of the 2^-16
+    left by each split product (sums of up to w terms, activations in FP32; measured 2e-6 to
+    1.1e-5); an entry in the wrong band slot, a transposed operand or a dropped term is off by
+    the size of the entries themselves."""
+    print(f"[ae grad split-bf16 N={N} n={n} b={b} s={s} act={act} B={B}]", flush=True)
+    ae = MaskedAE(N, n, b, s, act)
+    p = _params32(ae, 17)
+    X = _snapshots(N, B + 9, 18)
+    rows = si.rng(19).permutation(B + 9)[:B].astype(np.int32)
+    scale = si.rng(20).uniform(0.5, 2.0, size=N)
+    ref_loss, ref_g = ae.forward_backward(p, X[rows], scale)
+    tr = dr.AETrainer(N, n, b, s, act, B, dr.ae_pack(N, n, b, s, *p.as_list()), precision=1)
+    lt, gt = tr.step(torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32), device="cuda"),
+                     torch.as_tensor(rows, device="cuda"),
+                     torch.as_tensor(scale.astype(np.float32), device="cuda"), update=False, loss=True, grad=True)
+    lerr = abs(float(lt.item()) - ref_loss) / ref_loss
+    got = dr.ae_unpack(gt.cpu().numpy(), N, n, b, s)
+    names = ["W1e", "b1e", "W2e", "W1d", "b1d", "W2d"]
+    errs = {nm: float(np.max(np.abs(gv - rv)) / max(1e-300, np.max(np.abs(rv))))
+            for nm, gv, rv in zip(names, got, ref_g.as_list())}
+    print(f"  loss rel err {lerr:.1e}; gradient max entry errors / max entry",
+          {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    assert lerr <= 1e-5
+    for nm, e in errs.items():
+        assert e <= 5e-5, nm
+
+
 def test_ae_adam_steps_parity(dr):
     N, n, b, s, B = 120, 4, 3, 2, 16
     ae = MaskedAE(N, n, b, s, ACT_SIGMOID)

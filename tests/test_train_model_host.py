@@ -1,0 +1,48 @@
+"""Host-side export of GPU-trained autoencoders (the weights the GPU trainer returns, turned into
+the decoders the online solve reads) against the oracle's autoencoder on identical weights:
+unpacking, encoding, full decoding and the exported decoder with the de-normalisation folded in
+and the latent origin moved.  No GPU is needed: the packed layout is the trainer's."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle.autoencoder import ACT_SIGMOID, ACT_SWISH, MaskedAE, Normalisation, decode_jacobian, export_decoder
+from paper_2305_15163_amd import ddrom as dr
+from paper_2305_15163_amd import train_model as tm
+
+
+@pytest.mark.parametrize("N,n,b,s,act", [(60, 4, 3, 2, ACT_SIGMOID), (47, 6, 5, 5, ACT_SWISH)])
+def test_export_matches_oracle(N, n, b, s, act):
+    ae = MaskedAE(N, n, b, s, act)
+    p = ae.init_params(3)
+    g = si.rng(4)
+    p.b1e[:] = g.uniform(-0.3, 0.3, size=p.b1e.shape)
+    p.b1d[:] = g.uniform(-0.3, 0.3, size=p.b1d.shape)
+    packed = dr.ae_pack(N, n, b, s, *p.as_list()).astype(np.float64)
+    # the oracle on the same (FP32-rounded) weights
+    q = dr.ae_unpack(packed, N, n, b, s)
+    from oracle.autoencoder import AEParams
+    pr = AEParams(*[np.asarray(v, dtype=np.float64) for v in q])
+    wts = tm.unpack_weights(packed, N, n, b, s)
+    Xn = g.uniform(-1, 1, size=(7, N))
+    z_ref = ae.encode(pr, Xn)
+    z = tm.encode(wts, Xn, N * s, act)
+    assert np.max(np.abs(z - z_ref)) <= 1e-12 * max(1.0, np.max(np.abs(z_ref)))
+    Y = tm.decode_full(wts, z, N, b, s, act)
+    zd = z @ pr.W1d.T + pr.b1d
+    from oracle.autoencoder import act as act_fn
+    ad, _ = act_fn(zd, act)
+    Y_ref = (ae._dec_mat(pr) @ ad.T).T
+    assert np.max(np.abs(Y - Y_ref)) <= 1e-12 * max(1.0, np.max(np.abs(Y_ref)))
+    # exported decoder == the oracle's export of the same weights, normalisation and centre
+    mid, sc = g.normal(size=N), g.uniform(0.5, 2.0, size=N)
+    center = z.mean(axis=0)
+    dec = tm.export_decoder(wts, mid, sc, center, b, s)
+    ref = export_decoder(ae, pr, Normalisation(mid, sc), center)
+    assert np.allclose(dec["W1"], ref.W1, rtol=0, atol=0)
+    assert np.max(np.abs(dec["b1"] - ref.b1)) <= 1e-13
+    assert np.max(np.abs(dec["W2"] - ref.W2vals)) <= 1e-15 * np.max(np.abs(ref.W2vals)) + 0.0
+    assert np.array_equal(dec["xref"], ref.x_ref)
+    # and it decodes the raw state of the centred latent
+    x0, _ = decode_jacobian(ref, np.zeros(n))
+    assert np.max(np.abs(x0 - (tm.decode_full(wts, center[None], N, b, s, act)[0] * sc + mid))) <= 1e-12 * np.max(np.abs(x0))
