@@ -30,7 +30,7 @@ from .autoencoder import ACT_IDENTITY, ACT_SIGMOID, ACT_SWISH, MaskedAE, export_
 from .burgers import BurgersFOM, Grid, solve_fom
 from .ddmaps import build_dd
 from .hyperreduction import greedy_sample, pod_basis
-from .lsrom import pod_maps
+from .lsrom import gappy_pod_operator, pod_maps
 from .srpc import cover_ports, port_latent_size
 
 CONFIGS = {
@@ -90,6 +90,12 @@ CONFIGS = {
                    epochs=0, batch=32, train_grid=(16, 16), hr_frac=0.10, seed=1),
     "tinyls": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID, ls=True,
                    epochs=0, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
+    # LS-ROM with gappy-POD HR (Section 3.1): B_i = (Z_i Phi_i^r)^+ Z_i on the same sampled nodes,
+    # with the residual POD basis cut to at most the number of sampled rows
+    "tinylsg": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID, ls=True, gappy=True,
+                    epochs=0, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
+    "cfg0lsg": dict(nx=36, ny=36, nsx=2, nsy=2, n_om=6, n_ga=3, b=5, s=3, act=ACT_SIGMOID, ls=True, gappy=True,
+                    epochs=0, batch=4, train_grid=(5, 5), hr_frac=0.20, seed=0),
     # the paper's own workload (Sections 7.1-7.4): 480 x 24 grid on [-1, 1] x [0, 0.05], 2 x 2
     # split, latents (8, 4), Swish, three-band masks of 5 entries shifted by 5, 6400 snapshots on
     # an 80 x 80 parameter grid (10% held out), 2000 epochs at minibatch 32, residual POD from
@@ -334,6 +340,12 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None, t
                 x0, Phi = pod_maps(X[:, idx].T, n=n)
                 pack[f"{part}{i}_Phi"] = Phi
                 pack[f"{part}{i}_x0"] = x0
+            if cfg.get("gappy"):
+                # columns: the r_u rows of the sampled nodes (ascending), then their r_v rows
+                Phi_r = pod_basis(Rsnap[:, sd.res_rows].T, 1e-10)
+                nodes = np.sort(np.asarray(hr_nodes[i], dtype=np.int64))
+                Phi_r = Phi_r[:, :min(Phi_r.shape[1], 2 * len(nodes))]
+                pack[f"gp{i}_P"] = gappy_pod_operator(g, nodes, sd.res_rows, Phi_r).P
     if pc is not None:
         pack["srpc"] = np.int64(1)
         pack["port_act"] = np.int64(pc["act"])

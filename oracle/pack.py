@@ -58,9 +58,10 @@ def _srpc_model(pack, g, dec_om, hr) -> ROMModel:
 
 def load_ls_pack(pack, use_hr: bool = True):
     """LS-ROM pack (om{i}_Phi / om{i}_x0, ga{i}_Phi / ga{i}_x0 instead of decoders) -> the LS-ROM
-    oracle with collocation HR on the pack's nodes."""
+    oracle with HR on the pack's nodes: collocation, or gappy POD when the pack carries the
+    matrices gp{i}_P = (Z_i Phi_i^r)^+ (columns: r_u rows of the nodes, then r_v rows)."""
     from .burgers import BurgersFOM
-    from .lsrom import LSROM, collocation_operator
+    from .lsrom import LSROM, HROperator, collocation_operator
     if isinstance(pack, str):
         pack = dict(np.load(pack, allow_pickle=False))
     g = Grid(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"]))
@@ -68,5 +69,7 @@ def load_ls_pack(pack, use_hr: bool = True):
     dd = build_dd(g, int(pack["nsx"]), int(pack["nsy"]))
     get = lambda key: [np.asarray(pack[f"{key[0]}{i}_{key[1]}"], np.float64) for i in range(n)]
     hr = [collocation_operator(g, np.asarray(pack[f"hr{i}"], np.int64)) for i in range(n)] if use_hr else None
+    if use_hr and "gp0_P" in pack:
+        hr = [HROperator(op.rows, np.asarray(pack[f"gp{i}_P"], np.float64)) for i, op in enumerate(hr)]
     return LSROM(BurgersFOM(g), dd, np.asarray(pack["C"], np.float64), get(("om", "x0")), get(("om", "Phi")),
                  get(("ga", "x0")), get(("ga", "Phi")), hr=hr)
