@@ -47,12 +47,15 @@ DECODE_COUNTERS = dict(fetch_kib=10852.9, write_kib=288288.0, fetch_scale=262144
 
 
 def decoder_source_sha1():
+    """Hash of the decoder kernel's source text and of the ring sizes it is instantiated with."""
     import hashlib
     with open(os.path.join(ROOT, "paper_2305_15163_amd", "csrc", "kernels.hip")) as f:
         s = f.read()
-    i = s.index("template <typename T, int NL, int ACT, int WAVES, int TAG, int VO = 0>\n__global__")
+    with open(os.path.join(ROOT, "paper_2305_15163_amd", "csrc", "internal.h")) as f:
+        ring = "".join(ln for ln in f if ln.startswith("constexpr int DEC_RING"))
+    i = s.index("template <typename T, int NL, int ACT, int WAVES, int TAG, int VO = 0, int RING = DEC_RING>\n__global__")
     j = s.index("\n}\n", i) + 3
-    return hashlib.sha1(s[i:j].encode()).hexdigest()[:16]
+    return hashlib.sha1((s[i:j] + ring).encode()).hexdigest()[:16]
 
 
 CONFIGS = {
@@ -602,6 +605,34 @@ def main():
             prop_leg["rel_err_vs_fom"] = {"n": nq, "warm": error_summary(e_w, res_q["warm"]["status"][:nq], dr),
                                           "zero_start": error_summary(e_q0, res_q["zero_start"]["status"][:nq], dr)}
         line["rel_err_vs_fom"] = rel
+        # LS-ROM contrast (Section 3.3): POD maps on the same grid, split, latents, HR nodes and
+        # C, with collocation and with gappy-POD HR, same batch, options and FOM references
+        ls = {}
+        for tag, fname in (("collocation", f"{a.config}ls.npz"), ("gappy_pod", f"{a.config}lsg.npz")):
+            lpath = os.path.join(ROOT, "models", fname)
+            if not os.path.exists(lpath):
+                continue
+            lpack = dict(np.load(lpath, allow_pickle=False))
+            lm = dr.Model(lpack)
+            lws = dr.Workspace(lm, B)
+            dr.rom_solve_batch(lm, lws, mu, o)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            for _ in range(a.steps):
+                lr = dr.rom_solve_batch(lm, lws, mu, o)
+            torch.cuda.synchronize()
+            ldt = time.perf_counter() - t3
+            lres = {k: v.cpu().numpy() for k, v in lr.items()}
+            lwse = dr.Workspace(lm, n_err)
+            le = dr.relative_error(lm, lwse, torch.as_tensor(lres["xhat"][:n_err], device="cuda"), Xf_d).cpu().numpy()
+            ls[tag] = {"model": fname, "solves_per_s": B * a.steps / ldt, "iters_mean": float(lres["iters"].mean()),
+                       "status_counts": {dr.STATUS[k]: int((lres["status"] == k).sum())
+                                         for k in np.unique(lres["status"])},
+                       "rel_err_vs_fom": error_summary(le, lres["status"][:n_err], dr)}
+            print(f"[bench] LS-ROM ({tag}) {ls[tag]['solves_per_s']:.0f} solves/s", file=sys.stderr, flush=True)
+        if ls:
+            line["lsrom"] = dict(ls, workload="LS-ROM (POD maps, latents as the NM-ROM) on the same grid, split, "
+                                              "HR nodes and C; same batch, precision and stopping rule")
         # the FOM's Newton solve per parameter on one host core (the paper's speedup denominator)
         line["fom_newton_s_per_mu"] = {"value": fom_s, "n": len(Xf), "cores": 1,
                                        "solves_per_s_vs_fom": line["value"] * fom_s}

@@ -109,6 +109,14 @@ typedef struct {
     int n_ports;
     const ddrom_decoder_desc* dec_port;     /* [n_ports] */
     int port_activation;                    /* DDROM_ACT_* */
+    /* Gappy-POD hyper-reduction (Section 3.1) when hr_modes is not NULL: subdomain i's
+     * residual enters the objective as B_i r_i with B_i = (Z_i Phi_i^r)^+ Z_i, given as the
+     * dense matrix hr_gappy[i] = (Z_i Phi_i^r)^+, [hr_modes[i]][2 hr_count[i]] row-major, whose
+     * columns are the r_u rows of the sampled nodes (ascending) followed by their r_v rows;
+     * 1 <= hr_modes[i] <= 2 hr_count[i] and n_i^Omega + n_i^Gamma <= 12.  NULL: collocation,
+     * B_i = Z_i. */
+    const int* hr_modes;                    /* [n_sub] or NULL */
+    const double* const* hr_gappy;          /* [n_sub] -> [hr_modes[i]][2 hr_count[i]] */
 } ddrom_model_desc;
 
 typedef struct ddrom_model ddrom_model;

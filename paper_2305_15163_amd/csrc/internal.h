@@ -90,6 +90,15 @@ struct ResSeg {
     int pad;
 };
 
+// Gappy-POD hyper-reduction of one subdomain: the stored residual rows R [rows][nn + 1][Bp]
+// (r_u rows of the sampled nodes, then their r_v rows; entry 0 the residual, 1..nn its latent
+// gradient), the projected rows Y = P R [modes][nn + 1][Bp] and P [modes][rows] (offsets in
+// Bp-rows for R and Y, in doubles for P).
+struct GappySeg {
+    int nn, nb, rows, modes;
+    long long r_off, y_off, p_off;
+};
+
 struct ConChunk {
     int sd;
     int j0, j1;             // constraint rows
@@ -166,6 +175,15 @@ struct ddrom_model {
     std::vector<DecPlan> dec_plan[4];
     std::vector<ResPlan> res_plan;
     std::vector<ConPlan> con_plan;
+
+    // gappy-POD hyper-reduction (empty: collocation)
+    int gappy = 0;
+    std::vector<ddrom::GappySeg> gseg_h;
+    ddrom::GappySeg* gseg_d = nullptr;
+    double* gP_d = nullptr;                      // all subdomains' P
+    int2* gitems_d = nullptr;                    // (subdomain, mode) work items of the projection
+    int n_gitems = 0;
+    long long g_rrows = 0, g_yrows = 0;          // Bp-rows of R and Y
 };
 
 struct SolveState {
@@ -190,6 +208,8 @@ struct ddrom_workspace {
     void* dec_out = nullptr;        // decoder values + Jacobians, [dec_rows][Bp] (float or double)
     double* bc = nullptr;           // [n_bc][Bp]
     double* gn_part = nullptr;      // [n_slots][estride][Bp]
+    double* g_R = nullptr;          // gappy POD: stored residual rows [g_rrows][Bp]
+    double* g_Y = nullptr;          // gappy POD: projected rows [g_yrows][Bp]
     double* c_part = nullptr;       // [n_cparts][n_C][Bp]
     double* E_part = nullptr;       // [n_cparts][n_C][mmax][Bp]
     long long zero_row = 0;         // first Bp-row of an all-zero block at the end of dec_out

@@ -575,6 +575,118 @@ __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rch
 }
 
 // ------------------------------------------------------------------------------------
+// Gappy-POD hyper-reduction (Section 3.1): the objective takes B_i r_i with
+// B_i = (Z_i Phi_i^r)^+ Z_i = P_i Z_i, so the Gauss-Newton sums are those of the projected rows
+// Y_i = P_i [Z_i r_i | Z_i R_i]: H_i = sum_j y_j' y_j'^T, g_i = sum_j y_j' y_j0, rr = sum_j y_j0^2
+// over the modes j (y_j0 the projected residual, y_j' its latent gradient).  Three passes:
+//  k_res_rows  the sampled rows and their gradients by the same stencil code as k_res_gn, stored;
+//  k_gappy_y   Y = P R, one workgroup per (subdomain, mode) and 64-solve group;
+//  k_gappy_gn  the sums over the modes into the subdomain's partial slot.
+// ------------------------------------------------------------------------------------
+template <typename T, int NO, int NG>
+__global__ __launch_bounds__(256) void k_res_rows(const ResChunk* __restrict__ rchunks, int rbase,
+                                                  const ResSeg* __restrict__ rsegs, const DecSeg* __restrict__ segs,
+                                                  const GappySeg* __restrict__ gsegs, const int* __restrict__ gather,
+                                                  const T* __restrict__ dec, const double* __restrict__ bc,
+                                                  const int* __restrict__ live, const int* __restrict__ n_live, int B,
+                                                  int Bp, double nu, double hx, double hy, double* __restrict__ R,
+                                                  long long zero_row) {
+    constexpr int NN = NO + NG;
+    const int nl = live_count(n_live, B);
+    const int j0 = blockIdx.y * 64;
+    if (j0 >= nl) return;
+    const ResChunk rc = rchunks[rbase + xcd_item()];
+    const ResSeg rs = rsegs[rc.sd];
+    const GappySeg gs = gsegs[rc.sd];
+    const long long oo = segs[rs.seg_om].out, og = segs[rs.seg_ga].out;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int j = j0 + lane;
+    const T* dom = dec + (size_t)oo * Bp + j;
+    const T* dga = dec + (size_t)og * Bp + j;
+    const T* dz = dec + (size_t)zero_row * Bp + j;
+    const double* bcb = bc + slot_solve(live, j, nl);
+    const int* gp = gather + rs.gather;
+    double* Rs = R + (size_t)gs.r_off * Bp + j;
+    for (int p = rc.p0 + w; p < rc.p1; p += 4) {
+        NodeLoads<T, NO> A;
+        load_node<T, NO, NG>(gp + (size_t)p * N_SLOTS, dom, dga, dz, bcb, Bp, A);
+        double zu[NN], zv[NN], ru, rv;
+        node_z<T, NO, NG>(A, nu, hx, hy, zu, zv, ru, rv);
+        double* qu = Rs + (size_t)p * (NN + 1) * Bp;
+        double* qv = Rs + (size_t)(gs.nb + p) * (NN + 1) * Bp;
+        qu[0] = ru;
+        qv[0] = rv;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+            qu[(size_t)(1 + i) * Bp] = zu[i];
+            qv[(size_t)(1 + i) * Bp] = zv[i];
+        }
+    }
+}
+
+// Y[j][k][b] = sum_rows P[j][row] R[row][k][b]: the four waves take k = w, w + 4, ...; the
+// row sum runs in row order (the same for every solve and batch).
+__global__ __launch_bounds__(256) void k_gappy_y(const int2* __restrict__ items, const GappySeg* __restrict__ gsegs,
+                                                 const double* __restrict__ P, const double* __restrict__ R,
+                                                 double* __restrict__ Y, const int* __restrict__ n_live, int B,
+                                                 int Bp) {
+    const int nl = live_count(n_live, B);
+    const int j0 = blockIdx.y * 64;
+    if (j0 >= nl) return;
+    const int2 it = items[blockIdx.x];
+    const GappySeg gs = gsegs[it.x];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = j0 + lane;
+    const double* Pj = P + gs.p_off + (size_t)it.y * gs.rows;
+    const size_t rstride = (size_t)(gs.nn + 1) * Bp;
+    for (int k = w; k <= gs.nn; k += 4) {
+        const double* Rk = R + ((size_t)gs.r_off + k) * Bp + j;
+        double acc = 0.0;
+        for (int row = 0; row < gs.rows; ++row) acc = fma(Pj[row], Rk[row * rstride], acc);
+        Y[((size_t)gs.y_off + (size_t)it.y * (gs.nn + 1) + k) * Bp + j] = acc;
+    }
+}
+
+// Gauss-Newton sums of one subdomain's projected rows (one wave, 64 solves), written to its
+// partial slot in the layout k_res_gn uses (H upper triangle row by row, g, rr).
+template <int NN>
+__global__ __launch_bounds__(64) void k_gappy_gn(int sd, const GappySeg* __restrict__ gsegs,
+                                                 const double* __restrict__ Y, const int* __restrict__ n_live, int B,
+                                                 int Bp, double* __restrict__ part, int estride, int slot) {
+    using G = GnEntries<NN>;
+    const int nl = live_count(n_live, B);
+    const int j0 = blockIdx.y * 64;
+    if (j0 >= nl) return;
+    const GappySeg gs = gsegs[sd];
+    const int j = j0 + (int)threadIdx.x;
+    double H[G::NH], g[NN], rr = 0.0;
+#pragma unroll
+    for (int e = 0; e < G::NH; ++e) H[e] = 0.0;
+#pragma unroll
+    for (int e = 0; e < NN; ++e) g[e] = 0.0;
+    for (int q = 0; q < gs.modes; ++q) {
+        const double* y = Y + ((size_t)gs.y_off + (size_t)q * (NN + 1)) * Bp + j;
+        double v[NN + 1];
+#pragma unroll
+        for (int k = 0; k <= NN; ++k) v[k] = y[(size_t)k * Bp];
+        rr = fma(v[0], v[0], rr);
+        int e = 0;
+#pragma unroll
+        for (int i = 0; i < NN; ++i) {
+            g[i] = fma(v[1 + i], v[0], g[i]);
+#pragma unroll
+            for (int k = i; k < NN; ++k, ++e) H[e] = fma(v[1 + i], v[1 + k], H[e]);
+        }
+    }
+    double* pp = part + (size_t)slot * estride * Bp + j;
+#pragma unroll
+    for (int e = 0; e < G::NH; ++e) pp[(size_t)e * Bp] = H[e];
+#pragma unroll
+    for (int i = 0; i < NN; ++i) pp[(size_t)(G::NH + i) * Bp] = g[i];
+    pp[(size_t)(G::NH + NN) * Bp] = rr;
+}
+
+// ------------------------------------------------------------------------------------
 // Weak compatibility constraint: c_i = C A_i g_i^Gamma, E_i^Gamma = C A_i dg_i^Gamma/dxhat
 // ------------------------------------------------------------------------------------
 // One workgroup = (subdomain, 8 constraint rows, a run of interface rows) x 64 solve slots.
@@ -1950,13 +2062,62 @@ static int launch_res_item(const ddrom_model* m, int prec, const ddrom_model::Re
     return DDROM_EINVAL;
 }
 
+// Gappy POD: stored rows of one latent class of the residual plan.
+static int launch_res_rows(const ddrom_model* m, int prec, const ddrom_model::ResPlan& rs, const ddrom_workspace* ws,
+                           const int* live, const int* n_live, int B, hipStream_t s) {
+    dim3 grid(rs.c1 - rs.c0, ws->Bp / 64), block(256);
+#define ROWS_CASE(A, G)                                                                                           \
+    if (rs.n_om == A && rs.n_ga == G) {                                                                           \
+        if (prec == DDROM_PREC_FP64)                                                                              \
+            hipLaunchKernelGGL((k_res_rows<double, A, G>), grid, block, 0, s, m->rchunks_d, rs.c0, m->rsegs_d,     \
+                               m->segs_d, m->gseg_d, m->gather_d, (const double*)ws->dec_out, ws->bc, live, n_live, \
+                               B, ws->Bp, m->nu, m->hx, m->hy, ws->g_R, ws->zero_row);                            \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_res_rows<float, A, G>), grid, block, 0, s, m->rchunks_d, rs.c0, m->rsegs_d,      \
+                               m->segs_d, m->gseg_d, m->gather_d, (const float*)ws->dec_out, ws->bc, live, n_live,  \
+                               B, ws->Bp, m->nu, m->hx, m->hy, ws->g_R, ws->zero_row);                            \
+        HIPCHECK(hipGetLastError());                                                                              \
+        return 0;                                                                                                 \
+    }
+    ROWS_CASE(2, 1) ROWS_CASE(3, 2) ROWS_CASE(4, 2) ROWS_CASE(4, 4) ROWS_CASE(6, 3) ROWS_CASE(8, 4) ROWS_CASE(4, 0)
+    ROWS_CASE(6, 0) ROWS_CASE(8, 0)
+#undef ROWS_CASE
+    set_error("gappy POD: unsupported latent sizes (" + std::to_string(rs.n_om) + ", " + std::to_string(rs.n_ga) + ")");
+    return DDROM_EINVAL;
+}
+
+static int launch_gappy(const ddrom_model* m, const ddrom_workspace* ws, const int* n_live, int B, hipStream_t s) {
+    if (m->n_gitems > 0)
+        hipLaunchKernelGGL(k_gappy_y, dim3(m->n_gitems, ws->Bp / 64), dim3(256), 0, s, m->gitems_d, m->gseg_d,
+                           m->gP_d, ws->g_R, ws->g_Y, n_live, B, ws->Bp);
+    for (int sd = 0; sd < m->n_sub; ++sd) {
+        const int nn = m->gseg_h[sd].nn, slot = m->rsegs_h[sd].slot0;
+        const dim3 grid(1, ws->Bp / 64);
+#define GN_CASE(NV)                                                                                               \
+    case NV:                                                                                                      \
+        hipLaunchKernelGGL(k_gappy_gn<NV>, grid, dim3(64), 0, s, sd, m->gseg_d, ws->g_Y, n_live, B, ws->Bp,        \
+                           ws->gn_part, m->estride, slot);                                                        \
+        break;
+        switch (nn) {
+            GN_CASE(3) GN_CASE(4) GN_CASE(5) GN_CASE(6) GN_CASE(8) GN_CASE(9) GN_CASE(12)
+            default:
+                set_error("gappy POD: unsupported latent size " + std::to_string(nn));
+                return DDROM_EINVAL;
+        }
+#undef GN_CASE
+    }
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
 static int launch_res(const ddrom_model* m, int prec, const ddrom_workspace* ws, const int* live, const int* n_live,
                       int B, hipStream_t s) {
     for (const auto& pl : m->res_plan) {
-        const int rc = launch_res_item(m, prec, pl, ws, live, n_live, B, s);
+        const int rc = m->gappy ? launch_res_rows(m, prec, pl, ws, live, n_live, B, s)
+                                : launch_res_item(m, prec, pl, ws, live, n_live, B, s);
         if (rc) return rc;
     }
-    return 0;
+    return m->gappy ? launch_gappy(m, ws, n_live, B, s) : 0;
 }
 
 struct ModelDevInts {
@@ -2274,6 +2435,8 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
         {(void**)&w->RB, Bp * (size_t)(m->n_sub * (m->estride + m->n_C * std::max(1, m->mmax)) + std::max(1, m->n_C)) * sizeof(double)},
         {(void**)&w->st, Bp * sizeof(SolveState)},
         {(void**)&w->counter, sizeof(int) * 4},
+        {(void**)&w->g_R, std::max<size_t>(1, (size_t)m->g_rrows) * Bp * sizeof(double)},
+        {(void**)&w->g_Y, std::max<size_t>(1, (size_t)m->g_yrows) * Bp * sizeof(double)},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -2328,7 +2491,7 @@ int ddrom_workspace_create(const ddrom_model* m, int max_batch, ddrom_workspace*
 
 void ddrom_workspace_destroy(ddrom_workspace* w) {
     if (!w) return;
-    void* ptrs[] = {w->dec_out, w->bc, w->gn_part, w->c_part, w->E_part, w->x, w->xt, w->lam, w->lamt,
+    void* ptrs[] = {w->dec_out, w->bc, w->gn_part, w->g_R, w->g_Y, w->c_part, w->E_part, w->x, w->xt, w->lam, w->lamt,
                     w->step, w->live, w->mu, w->st, w->counter, w->RB};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);

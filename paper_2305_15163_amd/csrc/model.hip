@@ -723,6 +723,44 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         m->rchunks_h.swap(sorted);
     }
 
+    // ---- gappy-POD hyper-reduction: stored rows, projection items, one GN slot per subdomain ----
+    std::vector<double> gP;
+    std::vector<int2> gitems;
+    if (d->hr_modes) {
+        if (!d->hr_gappy) {
+            set_error("gappy POD: hr_gappy is NULL");
+            return DDROM_EINVAL;
+        }
+        m->gappy = 1;
+        m->gseg_h.resize(n_sub);
+        long long ro = 0, yo = 0;
+        for (int sd = 0; sd < n_sub; ++sd) {
+            GappySeg& g = m->gseg_h[sd];
+            g.nn = m->n_om[sd] + m->n_ga[sd];
+            g.nb = m->nb[sd];
+            g.rows = 2 * g.nb;
+            g.modes = d->hr_modes[sd];
+            if (g.modes < 1 || g.modes > g.rows || !d->hr_gappy[sd] || g.nn > 12) {
+                set_error("gappy POD: need 1 <= hr_modes[i] <= 2 hr_count[i], the matrix, and n_i <= 12");
+                return DDROM_EINVAL;
+            }
+            g.r_off = ro;
+            g.y_off = yo;
+            g.p_off = (long long)gP.size();
+            ro += (long long)g.rows * (g.nn + 1);
+            yo += (long long)g.modes * (g.nn + 1);
+            gP.insert(gP.end(), d->hr_gappy[sd], d->hr_gappy[sd] + (size_t)g.modes * g.rows);
+            for (int q = 0; q < g.modes; ++q) gitems.push_back(int2{sd, q});
+            // the projected sums of a subdomain go to one partial slot
+            m->rsegs_h[sd].slot0 = sd;
+            m->rsegs_h[sd].slot1 = sd + 1;
+        }
+        m->n_slots = n_sub;
+        m->g_rrows = ro;
+        m->g_yrows = yo;
+        m->n_gitems = (int)gitems.size();
+    }
+
     // ---- constraint work items ----
     std::vector<ConChunk> cch;
     std::vector<double> CAflat;
@@ -839,7 +877,9 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         (rc = upload(&m->bc_field_d, bc_field)) || (rc = upload(&m->CA_d, CAflat)) ||
         (rc = upload(&m->cchunks_d, cch)) || (rc = upload(&m->fom_src_d, fsrc)) ||
         (rc = upload(&m->fom_meta_d, fmeta)) || (rc = upload(&m->fom_sd_of_row_d, sd_of_row)) ||
-        (rc = upload(&m->state_dof_d, state_dof)) || (rc = upload(&m->Ahat_d, Ahat)))
+        (rc = upload(&m->state_dof_d, state_dof)) || (rc = upload(&m->Ahat_d, Ahat)) ||
+        (m->gappy && ((rc = upload(&m->gseg_d, m->gseg_h)) || (rc = upload(&m->gP_d, gP)) ||
+                      (rc = upload(&m->gitems_d, gitems)))))
         return rc;
     return 0;
 }
@@ -847,7 +887,8 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
 void free_model(ddrom_model* m) {
     void* ptrs[] = {m->W1f, m->b1f, m->W2f, m->xreff, m->W1d, m->b1d, m->W2d, m->xrefd, m->bands, m->segs_d,
                     m->chunks_d, m->gather_d, m->rsegs_d, m->rchunks_d, m->bc_xy_d, m->bc_field_d, m->CA_d,
-                    m->cchunks_d, m->fom_src_d, m->fom_meta_d, m->fom_sd_of_row_d, m->state_dof_d, m->Ahat_d};
+                    m->cchunks_d, m->fom_src_d, m->fom_meta_d, m->fom_sd_of_row_d, m->state_dof_d, m->Ahat_d,
+                    m->gseg_d, m->gP_d, m->gitems_d};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }

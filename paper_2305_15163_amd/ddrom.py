@@ -32,7 +32,8 @@ class ModelDesc(C.Structure):
                 ("C", C.POINTER(C.c_double)), ("dec_om", C.POINTER(DecoderDesc)), ("dec_ga", C.POINTER(DecoderDesc)),
                 ("hr_count", C.POINTER(C.c_int)), ("hr_nodes", C.POINTER(C.POINTER(C.c_int))),
                 ("tile", C.c_int * 3), ("n_ports", C.c_int), ("dec_port", C.POINTER(DecoderDesc)),
-                ("port_activation", C.c_int)]
+                ("port_activation", C.c_int), ("hr_modes", C.POINTER(C.c_int)),
+                ("hr_gappy", C.POINTER(C.POINTER(C.c_double)))]
 
 
 class MlpDesc(C.Structure):
@@ -166,11 +167,19 @@ def model_desc(pack: dict, tile=(0, 0, 0)):
     hr_ptrs = (C.POINTER(C.c_int) * n)(*[h.ctypes.data_as(C.POINTER(C.c_int)) for h in hr])
     keep.extend([hr_cnt, hr_ptrs])
     Cm = np.asarray(pack["C"], dtype=np.float64)
+    # gappy-POD hyper-reduction: gp{i}_P = (Z_i Phi_i^r)^+ [n_r][2 N_B]
+    if "gp0_P" in pack:
+        gp = [np.asarray(pack[f"gp{i}_P"], dtype=np.float64) for i in range(n)]
+        g_modes = (C.c_int * n)(*[int(P.shape[0]) for P in gp])
+        g_ptrs = (C.POINTER(C.c_double) * n)(*[dptr(P) for P in gp])
+        keep.extend([g_modes, g_ptrs])
+    else:
+        g_modes, g_ptrs = C.POINTER(C.c_int)(), C.POINTER(C.POINTER(C.c_double))()
     desc = ModelDesc(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"]), int(pack["nsx"]),
                      int(pack["nsy"]), int(pack["act"]), int(Cm.shape[0]), int(Cm.shape[1]), dptr(Cm),
                      decs["om"], decs["ga"] if not srpc else C.POINTER(DecoderDesc)(), hr_cnt, hr_ptrs,
                      (C.c_int * 3)(*[int(v) for v in tile]), n_ports, ports,
-                     int(pack["port_act"]) if srpc else 0)
+                     int(pack["port_act"]) if srpc else 0, g_modes, g_ptrs)
     return desc, keep
 
 

@@ -109,6 +109,22 @@ def tinyls_pack():
 
 
 @pytest.fixture(scope="session")
+def tinylsg_pack():
+    """tinyls with gappy-POD HR: B_i = (Z_i Phi_i^r)^+ Z_i on the same nodes."""
+    from oracle.build_model import build
+    pack, *_ = build("tinylsg", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
+def cfg0lsg_pack():
+    """cfg0ls with gappy-POD HR on the same nodes."""
+    from oracle.build_model import build
+    pack, *_ = build("cfg0lsg", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
 def cfg0ls_pack():
     """LS-ROM of the 36x36, 2x2 workload: POD bases (6, 3), the same HR nodes and C as its
     nonlinear-manifold model."""

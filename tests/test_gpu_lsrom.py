@@ -1,8 +1,9 @@
 """LS-ROM (Section 3.3) on the GPU, through the C ABI: the POD maps x = Phi xhat run as dense
 decoders with the identity activation (W1 = I, b1 = 0, W2 = Phi) on the same kernels, against
-the independent LS-ROM oracle (its own residual route, null-space QP steps) with collocation HR
-on the same nodes: maps and their constant Jacobians, FP64 solves (statuses, iteration counts,
-latents and multipliers to 1e-10) and FP32-map solves against the FOM."""
+the independent LS-ROM oracle (its own residual route, null-space QP steps) with collocation or
+gappy-POD HR (Section 3.1, B_i = (Z_i Phi_i^r)^+ Z_i) on the same nodes: maps and their constant
+Jacobians, Gauss-Newton blocks of the hyper-reduced objective, FP64 solves (statuses, iteration
+counts, latents and multipliers to 1e-10) and FP32-map solves against the FOM."""
 import numpy as np
 import pytest
 
@@ -24,7 +25,7 @@ def dr():
     return d
 
 
-@pytest.fixture(scope="module", params=["tinyls", "cfg0ls"])
+@pytest.fixture(scope="module", params=["tinyls", "cfg0ls", "tinylsg", "cfg0lsg"])
 def case(request, dr):
     pack = request.getfixturevalue(request.param + "_pack")
     print(f"[lsrom case {request.param}]", flush=True)
@@ -51,6 +52,31 @@ def test_lsrom_maps(dr, case):
             for b in range(B):
                 assert relerr(x[b], (x0 + Phi @ xh[b])[rows]) <= 1e-13
                 assert relerr(J[b], Phi[rows]) <= 1e-15
+
+
+def test_lsrom_gn_blocks(dr, case):
+    """H_i = J_i^T J_i, g_i = J_i^T (B_i r_i) and the summed squares of the hyper-reduced residual
+    B_i r_i (collocation: the sampled rows; gappy POD: their projection) against the oracle's
+    stacked residual and Jacobian."""
+    name, pack, gm, rom = case
+    B = 5
+    mus = si.heldout_mu(B, 9)
+    xh = si.normal((B, gm.n_D), seed=3, scale=0.5)
+    ws = dr.Workspace(gm, B)
+    H, g, EG, c, rr = (t.cpu().numpy() for t in dr.gn_blocks(gm, ws, mus, xh, precision=dr.PREC_FP64))
+    for b in range(B):
+        r, J = rom.residual(mus[b], xh[b])
+        o_r, o_x, rr_ref = 0, 0, 0.0
+        for i, (a, m) in enumerate(rom.sizes):
+            k = rom.hr[i].P.shape[0] if rom.hr[i].P is not None else len(rom.hr[i].rows)
+            ri, Ji = r[o_r:o_r + k], J[o_r:o_r + k, o_x:o_x + a + m]
+            assert relerr(H[b, i, :a + m, :a + m], Ji.T @ Ji) <= 1e-11
+            assert relerr(g[b, o_x:o_x + a + m], Ji.T @ ri) <= 1e-10
+            rr_ref += float(ri @ ri)
+            o_r += k
+            o_x += a + m
+        assert o_r == len(r)
+        assert relerr(rr[b], rr_ref) <= 1e-11
 
 
 @pytest.mark.parametrize("B", [1, 6])
