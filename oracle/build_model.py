@@ -94,6 +94,8 @@ CONFIGS = {
     # with the residual POD basis cut to at most the number of sampled rows
     "tinylsg": dict(nx=12, ny=8, nsx=2, nsy=2, n_om=4, n_ga=2, b=3, s=2, act=ACT_SIGMOID, ls=True, gappy=True,
                     epochs=0, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=7),
+    "cfg1lsg": dict(nx=240, ny=240, nsx=4, nsy=4, n_om=8, n_ga=4, b=9, s=2, act=ACT_SIGMOID, ls=True, gappy=True,
+                    epochs=0, batch=32, train_grid=(16, 16), hr_frac=0.10, seed=1),
     "cfg0lsg": dict(nx=36, ny=36, nsx=2, nsy=2, n_om=6, n_ga=3, b=5, s=3, act=ACT_SIGMOID, ls=True, gappy=True,
                     epochs=0, batch=4, train_grid=(5, 5), hr_frac=0.20, seed=0),
     # the paper's own workload (Sections 7.1-7.4): 480 x 24 grid on [-1, 1] x [0, 0.05], 2 x 2
@@ -103,7 +105,7 @@ CONFIGS = {
     # by --skeleton: the autoencoders are trained on the GPU from the written snapshot matrix.
     "paper": dict(nx=480, ny=24, nsx=2, nsy=2, n_om=8, n_ga=4, b=5, s=5, act=ACT_SWISH,
                   epochs=2000, batch=32, train_grid=(80, 80), res_grid=(20, 20), hr_count=100, hr_frac=None,
-                  seed=41),
+                  lam_range=(5.0, 25.0), seed=41),
     # small configurations for tests
     # the paper's architecture on a small elongated grid: Swish, three-band masks of 5 entries
     # shifted by 5 (a row's bands span 55 hidden units), latents (8, 4)
@@ -155,7 +157,7 @@ def snapshot_matrix(name: str, out: str, workers: int = 8, verbose=True):
     cfg = CONFIGS[name]
     g = Grid(cfg["nx"], cfg["ny"])
     dd = build_dd(g, cfg["nsx"], cfg["nsy"])
-    mus = si.training_grid(*cfg["train_grid"])
+    mus = si.training_grid(*cfg["train_grid"], lam_range=cfg.get("lam_range", si.LAM_RANGE))
     n_x = 2 * g.nx * g.ny
     if os.path.exists(out):
         X = np.load(out, mmap_mode="r+")
@@ -234,11 +236,12 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None, t
     cfg = CONFIGS[name]
     g = Grid(cfg["nx"], cfg["ny"])
     dd = build_dd(g, cfg["nsx"], cfg["nsy"])
-    mus = si.training_grid(*cfg["train_grid"])
+    lam_range = cfg.get("lam_range", si.LAM_RANGE)
+    mus = si.training_grid(*cfg["train_grid"], lam_range=lam_range)
     t0 = time.time()
     if "res_grid" in cfg:
         # residual snapshots from the Newton histories of a coarser parameter grid's solves
-        _, Rsnap = snapshots(g.nx, g.ny, si.training_grid(*cfg["res_grid"]), workers)
+        _, Rsnap = snapshots(g.nx, g.ny, si.training_grid(*cfg["res_grid"], lam_range=lam_range), workers)
         X = state_snapshots(g.nx, g.ny, mus, workers)
     else:
         X, Rsnap = snapshots(g.nx, g.ny, mus, workers)

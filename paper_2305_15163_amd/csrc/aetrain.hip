@@ -323,6 +323,87 @@ __global__ __launch_bounds__(256) void k_band_grad(int N, int w, int bw, int sw,
     }
 }
 
+// The same band-slot gradient with LDS staging: per 64 minibatch columns, the 16 rows of P and
+// the union of their three band windows of Q (columns [r0 s - b s, r0 s + b s + 16 ntile)) are
+// loaded with coalesced 16-byte loads into LDS rows padded to BG_LD floats (16-byte operand
+// reads without bank conflicts); each wave keeps the accumulators of up to 4 column tiles
+// (3 ntile <= 16, i.e. 15 s + b <= 80).
+constexpr int BG_K = 64, BG_LD = BG_K + 4;
+
+__device__ __forceinline__ float4 load_row4(const float* __restrict__ src, int avail, bool vec) {
+    if (vec && avail >= 4) return *reinterpret_cast<const float4*>(src);
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (avail > 0) v.x = src[0];
+    if (avail > 1) v.y = src[1];
+    if (avail > 2) v.z = src[2];
+    if (avail > 3) v.w = src[3];
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_band_grad_lds(int N, int w, int bw, int sw, int B,
+                                                       const float* __restrict__ P, const float* __restrict__ Q,
+                                                       float* __restrict__ G, int x3) {
+    extern __shared__ __align__(16) float sm[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * 16;
+    const int ntile = (15 * sw + bw + 15) / 16, ntt = 3 * ntile;
+    const int c_lo = r0 * sw - bw * sw, nc = 2 * bw * sw + 16 * ntile;
+    float* Ps = sm;                       // [16][BG_LD]
+    float* Qs = sm + 16 * BG_LD;          // [nc][BG_LD]
+    const int rl = lane & 15, kq = 4 * (lane >> 4);
+    const bool vec = (B & 3) == 0;
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int s0 = 0; s0 < B; s0 += BG_K) {
+        const int kn = min(BG_K, B - s0);
+        for (int e = tid; e < (16 + nc) * (BG_K / 4); e += 256) {
+            const int row = e / (BG_K / 4), q4 = (e % (BG_K / 4)) * 4;
+            float4 v = {0.f, 0.f, 0.f, 0.f};
+            if (row < 16) {
+                const int r = r0 + row;
+                if (r < N) v = load_row4(P + (size_t)r * B + s0 + q4, kn - q4, vec);
+            } else {
+                const int c = c_lo + row - 16;
+                if (c >= 0 && c < w) v = load_row4(Q + (size_t)c * B + s0 + q4, kn - q4, vec);
+            }
+            *reinterpret_cast<float4*>(sm + (size_t)row * BG_LD + q4) = v;
+        }
+        __syncthreads();
+        for (int it = 0; it < BG_K / 16 && s0 + it * 16 < B; ++it) {
+            const float4 av = *reinterpret_cast<const float4*>(Ps + rl * BG_LD + it * 16 + kq);
+            const float a[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int tt = wave + 4 * t;
+                if (tt >= ntt) break;
+                const int kb = tt / ntile - 1, ci = tt % ntile;
+                const int cl = bw * sw + kb * bw * sw + 16 * ci + rl;
+                const float4 bv = *reinterpret_cast<const float4*>(Qs + (size_t)cl * BG_LD + it * 16 + kq);
+                const float b[4] = {bv.x, bv.y, bv.z, bv.w};
+                acc[t] = mma16(a, b, acc[t], x3);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int tt = wave + 4 * t;
+        if (tt >= ntt) break;
+        const int kb = tt / ntile - 1, ci = tt % ntile;
+        const int off = kb * bw * sw;
+        const int cn = r0 * sw + off + 16 * ci + rl;
+        // every slot of the 16 rows lies in exactly one tile; slots whose column falls outside
+        // [0, w) summed zero operands and store 0
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = r0 + kq + i;
+            const int tq = cn - r * sw - off;
+            if (r < N && tq >= 0 && tq < bw) G[((size_t)r * 3 + (kb + 1)) * bw + tq] = acc[t][i];
+        }
+    }
+}
+
 // minibatch of normalised snapshots, feature-major: Xb[r][b] = X[rows[b]][r]
 __global__ void k_ae_gather(const float* __restrict__ X, int N, const int* __restrict__ rows, int B,
                             float* __restrict__ Xb) {
@@ -384,6 +465,19 @@ struct ddrom_ae_trainer {
     int split = 1;
     int x3 = 0;                // 1: split-BF16 (three products) for FP32-class operands
 };
+
+// Band-slot gradient G = sampled P Q^T: the LDS-staged kernel where its window fits, else the
+// plain one.
+static void band_grad(const ddrom_ae_trainer* t, int B, const float* P, const float* Q, float* G, hipStream_t s) {
+    const int ntile = (15 * t->sw + t->bw + 15) / 16;
+    const size_t lds = (size_t)(16 + 2 * t->bw * t->sw + 16 * ntile) * BG_LD * sizeof(float);
+    if (3 * ntile <= 16 && lds <= 65536)
+        hipLaunchKernelGGL(k_band_grad_lds, dim3(cdiv(t->N, 16)), dim3(256), lds, s, t->N, t->w, t->bw, t->sw, B, P,
+                           Q, G, t->x3);
+    else
+        hipLaunchKernelGGL(k_band_grad, dim3(cdiv(t->N, 16)), dim3(256), 0, s, t->N, t->w, t->bw, t->sw, B, P, Q, G,
+                           t->x3);
+}
 
 extern "C" {
 
@@ -496,7 +590,7 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
                        t->lpart, t->x3);
     if (loss_d) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, s, t->lpart, (int)(lgrid.x * lgrid.y), B, loss_d);
     // gradients
-    hipLaunchKernelGGL(k_band_grad, dim3(cdiv(N, 16)), blk, 0, s, N, w, bw, sw, B, t->dY, t->ad, G + t->o_w2d, t->x3);
+    band_grad(t, B, t->dY, t->ad, G + t->o_w2d, s);
     // dzd = (D2^T dY) o sigma'(zd)
     hipLaunchKernelGGL(k_band_t<2>, dim3(cdiv(w, 16), cdiv(B, 64)), blk, 0, s, N, w, bw, sw, B, P + t->o_w2d, t->dY,
                        t->dzd, (const float*)nullptr, (float*)nullptr, t->zd, act, t->x3);
@@ -520,7 +614,7 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
                        (long long)w, t->dxh, (long long)B, 1LL, t->dze, B, 1, (const float*)nullptr, (float*)nullptr,
                        t->ze, act, t->x3, 0);
     // gW1e[r][k][t] = sum_b x~[r][b] dze[c][b], gb1e = sum_b dze
-    hipLaunchKernelGGL(k_band_grad, dim3(cdiv(N, 16)), blk, 0, s, N, w, bw, sw, B, t->Xb, t->dze, G + t->o_w1e, t->x3);
+    band_grad(t, B, t->Xb, t->dze, G + t->o_w1e, s);
     hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 4)), blk, 0, s, t->dze, w, B, G + t->o_b1e);
     if (grad_d) AECHECK(hipMemcpyAsync(grad_d, G, (size_t)t->n_params * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (update) {

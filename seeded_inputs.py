@@ -6,8 +6,9 @@ numpy PCG64 stream keyed by an explicit integer seed, so the oracle and the HIP 
 receive bit-identical inputs.
 
 Contents
-  * parameter sets mu = (a, lambda) on the Burgers box D = [1, 1e4] x [5, 20]
-    (tensor linspace training grids and uniform held-out draws),
+  * parameter sets mu = (a, lambda) on the Burgers box D = [1, 1e4] x [5, 20] (the paper's own
+    workload uses lambda in [5, 25]: the range is an argument) as tensor linspace training grids
+    and uniform held-out draws,
   * the Gaussian test matrix C of the weak compatibility constraint
     (Section 3.1: C has i.i.d. normal entries),
   * Glorot-uniform initial weights for the shallow masked autoencoders,
@@ -25,21 +26,21 @@ def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(int(seed)))
 
 
-def training_grid(n_a: int, n_lam: int) -> np.ndarray:
+def training_grid(n_a: int, n_lam: int, lam_range=LAM_RANGE) -> np.ndarray:
     """Tensor grid of (a, lambda), endpoints included, a-fastest.  Shape [n_a*n_lam, 2]."""
     a = np.linspace(A_RANGE[0], A_RANGE[1], n_a)
-    lam = np.linspace(LAM_RANGE[0], LAM_RANGE[1], n_lam)
+    lam = np.linspace(lam_range[0], lam_range[1], n_lam)
     aa, ll = np.meshgrid(a, lam, indexing="xy")
     return np.stack([aa.ravel(), ll.ravel()], axis=1).astype(np.float64)
 
 
-def heldout_mu(n: int, seed: int, exclude: np.ndarray | None = None) -> np.ndarray:
+def heldout_mu(n: int, seed: int, exclude: np.ndarray | None = None, lam_range=LAM_RANGE) -> np.ndarray:
     """n parameter points drawn uniformly from D, rejecting exact hits on `exclude`."""
     g = rng(seed)
     out = []
     ex = set() if exclude is None else {tuple(p) for p in np.asarray(exclude)}
     while len(out) < n:
-        p = (g.uniform(*A_RANGE), g.uniform(*LAM_RANGE))
+        p = (g.uniform(*A_RANGE), g.uniform(*lam_range))
         if p not in ex:
             out.append(p)
     return np.asarray(out, dtype=np.float64).reshape(n, 2)
