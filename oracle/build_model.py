@@ -370,7 +370,24 @@ def main(argv=None):
     ap.add_argument("--skeleton", default=None, help="path stem: write <stem>_skel.npz (the pack without decoders, "
                                                      "with the training recipe), <stem>_X.npy (the state snapshots, "
                                                      "FP64) and <stem>_X_dd.npz (parameters, subdomain index lists)")
+    ap.add_argument("--slice", default=None, help="with --out: from the snapshot matrix <stem>.npy of --snapshots, "
+                                                  "write the largest interior subdomain's interior and interface "
+                                                  "snapshots (FP32) and their training seeds")
     a = ap.parse_args(argv)
+    if a.slice:
+        cfg = CONFIGS[a.config]
+        idx = np.load(a.slice + "_dd.npz")
+        n_sub = cfg["nsx"] * cfg["nsy"]
+        k = max(range(n_sub), key=lambda i: len(idx[f"om{i}"]))
+        X = np.load(a.slice + ".npy", mmap_mode="r")
+        if np.isnan(X[:, 0]).any():
+            raise RuntimeError("the snapshot matrix is not complete")
+        seeds = si.spawn_seeds(cfg["seed"], 2 * n_sub)      # the GPU model trainer's seeds
+        np.savez(a.out, sd=np.int64(k), X_om=np.asarray(X[:, idx[f"om{k}"]], dtype=np.float32),
+                 X_ga=np.asarray(X[:, idx[f"ga{k}"]], dtype=np.float32), seed_om=np.int64(seeds[2 * k]),
+                 seed_ga=np.int64(seeds[2 * k + 1]), mus=idx["mus"])
+        print("wrote", a.out, "subdomain", k, flush=True)
+        return 0
     if a.snapshots:
         snapshot_matrix(a.config, a.snapshots, a.workers)
         return 0

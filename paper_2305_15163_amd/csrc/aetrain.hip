@@ -91,6 +91,21 @@ __device__ __forceinline__ void act_fwd(float z, int act, float& a, float& d) {
 
 __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// LDS staging of minibatch-major rows: BG_K columns at a time, rows padded to BG_LD floats so
+// that 16-byte operand reads of 16 consecutive rows fall in distinct banks.
+constexpr int BG_K = 64, BG_LD = BG_K + 4;
+
+// Four consecutive floats of a row with `avail` valid entries (16-byte load when aligned).
+__device__ __forceinline__ float4 load_row4(const float* __restrict__ src, int avail, bool vec) {
+    if (vec && avail >= 4) return *reinterpret_cast<const float4*>(src);
+    float4 v = {0.f, 0.f, 0.f, 0.f};
+    if (avail > 0) v.x = src[0];
+    if (avail > 1) v.y = src[1];
+    if (avail > 2) v.z = src[2];
+    if (avail > 3) v.w = src[3];
+    return v;
+}
+
 // ---- dense products:  C[m][n] = sum_k A(m, k) B(k, n),  A(m, k) = A[m sam + k sak] ----
 // One wave per 16 x 16 output tile, four waves per workgroup (2 x 2 tiles, or 1 x 4 with wn).
 // With split > 1 the K range is cut in `split` parts written to C + z M ldc (summed by
@@ -101,7 +116,8 @@ __global__ __launch_bounds__(256) void k_dense(int M, int N, int K, const float*
                                                long long sak, const float* __restrict__ Bm, long long sbk,
                                                long long sbn, float* __restrict__ C, int ldc, int split,
                                                const float* __restrict__ bias, float* __restrict__ Z,
-                                               const float* __restrict__ aux, int act, int x3, int wn) {
+                                               const float* __restrict__ aux, int act, int x3, int wn,
+                                               float* __restrict__ bsum = nullptr) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // wn = 0: the four waves take 2 x 2 tiles (32 x 32 per workgroup); wn = 1: four tiles along N
     // (16 x 64 per workgroup), for products with at most 16 rows
@@ -124,8 +140,8 @@ __global__ __launch_bounds__(256) void k_dense(int M, int N, int K, const float*
             acc = mma16(a, b, acc, x3);
         }
     }
-    if (m0 >= M || n0 >= N) return;
     float* Cz = C + (size_t)z * M * ldc;
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int m = m0 + kq + i, n = n0 + (lane & 15);
@@ -144,6 +160,22 @@ __global__ __launch_bounds__(256) void k_dense(int M, int N, int K, const float*
             v *= d;
         }
         Cz[ci] = v;
+        part[i] = v;
+    }
+    if (bsum) {
+        // wn = 1 with one workgroup column (N <= 64): the row sums over the N columns (the bias
+        // gradient of the layer), lanes then waves in a fixed order
+        __shared__ float red[4][16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) part[i] += __shfl_xor(part[i], o, 64);
+        if ((lane & 15) == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[wave][kq + i] = part[i];
+        __syncthreads();
+        if (threadIdx.x < 16 && m0 + (int)threadIdx.x < M)
+            bsum[m0 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
     }
 }
 
@@ -172,13 +204,13 @@ template <int EPI>
 __global__ __launch_bounds__(256) void k_band_t(int N, int w, int bw, int sw, int B, const float* __restrict__ W,
                                                 const float* __restrict__ Ain, float* __restrict__ out,
                                                 const float* __restrict__ bias, float* __restrict__ Z,
-                                                const float* __restrict__ aux, int act, int x3) {
+                                                const float* __restrict__ aux, int act, int x3,
+                                                float* __restrict__ bsum) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c0 = blockIdx.x * 16, n0 = (blockIdx.y * 4 + wave) * 16;
-    if (n0 >= B) return;
     const int cm = c0 + (lane & 15), kq = 4 * (lane >> 4), bn = n0 + (lane & 15);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int kb = -1; kb <= 1; ++kb) {
+    for (int kb = -1; kb <= 1 && n0 < B; ++kb) {
         const int off = kb * bw * sw;
         const int r_lo = max(0, floor_div(c0 - (bw - 1) - off + sw - 1, sw));
         const int r_hi = min(N - 1, floor_div(c0 + 15 - off, sw));
@@ -195,6 +227,7 @@ __global__ __launch_bounds__(256) void k_band_t(int N, int w, int bw, int sw, in
             acc = mma16(a, b, acc, x3);
         }
     }
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int c = c0 + kq + i, n = n0 + (lane & 15);
@@ -213,6 +246,22 @@ __global__ __launch_bounds__(256) void k_band_t(int N, int w, int bw, int sw, in
             v *= d;
         }
         out[ci] = v;
+        part[i] = v;
+    }
+    if (bsum) {
+        // one workgroup row (B <= 64): the sums over the minibatch of the output (the bias
+        // gradient of the layer below), lanes then waves in a fixed order
+        __shared__ float red[4][16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) part[i] += __shfl_xor(part[i], o, 64);
+        if ((lane & 15) == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[wave][kq + i] = part[i];
+        __syncthreads();
+        if (threadIdx.x < 16 && c0 + (int)threadIdx.x < w)
+            bsum[c0 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
     }
 }
 
@@ -325,20 +374,8 @@ __global__ __launch_bounds__(256) void k_band_grad(int N, int w, int bw, int sw,
 
 // The same band-slot gradient with LDS staging: per 64 minibatch columns, the 16 rows of P and
 // the union of their three band windows of Q (columns [r0 s - b s, r0 s + b s + 16 ntile)) are
-// loaded with coalesced 16-byte loads into LDS rows padded to BG_LD floats (16-byte operand
-// reads without bank conflicts); each wave keeps the accumulators of up to 4 column tiles
-// (3 ntile <= 16, i.e. 15 s + b <= 80).
-constexpr int BG_K = 64, BG_LD = BG_K + 4;
-
-__device__ __forceinline__ float4 load_row4(const float* __restrict__ src, int avail, bool vec) {
-    if (vec && avail >= 4) return *reinterpret_cast<const float4*>(src);
-    float4 v = {0.f, 0.f, 0.f, 0.f};
-    if (avail > 0) v.x = src[0];
-    if (avail > 1) v.y = src[1];
-    if (avail > 2) v.z = src[2];
-    if (avail > 3) v.w = src[3];
-    return v;
-}
+// loaded with coalesced 16-byte loads into padded LDS rows; each wave keeps the accumulators of
+// up to 4 column tiles (3 ntile <= 16, i.e. 15 s + b <= 80).
 
 __global__ __launch_bounds__(256) void k_band_grad_lds(int N, int w, int bw, int sw, int B,
                                                        const float* __restrict__ P, const float* __restrict__ Q,
@@ -431,16 +468,12 @@ __global__ void k_loss_final(const double* __restrict__ part, int n, int B, floa
     loss[0] = (float)(s / B);
 }
 
-__global__ void k_ae_tick(int* t) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) t[0] += 1;
-}
-
+// Adam (Section 7.3), step number `step` (1, 2, ...) counted on the host.
 __global__ void k_ae_adam(long long n, float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                          float* __restrict__ v, const int* __restrict__ t, float lr) {
+                          float* __restrict__ v, int step, float lr) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float b1 = 0.9f, b2 = 0.999f;
-    const int step = t[0];
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi, vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -461,10 +494,22 @@ struct ddrom_ae_trainer {
     float *Xb = nullptr, *ze = nullptr, *ae = nullptr, *zd = nullptr, *ad = nullptr, *dY = nullptr, *dzd = nullptr;
     float *dze = nullptr, *xh = nullptr, *dxh = nullptr, *kpart = nullptr;
     double* lpart = nullptr;
-    int* t = nullptr;
+    int step = 0;              // Adam steps taken
     int split = 1;
     int x3 = 0;                // 1: split-BF16 (three products) for FP32-class operands
 };
+
+// Transposed band product (encoder forward: EPI 1; decoder backward: EPI 2), with the bias
+// gradient sum when one workgroup row covers the minibatch.  Returns whether bsum was formed.
+template <int EPI>
+static bool band_t(const ddrom_ae_trainer* t, int B, const float* W, const float* Ain, float* out, const float* bias,
+                   float* Z, const float* aux, float* bsum, hipStream_t s) {
+    const dim3 grid(cdiv(t->w, 16), cdiv(B, 64));
+    float* bs = grid.y == 1 ? bsum : nullptr;
+    hipLaunchKernelGGL(k_band_t<EPI>, grid, dim3(256), 0, s, t->N, t->w, t->bw, t->sw, B, W, Ain, out, bias, Z, aux,
+                       t->act, t->x3, bs);
+    return bs != nullptr;
+}
 
 // Band-slot gradient G = sampled P Q^T: the LDS-staged kernel where its window fits, else the
 // plain one.
@@ -512,7 +557,7 @@ int ddrom_ae_trainer_create(int N, int n, int b, int s, int activation, int max_
         {(void**)&t->zd, w * Bm * 4}, {(void**)&t->ad, w * Bm * 4}, {(void**)&t->dY, N * Bm * 4},
         {(void**)&t->dzd, w * Bm * 4}, {(void**)&t->dze, w * Bm * 4}, {(void**)&t->xh, n * Bm * 4},
         {(void**)&t->dxh, n * Bm * 4}, {(void**)&t->kpart, (size_t)t->split * n * Bm * 4},
-        {(void**)&t->lpart, (size_t)cdiv(N, 16) * cdiv(max_batch, 64) * 8}, {(void**)&t->t, sizeof(int)},
+        {(void**)&t->lpart, (size_t)cdiv(N, 16) * cdiv(max_batch, 64) * 8},
     };
     for (auto& a : allocs)
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -521,7 +566,7 @@ int ddrom_ae_trainer_create(int N, int n, int b, int s, int activation, int max_
             return DDROM_ENOMEM;
         }
     if (hipMemcpy(t->p, params_h, pb, hipMemcpyHostToDevice) != hipSuccess || hipMemset(t->m, 0, pb) != hipSuccess ||
-        hipMemset(t->v, 0, pb) != hipSuccess || hipMemset(t->t, 0, sizeof(int)) != hipSuccess) {
+        hipMemset(t->v, 0, pb) != hipSuccess) {
         set_error("trainer initialisation failed");
         ddrom_ae_trainer_destroy(t.release());
         return DDROM_EHIP;
@@ -533,7 +578,7 @@ int ddrom_ae_trainer_create(int N, int n, int b, int s, int activation, int max_
 void ddrom_ae_trainer_destroy(ddrom_ae_trainer* t) {
     if (!t) return;
     void* ptrs[] = {t->p, t->g, t->m, t->v, t->Xb, t->ze, t->ae, t->zd, t->ad, t->dY, t->dzd, t->dze, t->xh, t->dxh,
-                    t->kpart, t->lpart, t->t};
+                    t->kpart, t->lpart};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete t;
@@ -570,8 +615,7 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
     const dim3 blk(256);
     hipLaunchKernelGGL(k_ae_gather, dim3(cdiv((long long)N * B, 256)), blk, 0, s, X_d, N, rows_d, B, t->Xb);
     // encoder: ze = E1 x~ + b1e, ae = sigma(ze)
-    hipLaunchKernelGGL(k_band_t<1>, dim3(cdiv(w, 16), cdiv(B, 64)), blk, 0, s, N, w, bw, sw, B, P + t->o_w1e, t->Xb,
-                       t->ae, P + t->o_b1e, t->ze, (const float*)nullptr, act, t->x3);
+    band_t<1>(t, B, P + t->o_w1e, t->Xb, t->ae, P + t->o_b1e, t->ze, nullptr, nullptr, s);
     // xh = W2e ae (K = w, split)
     const int wn = n <= 16;
     const dim3 sgrid = wn ? dim3(cdiv(B, 64), cdiv(n, 16), t->split) : dim3(cdiv(B, 32), cdiv(n, 32), t->split);
@@ -592,13 +636,14 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
     // gradients
     band_grad(t, B, t->dY, t->ad, G + t->o_w2d, s);
     // dzd = (D2^T dY) o sigma'(zd)
-    hipLaunchKernelGGL(k_band_t<2>, dim3(cdiv(w, 16), cdiv(B, 64)), blk, 0, s, N, w, bw, sw, B, P + t->o_w2d, t->dY,
-                       t->dzd, (const float*)nullptr, (float*)nullptr, t->zd, act, t->x3);
+    // (with B <= 64 the bias gradient gb1d = sum_b dzd comes from the same kernel)
+    const bool fused_b1d = band_t<2>(t, B, P + t->o_w2d, t->dY, t->dzd, nullptr, nullptr, t->zd,
+                                     B <= 64 ? G + t->o_b1d : nullptr, s);
     // gW1d = dzd xh^T, gb1d = sum_b dzd
     hipLaunchKernelGGL(k_dense<0>, dim3(cdiv(n, 32), cdiv(w, 32), 1), blk, 0, s, w, n, B, t->dzd, (long long)B, 1LL,
                        t->xh, 1LL, (long long)B, G + t->o_w1d, n, 1, (const float*)nullptr, (float*)nullptr,
                        (const float*)nullptr, act, t->x3, 0);
-    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 4)), blk, 0, s, t->dzd, w, B, G + t->o_b1d);
+    if (!fused_b1d) hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 4)), blk, 0, s, t->dzd, w, B, G + t->o_b1d);
     // dxh = W1d^T dzd (K = w, split)
     hipLaunchKernelGGL(k_dense<0>, sgrid, blk, 0, s, n, B, w, P + t->o_w1d, 1LL, (long long)n, t->dzd, (long long)B,
                        1LL, t->kpart, B, t->split, (const float*)nullptr, (float*)nullptr, (const float*)nullptr, act,
@@ -610,16 +655,24 @@ int ae_train_step(ddrom_ae_trainer* t, const float* X_d, const int* rows_d, int 
                        t->ae, 1LL, (long long)B, G + t->o_w2e, w, 1, (const float*)nullptr, (float*)nullptr,
                        (const float*)nullptr, act, t->x3, 0);
     // dze = (W2e^T dxh) o sigma'(ze)
-    hipLaunchKernelGGL(k_dense<2>, dim3(cdiv(B, 32), cdiv(w, 32), 1), blk, 0, s, w, B, n, P + t->o_w2e, 1LL,
-                       (long long)w, t->dxh, (long long)B, 1LL, t->dze, B, 1, (const float*)nullptr, (float*)nullptr,
-                       t->ze, act, t->x3, 0);
+    // (with B <= 64, one workgroup column of 16 x 64 tiles, which also sums gb1e = sum_b dze)
+    const bool fused_b1e = B <= 64;
+    if (fused_b1e)
+        hipLaunchKernelGGL(k_dense<2>, dim3(1, cdiv(w, 16), 1), blk, 0, s, w, B, n, P + t->o_w2e, 1LL, (long long)w,
+                           t->dxh, (long long)B, 1LL, t->dze, B, 1, (const float*)nullptr, (float*)nullptr, t->ze, act,
+                           t->x3, 1, G + t->o_b1e);
+    else
+        hipLaunchKernelGGL(k_dense<2>, dim3(cdiv(B, 32), cdiv(w, 32), 1), blk, 0, s, w, B, n, P + t->o_w2e, 1LL,
+                           (long long)w, t->dxh, (long long)B, 1LL, t->dze, B, 1, (const float*)nullptr,
+                           (float*)nullptr, t->ze, act, t->x3, 0, (float*)nullptr);
     // gW1e[r][k][t] = sum_b x~[r][b] dze[c][b], gb1e = sum_b dze
     band_grad(t, B, t->Xb, t->dze, G + t->o_w1e, s);
-    hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 4)), blk, 0, s, t->dze, w, B, G + t->o_b1e);
+    if (!fused_b1e) hipLaunchKernelGGL(k_rowsum, dim3(cdiv(w, 4)), blk, 0, s, t->dze, w, B, G + t->o_b1e);
     if (grad_d) AECHECK(hipMemcpyAsync(grad_d, G, (size_t)t->n_params * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (update) {
-        hipLaunchKernelGGL(k_ae_tick, dim3(1), dim3(1), 0, s, t->t);
-        hipLaunchKernelGGL(k_ae_adam, dim3(cdiv(t->n_params, 256)), blk, 0, s, t->n_params, P, G, t->m, t->v, t->t, lr);
+        t->step += 1;
+        hipLaunchKernelGGL(k_ae_adam, dim3(cdiv(t->n_params, 256)), blk, 0, s, t->n_params, P, G, t->m, t->v,
+                           t->step, lr);
     }
     AECHECK(hipGetLastError());
     return 0;
