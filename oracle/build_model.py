@@ -212,7 +212,10 @@ def per_subdomain_choices(cfg: dict, n_sub: int):
         n_om = [int(cfg["n_om"])] * n_sub
     n_ga = [v // 2 for v in n_om] if cfg["n_ga"] == "half" else [int(cfg["n_ga"])] * n_sub
     hf = cfg["hr_frac"]
-    hr = list(g.uniform(hf[0], hf[1], size=n_sub)) if isinstance(hf, tuple) else [float(hf)] * n_sub
+    if hf is None:          # a fixed node count per subdomain (hr_count) instead
+        hr = [None] * n_sub
+    else:
+        hr = list(g.uniform(hf[0], hf[1], size=n_sub)) if isinstance(hf, tuple) else [float(hf)] * n_sub
     return n_om, n_ga, hr
 
 
