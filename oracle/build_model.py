@@ -347,10 +347,14 @@ def build(name: str, workers: int = 8, verbose=True, base: dict | None = None, t
                 pack[f"{part}{i}_Phi"] = Phi
                 pack[f"{part}{i}_x0"] = x0
             if cfg.get("gappy"):
-                # columns: the r_u rows of the sampled nodes (ascending), then their r_v rows
-                Phi_r = pod_basis(Rsnap[:, sd.res_rows].T, 1e-10)
+                # columns: the r_u rows of the sampled nodes (ascending), then their r_v rows; the
+                # basis keeps at least n_i^Omega + n_i^Gamma modes (fewer leave H_i singular) and
+                # at most the number of sampled rows
+                Ri = Rsnap[:, sd.res_rows].T
                 nodes = np.sort(np.asarray(hr_nodes[i], dtype=np.int64))
-                Phi_r = Phi_r[:, :min(Phi_r.shape[1], 2 * len(nodes))]
+                k = max(pod_basis(Ri, 1e-10).shape[1], n_om[i] + n_ga[i])
+                U = np.linalg.svd(Ri, full_matrices=False)[0]
+                Phi_r = U[:, :min(k, 2 * len(nodes), U.shape[1])]
                 pack[f"gp{i}_P"] = gappy_pod_operator(g, nodes, sd.res_rows, Phi_r).P
     if pc is not None:
         pack["srpc"] = np.int64(1)

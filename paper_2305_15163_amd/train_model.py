@@ -87,8 +87,8 @@ def _job(args):
     from paper_2305_15163_amd.train_ae import train_ae
     import seeded_inputs as si
     idx = np.load(stem + "_X_dd.npz")[f"{tag}{i}"]
-    Xall = np.load(stem + "_X.npy", mmap_mode="r")
-    X = np.ascontiguousarray(Xall[:, idx])
+    Xall = np.load(stem + "_X.npy", mmap_mode="r")           # FP64, or FP32 to move less data
+    X = np.ascontiguousarray(Xall[:, idx], dtype=np.float64)
     t0 = time.time()
     res = train_ae(X, n, b, s, act, seed, epochs, batch=batch, precision=precision)
     dt = time.time() - t0
