@@ -149,7 +149,7 @@ def _state_job(args):
     return k, res.x, res.converged
 
 
-def snapshot_matrix(name: str, out: str, workers: int = 8, verbose=True):
+def snapshot_matrix(name: str, out: str, workers: int = 8, verbose=True, train_grid=None):
     """The configuration's FOM snapshots [n_snap][N_x] (FP64, a-fastest parameter grid) written
     row by row into an .npy file as the solves finish; the subdomains' interior and interface
     index lists go beside it (<out stem>_dd.npz).  A partly written file is resumed: rows whose
@@ -157,7 +157,7 @@ def snapshot_matrix(name: str, out: str, workers: int = 8, verbose=True):
     cfg = CONFIGS[name]
     g = Grid(cfg["nx"], cfg["ny"])
     dd = build_dd(g, cfg["nsx"], cfg["nsy"])
-    mus = si.training_grid(*cfg["train_grid"], lam_range=cfg.get("lam_range", si.LAM_RANGE))
+    mus = si.training_grid(*(train_grid or cfg["train_grid"]), lam_range=cfg.get("lam_range", si.LAM_RANGE))
     n_x = 2 * g.nx * g.ny
     if os.path.exists(out):
         X = np.load(out, mmap_mode="r+")
@@ -377,10 +377,35 @@ def main(argv=None):
     ap.add_argument("--skeleton", default=None, help="path stem: write <stem>_skel.npz (the pack without decoders, "
                                                      "with the training recipe), <stem>_X.npy (the state snapshots, "
                                                      "FP64) and <stem>_X_dd.npz (parameters, subdomain index lists)")
+    ap.add_argument("--train-grid", type=int, nargs=2, default=None, help="parameter grid of --snapshots "
+                                                                         "(default: the configuration's)")
     ap.add_argument("--slice", default=None, help="with --out: from the snapshot matrix <stem>.npy of --snapshots, "
                                                   "write the largest interior subdomain's interior and interface "
                                                   "snapshots (FP32) and their training seeds")
+    ap.add_argument("--reskeleton", default=None, help="with --out: a trained pack of this configuration whose grid, "
+                                                       "split, latent sizes, HR nodes and C are kept, written as a "
+                                                       "skeleton <out>_skel.npz (decoders dropped, training recipe: "
+                                                       "2000 epochs at most, minibatch 32) with the split's index "
+                                                       "lists <out>_X_dd.npz")
     a = ap.parse_args(argv)
+    if a.reskeleton:
+        cfg = CONFIGS[a.config]
+        old_pack = dict(np.load(a.reskeleton, allow_pickle=False))
+        n_sub = int(old_pack["n_sub"])
+        keep = {k: v for k, v in old_pack.items() if not k.startswith(("om", "ga", "pt"))}
+        keep.update(train_n_om=np.array([np.asarray(old_pack[f"om{i}_W1"]).shape[1] for i in range(n_sub)]),
+                    train_n_ga=np.array([np.asarray(old_pack[f"ga{i}_W1"]).shape[1] for i in range(n_sub)]),
+                    train_bs=np.array([cfg["b"], cfg["s"]]), train_epochs=np.int64(2000), train_batch=np.int64(32),
+                    train_seed=np.int64(cfg["seed"]))
+        np.savez(a.out + "_skel.npz", **keep)
+        dd = build_dd(Grid(int(keep["nx"]), int(keep["ny"])), int(keep["nsx"]), int(keep["nsy"]))
+        idx = {}
+        for i, sd in enumerate(dd.subdomains):
+            idx[f"om{i}"] = np.asarray(sd.omega, dtype=np.int64)
+            idx[f"ga{i}"] = np.asarray(sd.gamma, dtype=np.int64)
+        np.savez(a.out + "_X_dd.npz", **idx)
+        print("wrote", a.out + "_skel.npz", flush=True)
+        return 0
     if a.slice:
         cfg = CONFIGS[a.config]
         idx = np.load(a.slice + "_dd.npz")
@@ -396,7 +421,7 @@ def main(argv=None):
         print("wrote", a.out, "subdomain", k, flush=True)
         return 0
     if a.snapshots:
-        snapshot_matrix(a.config, a.snapshots, a.workers)
+        snapshot_matrix(a.config, a.snapshots, a.workers, train_grid=a.train_grid)
         return 0
     if a.skeleton:
         pack, X, mus, _ = build(a.config, a.workers, train=False)

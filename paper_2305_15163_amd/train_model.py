@@ -82,12 +82,12 @@ def _job(args):
     """One autoencoder, in its own process: train on the GPU, export, and measure the relative
     reconstruction error on the held-out snapshots (host FP64 evaluation of the trained
     weights)."""
-    stem, tag, i, n, b, s, act, seed, epochs, batch, precision = args
+    stem, xpath, tag, i, n, b, s, act, seed, epochs, batch, precision = args
     import torch  # noqa: F401  (initialises the device in this process)
     from paper_2305_15163_amd.train_ae import train_ae
     import seeded_inputs as si
     idx = np.load(stem + "_X_dd.npz")[f"{tag}{i}"]
-    Xall = np.load(stem + "_X.npy", mmap_mode="r")           # FP64, or FP32 to move less data
+    Xall = np.load(xpath, mmap_mode="r")                      # FP64, or FP32 to move less data
     X = np.ascontiguousarray(Xall[:, idx], dtype=np.float64)
     t0 = time.time()
     res = train_ae(X, n, b, s, act, seed, epochs, batch=batch, precision=precision)
@@ -110,8 +110,11 @@ def _job(args):
     return tag, i, dec, rep
 
 
-def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision: int = 0, verbose: bool = True):
+def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision: int = 0, verbose: bool = True,
+                snapshots: str | None = None):
+    """snapshots: the state snapshot matrix (default <stem>_X.npy)."""
     skel = dict(np.load(stem + "_skel.npz", allow_pickle=False))
+    xpath = snapshots or stem + "_X.npy"
     n_sub = int(skel["n_sub"])
     b, s = (int(v) for v in skel["train_bs"])
     act = int(skel["act"])
@@ -122,9 +125,11 @@ def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision:
     jobs = []
     idx = np.load(stem + "_X_dd.npz")
     for i in range(n_sub):
-        jobs.append((stem, "om", i, int(skel["train_n_om"][i]), b, s, act, seeds[2 * i], ep, batch, precision))
-        jobs.append((stem, "ga", i, int(skel["train_n_ga"][i]), b, s, act, seeds[2 * i + 1], ep, batch, precision))
-    jobs.sort(key=lambda j: -len(idx[f"{j[1]}{j[2]}"]))     # largest first
+        jobs.append((stem, xpath, "om", i, int(skel["train_n_om"][i]), b, s, act, seeds[2 * i], ep, batch,
+                     precision))
+        jobs.append((stem, xpath, "ga", i, int(skel["train_n_ga"][i]), b, s, act, seeds[2 * i + 1], ep, batch,
+                     precision))
+    jobs.sort(key=lambda j: -len(idx[f"{j[2]}{j[3]}"]))     # largest first
     t0 = time.time()
     if procs > 1:
         import multiprocessing as mp
@@ -157,8 +162,9 @@ def main(argv=None):
     ap.add_argument("--procs", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=None, help="override the recipe's epoch count")
     ap.add_argument("--precision", type=int, default=0, help="0: BF16 operands, 1: split-BF16")
+    ap.add_argument("--snapshots", default=None, help="state snapshot matrix (default <stem>_X.npy)")
     a = ap.parse_args(argv)
-    pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision)
+    pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision, snapshots=a.snapshots)
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     np.savez(a.out, **pack)
     with open(os.path.splitext(a.out)[0] + "_train.json", "w") as f:
