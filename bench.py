@@ -498,6 +498,7 @@ def main():
     ap.add_argument("--no-ae", action="store_true", help="skip the autoencoder training leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-scale leg")
     ap.add_argument("--paper-only", action="store_true", help="run only the paper-scale leg")
+    ap.add_argument("--ae-only", action="store_true", help="run only the autoencoder training leg")
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the dominant kernel's timing launches and a device copy of known size "
                          "(the workload of the hardware-counter runs)")
@@ -513,6 +514,11 @@ def main():
 
     if a.roofline_only:
         roofline_only(a, torch, dr, si)
+        return
+
+    if a.ae_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"ae_training": ae_training_leg(a, torch, dr, si)}), flush=True)
         return
 
     if a.paper_only:

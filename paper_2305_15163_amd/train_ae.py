@@ -53,7 +53,7 @@ def glorot_init(N: int, n: int, b: int, s: int, seed: int) -> np.ndarray:
 
 def train_ae(X: np.ndarray, n: int, b: int, s: int, activation: int, seed: int, epochs: int, batch: int = 32,
              lr: float = 1e-3, test_frac: float = 0.1, plateau_patience: int = 50, stop_patience: int = 300,
-             init: np.ndarray | None = None, precision: int = 0, verbose: bool = False) -> AEResult:
+             init: np.ndarray | None = None, precision: int = 0, verbose: bool = False, tag: str = "") -> AEResult:
     """X: raw snapshots [n_snap][N].  `init` (packed) replaces the seeded Glorot draw;
     precision 0: BF16 operands, 1: split-BF16 (three products per tile)."""
     g = si.rng(seed)
@@ -108,5 +108,5 @@ def train_ae(X: np.ndarray, n: int, b: int, s: int, activation: int, seed: int, 
             if since_best > stop_patience:
                 break
         if verbose and ep % 50 == 0:
-            print(f"  epoch {ep}: train {tr_loss:.3e} test {te_loss:.3e} lr {cur_lr:.1e}", flush=True)
+            print(f"  {tag} epoch {ep}: train {tr_loss:.3e} test {te_loss:.3e} lr {cur_lr:.1e}", flush=True)
     return AEResult((best_p if best_p is not None else tr.params()).cpu().numpy(), mid, sc, ep, best, hist)

@@ -90,7 +90,7 @@ def _job(args):
     Xall = np.load(xpath, mmap_mode="r")                      # FP64, or FP32 to move less data
     X = np.ascontiguousarray(Xall[:, idx], dtype=np.float64)
     t0 = time.time()
-    res = train_ae(X, n, b, s, act, seed, epochs, batch=batch, precision=precision)
+    res = train_ae(X, n, b, s, act, seed, epochs, batch=batch, precision=precision, verbose=True, tag=f"{tag}{i}")
     dt = time.time() - t0
     N = X.shape[1]
     wts = unpack_weights(res.packed, N, n, b, s)
@@ -111,8 +111,9 @@ def _job(args):
 
 
 def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision: int = 0, verbose: bool = True,
-                snapshots: str | None = None):
-    """snapshots: the state snapshot matrix (default <stem>_X.npy)."""
+                snapshots: str | None = None, only=None):
+    """snapshots: the state snapshot matrix (default <stem>_X.npy).  only: the autoencoders to
+    train (tags such as "om0", "ga3"); the pack then holds only their decoders (see merge)."""
     skel = dict(np.load(stem + "_skel.npz", allow_pickle=False))
     xpath = snapshots or stem + "_X.npy"
     n_sub = int(skel["n_sub"])
@@ -129,6 +130,8 @@ def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision:
                      precision))
         jobs.append((stem, xpath, "ga", i, int(skel["train_n_ga"][i]), b, s, act, seeds[2 * i + 1], ep, batch,
                      precision))
+    if only:
+        jobs = [j for j in jobs if f"{j[2]}{j[3]}" in set(only)]
     jobs.sort(key=lambda j: -len(idx[f"{j[2]}{j[3]}"]))     # largest first
     t0 = time.time()
     if procs > 1:
@@ -155,16 +158,33 @@ def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision:
     return pack, reports, time.time() - t0
 
 
+def merge(paths, out):
+    """One pack from packs that each hold some subdomains' trained decoders (the rest equal)."""
+    pack = {}
+    for p in paths:
+        for k, v in np.load(p, allow_pickle=False).items():
+            pack.setdefault(k, v)
+    np.savez(out, **pack)
+    return pack
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("stem")
+    ap.add_argument("--merge", nargs="+", default=None, help="packs to merge into --out (no training)")
+    ap.add_argument("--only", default=None, help="comma-separated autoencoders to train (e.g. om0,ga0)")
+    ap.add_argument("stem", nargs="?")
     ap.add_argument("--out", required=True)
     ap.add_argument("--procs", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=None, help="override the recipe's epoch count")
     ap.add_argument("--precision", type=int, default=0, help="0: BF16 operands, 1: split-BF16")
     ap.add_argument("--snapshots", default=None, help="state snapshot matrix (default <stem>_X.npy)")
     a = ap.parse_args(argv)
-    pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision, snapshots=a.snapshots)
+    if a.merge:
+        merge(a.merge, a.out)
+        print(f"[train_model] merged {len(a.merge)} packs into {a.out}", flush=True)
+        return 0
+    pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision, snapshots=a.snapshots,
+                                    only=a.only.split(",") if a.only else None)
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     np.savez(a.out, **pack)
     with open(os.path.splitext(a.out)[0] + "_train.json", "w") as f:
