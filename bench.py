@@ -267,7 +267,7 @@ def cfg3_training(torch, dr):
 
 
 PAPER = dict(pack="paper_gpu.npz", ref="paper", batch=512, seed=7, lam_range=(5.0, 25.0),
-             workload="the paper's own workload (Sections 7.1-7.4): Burgers 480x24 on [-1,1]x[0,0.05], 2x2 "
+             workload="the paper's own workload (Sections 7.1-7.3, 7.6): Burgers 480x24 on [-1,1]x[0,0.05], 2x2 "
                       "subdomains, latents (8,4), Swish, band-5 shift-5 masks, 100 HR nodes per subdomain, "
                       "autoencoders trained on the GPU (6400 snapshots, 80x80 grid, 2000 epochs at most)")
 

@@ -98,7 +98,7 @@ CONFIGS = {
                     epochs=0, batch=32, train_grid=(16, 16), hr_frac=0.10, seed=1),
     "cfg0lsg": dict(nx=36, ny=36, nsx=2, nsy=2, n_om=6, n_ga=3, b=5, s=3, act=ACT_SIGMOID, ls=True, gappy=True,
                     epochs=0, batch=4, train_grid=(5, 5), hr_frac=0.20, seed=0),
-    # the paper's own workload (Sections 7.1-7.4): 480 x 24 grid on [-1, 1] x [0, 0.05], 2 x 2
+    # the paper's own workload (Sections 7.1-7.3, 7.6): 480 x 24 grid on [-1, 1] x [0, 0.05], 2 x 2
     # split, latents (8, 4), Swish, three-band masks of 5 entries shifted by 5, 6400 snapshots on
     # an 80 x 80 parameter grid (10% held out), 2000 epochs at minibatch 32, residual POD from
     # the Newton histories of the 400 solves of a 20 x 20 grid, 100 HR nodes per subdomain.  Built

@@ -236,7 +236,8 @@ struct ddrom_workspace {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, t0 = nullptr, t1 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_ga = nullptr, ev_con = nullptr;
     // cached graph of solver rounds
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph = nullptr;         // kGraphRounds solver rounds
+    hipGraphExec_t graph_tail = nullptr;    // kTailRounds solver rounds, once few solves still run
     std::string graph_key;
 };
 

@@ -2500,6 +2500,7 @@ void ddrom_workspace_destroy(ddrom_workspace* w) {
     if (w->kkt_scr) (void)hipFree(w->kkt_scr);
     if (w->err_part) (void)hipFree(w->err_part);
     if (w->graph) (void)hipGraphExecDestroy(w->graph);
+    if (w->graph_tail) (void)hipGraphExecDestroy(w->graph_tail);
     if (w->ev_in) (void)hipEventDestroy(w->ev_in);
     if (w->ev_out) (void)hipEventDestroy(w->ev_out);
     if (w->t0) (void)hipEventDestroy(w->t0);
@@ -2685,8 +2686,12 @@ struct FinalOut {
 };
 
 // prop != nullptr: warm start from the network's proposal, the zero start as fallback.
-// Rounds captured per graph launch; the host checks the live count between launches.
+// Rounds captured per graph launch; the host checks the live count between launches.  Once at
+// most kTailLive solves still run, graphs of kTailRounds rounds are launched instead, so that
+// few rounds run after the last solve stops.
 constexpr int kGraphRounds = 8;
+constexpr int kTailRounds = 2;
+constexpr int kTailLive = 64;
 
 // Upper bound on solver rounds: the first evaluation, max_iter steps of at most max_backtracks + 1
 // trial evaluations each, one more, and the two extra evaluations of a warm start.
@@ -2706,28 +2711,33 @@ static int solver_graph(const ddrom_model* m, ddrom_workspace* ws, int B, const 
     key << B << ":" << prec << ":" << o->max_iter << ":" << o->tol_abs << ":" << o->tol_rel << ":" << o->armijo_c1
         << ":" << o->max_backtracks << ":" << o->stall_tol << ":" << o->stall_ratio << ":" << lam_given << ":"
         << warm;
-    if (ws->graph && ws->graph_key == key.str()) return 0;
-    if (ws->graph) {
-        (void)hipGraphExecDestroy(ws->graph);
-        ws->graph = nullptr;
-    }
+    if (ws->graph && ws->graph_tail && ws->graph_key == key.str()) return 0;
+    for (hipGraphExec_t* ge : {&ws->graph, &ws->graph_tail})
+        if (*ge) {
+            (void)hipGraphExecDestroy(*ge);
+            *ge = nullptr;
+        }
     hipStream_t s = ws->stream;
-    hipGraph_t g;
-    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int crc = 0;
-    for (int k = 0; k < kGraphRounds && !crc; ++k) crc = round_launch(m, ws, prec, B, ua, s);
-    hipError_t ce = hipStreamEndCapture(s, &g);
-    if (crc) return crc;
-    if (ce != hipSuccess) {
-        set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
-        return DDROM_EHIP;
-    }
-    hipError_t ie = hipGraphInstantiate(&ws->graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) {
-        ws->graph = nullptr;
-        set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
-        return DDROM_EHIP;
+    for (int which = 0; which < 2; ++which) {
+        const int rounds = which == 0 ? kGraphRounds : kTailRounds;
+        hipGraphExec_t* ge = which == 0 ? &ws->graph : &ws->graph_tail;
+        hipGraph_t g;
+        HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int crc = 0;
+        for (int k = 0; k < rounds && !crc; ++k) crc = round_launch(m, ws, prec, B, ua, s);
+        hipError_t ce = hipStreamEndCapture(s, &g);
+        if (crc) return crc;
+        if (ce != hipSuccess) {
+            set_error(std::string("graph capture failed: ") + hipGetErrorString(ce));
+            return DDROM_EHIP;
+        }
+        hipError_t ie = hipGraphInstantiate(ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            *ge = nullptr;
+            set_error(std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+            return DDROM_EHIP;
+        }
     }
     ws->graph_key = key.str();
     return 0;
@@ -2770,12 +2780,15 @@ static int solve_common(const ddrom_model* m, ddrom_workspace* ws, const double*
     long long done = 0;
     if (use_graph) {
         if ((rc = solver_graph(m, ws, B, o, ua, l0 != nullptr, warm))) return rc;
+        int live = B;
         while (done < max_rounds) {
-            HIPCHECK(hipGraphLaunch(ws->graph, s));
-            done += kGraphRounds;
+            const bool tail = live <= kTailLive;
+            HIPCHECK(hipGraphLaunch(tail ? ws->graph_tail : ws->graph, s));
+            done += tail ? kTailRounds : kGraphRounds;
             HIPCHECK(hipMemcpyAsync(ws->counter_h, ws->counter, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
-            if (*ws->counter_h == 0) break;
+            live = *ws->counter_h;
+            if (live == 0) break;
         }
     } else {
         while (done < max_rounds) {

@@ -12,6 +12,8 @@ training snapshot (b1 <- b1 + W1 m, which leaves the trial manifold unchanged).
 
 Usage:  python -m paper_2305_15163_amd.train_model <stem> --out models/<name>.npz [--procs 8]
         (<stem>_skel.npz, <stem>_X.npy, <stem>_X_dd.npz)
+        In parts: --only om0,ga0,... --subset-to <stem2> (write those autoencoders' columns), then
+        train <stem2> --only ... --out part.npz on each part, then --merge part*.npz --out pack.npz.
 """
 from __future__ import annotations
 
@@ -168,12 +170,30 @@ def merge(paths, out):
     return pack
 
 
+def subset_data(stem: str, tags, out_stem: str, snapshots: str | None = None):
+    """The snapshot columns the autoencoders `tags` read (FP32) with their index lists renumbered,
+    and the skeleton, under out_stem: training data for `train_model --only` that is smaller than
+    the whole matrix (for moving it to another machine)."""
+    import shutil
+    idx = np.load(stem + "_X_dd.npz")
+    X = np.load(snapshots or stem + "_X.npy", mmap_mode="r")
+    cols = np.unique(np.concatenate([idx[t] for t in tags]))
+    pos = np.full(X.shape[1], -1, dtype=np.int64)
+    pos[cols] = np.arange(len(cols))
+    np.save(out_stem + "_X.npy", np.asarray(X[:, cols], dtype=np.float32))
+    np.savez(out_stem + "_X_dd.npz", **{t: pos[idx[t]] for t in tags})
+    shutil.copy(stem + "_skel.npz", out_stem + "_skel.npz")
+    return len(cols)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--merge", nargs="+", default=None, help="packs to merge into --out (no training)")
+    ap.add_argument("--subset-to", default=None, help="with --only: write the columns those autoencoders read "
+                                                      "(and the skeleton) under this stem; no training")
     ap.add_argument("--only", default=None, help="comma-separated autoencoders to train (e.g. om0,ga0)")
     ap.add_argument("stem", nargs="?")
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default=None)
     ap.add_argument("--procs", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=None, help="override the recipe's epoch count")
     ap.add_argument("--precision", type=int, default=0, help="0: BF16 operands, 1: split-BF16")
@@ -182,6 +202,10 @@ def main(argv=None):
     if a.merge:
         merge(a.merge, a.out)
         print(f"[train_model] merged {len(a.merge)} packs into {a.out}", flush=True)
+        return 0
+    if a.subset_to:
+        n = subset_data(a.stem, a.only.split(","), a.subset_to, a.snapshots)
+        print(f"[train_model] wrote {n} columns under {a.subset_to}", flush=True)
         return 0
     pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision, snapshots=a.snapshots,
                                     only=a.only.split(",") if a.only else None)
