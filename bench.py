@@ -267,6 +267,10 @@ def cfg3_training(torch, dr):
 
 
 PAPER = dict(pack="paper_gpu.npz", ref="paper", batch=512, seed=7, lam_range=(5.0, 25.0),
+             # latent sizes, GPU-trained pack, the paper's error at mu* (Section 7.6 table)
+             sweep=((4, 2, "paper_gpu_L4.npz", 7.04e-3), (6, 3, "paper_gpu_L6.npz", 2.60e-3),
+                    (8, 4, "paper_gpu.npz", 1.64e-3), (10, 5, "paper_gpu_L10.npz", 1.19e-3),
+                    (16, 8, "paper_gpu_L16.npz", 9.80e-4)),
              workload="the paper's own workload (Sections 7.1-7.3, 7.6): Burgers 480x24 on [-1,1]x[0,0.05], 2x2 "
                       "subdomains, latents (8,4), Swish, band-5 shift-5 masks, 100 HR nodes per subdomain, "
                       "autoencoders trained on the GPU (6400 snapshots, 80x80 grid, 2000 epochs at most)")
@@ -326,6 +330,28 @@ def paper_leg(a, torch, dr, si):
         print(f"[bench] paper-scale ({tag}): {leg['batched']['solves_per_s']:.0f} solves/s, mu* error "
               f"{leg['mu_star'].get('rel_err_vs_fom', float('nan')):.3e}", file=sys.stderr, flush=True)
     out["paper_reported_rel_err_mu_star"] = 1.64e-3
+    # the latent sweep of the paper's Section 7.6 table, where its GPU-trained packs exist
+    sweep = []
+    for (n_om, n_ga, fname, paper_err) in PAPER["sweep"]:
+        spath = os.path.join(ROOT, "models", fname)
+        if not os.path.exists(spath):
+            continue
+        sm = dr.Model(dict(np.load(spath, allow_pickle=False)))
+        sws1, sws64 = dr.Workspace(sm, 1), dr.Workspace(sm, 64)
+        row = {"latents": [n_om, n_ga], "pack": fname, "paper_rel_err_mu_star": paper_err}
+        rs = dr.rom_solve_batch(sm, sws1, torch.as_tensor(star, device="cuda"), rules["paper_f64"])
+        if X_star is not None:
+            row["rel_err_mu_star"] = float(dr.relative_error(sm, sws1, rs["xhat"],
+                                                             torch.as_tensor(X_star, device="cuda")).cpu()[0])
+        row["mu_star_status"] = dr.STATUS[int(rs["status"][0])]
+        if X_held is not None:
+            r64 = dr.rom_solve_batch(sm, sws64, mu[:64], rules["batch_rule_f32"])
+            e = dr.relative_error(sm, sws64, r64["xhat"], torch.as_tensor(X_held, device="cuda")).cpu().numpy()
+            row["rel_err_vs_fom_64"] = error_summary(e, r64["status"].cpu().numpy(), dr)
+        sweep.append(row)
+        print(f"[bench] paper-scale latents ({n_om},{n_ga}): mu* error {row.get('rel_err_mu_star', float('nan')):.3e} "
+              f"(paper {paper_err:.2e})", file=sys.stderr, flush=True)
+    out["latent_sweep"] = sweep
     return out
 
 

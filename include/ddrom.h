@@ -142,7 +142,12 @@ const char* ddrom_last_error(void);
 /* Build the device model: DD maps (Section 2), ports and A_i, C A_i, the interior
  * decoder subnets of eq. subnet for the HR-sampled stencils (Section 5.4), full interface
  * decoders (Section 5.3: the weak constraint needs every interface row), stencil gather
- * tables and the boundary points touched by sampled stencils.  Synchronous. */
+ * tables and the boundary points touched by sampled stencils.  Synchronous.
+ * Supported latent sizes: each decoder's n in {2, 3, 4, 5, 6, 8, 10, 12, 16}; per subdomain
+ * (n_i^Omega, n_i^Gamma) among the residual kernel's classes (2,1), (3,2), (4,2), (4,4), (6,3),
+ * (8,4), (10,5), (12,6), (16,8) and (4|6|8, 0), with n_i^Omega + n_i^Gamma <= 20 and
+ * n_i^Gamma <= 12, or <= 24 with n_i^Gamma <= 8.  Other sizes return DDROM_EINVAL (at creation
+ * or at the first launch that needs them). */
 int ddrom_model_create(const ddrom_model_desc* desc, ddrom_model** out);
 void ddrom_model_destroy(ddrom_model* m);
 

@@ -111,6 +111,11 @@ CONFIGS = {
     # shifted by 5 (a row's bands span 55 hidden units), latents (8, 4)
     "tinywide": dict(nx=40, ny=8, nsx=2, nsy=2, n_om=8, n_ga=4, b=5, s=5, act=ACT_SWISH,
                      epochs=100, batch=4, train_grid=(4, 4), hr_frac=0.5, seed=12),
+    # the largest latents of the paper's sweep, (10, 5) and (16, 8), on the same small grid
+    "tinyl10": dict(nx=40, ny=8, nsx=2, nsy=2, n_om=10, n_ga=5, b=5, s=5, act=ACT_SWISH,
+                    epochs=100, batch=4, train_grid=(5, 5), hr_frac=0.6, seed=13),
+    "tinyl16": dict(nx=40, ny=8, nsx=2, nsy=2, n_om=16, n_ga=8, b=5, s=5, act=ACT_SWISH,
+                    epochs=100, batch=4, train_grid=(6, 6), hr_frac=0.7, seed=14),
     "tinymix": dict(nx=16, ny=12, nsx=2, nsy=2, n_om="draw", n_ga="half", b=3, s=2, act=ACT_SIGMOID,
                     epochs=300, batch=4, train_grid=(4, 4), hr_frac=(0.3, 0.6), seed=31),
     "tinybig": dict(nx=48, ny=48, nsx=8, nsy=8, n_om=6, n_ga=3, b=3, s=2, act=ACT_SIGMOID,
@@ -387,7 +392,23 @@ def main(argv=None):
                                                        "skeleton <out>_skel.npz (decoders dropped, training recipe: "
                                                        "2000 epochs at most, minibatch 32) with the split's index "
                                                        "lists <out>_X_dd.npz")
+    ap.add_argument("--relatent", default=None, help="with --out and --latents: a skeleton of this configuration "
+                                                     "with other latent sizes (the test matrix C drawn again for "
+                                                     "the new n_C; grid, split and HR nodes kept)")
+    ap.add_argument("--latents", type=int, nargs=2, default=None, help="n^Omega n^Gamma for --relatent")
     a = ap.parse_args(argv)
+    if a.relatent:
+        cfg = CONFIGS[a.config]
+        sk = dict(np.load(a.relatent, allow_pickle=False))
+        n_sub = int(sk["n_sub"])
+        n_om, n_ga = a.latents
+        n_C = n_sub * n_ga // 2
+        seeds = si.spawn_seeds(cfg["seed"], 2 * n_sub + 1)
+        sk.update(train_n_om=np.full(n_sub, n_om, dtype=np.int64), train_n_ga=np.full(n_sub, n_ga, dtype=np.int64),
+                  C=si.gaussian_matrix(n_C, np.asarray(sk["C"]).shape[1], seeds[-1]))
+        np.savez(a.out + "_skel.npz", **sk)
+        print("wrote", a.out + "_skel.npz", "n_C", n_C, flush=True)
+        return 0
     if a.reskeleton:
         cfg = CONFIGS[a.config]
         old_pack = dict(np.load(a.reskeleton, allow_pickle=False))

@@ -1999,7 +1999,8 @@ static int launch_decode_items(const ddrom_model* m, int prec, int act, int c0, 
         else { DEC_ACT(NLV, DDROM_ACT_IDENTITY) }                                                                 \
         break;
     switch (n) {
-        DEC_CASE(2) DEC_CASE(3) DEC_CASE(4) DEC_CASE(6) DEC_CASE(8) DEC_CASE(12)
+        DEC_CASE(2) DEC_CASE(3) DEC_CASE(4) DEC_CASE(5) DEC_CASE(6) DEC_CASE(8) DEC_CASE(10) DEC_CASE(12)
+        DEC_CASE(16)
         default:
             set_error("unsupported latent size " + std::to_string(n));
             return DDROM_EINVAL;
@@ -2056,6 +2057,7 @@ static int launch_res_item(const ddrom_model* m, int prec, const ddrom_model::Re
         return 0;                                                                                                 \
     }
     RES_CASE(2, 1) RES_CASE(3, 2) RES_CASE(4, 2) RES_CASE(4, 4) RES_CASE(6, 3) RES_CASE(8, 4) RES_CASE(12, 6) RES_CASE(4, 0)
+    RES_CASE(10, 5) RES_CASE(16, 8)
     RES_CASE(6, 0) RES_CASE(8, 0)
 #undef RES_CASE
     set_error("unsupported latent sizes (" + std::to_string(rs.n_om) + ", " + std::to_string(rs.n_ga) + ")");
@@ -2163,7 +2165,7 @@ static int launch_con(const ddrom_model* m, int prec, const ddrom_workspace* ws,
                                ws->c_part, ws->E_part, std::max(1, m->mmax));                                     \
         break;
             switch (ng) {
-                CON_CASE(1) CON_CASE(2) CON_CASE(3) CON_CASE(4) CON_CASE(6)
+                CON_CASE(1) CON_CASE(2) CON_CASE(3) CON_CASE(4) CON_CASE(5) CON_CASE(6) CON_CASE(8)
                 default:
                     set_error("unsupported interface latent size " + std::to_string(ng));
                     return DDROM_EINVAL;
@@ -2213,7 +2215,8 @@ static UpdArgs upd_args(const ddrom_model* m, ddrom_workspace* ws, int B, const 
 }
 
 // Block bounds (NN >= n_i^Omega + n_i^Gamma, MG >= n_i^Gamma) of the compiled update kernels.
-static const int kUpdShapes[][2] = {{3, 1}, {4, 0}, {5, 2}, {6, 0}, {6, 2}, {8, 0}, {9, 3}, {12, 4}, {18, 6}, {20, 12}};
+static const int kUpdShapes[][2] = {{3, 1}, {4, 0}, {5, 2}, {6, 0}, {6, 2}, {8, 0}, {9, 3}, {12, 4}, {18, 6}, {20, 12},
+                                     {24, 8}};
 
 // Block bounds of the update kernel for a model, and whether its big arrays need global scratch
 // (doubles per slot in *gbig, 0 when they fit in LDS).
@@ -2283,7 +2286,7 @@ static int launch_update(const ddrom_model* m, const ddrom_workspace* ws, const 
         else hipLaunchKernelGGL((k_update<A, G, 0>), dim3(B), dim3(64 * nw), lds, s, a);               \
     }
     UPD_CASE(3, 1) UPD_CASE(4, 0) UPD_CASE(5, 2) UPD_CASE(6, 0) UPD_CASE(6, 2) UPD_CASE(8, 0) UPD_CASE(9, 3)
-    UPD_CASE(12, 4) UPD_CASE(18, 6) UPD_CASE(20, 12)
+    UPD_CASE(12, 4) UPD_CASE(18, 6) UPD_CASE(20, 12) UPD_CASE(24, 8)
 #undef UPD_CASE
     HIPCHECK(hipGetLastError());
     return 0;

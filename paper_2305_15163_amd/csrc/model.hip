@@ -363,8 +363,9 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
         }
         m->n_om[sd] = a.n;
         m->n_ga[sd] = m->srpc ? n_ga_srpc[sd] : (g.N > 0 ? g.n : 0);
-        if (m->n_om[sd] + m->n_ga[sd] > 20 || m->n_ga[sd] > 12) {
-            set_error("n_i^Omega + n_i^Gamma above 20 or n_i^Gamma above 12 is not supported by the KKT kernel");
+        if (m->n_om[sd] + m->n_ga[sd] > 24 || m->n_ga[sd] > 12 || (m->n_om[sd] + m->n_ga[sd] > 20 && m->n_ga[sd] > 8)) {
+            set_error("latent sizes beyond the KKT kernel's shapes (n_i^Omega + n_i^Gamma <= 20 with n_i^Gamma <= 12, "
+                      "or <= 24 with n_i^Gamma <= 8)");
             return DDROM_EINVAL;
         }
         m->xoff[sd] = nD;

@@ -52,6 +52,22 @@ def tinywide_pack():
 
 
 @pytest.fixture(scope="session")
+def tinyl10_pack():
+    """40x8, 2x2, Swish band-5 shift-5 masks, latents (10, 5)."""
+    from oracle.build_model import build
+    pack, *_ = build("tinyl10", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
+def tinyl16_pack():
+    """40x8, 2x2, Swish band-5 shift-5 masks, latents (16, 8): 24 latents per subdomain."""
+    from oracle.build_model import build
+    pack, *_ = build("tinyl16", workers=1, verbose=False)
+    return pack
+
+
+@pytest.fixture(scope="session")
 def tinybig_pack():
     """48x48 grid, 8x8 subdomains, 96 constraints: the KKT system exceeds one wave's rows."""
     from oracle.build_model import build

@@ -26,7 +26,7 @@ def dr():
     return d
 
 
-@pytest.fixture(scope="module", params=["tiny", "cfg0", "tinymix", "tinywide"])
+@pytest.fixture(scope="module", params=["tiny", "cfg0", "tinymix", "tinywide", "tinyl10", "tinyl16"])
 def case(request, dr):
     pack = request.getfixturevalue(request.param + "_pack")
     print(f"[case {request.param}]", flush=True)
