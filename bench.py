@@ -457,7 +457,7 @@ def fom_reference(name, sets):
     for sname, mus in sets:
         key = f"{sname}_mu"
         if key in ref and ref[key].shape == np.shape(mus) and np.array_equal(ref[key], mus):
-            out.append(np.asarray(ref[f"{sname}_x"]))
+            out.append(np.asarray(ref[f"{sname}_x"], dtype=np.float64))
         else:
             print(f"[bench] {path}: set {sname} does not hold the benchmark's parameters", file=sys.stderr,
                   flush=True)
@@ -779,7 +779,7 @@ def main():
             prop_leg["rel_err_vs_fom"] = {"n": nq, "warm": error_summary(e_w, res_q["warm"]["status"][:nq], dr),
                                           "zero_start": error_summary(e_q0, res_q["zero_start"]["status"][:nq], dr)}
         line["rel_err_vs_fom"] = rel
-        line["rel_err_vs_fom"]["reference"] = f"models/{a.config}_fomref.npz (FP64 FOM Newton states)"
+        line["rel_err_vs_fom"]["reference"] = f"models/{a.config}_fomref.npz (FP64 FOM Newton states, stored in FP32)"
         # LS-ROM contrast (Section 3.3): POD maps on the same grid, split, latents, HR nodes and
         # C, with collocation and with gappy-POD HR, same batch, options and FOM references
         ls = {}
