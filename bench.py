@@ -217,15 +217,14 @@ def ae_training_leg(a, torch, dr, si):
 def cfg3_training(torch, dr):
     """GPU training on the FOM snapshots of the 480x480, 4x4 workload (1024 snapshots on a 32 x 32
     parameter grid, 10% held out), for the largest subdomain's interior and interface
-    autoencoders (models/cfg3_sd<k>.npz, raw states in FP32): the recipe (2000 epochs at most,
+    autoencoders (models/cfg3_slice.npz, raw states in FP32): the recipe (2000 epochs at most,
     minibatch 64, plateau decay, early stopping), and a run of the same seed, split, initial
     weights and minibatch order for the epochs of the FP64 CPU-trained reference
     (models/cfg3_ae_ref_<part><k>.json), whose held-out reconstruction error it is set beside."""
-    import glob
     from paper_2305_15163_amd.train_ae import train_ae
     from paper_2305_15163_amd.train_model import decode_full, encode, unpack_weights
     import seeded_inputs as si
-    files = sorted(glob.glob(os.path.join(ROOT, "models", "cfg3_sd*.npz")))
+    files = [f for f in [os.path.join(ROOT, "models", "cfg3_slice.npz")] if os.path.exists(f)]
     if not files:
         print("[bench] no FOM snapshot slices of the 480x480 workload: GPU training on snapshots skipped",
               file=sys.stderr, flush=True)
@@ -352,6 +351,44 @@ def paper_leg(a, torch, dr, si):
         print(f"[bench] paper-scale latents ({n_om},{n_ga}): mu* error {row.get('rel_err_mu_star', float('nan')):.3e} "
               f"(paper {paper_err:.2e})", file=sys.stderr, flush=True)
     out["latent_sweep"] = sweep
+    # the same path without hyper-reduction (every owned node sampled)
+    npath = os.path.join(ROOT, "models", "paper_gpu_nohr.npz")
+    if os.path.exists(npath) and X_star is not None:
+        nm_ = dr.Model(dict(np.load(npath, allow_pickle=False)))
+        nws1 = dr.Workspace(nm_, 1)
+        rs = dr.rom_solve_batch(nm_, nws1, torch.as_tensor(star, device="cuda"), rules["paper_f64"])
+        out["without_hr"] = {"pack": "paper_gpu_nohr.npz", "paper_rel_err_mu_star": 1.28e-3,
+                             "mu_star_status": dr.STATUS[int(rs["status"][0])],
+                             "rel_err_mu_star": float(dr.relative_error(nm_, nws1, rs["xhat"], torch.as_tensor(
+                                 X_star, device="cuda")).cpu()[0])}
+        print(f"[bench] paper-scale without HR: mu* error {out['without_hr']['rel_err_mu_star']:.3e} (paper 1.28e-3)",
+              file=sys.stderr, flush=True)
+    # the LS-ROM contrast of Section 7.6 (POD maps of the same snapshots, latents (8,4), the same
+    # HR nodes and C, collocation)
+    lpath = os.path.join(ROOT, "models", "paper_ls.npz")
+    if os.path.exists(lpath):
+        lm = dr.Model(dict(np.load(lpath, allow_pickle=False)))
+        lws1, lws = dr.Workspace(lm, 1), dr.Workspace(lm, B)
+        ls = {"pack": "paper_ls.npz", "paper_rel_err_mu_star": 1.44e-2}
+        rs = dr.rom_solve_batch(lm, lws1, torch.as_tensor(star, device="cuda"), rules["paper_f64"])
+        ls["mu_star_status"] = dr.STATUS[int(rs["status"][0])]
+        if X_star is not None:
+            ls["rel_err_mu_star"] = float(dr.relative_error(lm, lws1, rs["xhat"],
+                                                            torch.as_tensor(X_star, device="cuda")).cpu()[0])
+        dr.rom_solve_batch(lm, lws, mu, rules["batch_rule_f32"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            rl = dr.rom_solve_batch(lm, lws, mu, rules["batch_rule_f32"])
+        torch.cuda.synchronize()
+        ls["batched_solves_per_s"] = B * a.steps / (time.perf_counter() - t0)
+        if X_held is not None:
+            w64 = dr.Workspace(lm, 64)
+            e = dr.relative_error(lm, w64, rl["xhat"][:64].contiguous(), torch.as_tensor(X_held, device="cuda")).cpu().numpy()
+            ls["rel_err_vs_fom_64"] = error_summary(e, rl["status"][:64].cpu().numpy(), dr)
+        out["lsrom"] = ls
+        print(f"[bench] paper-scale LS-ROM: mu* error {ls.get('rel_err_mu_star', float('nan')):.3e} (paper 1.44e-2), "
+              f"{ls['batched_solves_per_s']:.0f} solves/s", file=sys.stderr, flush=True)
     return out
 
 

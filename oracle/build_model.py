@@ -396,7 +396,37 @@ def main(argv=None):
                                                      "with other latent sizes (the test matrix C drawn again for "
                                                      "the new n_C; grid, split and HR nodes kept)")
     ap.add_argument("--latents", type=int, nargs=2, default=None, help="n^Omega n^Gamma for --relatent")
+    ap.add_argument("--ls-from", default=None, help="with --snapshot-matrix and --out: the LS-ROM pack (POD maps of "
+                                                    "the snapshot columns at the skeleton's latent sizes, collocation "
+                                                    "HR on its nodes, its C) of a skeleton")
+    ap.add_argument("--snapshot-matrix", default=None)
+    ap.add_argument("--all-nodes-from", default=None, help="with --out: the pack with every owned node sampled "
+                                                           "(the method without hyper-reduction)")
     a = ap.parse_args(argv)
+    if a.all_nodes_from:
+        pack = dict(np.load(a.all_nodes_from, allow_pickle=False))
+        dd = build_dd(Grid(int(pack["nx"]), int(pack["ny"]), float(pack["nu"]), float(pack["ly"])), int(pack["nsx"]),
+                      int(pack["nsy"]))
+        for i, sd in enumerate(dd.subdomains):
+            pack[f"hr{i}"] = np.asarray(sd.own_nodes, dtype=np.int64)
+        np.savez(a.out, **pack)
+        print("wrote", a.out, flush=True)
+        return 0
+    if a.ls_from:
+        sk = dict(np.load(a.ls_from, allow_pickle=False))
+        X = np.load(a.snapshot_matrix, mmap_mode="r")
+        dd = build_dd(Grid(int(sk["nx"]), int(sk["ny"]), float(sk["nu"]), float(sk["ly"])), int(sk["nsx"]),
+                      int(sk["nsy"]))
+        pack = {k: v for k, v in sk.items() if not k.startswith("train_")}
+        pack["act"] = np.int64(ACT_IDENTITY)
+        for i, sd in enumerate(dd.subdomains):
+            for part, idx, n in (("om", sd.omega, int(sk["train_n_om"][i])), ("ga", sd.gamma, int(sk["train_n_ga"][i]))):
+                x0, Phi = pod_maps(np.asarray(X[:, idx], dtype=np.float64).T, n=n)
+                pack[f"{part}{i}_Phi"] = Phi
+                pack[f"{part}{i}_x0"] = x0
+        np.savez(a.out, **pack)
+        print("wrote", a.out, flush=True)
+        return 0
     if a.relatent:
         cfg = CONFIGS[a.config]
         sk = dict(np.load(a.relatent, allow_pickle=False))
