@@ -2881,18 +2881,24 @@ int rom_solve_multi(int n_models, const ddrom_model* const* models, ddrom_worksp
         if ((rc = solver_graph(m, ws, B, o, upd_args(m, ws, B, o, 0), 0, 0))) return rc;
     }
     const long long max_rounds = solver_max_rounds(o, 0);
-    for (long long done = 0; done < max_rounds; done += kGraphRounds) {
+    // per model: rounds done and solves still running (2-round tail graphs once few run)
+    std::vector<long long> done(n_models, 0);
+    std::vector<int> live(Bs, Bs + n_models);
+    for (;;) {
         int any = 0;
         for (int k = 0; k < n_models; ++k) {
             if (!running[k]) continue;
-            HIPCHECK(hipGraphLaunch(wss[k]->graph, wss[k]->stream));
+            const bool tail = live[k] <= kTailLive;
+            HIPCHECK(hipGraphLaunch(tail ? wss[k]->graph_tail : wss[k]->graph, wss[k]->stream));
+            done[k] += tail ? kTailRounds : kGraphRounds;
             HIPCHECK(hipMemcpyAsync(wss[k]->counter_h, wss[k]->counter, sizeof(int), hipMemcpyDeviceToHost,
                                     wss[k]->stream));
         }
         for (int k = 0; k < n_models; ++k) {
             if (!running[k]) continue;
             HIPCHECK(hipStreamSynchronize(wss[k]->stream));
-            running[k] = *wss[k]->counter_h != 0;
+            live[k] = *wss[k]->counter_h;
+            running[k] = live[k] != 0 && done[k] < max_rounds;
             any |= running[k];
         }
         if (!any) break;

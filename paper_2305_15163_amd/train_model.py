@@ -170,17 +170,31 @@ def merge(paths, out):
     return pack
 
 
-def subset_data(stem: str, tags, out_stem: str, snapshots: str | None = None):
+def grid_rows(mus: np.ndarray, every: int) -> np.ndarray:
+    """Rows of a snapshot matrix on a tensor parameter grid (mus [n_snap][2]) whose two grid
+    indices are both multiples of `every`: a coarser tensor grid over the same box."""
+    ia = np.searchsorted(np.unique(mus[:, 0]), mus[:, 0])
+    il = np.searchsorted(np.unique(mus[:, 1]), mus[:, 1])
+    return np.flatnonzero((ia % every == 0) & (il % every == 0))
+
+
+def subset_data(stem: str, tags, out_stem: str, snapshots: str | None = None, every: int = 1):
     """The snapshot columns the autoencoders `tags` read (FP32) with their index lists renumbered,
     and the skeleton, under out_stem: training data for `train_model --only` that is smaller than
-    the whole matrix (for moving it to another machine)."""
+    the whole matrix (for moving it to another machine).  every > 1 keeps only the snapshots of
+    the coarser parameter grid (grid_rows; the parameters come from the matrix's _dd file)."""
     import shutil
     idx = np.load(stem + "_X_dd.npz")
-    X = np.load(snapshots or stem + "_X.npy", mmap_mode="r")
+    xpath = snapshots or stem + "_X.npy"
+    X = np.load(xpath, mmap_mode="r")
+    rows = slice(None)
+    if every > 1:
+        rows = grid_rows(np.load(os.path.splitext(xpath)[0] + "_dd.npz")["mus"], every)
     cols = np.unique(np.concatenate([idx[t] for t in tags]))
     pos = np.full(X.shape[1], -1, dtype=np.int64)
     pos[cols] = np.arange(len(cols))
-    np.save(out_stem + "_X.npy", np.asarray(X[:, cols], dtype=np.float32))
+    Xs = np.asarray(X[rows], dtype=np.float32) if every > 1 else X
+    np.save(out_stem + "_X.npy", np.asarray(Xs[:, cols], dtype=np.float32))
     np.savez(out_stem + "_X_dd.npz", **{t: pos[idx[t]] for t in tags})
     shutil.copy(stem + "_skel.npz", out_stem + "_skel.npz")
     return len(cols)
@@ -198,13 +212,15 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=None, help="override the recipe's epoch count")
     ap.add_argument("--precision", type=int, default=0, help="0: BF16 operands, 1: split-BF16")
     ap.add_argument("--snapshots", default=None, help="state snapshot matrix (default <stem>_X.npy)")
+    ap.add_argument("--every", type=int, default=1, help="with --subset-to: keep every k-th parameter of "
+                                                         "the snapshot grid in both directions")
     a = ap.parse_args(argv)
     if a.merge:
         merge(a.merge, a.out)
         print(f"[train_model] merged {len(a.merge)} packs into {a.out}", flush=True)
         return 0
     if a.subset_to:
-        n = subset_data(a.stem, a.only.split(","), a.subset_to, a.snapshots)
+        n = subset_data(a.stem, a.only.split(","), a.subset_to, a.snapshots, a.every)
         print(f"[train_model] wrote {n} columns under {a.subset_to}", flush=True)
         return 0
     pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision, snapshots=a.snapshots,

@@ -46,3 +46,27 @@ def test_export_matches_oracle(N, n, b, s, act):
     # and it decodes the raw state of the centred latent
     x0, _ = decode_jacobian(ref, np.zeros(n))
     assert np.max(np.abs(x0 - (tm.decode_full(wts, center[None], N, b, s, act)[0] * sc + mid))) <= 1e-12 * np.max(np.abs(x0))
+
+
+def test_subset_every_keeps_coarse_grid(tmp_path):
+    """--subset-to with --every 2: the snapshots of the coarser tensor grid (both grid indices
+    even) and the tagged autoencoders' columns, in FP32, with the index lists renumbered."""
+    mus = si.training_grid(4, 4)
+    X = np.arange(16 * 10, dtype=np.float64).reshape(16, 10) / 7.0
+    stem, xs = str(tmp_path / "m"), str(tmp_path / "s_X")
+    np.save(xs + ".npy", X)
+    np.savez(xs + "_dd.npz", mus=mus)
+    np.savez(stem + "_X_dd.npz", om0=np.array([7, 2, 5]), ga0=np.array([5, 9]), om1=np.array([0, 1]))
+    np.savez(stem + "_skel.npz", n_sub=np.array(2))
+    rows = tm.grid_rows(mus, 2)
+    a_vals, l_vals = np.unique(mus[:, 0]), np.unique(mus[:, 1])
+    want = [k for k in range(16) if list(a_vals).index(mus[k, 0]) % 2 == 0
+            and list(l_vals).index(mus[k, 1]) % 2 == 0]
+    assert list(rows) == want and len(rows) == 4
+    n = tm.subset_data(stem, ["om0", "ga0"], str(tmp_path / "p"), xs + ".npy", every=2)
+    assert n == 4
+    Xp = np.load(str(tmp_path / "p_X.npy"))
+    dd = np.load(str(tmp_path / "p_X_dd.npz"))
+    assert Xp.dtype == np.float32 and Xp.shape == (4, 4)
+    for t in ("om0", "ga0"):
+        assert np.array_equal(Xp[:, dd[t]], X[rows][:, np.load(stem + "_X_dd.npz")[t]].astype(np.float32))
