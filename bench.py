@@ -91,7 +91,7 @@ def decoder_work(model, B):
 
 
 UNEVEN = dict(models=("cfg2a", "cfg2b", "cfg2c"), batch=1024, seed=2, precision=1, tol_rel=1e-6, stall_tol=1e-5,
-              stall_ratio=0.5,
+              stall_ratio=0.5, n_err=16,
               max_iter=60,
               workload="uneven batch: 1024 held-out (a,lambda) split evenly (seeded) over three Burgers models "
                        "with 60x60-node subdomains: 120x120 2x2, 240x240 4x4, 480x480 8x8; per-subdomain latent "
@@ -158,6 +158,14 @@ def uneven_leg(a, torch, dr):
         it = r["iters"].cpu().numpy()
         info[k]["iters_mean"] = float(it.mean())
         info[k]["status_counts"] = {dr.STATUS[s]: int((st == s).sum()) for s in np.unique(st)}
+        # error against the FOM (eq. relative_error) on the model's first solves, when the offline
+        # reference states of exactly those parameters are stored
+        ne = min(cfg["n_err"], len(mus[k]))
+        Xf = fom_reference(cfg["models"][k], [("uneven", mus[k][:ne].cpu().numpy())])[0]
+        if Xf is not None:
+            e = dr.relative_error(models[k], wss[k], r["xhat"][:ne].contiguous(),
+                                  torch.as_tensor(Xf, device="cuda")).cpu().numpy()
+            info[k]["rel_err_vs_fom"] = error_summary(e, st[:ne], dr)
     stopped_ok = sum(v.get("converged", 0) + v.get("stalled", 0) for v in (i["status_counts"] for i in info))
     converged = sum(i["status_counts"].get("converged", 0) for i in info)
     return {"workload": cfg["workload"], "solves_per_s": B * a.steps / dt_m, "ms_per_step": 1e3 * dt_m / a.steps,

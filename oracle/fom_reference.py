@@ -10,6 +10,10 @@ Usage:
       --out models/cfg1_fomref.npz [--workers 8]
   python -m oracle.fom_reference --grid 480 24 --mu-star --set heldout:7:64:64 --lam-range 5 25 \
       --out models/paper_fomref.npz
+  python -m oracle.fom_reference --grid 480 480 --set uneven:2:1024:8:2/3 --out models/cfg2c_fomref.npz
+
+A fifth field k/m keeps only the draws that seeded_inputs.model_assignment(count, m, seed) gives
+to model k (the uneven batch's split of its parameters over m models), then the first `take`.
 
 The file holds, per set name s: s_mu [n][2], s_x [n][N_x] (the FP64 Newton states rounded to FP32:
 their relative rounding, 6e-8, is far below the errors measured against them), and
@@ -65,9 +69,13 @@ def main(argv=None):
     if a.mu_star:
         sets.append(("star", np.array([MU_STAR], dtype=np.float64)))
     for spec in a.set:
-        name, seed, count, take = spec.split(":")
+        name, seed, count, take, *part = spec.split(":")
         lr = tuple(a.lam_range) if a.lam_range else si.LAM_RANGE
-        sets.append((name, si.heldout_mu(int(count), int(seed), lam_range=lr)[:int(take)]))
+        mus = si.heldout_mu(int(count), int(seed), lam_range=lr)
+        if part:
+            k, m = (int(v) for v in part[0].split("/"))
+            mus = mus[si.model_assignment(int(count), m, int(seed)) == k]
+        sets.append((name, mus[:int(take)]))
     for name, mus in sets:
         t0 = time.time()
         X, ts = states(nx, ny, mus, a.workers)
