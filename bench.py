@@ -95,7 +95,10 @@ UNEVEN = dict(models=("cfg2a", "cfg2b", "cfg2c"), batch=1024, seed=2, precision=
               max_iter=60,
               workload="uneven batch: 1024 held-out (a,lambda) split evenly (seeded) over three Burgers models "
                        "with 60x60-node subdomains: 120x120 2x2, 240x240 4x4, 480x480 8x8; per-subdomain latent "
-                       "sizes from {4,6,8,12} and HR fractions from [5%, 25%]; FP32 decoder + FP64 KKT; zero start")
+                       "sizes from {4,6,8,12} and HR fractions from [5%, 25%]; FP32 decoder + FP64 KKT; zero start",
+              # autoencoders trained on the GPU on FOM snapshots (models/<model>_gpu.npz) when present,
+              # else the CPU-trained packs of the offline pipeline (models/<model>.npz)
+              gpu_trained="1024 (120x120) or 256 (240x240, 480x480) FOM snapshots, GPU training to 2000 epochs")
 
 
 def uneven_leg(a, torch, dr):
@@ -105,7 +108,9 @@ def uneven_leg(a, torch, dr):
     from paper_2305_15163_amd import autotune
     import seeded_inputs as si
     cfg = UNEVEN
-    paths = [os.path.join(ROOT, "models", f"{c}.npz") for c in cfg["models"]]
+    gpu = [os.path.join(ROOT, "models", f"{c}_gpu.npz") for c in cfg["models"]]
+    trained_on_gpu = all(os.path.exists(p) for p in gpu) and not a.uneven_cpu_packs
+    paths = gpu if trained_on_gpu else [os.path.join(ROOT, "models", f"{c}.npz") for c in cfg["models"]]
     missing = [p for p in paths if not os.path.exists(p)]
     if missing:
         print(f"[bench] uneven batch skipped: missing {missing}", file=sys.stderr, flush=True)
@@ -173,7 +178,10 @@ def uneven_leg(a, torch, dr):
             info[k]["rel_err_vs_fom"] = error_summary(e, st[:ne], dr)
     stopped_ok = sum(v.get("converged", 0) + v.get("stalled", 0) for v in (i["status_counts"] for i in info))
     converged = sum(i["status_counts"].get("converged", 0) for i in info)
-    return {"workload": cfg["workload"], "solves_per_s": B * a.steps / dt_m, "ms_per_step": 1e3 * dt_m / a.steps,
+    return {"workload": cfg["workload"], "packs": [os.path.relpath(p, ROOT) for p in paths],
+            "autoencoders": ("trained on the GPU: " + cfg["gpu_trained"]) if trained_on_gpu else
+                            "trained by the FP64 CPU pipeline (8 x 8 parameter grid, 300 epochs)",
+            "solves_per_s": B * a.steps / dt_m, "ms_per_step": 1e3 * dt_m / a.steps,
             "converged_solves_per_s": converged * a.steps / dt_m,
             "converged_or_stalled_solves_per_s": stopped_ok * a.steps / dt_m,
             "separate_batches_solves_per_s": B * a.steps / dt_s, "models": info,
@@ -571,6 +579,8 @@ def main():
     ap.add_argument("--proposal-batch", type=int, default=2048, help="held-out parameters of the proposal leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the three-model uneven batch leg")
     ap.add_argument("--uneven-only", action="store_true", help="run only the three-model uneven batch leg")
+    ap.add_argument("--uneven-cpu-packs", action="store_true",
+                    help="uneven leg on the CPU-trained packs even where GPU-trained ones exist")
     ap.add_argument("--no-ae", action="store_true", help="skip the autoencoder training leg")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-scale leg")
     ap.add_argument("--paper-only", action="store_true", help="run only the paper-scale leg")

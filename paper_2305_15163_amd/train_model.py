@@ -80,11 +80,27 @@ def export_decoder(wts: dict, mid: np.ndarray, sc: np.ndarray, center: np.ndarra
                 xref=mid.copy(), bs=np.array([b, s]))
 
 
+def raw_decoder(wts: dict, mid: np.ndarray, sc: np.ndarray, center: np.ndarray, b: int, s: int) -> dict:
+    """What export_decoder is formed from, in half the bytes: the trained decoder weights are FP32
+    values, so they are stored in FP32 (losslessly) beside the FP64 normalisation and centre."""
+    return dict(W1=wts["W1d"].astype(np.float32), b1=wts["b1d"].astype(np.float32),
+                W2=wts["W2d"].astype(np.float32), sc=sc.copy(), mid=mid.copy(), center=center.copy(),
+                bs=np.array([b, s]))
+
+
+def decoder_from_raw(r: dict) -> dict:
+    """export_decoder of the weights raw_decoder stored (the same values, formed the same way)."""
+    b, s = (int(v) for v in r["bs"])
+    wts = dict(W1d=np.asarray(r["W1"], dtype=np.float64), b1d=np.asarray(r["b1"], dtype=np.float64),
+               W2d=np.asarray(r["W2"], dtype=np.float64))
+    return export_decoder(wts, np.asarray(r["mid"]), np.asarray(r["sc"]), np.asarray(r["center"]), b, s)
+
+
 def _job(args):
     """One autoencoder, in its own process: train on the GPU, export, and measure the relative
     reconstruction error on the held-out snapshots (host FP64 evaluation of the trained
     weights)."""
-    stem, xpath, tag, i, n, b, s, act, seed, epochs, batch, precision = args
+    stem, xpath, tag, i, n, b, s, act, seed, epochs, batch, precision, raw = args
     import torch  # noqa: F401  (initialises the device in this process)
     from paper_2305_15163_amd.train_ae import train_ae
     import seeded_inputs as si
@@ -102,7 +118,7 @@ def _job(args):
     test_idx, train_idx = perm[:n_test], perm[n_test:]
     Xn_tr = (X[train_idx] - res.mid) / res.scale
     center = encode(wts, Xn_tr, N * s, act).mean(axis=0)
-    dec = export_decoder(wts, res.mid, res.scale, center, b, s)
+    dec = (raw_decoder if raw else export_decoder)(wts, res.mid, res.scale, center, b, s)
     Xt = X[test_idx] if n_test else X[train_idx]
     rec = decode_full(wts, encode(wts, (Xt - res.mid) / res.scale, N * s, act), N, b, s, act) * res.scale + res.mid
     rel = np.linalg.norm(rec - Xt, axis=1) / np.maximum(1e-300, np.linalg.norm(Xt, axis=1))
@@ -113,9 +129,11 @@ def _job(args):
 
 
 def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision: int = 0, verbose: bool = True,
-                snapshots: str | None = None, only=None):
+                snapshots: str | None = None, only=None, raw: bool = False):
     """snapshots: the state snapshot matrix (default <stem>_X.npy).  only: the autoencoders to
-    train (tags such as "om0", "ga3"); the pack then holds only their decoders (see merge)."""
+    train (tags such as "om0", "ga3"; default: every autoencoder the index-list file names); the
+    pack then holds only their decoders (see merge).  raw: the pack holds only the decoders, as
+    raw_decoder stores them (<tag>_raw_<key>), for merge to finish with the skeleton."""
     skel = dict(np.load(stem + "_skel.npz", allow_pickle=False))
     xpath = snapshots or stem + "_X.npy"
     n_sub = int(skel["n_sub"])
@@ -129,11 +147,12 @@ def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision:
     idx = np.load(stem + "_X_dd.npz")
     for i in range(n_sub):
         jobs.append((stem, xpath, "om", i, int(skel["train_n_om"][i]), b, s, act, seeds[2 * i], ep, batch,
-                     precision))
+                     precision, raw))
         jobs.append((stem, xpath, "ga", i, int(skel["train_n_ga"][i]), b, s, act, seeds[2 * i + 1], ep, batch,
-                     precision))
-    if only:
-        jobs = [j for j in jobs if f"{j[2]}{j[3]}" in set(only)]
+                     precision, raw))
+    if not only:     # a subset written by subset_data holds only its autoencoders' index lists
+        only = [t for t in idx.files if t[:2] in ("om", "ga") and t[2:].isdigit()]
+    jobs = [j for j in jobs if f"{j[2]}{j[3]}" in set(only)]
     jobs.sort(key=lambda j: -len(idx[f"{j[2]}{j[3]}"]))     # largest first
     t0 = time.time()
     if procs > 1:
@@ -150,22 +169,38 @@ def train_model(stem: str, procs: int = 8, epochs: int | None = None, precision:
             out.append(_job(j))
             if verbose:
                 print("[train_model]", json.dumps(out[-1][3]), flush=True)
-    pack = {k: v for k, v in skel.items() if not k.startswith("train_")}
+    pack = {} if raw else {k: v for k, v in skel.items() if not k.startswith("train_")}
     reports = []
     for tag, i, dec, rep in out:
         for key, v in dec.items():
-            pack[f"{tag}{i}_{key}"] = v
+            pack[f"{tag}{i}_raw_{key}" if raw else f"{tag}{i}_{key}"] = v
         reports.append(rep)
     reports.sort(key=lambda r: r["ae"])
     return pack, reports, time.time() - t0
 
 
-def merge(paths, out):
-    """One pack from packs that each hold some subdomains' trained decoders (the rest equal)."""
+def merge(paths, out, skeleton: str | None = None):
+    """One pack from packs that each hold some subdomains' trained decoders (the rest equal).
+    Parts written with raw=True hold only decoders: their exported form is formed here
+    (decoder_from_raw) and the rest of the pack comes from the skeleton <skeleton>_skel.npz."""
     pack = {}
+    if skeleton:
+        skel = np.load(skeleton + "_skel.npz", allow_pickle=False)
+        pack.update({k: skel[k] for k in skel.files if not k.startswith("train_")})
     for p in paths:
-        for k, v in np.load(p, allow_pickle=False).items():
-            pack.setdefault(k, v)
+        part = np.load(p, allow_pickle=False)
+        raws = {}
+        for k in part.files:
+            if "_raw_" in k:
+                tag, key = k.split("_raw_")
+                raws.setdefault(tag, {})[key] = part[k]
+            else:
+                pack.setdefault(k, part[k])
+        if raws and not skeleton:
+            raise ValueError(f"{p} holds raw decoders: give the skeleton to merge them")
+        for tag, r in raws.items():
+            for key, v in decoder_from_raw(r).items():
+                pack.setdefault(f"{tag}_{key}", v)
     np.savez(out, **pack)
     return pack
 
@@ -212,11 +247,15 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=None, help="override the recipe's epoch count")
     ap.add_argument("--precision", type=int, default=0, help="0: BF16 operands, 1: split-BF16")
     ap.add_argument("--snapshots", default=None, help="state snapshot matrix (default <stem>_X.npy)")
+    ap.add_argument("--raw", action="store_true", help="write only the decoders, in FP32 where they are "
+                                                        "FP32 values (about half the bytes); --merge with "
+                                                        "--skeleton then forms the pack")
+    ap.add_argument("--skeleton", default=None, help="with --merge: the skeleton stem of raw parts")
     ap.add_argument("--every", type=int, default=1, help="with --subset-to: keep every k-th parameter of "
                                                          "the snapshot grid in both directions")
     a = ap.parse_args(argv)
     if a.merge:
-        merge(a.merge, a.out)
+        merge(a.merge, a.out, a.skeleton)
         print(f"[train_model] merged {len(a.merge)} packs into {a.out}", flush=True)
         return 0
     if a.subset_to:
@@ -224,7 +263,7 @@ def main(argv=None):
         print(f"[train_model] wrote {n} columns under {a.subset_to}", flush=True)
         return 0
     pack, reports, dt = train_model(a.stem, a.procs, a.epochs, a.precision, snapshots=a.snapshots,
-                                    only=a.only.split(",") if a.only else None)
+                                    only=a.only.split(",") if a.only else None, raw=a.raw)
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     np.savez(a.out, **pack)
     with open(os.path.splitext(a.out)[0] + "_train.json", "w") as f:

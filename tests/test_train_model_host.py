@@ -70,3 +70,28 @@ def test_subset_every_keeps_coarse_grid(tmp_path):
     assert Xp.dtype == np.float32 and Xp.shape == (4, 4)
     for t in ("om0", "ga0"):
         assert np.array_equal(Xp[:, dd[t]], X[rows][:, np.load(stem + "_X_dd.npz")[t]].astype(np.float32))
+
+
+def test_raw_decoder_round_trip(tmp_path):
+    """A raw part (FP32 decoder weights, FP64 normalisation and centre) merged with its skeleton
+    gives the pack export_decoder writes, bit for bit."""
+    N, n, b, s = 40, 4, 3, 2
+    ae = MaskedAE(N, n, b, s, ACT_SIGMOID)
+    p = ae.init_params(9)
+    packed = dr.ae_pack(N, n, b, s, *p.as_list()).astype(np.float32).astype(np.float64)
+    wts = tm.unpack_weights(packed, N, n, b, s)
+    g = si.rng(11)
+    mid, sc, center = g.normal(size=N), g.uniform(0.5, 2.0, size=N), g.normal(size=n)
+    full = tm.export_decoder(wts, mid, sc, center, b, s)
+    raw = tm.raw_decoder(wts, mid, sc, center, b, s)
+    assert raw["W2"].dtype == np.float32 and raw["W1"].dtype == np.float32
+    part = str(tmp_path / "part.npz")
+    np.savez(part, **{f"om3_raw_{k}": v for k, v in raw.items()})
+    np.savez(str(tmp_path / "m_skel.npz"), n_sub=np.array(4), train_seed=np.array(1))
+    out = str(tmp_path / "pack.npz")
+    pack = tm.merge([part], out, skeleton=str(tmp_path / "m"))
+    assert "train_seed" not in pack and int(pack["n_sub"]) == 4
+    for k, v in full.items():
+        assert np.array_equal(pack[f"om3_{k}"], v), k
+    with pytest.raises(ValueError):
+        tm.merge([part], out)
