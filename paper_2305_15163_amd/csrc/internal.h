@@ -99,6 +99,11 @@ struct GappySeg {
     long long r_off, y_off, p_off;
 };
 
+// Gappy-POD projection: modes per work item (each item streams its subdomain's stored rows once
+// for this many modes), and the operator rows staged in LDS at a time.
+constexpr int kGappyModes = 8;
+constexpr int kGappyRowChunk = 256;
+
 struct ConChunk {
     int sd;
     int j0, j1;             // constraint rows

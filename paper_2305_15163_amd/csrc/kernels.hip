@@ -580,7 +580,7 @@ __global__ __launch_bounds__(256) void k_res_gn(const ResChunk* __restrict__ rch
 // Y_i = P_i [Z_i r_i | Z_i R_i]: H_i = sum_j y_j' y_j'^T, g_i = sum_j y_j' y_j0, rr = sum_j y_j0^2
 // over the modes j (y_j0 the projected residual, y_j' its latent gradient).  Three passes:
 //  k_res_rows  the sampled rows and their gradients by the same stencil code as k_res_gn, stored;
-//  k_gappy_y   Y = P R, one workgroup per (subdomain, mode) and 64-solve group;
+//  k_gappy_y   Y = P R, one workgroup per (subdomain, 8 modes) and 64-solve group;
 //  k_gappy_gn  the sums over the modes into the subdomain's partial slot.
 // ------------------------------------------------------------------------------------
 template <typename T, int NO, int NG>
@@ -630,34 +630,89 @@ __global__ __launch_bounds__(256) void k_gappy_y(const int2* __restrict__ items,
                                                  const double* __restrict__ P, const double* __restrict__ R,
                                                  double* __restrict__ Y, const int* __restrict__ n_live, int B,
                                                  int Bp) {
+    // One work item: modes q0 .. q0 + kGappyModes - 1 of one subdomain for 64 solves.  The
+    // operator rows are staged in LDS transposed ([row][mode]), kGappyRowChunk rows at a time;
+    // wave w takes the columns k = w, w + 4, ... of the stored rows (value, then one gradient
+    // per latent), so each stored row is read once for all of the item's modes.  Every Y entry
+    // is the sum over rows in ascending order.
+    constexpr int MT = kGappyModes, KW = 4;     // KW: columns per wave (nn + 1 <= 13 over 4 waves)
+    __shared__ __align__(16) double sP[kGappyRowChunk * MT];
     const int nl = live_count(n_live, B);
     const int j0 = blockIdx.y * 64;
     if (j0 >= nl) return;
-    const int2 it = items[blockIdx.x];
+    const int2 it = items[xcd_item()];
     const GappySeg gs = gsegs[it.x];
-    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = j0 + lane;
-    const double* Pj = P + gs.p_off + (size_t)it.y * gs.rows;
+    const int nm = min(MT, gs.modes - it.y);
+    const double* Pq = P + gs.p_off + (size_t)it.y * gs.rows;
     const size_t rstride = (size_t)(gs.nn + 1) * Bp;
-    for (int k = w; k <= gs.nn; k += 4) {
-        const double* Rk = R + ((size_t)gs.r_off + k) * Bp + j;
-        double acc = 0.0;
-        for (int row = 0; row < gs.rows; ++row) acc = fma(Pj[row], Rk[row * rstride], acc);
-        Y[((size_t)gs.y_off + (size_t)it.y * (gs.nn + 1) + k) * Bp + j] = acc;
+    const double* Rb = R + (size_t)gs.r_off * Bp + j;
+    double acc[KW][MT];
+#pragma unroll
+    for (int c = 0; c < KW; ++c)
+#pragma unroll
+        for (int q = 0; q < MT; ++q) acc[c][q] = 0.0;
+    const int nk = (gs.nn + 1 - w + 3) / 4;    // columns of this wave (wave-uniform)
+    for (int r0 = 0; r0 < gs.rows; r0 += kGappyRowChunk) {
+        const int nr = min(kGappyRowChunk, gs.rows - r0);
+        __syncthreads();     // the previous chunk has been read
+        for (int i = tid; i < nr * MT; i += 256) {
+            const int row = i / MT, q = i % MT;
+            sP[i] = q < nm ? Pq[(size_t)q * gs.rows + r0 + row] : 0.0;
+        }
+        __syncthreads();
+        // U rows per step: their loads are all issued before the products, so a wave keeps up
+        // to U * KW loads in flight (one workgroup per CU leaves little else to hide latency)
+        constexpr int U = 8;
+        for (int row = 0; row < nr; row += U) {
+            double rv[U][KW];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double* Rr = Rb + (size_t)(r0 + row + u) * rstride;
+#pragma unroll
+                for (int c = 0; c < KW; ++c) rv[u][c] = (row + u < nr && c < nk) ? Rr[(size_t)(w + 4 * c) * Bp] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (row + u >= nr) break;
+                const double* pr = sP + (row + u) * MT;
+                double pv[MT];
+#pragma unroll
+                for (int q = 0; q < MT; ++q) pv[q] = pr[q];
+#pragma unroll
+                for (int c = 0; c < KW; ++c)
+                    if (c < nk)
+#pragma unroll
+                        for (int q = 0; q < MT; ++q) acc[c][q] = fma(pv[q], rv[u][c], acc[c][q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < KW; ++c) {
+        if (c >= nk) continue;
+        const int k = w + 4 * c;
+#pragma unroll
+        for (int q = 0; q < MT; ++q)
+            if (q < nm) Y[((size_t)gs.y_off + (size_t)(it.y + q) * (gs.nn + 1) + k) * Bp + j] = acc[c][q];
     }
 }
 
-// Gauss-Newton sums of one subdomain's projected rows (one wave, 64 solves), written to its
-// partial slot in the layout k_res_gn uses (H upper triangle row by row, g, rr).
+// Gauss-Newton sums of one subdomain's projected rows (one wave, 64 solves), written to the
+// subdomain's partial slot (slot sd) in the layout k_res_gn uses (H upper triangle row by row,
+// g, rr).  Subdomain blockIdx.x; subdomains with another latent size are left to the launch
+// of their NN.
 template <int NN>
-__global__ __launch_bounds__(64) void k_gappy_gn(int sd, const GappySeg* __restrict__ gsegs,
-                                                 const double* __restrict__ Y, const int* __restrict__ n_live, int B,
-                                                 int Bp, double* __restrict__ part, int estride, int slot) {
+__global__ __launch_bounds__(64) void k_gappy_gn(const GappySeg* __restrict__ gsegs, const double* __restrict__ Y,
+                                                 const int* __restrict__ n_live, int B, int Bp,
+                                                 double* __restrict__ part, int estride) {
     using G = GnEntries<NN>;
     const int nl = live_count(n_live, B);
     const int j0 = blockIdx.y * 64;
     if (j0 >= nl) return;
+    const int sd = blockIdx.x, slot = sd;
     const GappySeg gs = gsegs[sd];
+    if (gs.nn != NN) return;
     const int j = j0 + (int)threadIdx.x;
     double H[G::NH], g[NN], rr = 0.0;
 #pragma unroll
@@ -2092,13 +2147,21 @@ static int launch_gappy(const ddrom_model* m, const ddrom_workspace* ws, const i
     if (m->n_gitems > 0)
         hipLaunchKernelGGL(k_gappy_y, dim3(m->n_gitems, ws->Bp / 64), dim3(256), 0, s, m->gitems_d, m->gseg_d,
                            m->gP_d, ws->g_R, ws->g_Y, n_live, B, ws->Bp);
+    // one launch per latent size present (every subdomain's sums go to its own slot, sd)
+    std::vector<int> sizes;
     for (int sd = 0; sd < m->n_sub; ++sd) {
-        const int nn = m->gseg_h[sd].nn, slot = m->rsegs_h[sd].slot0;
-        const dim3 grid(1, ws->Bp / 64);
+        if (m->rsegs_h[sd].slot0 != sd) {
+            set_error("gappy POD: partial slot of a subdomain is not its index");
+            return DDROM_EINVAL;
+        }
+        if (std::find(sizes.begin(), sizes.end(), m->gseg_h[sd].nn) == sizes.end()) sizes.push_back(m->gseg_h[sd].nn);
+    }
+    for (const int nn : sizes) {
+        const dim3 grid(m->n_sub, ws->Bp / 64);
 #define GN_CASE(NV)                                                                                               \
     case NV:                                                                                                      \
-        hipLaunchKernelGGL(k_gappy_gn<NV>, grid, dim3(64), 0, s, sd, m->gseg_d, ws->g_Y, n_live, B, ws->Bp,        \
-                           ws->gn_part, m->estride, slot);                                                        \
+        hipLaunchKernelGGL(k_gappy_gn<NV>, grid, dim3(64), 0, s, m->gseg_d, ws->g_Y, n_live, B, ws->Bp,            \
+                           ws->gn_part, m->estride);                                                              \
         break;
         switch (nn) {
             GN_CASE(3) GN_CASE(4) GN_CASE(5) GN_CASE(6) GN_CASE(8) GN_CASE(9) GN_CASE(12)

@@ -751,7 +751,7 @@ int build_model(const ddrom_model_desc* d, ddrom_model* m) {
             ro += (long long)g.rows * (g.nn + 1);
             yo += (long long)g.modes * (g.nn + 1);
             gP.insert(gP.end(), d->hr_gappy[sd], d->hr_gappy[sd] + (size_t)g.modes * g.rows);
-            for (int q = 0; q < g.modes; ++q) gitems.push_back(int2{sd, q});
+            for (int q = 0; q < g.modes; q += ddrom::kGappyModes) gitems.push_back(int2{sd, q});
             // the projected sums of a subdomain go to one partial slot
             m->rsegs_h[sd].slot0 = sd;
             m->rsegs_h[sd].slot1 = sd + 1;
