@@ -261,10 +261,13 @@ def cfg3_training(torch, dr):
         runs = {}
         ref_path = os.path.join(ROOT, "models", f"cfg3_ae_ref_{part}{k}.json")
         ref = json.load(open(ref_path)) if os.path.exists(ref_path) else None
-        plan = [("recipe", 2000)] + ([("same_as_cpu_reference", int(ref["epochs"]))] if ref else [])
-        for tag, epochs in plan:
+        # the recipe in BF16; the reference's epoch count in BF16 and in split-BF16 (FP32-class
+        # products), each with the recipe's schedule (plateau decay, early stopping)
+        plan = [("recipe", 2000, 0)] + ([("same_as_cpu_reference", int(ref["epochs"]), 0),
+                                          ("same_as_cpu_reference_split_bf16", int(ref["epochs"]), 1)] if ref else [])
+        for tag, epochs, prec in plan:
             t0 = time.perf_counter()
-            r = train_ae(X, n, 9, 2, 0, seed, epochs, batch=64)
+            r = train_ae(X, n, 9, 2, 0, seed, epochs, batch=64, precision=prec)
             dt = time.perf_counter() - t0
             w = unpack_weights(r.packed, N, n, 9, 2)
             g = si.rng(seed)
@@ -274,7 +277,8 @@ def cfg3_training(torch, dr):
             rec = decode_full(w, encode(w, (Xt - r.mid) / r.scale, 2 * N, 0), N, 9, 2, 0) * r.scale + r.mid
             rel = np.linalg.norm(rec - Xt, axis=1) / np.linalg.norm(Xt, axis=1)
             steps = r.epochs * -(-(X.shape[0] - n_test) // 64)
-            runs[tag] = {"epochs": r.epochs, "seconds": dt, "steps_per_s": steps / dt,
+            runs[tag] = {"epochs": r.epochs, "precision": ("bf16", "split_bf16")[prec], "seconds": dt,
+                         "steps_per_s": steps / dt,
                          "best_test_loss": r.best_test, "rel_rec_err_mean": float(rel.mean()),
                          "rel_rec_err_max": float(rel.max())}
             print(f"[bench] cfg3 {part}{k} GPU {tag}: {r.epochs} epochs in {dt:.1f}s, held-out rel. error "
