@@ -114,3 +114,49 @@ def test_lsrom_fp32_maps(dr, case):
     for b in range(B):
         print(name, b, "rel err fp64 %.3e fp32 %.3e" % (e64[b], e32[b]), flush=True)
         assert e32[b] <= 1.1 * e64[b] + 1e-4
+
+
+def test_gappy_blocks_at_benchmark_size(dr):
+    """Gappy POD at the benchmark's grid and split (240x240, 4x4, POD maps (8,4), 360 sampled
+    nodes: 720 stored rows and 12-15 modes per subdomain, so the projection takes several row
+    chunks and mode tiles) over two 64-solve groups: GN blocks of sampled lanes and two FP64
+    solves against the oracle.  At this size the zero start's KKT residual is about 1e14 and the
+    solves stop near 1e3 (tolerance 1e-10 relative), so the two sides' latents, formed by
+    different KKT routes, agree to rounding amplified by that range: 7.8e-10 measured, bound
+    1e-8; the blocks themselves agree to 1e-11."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "models", "cfg1lsg.npz")
+    if not os.path.exists(path):
+        pytest.skip("models/cfg1lsg.npz not built")
+    pack = dict(np.load(path, allow_pickle=False))
+    gm, rom = dr.Model(pack), load_ls_pack(pack)
+    assert max(h.P.shape[0] for h in rom.hr) > 8 and max(h.P.shape[1] for h in rom.hr) > 256
+    B = 70
+    print("[gappy 240x240 4x4] GN blocks, B = 70", flush=True)
+    mus = si.heldout_mu(B, 41)
+    xh = si.normal((B, gm.n_D), seed=43, scale=0.5)
+    ws = dr.Workspace(gm, B)
+    H, g, EG, c, rr = (t.cpu().numpy() for t in dr.gn_blocks(gm, ws, mus, xh, precision=dr.PREC_FP64))
+    for b in (0, 37, 69):
+        r, J = rom.residual(mus[b], xh[b])
+        o_r, o_x, rr_ref = 0, 0, 0.0
+        for i, (a, m) in enumerate(rom.sizes):
+            k = rom.hr[i].P.shape[0]
+            ri, Ji = r[o_r:o_r + k], J[o_r:o_r + k, o_x:o_x + a + m]
+            assert relerr(H[b, i, :a + m, :a + m], Ji.T @ Ji) <= 1e-11
+            assert relerr(g[b, o_x:o_x + a + m], Ji.T @ ri) <= 1e-10
+            rr_ref += float(ri @ ri)
+            o_r += k
+            o_x += a + m
+        assert relerr(rr[b], rr_ref) <= 1e-11
+    print("[gappy 240x240 4x4] FP64 solves, B = 2", flush=True)
+    mus = si.heldout_mu(2, 47)
+    ws = dr.Workspace(gm, 2)
+    out = {k: v.cpu().numpy() for k, v in dr.rom_solve_batch(gm, ws, mus, dr.opts(max_iter=40, tol_rel=1e-10,
+                                                                                  precision=dr.PREC_FP64)).items()}
+    for b in range(2):
+        ref = lsrom.solve(rom, mus[b], max_iter=40, tol_abs=0.0, tol_rel=1e-10)
+        print("gappy 240x240", b, "status", out["status"][b], ref.status, "iters", out["iters"][b], ref.iters,
+              "x err %.2e" % relerr(out["xhat"][b], ref.xhat), flush=True)
+        assert int(out["status"][b]) == ref.status and int(out["iters"][b]) == ref.iters
+        assert relerr(out["xhat"][b], ref.xhat) <= 1e-8
